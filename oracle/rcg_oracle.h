@@ -1,0 +1,90 @@
+/*
+ * Test-infrastructure oracle: plain, slow, FP64 CPU implementation of the
+ * regularized colour-gradient (RCG) two-component lattice Boltzmann step of
+ * Montessori, Lauricella, Tirelli, Succi, "Regularized lattice Boltzmann
+ * multicomponent models for low Capillary and Reynolds microfluidics flows"
+ * (arXiv:1711.02003), Sec. II, Eqs. (1)-(11).
+ *
+ * This code exists only to check the GPU implementation.  Only the tests,
+ * the smoke check and the benchmark's CPU-baseline leg may load it.  It
+ * shares no code, header, table or helper with the GPU library.
+ *
+ * State layout (array-of-structures, the oracle's own choice):
+ *     f[((node * 2) + k) * Q + i],   node = x + nx * (y + ny * z),
+ *     k = 0 (red, "zeta", dispersed) or 1 (blue, "xi", continuous),
+ *     i = 0..Q-1 with i = 0 the rest velocity.
+ * The stored state is the pre-collision population S_t (after streaming).
+ */
+#ifndef RCG_ORACLE_H
+#define RCG_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { ORC_D2Q9 = 0, ORC_D3Q19 = 1 };
+enum { ORC_REGULARIZED = 0, ORC_BGK = 1 };
+
+/* Mask codes: 0 fluid, 1 wall (half-way bounce-back), 2..127 inlet number
+ * (code - 2), 128..255 outlet number (code - 128). */
+typedef struct {
+    double u[3];      /* inlet velocity (lattice units) */
+    double rho_w[2];  /* injected density of each colour */
+} orc_inlet;
+
+typedef struct {
+    double rho;       /* prescribed total density (pressure rho/3) */
+} orc_outlet;
+
+typedef struct {
+    int lattice;            /* ORC_D2Q9 or ORC_D3Q19 */
+    int collision;          /* ORC_REGULARIZED or ORC_BGK */
+    int nx, ny, nz;         /* nz = 1 for D2Q9 */
+    double tau[2];          /* relaxation times, Eq. (5): omega_k = 1/tau_k */
+    double A[2];            /* surface-tension parameters A_k, Eq. (9) */
+    double alpha[2];        /* density-ratio parameters alpha_k, Eq. (7) */
+    double beta;            /* recolouring parameter, Eq. (10) */
+    double eps_F;           /* |F| at or below which F is treated as zero */
+    const uint8_t *mask;    /* nx*ny*nz codes, NULL = every node fluid */
+    int n_inlets;
+    const orc_inlet *inlets;
+    int n_outlets;
+    const orc_outlet *outlets;
+    int n_threads;          /* OpenMP threads, <= 0 = library default */
+} orc_params;
+
+/* Lattice tables as the oracle builds them (for pins in tests).
+ * c: Q*3 ints, w, phi (for given alpha), B: Q doubles each. Returns Q. */
+int orc_lattice(int lattice, double alpha, int *c, double *w, double *phi,
+                double *B, int *opp);
+
+/* S_0 = colour equilibria f^{k,eq}(rho^k, u) of Eq. (6); rhoR, rhoB: N,
+ * u: 3N (component-major, u[a*N + node]) or NULL for rest. */
+int orc_init(const orc_params *p, const double *rhoR, const double *rhoB,
+             const double *u, double *f);
+
+/* Advance f (pre-collision state) by nsteps.  Returns 0 on success. */
+int orc_step(const orc_params *p, double *f, int nsteps);
+
+/* Moments of the pre-collision state: rho^R, rho^B (N each), u (3N,
+ * component-major), psi (N).  Non-fluid nodes get zeros.  Any pointer may be
+ * NULL. */
+int orc_fields(const orc_params *p, const double *f, double *rhoR,
+               double *rhoB, double *u, double *psi);
+
+/* Colour gradient F (3N, component-major) of the pre-collision state. */
+int orc_gradient(const orc_params *p, const double *f, double *F);
+
+/* Collision at one node, exposed for closed-form pins: fin = 2*Q
+ * pre-collision values [k][i], F = colour gradient, fout = 2*Q
+ * post-recolouring values [k][i].  Also returns (optionally) f2 = the Q
+ * total post-perturbation values before recolouring. */
+int orc_collide_node(const orc_params *p, const double *fin, const double *F,
+                     double *fout, double *f2);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
