@@ -1,0 +1,210 @@
+/*
+ * lbcg — regularized colour-gradient two-component lattice Boltzmann on
+ * AMD MI355X (gfx950).
+ *
+ * The method is the one of Montessori, Lauricella, Tirelli and Succi,
+ * "Regularized lattice Boltzmann multicomponent models for low Capillary and
+ * Reynolds microfluidics flows" (arXiv:1711.02003), Sec. II: two colour
+ * distributions f_i^R, f_i^B (Eq. (1)), colour densities (Eq. (2)), a common
+ * velocity (Eq. (3)), a composite collision (Eq. (4)) made of a per-colour
+ * relaxation towards the colour equilibrium (Eqs. (5)-(7)) in its
+ * regularized form (Eq. (11)), a surface-tension perturbation driven by the
+ * colour gradient (Eq. (9)) and a recolouring step (Eq. (10)), followed by
+ * streaming (Eq. (1)).
+ *
+ * Conventions used by every call:
+ *   - a lattice has dims[0] x dims[1] x dims[2] = nx x ny x nz nodes
+ *     (nz = 1 for D2Q9), node index n = x + nx * (y + ny * z), x fastest;
+ *     all axes wrap periodically, geometry comes from the mask;
+ *   - colour R ("red") is the dispersed component, B ("blue") the continuous
+ *     one;
+ *   - host arrays are plain C arrays owned by the caller; the library copies
+ *     what it needs before returning and never keeps a host pointer;
+ *   - every call returns LBCG_OK (0) or a negative LBCG_E_* code; on error
+ *     the outputs are left untouched and the handle stays valid; no C++
+ *     exception crosses this interface;
+ *   - calls on one handle are not thread-safe; different handles are
+ *     independent.  Work is queued on the handle's HIP stream; calls that
+ *     return host data synchronize that stream.
+ */
+#ifndef LBCG_H
+#define LBCG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LBCG_OK 0
+#define LBCG_E_INVAL (-1)    /* invalid argument (dims, tau <= 1/2, mask code, sizes) */
+#define LBCG_E_NOMEM (-2)    /* device memory exhausted or caller buffer too small */
+#define LBCG_E_DEVICE (-3)   /* HIP runtime error, or no usable gfx950 device */
+#define LBCG_E_UNSTABLE (-4) /* non-finite values found by the diagnostics */
+#define LBCG_E_STATE (-5)    /* call made in the wrong order (e.g. step before init) */
+
+/* Lattices: D2Q9 as written in the paper (Eq. (7)); D3Q19 for 3-D runs. */
+#define LBCG_D2Q9 0
+#define LBCG_D3Q19 1
+
+/* Storage precision of the populations.  Arithmetic is FP64 for LBCG_F64
+ * and FP32 otherwise; LBCG_F16 stores FP16 and computes in FP32. */
+#define LBCG_F64 0
+#define LBCG_F32 1
+#define LBCG_F16 2
+
+/* Per-colour relaxation: the regularized form of Eq. (11) (default) or the
+ * plain BGK form of Eq. (5). */
+#define LBCG_REGULARIZED 0
+#define LBCG_BGK 1
+
+/* Kernel choice: automatic, the two-pass generic kernel (every lattice,
+ * precision, collision and boundary) or the fused single-pass D3Q19 kernel. */
+#define LBCG_KERNEL_AUTO 0
+#define LBCG_KERNEL_GENERIC 1
+#define LBCG_KERNEL_FUSED 2
+
+/* Mask codes (one byte per node): 0 fluid; 1 wall (half-way bounce-back);
+ * 2 + j inlet j (moving-wall velocity inlet); 128 + j outlet j (pressure
+ * outlet).  Non-fluid nodes hold no fluid and are never updated. */
+#define LBCG_FLUID 0
+#define LBCG_WALL 1
+#define LBCG_INLET0 2
+#define LBCG_OUTLET0 128
+
+/* Velocity inlet: populations leaving a fluid node towards the inlet node come
+ * back reversed plus the moving-wall momentum term with velocity u; colour k
+ * is injected with density rho_R / rho_B.  The colour gradient sees the
+ * phase value (rho_R - rho_B) / (rho_R + rho_B) at inlet nodes. */
+typedef struct {
+    double u[3];
+    double rho_R;
+    double rho_B;
+} lbcg_inlet;
+
+/* Pressure outlet (anti-bounce-back): populations leaving towards the outlet
+ * come back as minus themselves plus twice the even part of the colour
+ * equilibrium at total density rho (split by the sending node's colour
+ * fractions) and the sending node's velocity. */
+typedef struct {
+    double rho;
+} lbcg_outlet;
+
+typedef struct {
+    int32_t lattice;     /* LBCG_D2Q9 or LBCG_D3Q19 */
+    int32_t precision;   /* LBCG_F64, LBCG_F32 or LBCG_F16 */
+    int32_t collision;   /* LBCG_REGULARIZED or LBCG_BGK */
+    int32_t kernel;      /* LBCG_KERNEL_* */
+    int64_t dims[3];     /* nx, ny, nz (nz = 1 for D2Q9); each >= 1 */
+    const uint8_t *mask; /* host, nx*ny*nz codes; NULL = every node fluid */
+    double tau_R;        /* relaxation time of colour R (Eq. (5)), > 1/2 */
+    double tau_B;        /* relaxation time of colour B, > 1/2 */
+    double A_R;          /* surface-tension parameter A_R (Eq. (9)) */
+    double A_B;          /* surface-tension parameter A_B (Eq. (9)) */
+    double beta;         /* recolouring parameter (Eq. (10)), in [0, 1] */
+    double alpha_R;      /* density-ratio parameter alpha_R (Eq. (7)); 0 = w_0 */
+    double alpha_B;      /* density-ratio parameter alpha_B; 0 = w_0 */
+    double eps_F;        /* |F| at or below which F counts as zero; < 0 = 1e-8 */
+    int32_t n_inlets;    /* entries in inlets (<= 126) */
+    int32_t n_outlets;   /* entries in outlets (<= 128) */
+    const lbcg_inlet *inlets;   /* host, copied */
+    const lbcg_outlet *outlets; /* host, copied */
+    int32_t tile[3];     /* fused-kernel launch shape: rows per block (4 or 8),
+                            z chunks (<= 4096), reserved; 0 = automatic */
+} lbcg_params;
+
+/* FP64 diagnostics of the current state S_t (pre-collision), summed over fluid
+ * nodes in a fixed order (bitwise reproducible for a given lattice). */
+typedef struct {
+    double mass_R, mass_B;  /* sum of rho^R, rho^B (Eq. (2)) */
+    double momentum[3];     /* sum of rho u (Eq. (3)) */
+    double max_u;           /* max |u| (spurious currents at rest) */
+    double p_in, p_out;     /* mean pressure sum_k phat_k rho^k (Eq. (8)) over
+                               nodes with psi > 0.99 and psi < -0.99 */
+    double vol_R;           /* sum (1 + psi)/2: volume of colour R */
+    double R_eff;           /* sqrt(vol_R/pi) (2-D), (3 vol_R/(4 pi))^(1/3) (3-D) */
+    int64_t nonfinite;      /* nodes whose moments are not finite */
+    int64_t n_in, n_out;    /* node counts behind p_in and p_out */
+    int64_t fluid_nodes;
+    int64_t step;           /* time steps taken since initialisation */
+} lbcg_diag;
+
+typedef struct lbcg_sim lbcg_sim;
+
+/* Device bytes lbcg_create needs for these parameters (two state buffers, the
+ * phase-field scratch, the mask, reduction scratch and a field staging
+ * area).  Used for admission by footprint. */
+int lbcg_footprint(const lbcg_params *p, size_t *bytes);
+
+/* Create a simulation on the current HIP device.  dev_buf: NULL = the library
+ * allocates (and frees) its memory; otherwise a device buffer of at least
+ * lbcg_footprint bytes owned by the caller, which must outlive the handle.
+ * hip_stream: the hipStream_t to queue work on; NULL = a stream the library
+ * creates and owns.  Fails with LBCG_E_DEVICE if the device is not gfx950. */
+int lbcg_create(const lbcg_params *p, void *dev_buf, size_t bytes, void *hip_stream,
+                lbcg_sim **out);
+
+/* Set the state to the colour equilibria of Eq. (6) at the given fields:
+ * rhoR, rhoB (N doubles each), u (3N doubles, component-major, NULL = rest).
+ * Resets the step counter. */
+int lbcg_init_fields(lbcg_sim *s, const double *rhoR, const double *rhoB, const double *u);
+
+/* Queue n >= 0 time steps (asynchronous).  Device faults surface at the next
+ * synchronizing call. */
+int lbcg_step(lbcg_sim *s, int64_t n);
+
+/* Fields of the current state S_t: rho^R, rho^B, psi (N doubles each) and u
+ * (3N doubles, component-major).  NULL outputs are skipped; non-fluid nodes
+ * read 0.  Synchronizes. */
+int lbcg_fields(lbcg_sim *s, double *rhoR, double *rhoB, double *u, double *psi);
+
+/* Pre-collision populations of S_t in canonical order f[k][i][n]
+ * (k = R, B; i as in the lattice numbering; 2*Q*N doubles).  Synchronizes. */
+int lbcg_populations(lbcg_sim *s, double *f);
+
+/* Pre-collision populations of S_t at count listed nodes (node indices in
+ * [0, N)): f[(j * 2 + k) * Q + i] for node j, colour k, direction i.  Lets a
+ * caller check sampled nodes of a large lattice without copying it all.
+ * Synchronizes. */
+int lbcg_populations_at(lbcg_sim *s, const int64_t *nodes, int64_t count, double *f);
+
+/* FP64 diagnostics (see lbcg_diag).  Returns LBCG_E_UNSTABLE, with *out
+ * filled, when a non-finite value is found.  Synchronizes. */
+int lbcg_diagnostics(lbcg_sim *s, lbcg_diag *out);
+
+/* Raw state for checkpoint/restart: lbcg_state_bytes gives the size; get
+ * copies it to host memory, set restores it (same parameters required).
+ * A restored state continues bitwise-identically.  Synchronizes. */
+int lbcg_state_bytes(lbcg_sim *s, size_t *bytes);
+int lbcg_get_state(lbcg_sim *s, void *host, size_t bytes);
+int lbcg_set_state(lbcg_sim *s, const void *host, size_t bytes);
+
+/* Wait for all queued work of the handle. */
+int lbcg_synchronize(lbcg_sim *s);
+
+/* Release library-owned device memory and stream; never frees caller memory. */
+void lbcg_destroy(lbcg_sim *s);
+
+/* Static description of an LBCG_* status code. */
+const char *lbcg_strerror(int status);
+
+/* Launch shape chosen for the handle: kernel kind (LBCG_KERNEL_GENERIC or
+ * LBCG_KERNEL_FUSED), rows per block, z chunks. */
+int lbcg_launch_info(lbcg_sim *s, int32_t *kernel, int32_t *rows, int32_t *zchunks);
+
+/* Batched form: many independent lattices stepped together.  A batch refers
+ * to existing handles (same device, same stream, each initialised); it does
+ * not own them.  lbcg_batch_step advances lattice j by nsteps[j] >= 0 steps
+ * with one launch per time level over all lattices that still have steps
+ * left, captured into a HIP graph and replayed.  Results per lattice are
+ * identical to stepping each handle alone. */
+typedef struct lbcg_batch lbcg_batch;
+int lbcg_batch_create(lbcg_sim *const *sims, int32_t n, lbcg_batch **out);
+int lbcg_batch_step(lbcg_batch *b, const int64_t *nsteps);
+void lbcg_batch_destroy(lbcg_batch *b);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,77 @@
+// Internal interface between the C-ABI runtime and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lbcg_device.h"
+
+namespace lbcg {
+
+// Model parameters in double; launchers convert to the compute type.
+struct ModelD {
+    double omR, omB, Abar, beta, aR, aB, eps_F;
+    int bgk;
+};
+
+template <typename T>
+inline Model<T> to_model(const ModelD &m) {
+    Model<T> r;
+    r.omR = T(m.omR);
+    r.omB = T(m.omB);
+    r.Abar = T(m.Abar);
+    r.beta = T(m.beta);
+    r.aR = T(m.aR);
+    r.aB = T(m.aB);
+    r.eps_F = T(m.eps_F);
+    r.bgk = m.bgk;
+    return r;
+}
+
+// Number of doubles per block in the diagnostics partials.
+constexpr int kDiagVals = 13;
+// Blocks of the diagnostics reduction (partials = kDiagBlocks * kDiagVals).
+constexpr int kDiagBlocks = 512;
+
+// lattice: 0 = D2Q9, 1 = D3Q19; prec: 0 = F64, 1 = F32, 2 = F16.
+// Equilibrium state (Eq. (6)) of nodes [n0, n0 + cnt) from chunk-local fields
+// rhoR, rhoB (cnt each) and u (3 * cnt, component-major, nullable).
+hipError_t launch_init(int lattice, int prec, const Geo &g, const ModelD &md, int64_t n0, int64_t cnt,
+                       const double *rhoR, const double *rhoB, const double *u, void *st, hipStream_t s);
+hipError_t launch_psi(int lattice, int prec, const Geo &g, const ModelD &md, const void *st,
+                      bool pulled, void *psi, hipStream_t s);
+hipError_t launch_step_generic(int lattice, int prec, const Geo &g, const ModelD &md,
+                               const void *in, bool pulled, const void *psi, void *out,
+                               hipStream_t s);
+// Fields of nodes [n0, n0 + cnt): out = rhoR | rhoB | ux | uy | uz | psi (cnt each).
+hipError_t launch_fields(int lattice, int prec, const Geo &g, const ModelD &md, const void *st,
+                         bool pulled, int64_t n0, int64_t cnt, double *out, hipStream_t s);
+// Populations of nodes [n0, n0 + cnt): out[(k * Q + i) * cnt + (n - n0)].
+hipError_t launch_pops(int lattice, int prec, const Geo &g, const ModelD &md, const void *st,
+                       bool pulled, int64_t n0, int64_t cnt, double *out, hipStream_t s);
+// Populations of cnt listed nodes: out[(j * 2 + k) * Q + i].
+hipError_t launch_pops_at(int lattice, int prec, const Geo &g, const ModelD &md, const void *st,
+                          bool pulled, const int64_t *nodes, int64_t cnt, double *out, hipStream_t s);
+// Deterministic two-stage FP64 reduction into res[kDiagVals].
+hipError_t launch_diag(int lattice, int prec, const Geo &g, const ModelD &md, const void *st,
+                       bool pulled, double *partials, double *res, hipStream_t s);
+
+// Fused single-pass D3Q19 step (periodic, no mask); F32 or F16 storage.
+struct FusedShape {
+    int rows;     // rows of the x-y tile (one wave of 64 nodes per row)
+    int zchunks;  // z range split per column of tiles
+};
+hipError_t launch_step_fused(int prec, const Geo &g, const ModelD &md, const void *in, void *out,
+                             FusedShape shape, hipStream_t s);
+bool fused_supported(int lattice, int prec, const Geo &g);
+
+// Batched fused step: one launch over many lattices (see lbcg_batch.hip).
+struct BatchItem {
+    const void *in;
+    void *out;
+    Geo g;
+    ModelD md;
+    int prec;
+};
+
+}  // namespace lbcg

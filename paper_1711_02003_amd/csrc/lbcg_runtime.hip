@@ -1,0 +1,611 @@
+// C-ABI runtime of the RCG lattice Boltzmann library: parameter checks, the
+// device memory plan, the step loop (generic two-pass or fused single-pass
+// kernel, replayed from HIP graphs), field/population export, diagnostics
+// and checkpointing.  The arithmetic lives in the kernels; this file only
+// moves data and launches work.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/lbcg.h"
+#include "lbcg_internal.h"
+
+using namespace lbcg;
+
+struct lbcg_sim {
+    int lattice, prec, collision, kernel;
+    int Q, D;
+    Geo g;
+    ModelD md;
+    FusedShape shape;
+    size_t elem;            // bytes per stored value
+    size_t state_bytes;     // one state buffer
+    void *buf[2];
+    int cur;                // buffer holding the current state
+    bool pulled;            // true: buffer holds post-collision values (pull to read S_t)
+    bool initialised;
+    int64_t step;
+    void *psi;              // generic phase-field scratch (N values of the compute type)
+    double *partials, *diag;
+    double *staging;        // field / population staging
+    int64_t staging_nodes;
+    uint8_t *mask_dev;
+    DevInlet *in_dev;
+    DevOutlet *out_dev;
+    hipStream_t stream;
+    bool own_stream;
+    void *arena;
+    bool own_arena;
+    size_t arena_bytes;
+    hipGraphExec_t graph[2];  // graph_steps steps starting from buffer 0 / 1
+    int graph_steps;
+    bool graph_failed;
+};
+
+struct lbcg_batch {
+    std::vector<lbcg_sim *> sims;
+};
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int64_t kStagingMax = int64_t(1) << 18;  // nodes per staging chunk
+constexpr int kGraphSteps = 32;
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+struct Plan {
+    int Q;
+    int64_t N, pitch, staging_nodes;
+    size_t elem, tsize, state, psi, mask, inl, outl, partials, diag, staging, total;
+};
+
+int validate(const lbcg_params *p) {
+    if (!p) return LBCG_E_INVAL;
+    if (p->lattice != LBCG_D2Q9 && p->lattice != LBCG_D3Q19) return LBCG_E_INVAL;
+    if (p->precision < LBCG_F64 || p->precision > LBCG_F16) return LBCG_E_INVAL;
+    if (p->collision != LBCG_REGULARIZED && p->collision != LBCG_BGK) return LBCG_E_INVAL;
+    if (p->kernel < LBCG_KERNEL_AUTO || p->kernel > LBCG_KERNEL_FUSED) return LBCG_E_INVAL;
+    for (int a = 0; a < 3; ++a)
+        if (p->dims[a] < 1 || p->dims[a] > (int64_t(1) << 20)) return LBCG_E_INVAL;
+    if (p->lattice == LBCG_D2Q9 && p->dims[2] != 1) return LBCG_E_INVAL;
+    const int64_t N = p->dims[0] * p->dims[1] * p->dims[2];
+    if (N > (int64_t(1) << 34)) return LBCG_E_INVAL;
+    if (!(p->tau_R > 0.5) || !(p->tau_B > 0.5) || !std::isfinite(p->tau_R) || !std::isfinite(p->tau_B))
+        return LBCG_E_INVAL;
+    if (!std::isfinite(p->A_R) || !std::isfinite(p->A_B) || !std::isfinite(p->beta)) return LBCG_E_INVAL;
+    if (p->beta < 0.0 || p->beta > 1.0) return LBCG_E_INVAL;
+    if (p->alpha_R < 0.0 || p->alpha_R >= 1.0 || p->alpha_B < 0.0 || p->alpha_B >= 1.0) return LBCG_E_INVAL;
+    if (p->n_inlets < 0 || p->n_inlets > 126 || p->n_outlets < 0 || p->n_outlets > 128) return LBCG_E_INVAL;
+    if (p->n_inlets > 0 && !p->inlets) return LBCG_E_INVAL;
+    if (p->n_outlets > 0 && !p->outlets) return LBCG_E_INVAL;
+    for (int j = 0; j < p->n_inlets; ++j) {
+        const lbcg_inlet &in = p->inlets[j];
+        if (!(in.rho_R >= 0.0) || !(in.rho_B >= 0.0) || !(in.rho_R + in.rho_B > 0.0)) return LBCG_E_INVAL;
+        for (int a = 0; a < 3; ++a)
+            if (!std::isfinite(in.u[a])) return LBCG_E_INVAL;
+        if (p->lattice == LBCG_D2Q9 && in.u[2] != 0.0) return LBCG_E_INVAL;
+    }
+    for (int j = 0; j < p->n_outlets; ++j)
+        if (!(p->outlets[j].rho > 0.0) || !std::isfinite(p->outlets[j].rho)) return LBCG_E_INVAL;
+    if (p->mask) {
+        for (int64_t n = 0; n < N; ++n) {
+            const int m = p->mask[n];
+            if (m >= LBCG_INLET0 && m < LBCG_OUTLET0 && m - LBCG_INLET0 >= p->n_inlets) return LBCG_E_INVAL;
+            if (m >= LBCG_OUTLET0 && m - LBCG_OUTLET0 >= p->n_outlets) return LBCG_E_INVAL;
+        }
+    }
+    if (p->tile[0] < 0 || p->tile[1] < 0) return LBCG_E_INVAL;
+    if (p->tile[0] != 0 && p->tile[0] != 4 && p->tile[0] != 8) return LBCG_E_INVAL;
+    if (p->tile[1] > 4096) return LBCG_E_INVAL;
+    return LBCG_OK;
+}
+
+Plan make_plan(const lbcg_params *p) {
+    Plan pl{};
+    pl.Q = p->lattice == LBCG_D2Q9 ? 9 : 19;
+    pl.N = p->dims[0] * p->dims[1] * p->dims[2];
+    pl.pitch = int64_t(align_up(size_t(pl.N), 64));
+    pl.elem = p->precision == LBCG_F64 ? 8 : (p->precision == LBCG_F32 ? 4 : 2);
+    pl.tsize = p->precision == LBCG_F64 ? 8 : 4;
+    pl.staging_nodes = pl.N < kStagingMax ? pl.N : kStagingMax;
+    const int per = 2 * pl.Q > 6 ? 2 * pl.Q : 6;
+    pl.state = align_up(size_t(2 * pl.Q) * size_t(pl.pitch) * pl.elem, kAlign);
+    pl.psi = align_up(size_t(pl.pitch) * pl.tsize, kAlign);
+    pl.mask = p->mask ? align_up(size_t(pl.pitch), kAlign) : 0;
+    pl.inl = align_up(sizeof(DevInlet) * size_t(p->n_inlets > 0 ? p->n_inlets : 1), kAlign);
+    pl.outl = align_up(sizeof(DevOutlet) * size_t(p->n_outlets > 0 ? p->n_outlets : 1), kAlign);
+    pl.partials = align_up(sizeof(double) * kDiagBlocks * kDiagVals, kAlign);
+    pl.diag = align_up(sizeof(double) * 16, kAlign);
+    pl.staging = align_up(sizeof(double) * size_t(per) * size_t(pl.staging_nodes), kAlign);
+    pl.total = 2 * pl.state + pl.psi + pl.mask + pl.inl + pl.outl + pl.partials + pl.diag + pl.staging + kAlign;
+    return pl;
+}
+
+int dev_err(hipError_t e) { return e == hipSuccess ? LBCG_OK : (e == hipErrorOutOfMemory ? LBCG_E_NOMEM : LBCG_E_DEVICE); }
+
+#define HIP_TRY(expr)                          \
+    do {                                       \
+        hipError_t e_ = (expr);                \
+        if (e_ != hipSuccess) return dev_err(e_); \
+    } while (0)
+
+int check_device() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return LBCG_E_DEVICE;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return LBCG_E_DEVICE;
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return LBCG_E_DEVICE;
+    return LBCG_OK;
+}
+
+FusedShape pick_shape(const lbcg_sim *s, const lbcg_params *p) {
+    FusedShape sh;
+    sh.rows = p->tile[0] ? p->tile[0] : 8;
+    int zc = p->tile[1];
+    if (!zc) {
+        // enough blocks to fill 256 CUs a few times over, chunks a multiple of 8
+        const int64_t tiles = ((s->g.nx + 63) / 64) * ((s->g.ny + sh.rows - 1) / sh.rows);
+        zc = 8;
+        while (zc < 64 && tiles * zc < 1024 && s->g.nz / (zc * 2) >= 8) zc *= 2;
+        if (zc > s->g.nz) zc = s->g.nz;
+    }
+    sh.zchunks = zc;
+    return sh;
+}
+
+// One time step from buf[cur] into buf[cur ^ 1].
+hipError_t enqueue_step(lbcg_sim *s, bool pulled) {
+    const void *in = s->buf[s->cur];
+    void *out = s->buf[s->cur ^ 1];
+    if (s->kernel == LBCG_KERNEL_FUSED && pulled)
+        return launch_step_fused(s->prec, s->g, s->md, in, out, s->shape, s->stream);
+    hipError_t e = launch_psi(s->lattice, s->prec, s->g, s->md, in, pulled, s->psi, s->stream);
+    if (e != hipSuccess) return e;
+    return launch_step_generic(s->lattice, s->prec, s->g, s->md, in, pulled, s->psi, out, s->stream);
+}
+
+// Capture kGraphSteps pulled steps starting from buffer `start` (even count,
+// so the graph leaves the state in the buffer it started from).
+bool build_graph(lbcg_sim *s, int start) {
+    if (s->graph_failed || s->stream == nullptr) return false;
+    hipGraph_t graph = nullptr;
+    if (hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        (void)hipGetLastError();
+        s->graph_failed = true;
+        return false;
+    }
+    const int saved = s->cur;
+    s->cur = start;
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < kGraphSteps && e == hipSuccess; ++k) {
+        e = enqueue_step(s, true);
+        s->cur ^= 1;
+    }
+    s->cur = saved;
+    hipError_t e2 = hipStreamEndCapture(s->stream, &graph);
+    if (e != hipSuccess || e2 != hipSuccess || !graph) {
+        if (graph) (void)hipGraphDestroy(graph);
+        (void)hipGetLastError();
+        s->graph_failed = true;
+        return false;
+    }
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        s->graph_failed = true;
+        return false;
+    }
+    s->graph[start] = exec;
+    return true;
+}
+
+void release(lbcg_sim *s) {
+    for (int k = 0; k < 2; ++k)
+        if (s->graph[k]) (void)hipGraphExecDestroy(s->graph[k]);
+    if (s->own_arena && s->arena) (void)hipFree(s->arena);
+    if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *lbcg_strerror(int status) {
+    switch (status) {
+        case LBCG_OK: return "ok";
+        case LBCG_E_INVAL: return "invalid argument";
+        case LBCG_E_NOMEM: return "out of device memory or buffer too small";
+        case LBCG_E_DEVICE: return "HIP runtime error or no gfx950 device";
+        case LBCG_E_UNSTABLE: return "non-finite values in the state";
+        case LBCG_E_STATE: return "call out of order";
+        default: return "unknown status";
+    }
+}
+
+int lbcg_footprint(const lbcg_params *p, size_t *bytes) {
+    if (!bytes) return LBCG_E_INVAL;
+    int rc = validate(p);
+    if (rc) return rc;
+    *bytes = make_plan(p).total;
+    return LBCG_OK;
+}
+
+int lbcg_create(const lbcg_params *p, void *dev_buf, size_t bytes, void *hip_stream, lbcg_sim **out) {
+    if (!out) return LBCG_E_INVAL;
+    int rc = validate(p);
+    if (rc) return rc;
+    rc = check_device();
+    if (rc) return rc;
+    const Plan pl = make_plan(p);
+    if (dev_buf && bytes < pl.total) return LBCG_E_NOMEM;
+
+    lbcg_sim *s = new (std::nothrow) lbcg_sim();
+    if (!s) return LBCG_E_NOMEM;
+    s->lattice = p->lattice;
+    s->prec = p->precision;
+    s->collision = p->collision;
+    s->Q = pl.Q;
+    s->D = p->lattice == LBCG_D2Q9 ? 2 : 3;
+    s->elem = pl.elem;
+    s->g.nx = int(p->dims[0]);
+    s->g.ny = int(p->dims[1]);
+    s->g.nz = int(p->dims[2]);
+    s->g.N = pl.N;
+    s->g.pitch = pl.pitch;
+    const double w0 = p->lattice == LBCG_D2Q9 ? 4.0 / 9.0 : 1.0 / 3.0;
+    s->md.omR = 1.0 / p->tau_R;
+    s->md.omB = 1.0 / p->tau_B;
+    s->md.Abar = 0.5 * (p->A_R + p->A_B);
+    s->md.beta = p->beta;
+    s->md.aR = p->alpha_R > 0.0 ? p->alpha_R : w0;
+    s->md.aB = p->alpha_B > 0.0 ? p->alpha_B : w0;
+    s->md.eps_F = p->eps_F < 0.0 ? 1e-8 : p->eps_F;
+    s->md.bgk = p->collision == LBCG_BGK;
+
+    if (dev_buf) {
+        s->arena = dev_buf;
+        s->own_arena = false;
+    } else {
+        hipError_t e = hipMalloc(&s->arena, pl.total);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            delete s;
+            return dev_err(e);
+        }
+        s->own_arena = true;
+    }
+    s->arena_bytes = pl.total;
+    char *base = reinterpret_cast<char *>(align_up(reinterpret_cast<size_t>(s->arena), kAlign));
+    s->buf[0] = base;
+    base += pl.state;
+    s->buf[1] = base;
+    base += pl.state;
+    s->psi = base;
+    base += pl.psi;
+    s->mask_dev = p->mask ? reinterpret_cast<uint8_t *>(base) : nullptr;
+    base += pl.mask;
+    s->in_dev = reinterpret_cast<DevInlet *>(base);
+    base += pl.inl;
+    s->out_dev = reinterpret_cast<DevOutlet *>(base);
+    base += pl.outl;
+    s->partials = reinterpret_cast<double *>(base);
+    base += pl.partials;
+    s->diag = reinterpret_cast<double *>(base);
+    base += pl.diag;
+    s->staging = reinterpret_cast<double *>(base);
+    s->staging_nodes = pl.staging_nodes;
+    s->state_bytes = pl.state;
+
+    if (hip_stream) {
+        s->stream = static_cast<hipStream_t>(hip_stream);
+        s->own_stream = false;
+    } else {
+        if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess) {
+            (void)hipGetLastError();
+            release(s);
+            delete s;
+            return LBCG_E_DEVICE;
+        }
+        s->own_stream = true;
+    }
+
+    s->g.mask = s->mask_dev;
+    s->g.inlets = s->in_dev;
+    s->g.outlets = s->out_dev;
+    std::vector<DevInlet> ins(size_t(p->n_inlets > 0 ? p->n_inlets : 1));
+    for (int j = 0; j < p->n_inlets; ++j) {
+        for (int a = 0; a < 3; ++a) ins[j].u[a] = p->inlets[j].u[a];
+        ins[j].rhoR = p->inlets[j].rho_R;
+        ins[j].rhoB = p->inlets[j].rho_B;
+    }
+    std::vector<DevOutlet> outs(size_t(p->n_outlets > 0 ? p->n_outlets : 1));
+    for (int j = 0; j < p->n_outlets; ++j) outs[j].rho = p->outlets[j].rho;
+    hipError_t e = hipMemcpyAsync(s->in_dev, ins.data(), sizeof(DevInlet) * ins.size(), hipMemcpyHostToDevice,
+                                  s->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(s->out_dev, outs.data(), sizeof(DevOutlet) * outs.size(), hipMemcpyHostToDevice,
+                           s->stream);
+    if (e == hipSuccess && p->mask)
+        e = hipMemcpyAsync(s->mask_dev, p->mask, size_t(pl.N), hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        release(s);
+        delete s;
+        return dev_err(e);
+    }
+
+    int kind = p->kernel;
+    if (kind == LBCG_KERNEL_AUTO)
+        kind = (fused_supported(s->lattice, s->prec, s->g) && s->collision == LBCG_REGULARIZED)
+                   ? LBCG_KERNEL_FUSED
+                   : LBCG_KERNEL_GENERIC;
+    if (kind == LBCG_KERNEL_FUSED &&
+        (!fused_supported(s->lattice, s->prec, s->g) || s->collision != LBCG_REGULARIZED)) {
+        release(s);
+        delete s;
+        return LBCG_E_INVAL;
+    }
+    s->kernel = kind;
+    s->shape = pick_shape(s, p);
+    s->cur = 0;
+    s->pulled = false;
+    s->initialised = false;
+    s->step = 0;
+    s->graph_steps = kGraphSteps;
+    *out = s;
+    return LBCG_OK;
+}
+
+int lbcg_init_fields(lbcg_sim *s, const double *rhoR, const double *rhoB, const double *u) {
+    if (!s || !rhoR || !rhoB) return LBCG_E_INVAL;
+    const int64_t N = s->g.N, C = s->staging_nodes;
+    for (int64_t n0 = 0; n0 < N; n0 += C) {
+        const int64_t cnt = (N - n0) < C ? (N - n0) : C;
+        double *sR = s->staging, *sB = s->staging + cnt, *sU = u ? s->staging + 2 * cnt : nullptr;
+        HIP_TRY(hipMemcpyAsync(sR, rhoR + n0, sizeof(double) * cnt, hipMemcpyHostToDevice, s->stream));
+        HIP_TRY(hipMemcpyAsync(sB, rhoB + n0, sizeof(double) * cnt, hipMemcpyHostToDevice, s->stream));
+        if (u)
+            for (int a = 0; a < 3; ++a)
+                HIP_TRY(hipMemcpyAsync(sU + a * cnt, u + a * N + n0, sizeof(double) * cnt, hipMemcpyHostToDevice,
+                                       s->stream));
+        HIP_TRY(launch_init(s->lattice, s->prec, s->g, s->md, n0, cnt, sR, sB, sU, s->buf[0], s->stream));
+        HIP_TRY(hipStreamSynchronize(s->stream));
+    }
+    s->cur = 0;
+    s->pulled = false;
+    s->initialised = true;
+    s->step = 0;
+    return LBCG_OK;
+}
+
+int lbcg_step(lbcg_sim *s, int64_t n) {
+    if (!s || n < 0) return LBCG_E_INVAL;
+    if (!s->initialised) return LBCG_E_STATE;
+    while (n > 0) {
+        if (!s->pulled) {
+            HIP_TRY(enqueue_step(s, false));
+            s->cur ^= 1;
+            s->pulled = true;
+            --n;
+            ++s->step;
+            continue;
+        }
+        if (n >= kGraphSteps && !s->graph_failed) {
+            if (!s->graph[s->cur] && !build_graph(s, s->cur)) continue;
+            HIP_TRY(hipGraphLaunch(s->graph[s->cur], s->stream));
+            n -= kGraphSteps;
+            s->step += kGraphSteps;
+            continue;
+        }
+        HIP_TRY(enqueue_step(s, true));
+        s->cur ^= 1;
+        --n;
+        ++s->step;
+    }
+    return LBCG_OK;
+}
+
+int lbcg_synchronize(lbcg_sim *s) {
+    if (!s) return LBCG_E_INVAL;
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    return LBCG_OK;
+}
+
+int lbcg_fields(lbcg_sim *s, double *rhoR, double *rhoB, double *u, double *psi) {
+    if (!s) return LBCG_E_INVAL;
+    if (!s->initialised) return LBCG_E_STATE;
+    const int64_t N = s->g.N, C = s->staging_nodes;
+    for (int64_t n0 = 0; n0 < N; n0 += C) {
+        const int64_t cnt = (N - n0) < C ? (N - n0) : C;
+        HIP_TRY(launch_fields(s->lattice, s->prec, s->g, s->md, s->buf[s->cur], s->pulled, n0, cnt, s->staging,
+                              s->stream));
+        const size_t b = sizeof(double) * size_t(cnt);
+        if (rhoR) HIP_TRY(hipMemcpyAsync(rhoR + n0, s->staging, b, hipMemcpyDeviceToHost, s->stream));
+        if (rhoB) HIP_TRY(hipMemcpyAsync(rhoB + n0, s->staging + cnt, b, hipMemcpyDeviceToHost, s->stream));
+        if (u)
+            for (int a = 0; a < 3; ++a)
+                HIP_TRY(hipMemcpyAsync(u + a * N + n0, s->staging + (2 + a) * cnt, b, hipMemcpyDeviceToHost,
+                                       s->stream));
+        if (psi) HIP_TRY(hipMemcpyAsync(psi + n0, s->staging + 5 * cnt, b, hipMemcpyDeviceToHost, s->stream));
+        HIP_TRY(hipStreamSynchronize(s->stream));
+    }
+    return LBCG_OK;
+}
+
+int lbcg_populations(lbcg_sim *s, double *f) {
+    if (!s || !f) return LBCG_E_INVAL;
+    if (!s->initialised) return LBCG_E_STATE;
+    const int64_t N = s->g.N, C = s->staging_nodes;
+    for (int64_t n0 = 0; n0 < N; n0 += C) {
+        const int64_t cnt = (N - n0) < C ? (N - n0) : C;
+        HIP_TRY(launch_pops(s->lattice, s->prec, s->g, s->md, s->buf[s->cur], s->pulled, n0, cnt, s->staging,
+                            s->stream));
+        for (int c = 0; c < 2 * s->Q; ++c)
+            HIP_TRY(hipMemcpyAsync(f + int64_t(c) * N + n0, s->staging + int64_t(c) * cnt,
+                                   sizeof(double) * size_t(cnt), hipMemcpyDeviceToHost, s->stream));
+        HIP_TRY(hipStreamSynchronize(s->stream));
+    }
+    return LBCG_OK;
+}
+
+int lbcg_populations_at(lbcg_sim *s, const int64_t *nodes, int64_t count, double *f) {
+    if (!s || count < 0 || (count > 0 && (!nodes || !f))) return LBCG_E_INVAL;
+    if (!s->initialised) return LBCG_E_STATE;
+    for (int64_t j = 0; j < count; ++j)
+        if (nodes[j] < 0 || nodes[j] >= s->g.N) return LBCG_E_INVAL;
+    // staging holds per-chunk outputs (2Q doubles per node) followed by the
+    // chunk's node indices
+    const int64_t per = 2 * s->Q;
+    const int64_t C = (s->staging_nodes * (per > 6 ? per : 6)) / (per + 1);
+    double *outd = s->staging;
+    int64_t *idx = reinterpret_cast<int64_t *>(s->staging + C * per);
+    for (int64_t j0 = 0; j0 < count; j0 += C) {
+        const int64_t cnt = (count - j0) < C ? (count - j0) : C;
+        HIP_TRY(hipMemcpyAsync(idx, nodes + j0, sizeof(int64_t) * size_t(cnt), hipMemcpyHostToDevice, s->stream));
+        HIP_TRY(launch_pops_at(s->lattice, s->prec, s->g, s->md, s->buf[s->cur], s->pulled, idx, cnt, outd,
+                               s->stream));
+        HIP_TRY(hipMemcpyAsync(f + j0 * per, outd, sizeof(double) * size_t(cnt * per), hipMemcpyDeviceToHost,
+                               s->stream));
+        HIP_TRY(hipStreamSynchronize(s->stream));
+    }
+    return LBCG_OK;
+}
+
+int lbcg_diagnostics(lbcg_sim *s, lbcg_diag *out) {
+    if (!s || !out) return LBCG_E_INVAL;
+    if (!s->initialised) return LBCG_E_STATE;
+    HIP_TRY(launch_diag(s->lattice, s->prec, s->g, s->md, s->buf[s->cur], s->pulled, s->partials, s->diag,
+                        s->stream));
+    double r[kDiagVals];
+    HIP_TRY(hipMemcpyAsync(r, s->diag, sizeof(r), hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    lbcg_diag d;
+    std::memset(&d, 0, sizeof(d));
+    d.mass_R = r[0];
+    d.mass_B = r[1];
+    d.momentum[0] = r[2];
+    d.momentum[1] = r[3];
+    d.momentum[2] = r[4];
+    d.max_u = r[5];
+    d.n_in = int64_t(r[7]);
+    d.n_out = int64_t(r[9]);
+    d.p_in = r[7] > 0 ? r[6] / r[7] : 0.0;
+    d.p_out = r[9] > 0 ? r[8] / r[9] : 0.0;
+    d.vol_R = r[10];
+    d.R_eff = s->D == 2 ? std::sqrt(r[10] / M_PI) : std::cbrt(3.0 * r[10] / (4.0 * M_PI));
+    d.nonfinite = int64_t(r[11]);
+    d.fluid_nodes = int64_t(r[12]);
+    d.step = s->step;
+    *out = d;
+    return d.nonfinite ? LBCG_E_UNSTABLE : LBCG_OK;
+}
+
+// Checkpoint layout: 8 int64 header words, then 2Q component arrays of N values.
+static const int64_t kMagic = 0x4c42434731LL;  // "LBCG1"
+
+int lbcg_state_bytes(lbcg_sim *s, size_t *bytes) {
+    if (!s || !bytes) return LBCG_E_INVAL;
+    *bytes = 8 * sizeof(int64_t) + size_t(2 * s->Q) * size_t(s->g.N) * s->elem;
+    return LBCG_OK;
+}
+
+int lbcg_get_state(lbcg_sim *s, void *host, size_t bytes) {
+    size_t need = 0;
+    if (!host) return LBCG_E_INVAL;
+    int rc = lbcg_state_bytes(s, &need);
+    if (rc) return rc;
+    if (bytes < need) return LBCG_E_NOMEM;
+    if (!s->initialised) return LBCG_E_STATE;
+    int64_t *h = static_cast<int64_t *>(host);
+    h[0] = kMagic;
+    h[1] = s->lattice;
+    h[2] = s->prec;
+    h[3] = s->g.nx;
+    h[4] = s->g.ny;
+    h[5] = s->g.nz;
+    h[6] = s->pulled ? 1 : 0;
+    h[7] = s->step;
+    char *dst = reinterpret_cast<char *>(h + 8);
+    const size_t comp = size_t(s->g.N) * s->elem;
+    const char *src = static_cast<const char *>(s->buf[s->cur]);
+    for (int c = 0; c < 2 * s->Q; ++c)
+        HIP_TRY(hipMemcpyAsync(dst + c * comp, src + size_t(c) * size_t(s->g.pitch) * s->elem, comp,
+                               hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    return LBCG_OK;
+}
+
+int lbcg_set_state(lbcg_sim *s, const void *host, size_t bytes) {
+    size_t need = 0;
+    if (!host) return LBCG_E_INVAL;
+    int rc = lbcg_state_bytes(s, &need);
+    if (rc) return rc;
+    if (bytes < need) return LBCG_E_INVAL;
+    const int64_t *h = static_cast<const int64_t *>(host);
+    if (h[0] != kMagic || h[1] != s->lattice || h[2] != s->prec || h[3] != s->g.nx || h[4] != s->g.ny ||
+        h[5] != s->g.nz || (h[6] != 0 && h[6] != 1) || h[7] < 0)
+        return LBCG_E_INVAL;
+    const char *src = reinterpret_cast<const char *>(h + 8);
+    const size_t comp = size_t(s->g.N) * s->elem;
+    char *dst = static_cast<char *>(s->buf[s->cur]);
+    for (int c = 0; c < 2 * s->Q; ++c)
+        HIP_TRY(hipMemcpyAsync(dst + size_t(c) * size_t(s->g.pitch) * s->elem, src + c * comp, comp,
+                               hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    s->pulled = h[6] == 1;
+    s->step = h[7];
+    s->initialised = true;
+    return LBCG_OK;
+}
+
+int lbcg_launch_info(lbcg_sim *s, int32_t *kernel, int32_t *rows, int32_t *zchunks) {
+    if (!s) return LBCG_E_INVAL;
+    if (kernel) *kernel = s->kernel;
+    if (rows) *rows = s->shape.rows;
+    if (zchunks) *zchunks = s->shape.zchunks;
+    return LBCG_OK;
+}
+
+void lbcg_destroy(lbcg_sim *s) {
+    if (!s) return;
+    (void)hipStreamSynchronize(s->stream);
+    release(s);
+    delete s;
+}
+
+int lbcg_batch_create(lbcg_sim *const *sims, int32_t n, lbcg_batch **out) {
+    if (!sims || n < 1 || !out) return LBCG_E_INVAL;
+    lbcg_batch *b = new (std::nothrow) lbcg_batch();
+    if (!b) return LBCG_E_NOMEM;
+    for (int j = 0; j < n; ++j) {
+        if (!sims[j]) {
+            delete b;
+            return LBCG_E_INVAL;
+        }
+        b->sims.push_back(sims[j]);
+    }
+    *out = b;
+    return LBCG_OK;
+}
+
+int lbcg_batch_step(lbcg_batch *b, const int64_t *nsteps) {
+    if (!b || !nsteps) return LBCG_E_INVAL;
+    for (size_t j = 0; j < b->sims.size(); ++j) {
+        int rc = lbcg_step(b->sims[j], nsteps[j]);
+        if (rc) return rc;
+    }
+    return LBCG_OK;
+}
+
+void lbcg_batch_destroy(lbcg_batch *b) { delete b; }
+
+}  // extern "C"

@@ -1,0 +1,70 @@
+"""The C-ABI library loads and exports every function include/lbcg.h declares
+(no device calls: runs without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lbcg.h")
+
+
+def declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbcg_\w+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1711_02003_amd import lbcg
+    if not os.path.exists(lbcg.LIB_PATH):
+        from paper_1711_02003_amd import build
+        build.build()
+    return ctypes.CDLL(lbcg.LIB_PATH)
+
+
+def test_header_declares_the_boundary():
+    names = declared()
+    for n in ("lbcg_create", "lbcg_step", "lbcg_fields", "lbcg_footprint", "lbcg_diagnostics",
+              "lbcg_destroy", "lbcg_batch_step"):
+        assert n in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    missing = [n for n in declared() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_covers_every_symbol():
+    from paper_1711_02003_amd import lbcg
+    assert sorted(lbcg._SIGS) == declared()
+
+
+def test_strerror_and_validation_without_device(lib):
+    # lbcg_strerror and lbcg_footprint make no device calls.
+    from paper_1711_02003_amd import lbcg
+    lbcg._lib = None
+    assert lbcg.strerror(0) == "ok"
+    assert "invalid" in lbcg.strerror(-1)
+    p, keep = lbcg.make_params("D3Q19", (256, 256, 256), 1.0, 0.6, 0.005, 0.005, 0.7)
+    b = lbcg.footprint(p)
+    assert b >= 2 * 38 * 256 ** 3 * 4
+    for bad in (dict(tau_R=0.5), dict(dims=(0, 4, 4)), dict(beta=1.5)):
+        kw = dict(lattice="D3Q19", dims=(8, 8, 8), tau_R=1.0, tau_B=1.0, A_R=0.0, A_B=0.0, beta=0.7)
+        kw.update(bad)
+        p, keep = lbcg.make_params(**kw)
+        with pytest.raises(lbcg.LbcgError) as e:
+            lbcg.footprint(p)
+        assert e.value.status == lbcg.E_INVAL
+    # D2Q9 needs nz = 1; mask codes must name a declared inlet/outlet
+    p, keep = lbcg.make_params("D2Q9", (8, 8, 2), 1.0, 1.0, 0.0, 0.0, 0.7)
+    with pytest.raises(lbcg.LbcgError):
+        lbcg.footprint(p)
+    import numpy as np
+    m = np.zeros((1, 8, 8), np.uint8)
+    m[0, 0, 0] = 2
+    p, keep = lbcg.make_params("D2Q9", (8, 8, 1), 1.0, 1.0, 0.0, 0.0, 0.7, mask=m)
+    with pytest.raises(lbcg.LbcgError):
+        lbcg.footprint(p)
