@@ -1,0 +1,177 @@
+"""Benchmark of the regularized colour-gradient D3Q19 step on one MI355X.
+
+Workload: the 27-droplet periodic D3Q19 box, 256^3, FP32 storage and
+arithmetic (tau_R = 1, tau_B = 0.6, A = 0.005, beta = 0.7), fused
+single-pass kernel.  A step is one full time step of every node (both
+colours).  Prints one JSON line:
+
+  value      whole-job two-component MLUPS (fluid nodes x steps / time), inputs
+             resident in HBM, timed with HIP events on the simulation's stream;
+  roofline   HBM roofline of the fused kernel: algorithmic bytes per node
+             (read + write every population of both colours once, 2 x 38 x 4 =
+             304 B) x nodes / average kernel time, against 8 TB/s; traffic =
+             HBM bytes per launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE
+             counters scaled by a copy-kernel calibration (null when the
+             kernel source changed since the counters were taken);
+  cpu_baseline  the FP64 CPU oracle timed on this host on a bounded sample;
+  copy_probe achieved bandwidth of a plain device-to-device copy (context).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fused_d3q19_f32_256_traffic.txt")
+KERNEL_SOURCES = ["paper_1711_02003_amd/csrc/lbcg_fused.hip", "paper_1711_02003_amd/csrc/lbcg_device.h"]
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic():
+    """HBM bytes per launch from the committed counter summary, if current."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line:
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_hash") != kernel_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_probe(torch, nbytes=2 << 30, reps=10):
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    src.fill_(1.0)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    return {"gbps": round(2 * nbytes / ms / 1e6, 1), "bytes_per_copy": 2 * nbytes}
+
+
+def cpu_baseline(w, steps=2, threads=16):
+    import oracle
+    from tests.helpers import oracle_for
+    oracle.build(force=False)
+    o = oracle_for(oracle, w, threads=threads)
+    t = time.time()
+    o.step(steps)
+    dt = time.time() - t
+    return {"value": round(w.fluid_nodes * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{steps} of the workload's {w.steps} steps on the full {w.dims[0]}^3 lattice, "
+                      f"FP64, OpenMP over nodes"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--size", type=int, default=256)
+    ap.add_argument("--precision", default="f32", choices=["f32", "f16"])
+    ap.add_argument("--rows", type=int, default=0)
+    ap.add_argument("--zchunks", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-copy-probe", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+                                   "(the multi-GPU slab decomposition is design only)"}))
+        sys.exit(2)
+
+    import torch
+
+    from paper_1711_02003_amd import lbcg
+    from paper_1711_02003_amd import workloads as W
+
+    w = W.config2(L=args.size, seed=2)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        sim = lbcg.Sim.from_workload(w, precision=args.precision, kernel=lbcg.KERNEL_FUSED,
+                                     tile=(args.rows, args.zchunks, 0))
+    info = sim.launch_info()
+    sim.step(args.warmup)
+    sim.synchronize()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    sim.step(args.steps)
+    e1.record(stream)
+    e1.synchronize()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    ms_step = ms / args.steps
+    diag = sim.diagnostics()
+    sim.close()
+    if diag["status"] != 0:
+        print(json.dumps({"error": "non-finite state after the timed steps"}))
+        sys.exit(1)
+
+    N = w.fluid_nodes
+    elem = 4 if args.precision == "f32" else 2
+    bytes_node = 2 * 2 * 19 * elem
+    mlups = N * args.steps / (ms / 1e3) / 1e6
+    achieved = bytes_node * N / (ms_step / 1e3) / 1e9
+    traffic = read_traffic() if args.precision == "f32" and args.size == 256 else None
+    out = {
+        "metric": "two-component MLUPS, D3Q19 regularized colour-gradient step",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.precision,
+        "data": "synthetic",
+        "config": {"workload": w.name, "lattice": "D3Q19", "dims": list(w.dims),
+                   "droplets": 27, "tau_R": w.tau_R, "tau_B": w.tau_B, "A": w.A, "beta": w.beta,
+                   "storage": args.precision, "kernel": "fused",
+                   "rows": info["rows"], "zchunks": info["zchunks"]},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "bytes_per_node": bytes_node},
+        "wall_s": round(wall, 3),
+    }
+    if not args.no_copy_probe:
+        out["copy_probe"] = copy_probe(torch)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

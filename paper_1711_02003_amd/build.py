@@ -11,8 +11,11 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbcg.so")
 
 # -packed-fp32-ops: keep the compiler from emitting packed FP32 instructions.
+# -ffp-contract=on: fuse a*b+c only inside one source expression, so every
+# kernel instantiation rounds identically (bitwise results independent of the
+# launch shape).
 HIPCC_FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=on",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
 ]

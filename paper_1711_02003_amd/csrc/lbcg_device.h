@@ -4,14 +4,21 @@
 // update.  Everything here is header-only so the generic and the fused
 // kernels inline the same arithmetic.
 //
-// Storage (per population i of a node): the total deviation
-//     df_i = f_i^R + f_i^B - w_i          (rest reference density 1)
-// and the red fraction
-//     chi_i = f_i^R / (f_i^R + f_i^B).
+// Storage (per population i of a node), two values:
+//   df_i = f_i^R + f_i^B - w_i       total deviation from the rest state at
+//                                    density 1 (FP16 keeps df_i / w_i);
+//   m_i  = the minority colour's share of f_i (f_i^B / f_i when red is the
+//          majority of the population, f_i^R / f_i otherwise), rounded to
+//          one bit less than the storage format, with the freed lowest bit
+//          holding the majority flag (1 = red majority).
 // The total deviation keeps the small hydrodynamic signal (density and
-// velocity perturbations) at full relative precision; chi is exactly 1 or 0
-// in the bulk of each colour, so colour bookkeeping adds no round-off there.
-// FP16 storage keeps df_i / w_i instead of df_i to stay in the normal range.
+// velocity perturbations) at full relative precision.  Storing the minority
+// share keeps the thin tails of each colour inside the other one at full
+// relative precision too: a plain red fraction would be rounded to exactly 1
+// deep inside red drops (the spacing of floating-point numbers just below 1
+// is coarse) and so turn a little blue into red every step.  Sums that would
+// cancel exactly in the bulk (sum_i w_i = 1, sum_i w_i Q_i = 0) are done with
+// integer-scaled weights, so bulk nodes carry no colour round-off at all.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -32,6 +39,8 @@ struct D2Q9 {
     static constexpr int opp[9] = {0, 5, 6, 7, 8, 1, 2, 3, 4};
     // weights 4/9, 1/9, 1/36 by squared speed 0, 1, 2
     static constexpr double wc[3] = {4.0 / 9.0, 1.0 / 9.0, 1.0 / 36.0};
+    // the same weights in units of 1/36
+    static constexpr int w36[3] = {16, 4, 1};
 };
 
 // D3Q19: rest; +x -x +y -y +z -z; the twelve face diagonals grouped by plane
@@ -43,6 +52,7 @@ struct D3Q19 {
     static constexpr int cz[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1};
     static constexpr int opp[19] = {0, 2, 1, 4, 3, 6, 5, 10, 9, 8, 7, 14, 13, 12, 11, 18, 17, 16, 15};
     static constexpr double wc[3] = {1.0 / 3.0, 1.0 / 18.0, 1.0 / 36.0};
+    static constexpr int w36[3] = {12, 2, 1};
 };
 
 template <class L>
@@ -52,6 +62,16 @@ __host__ __device__ constexpr int csq(int i) {
 template <class L>
 __host__ __device__ constexpr double wgt(int i) {
     return L::wc[csq<L>(i)];
+}
+// 36 w_i (an integer) and 108 w_i (c_ia^2 - 1/3) = 3 * 36 w_i c_ia^2 - 36 w_i
+template <class L>
+__host__ __device__ constexpr int w36(int i) {
+    return L::w36[csq<L>(i)];
+}
+template <class L>
+__host__ __device__ constexpr int wq108(int i, int a) {
+    return 3 * w36<L>(i) * (a == 0 ? L::cx[i] * L::cx[i] : (a == 1 ? L::cy[i] * L::cy[i] : L::cz[i] * L::cz[i])) -
+           w36<L>(i);
 }
 // Perturbation constants B_i = w_i (|c_i|^2 - (D - 1) c_s^2): the choice with
 // sum_i B_i = c_s^2 (mass kept) and sum_i B_i c_i c_i = 3 c_s^4 I.
@@ -80,6 +100,8 @@ struct Model {
     T Abar;          // (A_R + A_B)/2: the perturbations of both colours summed
     T beta;
     T aR, aB;        // alpha_k (Eq. (7)); w_0 for equal densities
+    T dR0, dB0;      // phi_0^k - w_0 = alpha_k - w_0
+    T kR, kB;        // (phi_i^k - w_i) / w_i = (w_0 - alpha_k) / (1 - w_0), i > 0
     T eps_F;
     int bgk;         // plain BGK relaxation (Eq. (5)) instead of Eq. (11)
 };
@@ -95,13 +117,73 @@ struct Geo {
 
 __device__ __forceinline__ int wrap_m1(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
 
+// Reciprocal and square root for quantities whose rounding does not feed the
+// colour bookkeeping (velocity, 1/|F|).  FP32: the hardware reciprocal refined
+// by one Newton step, and the hardware square root.  FP64: exact division and
+// square root.
+template <typename T>
+__device__ __forceinline__ T rcp(T x);
+template <>
+__device__ __forceinline__ float rcp<float>(float x) {
+    const float r = __builtin_amdgcn_rcpf(x);
+    const float e = __builtin_fmaf(-x, r, 1.0f);
+    return __builtin_fmaf(r, e, r);
+}
+template <>
+__device__ __forceinline__ double rcp<double>(double x) { return 1.0 / x; }
+template <typename T>
+__device__ __forceinline__ T sqrt_(T x);
+template <>
+__device__ __forceinline__ float sqrt_<float>(float x) { return __builtin_amdgcn_sqrtf(x); }
+template <>
+__device__ __forceinline__ double sqrt_<double>(double x) { return sqrt(x); }
+
 // ---------------------------------------------------------------- codec
+// Round away the lowest bit (to nearest, ties to even on the next bit) and put
+// the flag there.  U is the unsigned integer of the storage width.
+template <typename U>
+__device__ __forceinline__ U pack_flag(U b, bool flag) {
+    const U b0 = b & U(1), b1 = (b >> 1) & U(1);
+    b = U(b + (b0 & b1) - (b0 & (b1 ^ U(1))));
+    return U((b & U(~U(1))) | U(flag ? 1 : 0));
+}
+
 template <typename S>
-struct Codec {
+struct Codec;
+template <>
+struct Codec<double> {
     template <class L, typename T>
-    __device__ static __forceinline__ T df(S v, int) { return T(v); }
+    __device__ static __forceinline__ T df(double v, int) { return T(v); }
     template <class L, typename T>
-    __device__ static __forceinline__ S enc_df(T v, int) { return S(v); }
+    __device__ static __forceinline__ double enc_df(T v, int) { return double(v); }
+    template <typename T>
+    __device__ static __forceinline__ T col(double v, bool &flag) {
+        const uint64_t b = uint64_t(__double_as_longlong(v));
+        flag = b & 1;
+        return T(__longlong_as_double((long long)(b & ~uint64_t(1))));
+    }
+    template <typename T>
+    __device__ static __forceinline__ double enc_col(T m, bool flag) {
+        return __longlong_as_double(
+            (long long)pack_flag<uint64_t>(uint64_t(__double_as_longlong(double(m))), flag));
+    }
+};
+template <>
+struct Codec<float> {
+    template <class L, typename T>
+    __device__ static __forceinline__ T df(float v, int) { return T(v); }
+    template <class L, typename T>
+    __device__ static __forceinline__ float enc_df(T v, int) { return float(v); }
+    template <typename T>
+    __device__ static __forceinline__ T col(float v, bool &flag) {
+        const uint32_t b = __float_as_uint(v);
+        flag = b & 1u;
+        return T(__uint_as_float(b & ~1u));
+    }
+    template <typename T>
+    __device__ static __forceinline__ float enc_col(T m, bool flag) {
+        return __uint_as_float(pack_flag<uint32_t>(__float_as_uint(float(m)), flag));
+    }
 };
 template <>
 struct Codec<_Float16> {
@@ -111,97 +193,169 @@ struct Codec<_Float16> {
     __device__ static __forceinline__ _Float16 enc_df(T v, int i) {
         return _Float16(float(v * T(1.0 / wgt<L>(i))));
     }
+    template <typename T>
+    __device__ static __forceinline__ T col(_Float16 v, bool &flag) {
+        const uint16_t b = __builtin_bit_cast(uint16_t, v);
+        flag = b & 1u;
+        return T(float(__builtin_bit_cast(_Float16, uint16_t(b & ~1u))));
+    }
+    template <typename T>
+    __device__ static __forceinline__ _Float16 enc_col(T m, bool flag) {
+        const uint16_t b = __builtin_bit_cast(uint16_t, _Float16(float(m)));
+        return __builtin_bit_cast(_Float16, pack_flag<uint16_t>(b, flag));
+    }
+};
+
+// One node's populations in registers: total deviations, minority shares and
+// the majority flags (bit i set = red majority of population i).
+template <class L, typename T>
+struct Pops {
+    T df[L::Q];
+    T mm[L::Q];
+    uint32_t red;
+    __device__ __forceinline__ bool flag(int i) const { return (red >> i) & 1u; }
+    __device__ __forceinline__ void set(int i, T d, T m, bool fl) {
+        df[i] = d;
+        mm[i] = m;
+        red = fl ? (red | (1u << i)) : (red & ~(1u << i));
+    }
+    // red part of population i
+    __device__ __forceinline__ T fred(int i) const {
+        const T f = T(wgt<L>(i)) + df[i];
+        const T mu = mm[i] * f;
+        return flag(i) ? f - mu : mu;
+    }
 };
 
 template <class L, typename S, typename T>
 __device__ __forceinline__ void load_raw(const S *__restrict__ st, int64_t pitch, int64_t node, int i,
-                                         T &df, T &chi) {
-    df = Codec<S>::template df<L, T>(st[int64_t(i) * pitch + node], i);
-    chi = T(st[int64_t(L::Q + i) * pitch + node]);
+                                         Pops<L, T> &p) {
+    bool fl;
+    const T d = Codec<S>::template df<L, T>(st[int64_t(i) * pitch + node], i);
+    const T m = Codec<S>::template col<T>(st[int64_t(L::Q + i) * pitch + node], fl);
+    p.set(i, d, m, fl);
+}
+
+// Minority share and majority flag from the red and blue shares of a
+// population (each formed directly, so the minority one is precise).
+template <typename T>
+__device__ __forceinline__ void split_shares(T shareR, T shareB, T &m, bool &redmaj) {
+    redmaj = shareR >= shareB;
+    m = redmaj ? shareB : shareR;
 }
 
 // ---------------------------------------------------------------- moments
-// Density and red density (Eq. (2)); also what the phase field needs.  Every
+// Densities (Eq. (2)): the deviation of the total density, and the red and
+// blue densities, each accumulated so that a node's minority colour is summed
+// directly from its small shares (precise in the other colour's bulk).  Every
 // path computes psi through this one expression sequence, so psi is bitwise
 // the same whichever kernel or tile shape produced it.
 template <class L, typename T>
-__device__ __forceinline__ void densities(const T *df, const T *chi, T &drho_out, T &rhoR) {
-    T drho = 0, r1 = 0, r2 = 0;
-    const T c0 = chi[0];
+__device__ __forceinline__ void densities(const Pops<L, T> &p, T &drho_out, T &rR, T &rB) {
+    // Colour sums are kept in units of 1/36 (the weights are then the integers
+    // 36 w_i) and rounded once at the end: a rounded weight constant would
+    // shift every mixed node's colour mass the same way, step after step.
+    T drho = 0, A = 0, Mu = 0;
+    int K = 0;
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) {
-        drho += df[i];
-        r1 += (chi[i] - c0) * T(wgt<L>(i));
-        r2 += chi[i] * df[i];
+        const T d = p.df[i];
+        const bool fl = p.flag(i);
+        const T mu = p.mm[i] * (T(w36<L>(i)) + T(36) * d);  // 36 x minority part
+        drho += d;
+        A += fl ? d : T(0);
+        K += fl ? w36<L>(i) : 0;
+        Mu += fl ? -mu : mu;
     }
     drho_out = drho;
-    rhoR = c0 + r1 + r2;
+    // red: f_i of the red-majority populations less their blue parts, plus the
+    // red parts of the others; blue alike.
+    rR = ((T(K) + T(36) * A) + Mu) / T(36);
+    rB = ((T(36 - K) + T(36) * (drho - A)) - Mu) / T(36);
 }
 
-// Phase field psi = (rho^R - rho^B) / rho from the density deviation and the
-// red density.
+// Phase field psi = (rho^R - rho^B) / rho, from the minority colour's density
+// so that it is exactly +1 or -1 in the bulk of either colour.
 template <typename T>
-__device__ __forceinline__ T psi_of(T drho, T rhoR) {
+__device__ __forceinline__ T psi_of(T drho, T rR, T rB) {
     const T rho = T(1) + drho;
-    return (rhoR - (rho - rhoR)) / rho;
+    return rR >= rB ? T(1) - T(2) * rB / rho : T(2) * rR / rho - T(1);
 }
 
-// Moments of one node from its (df, chi) populations: density deviation,
-// red density (Eq. (2)), total momentum (Eq. (3)) and the trace-adjusted
-// momentum fluxes sum_i f_i Q_i and sum_i f_i^R Q_i with Q_i = c_i c_i - I/3
-// (components xx, yy, zz, xy, xz, yz).  sum_i w_i = 1 and sum_i w_i Q_i = 0
-// let the rest-state part cancel exactly.
+// Moments of one node: densities, total momentum (Eq. (3)) and the
+// trace-adjusted momentum fluxes sum_i f_i Q_i and sum_i f_i^R Q_i with
+// Q_i = c_i c_i - I/3 (components xx, yy, zz, xy, xz, yz).
 template <typename T>
 struct Mom {
-    T drho, rhoR;
+    T drho, rhoR, rhoB;
     T j[3];
     T S[6];
     T PR[6];
 };
 
 template <class L, typename T>
-__device__ __forceinline__ void moments(const T *df, const T *chi, Mom<T> &m) {
-    T drho, rhoR;
-    densities<L, T>(df, chi, drho, rhoR);
+__device__ __forceinline__ void moments(const Pops<L, T> &p, Mom<T> &m) {
+    densities<L, T>(p, m.drho, m.rhoR, m.rhoB);
+    // sum_i f_i^R Q_i in units of 1/108 (diagonal: 108 w_i (c_a^2 - 1/3) is
+    // the integer 36 w_i (3 c_a^2 - 1)) and 1/36 (off-diagonal), as above.
     T jx = 0, jy = 0, jz = 0;
     T S[6] = {0, 0, 0, 0, 0, 0}, P[6] = {0, 0, 0, 0, 0, 0};
-    const T c0 = chi[0];
+    int KQ[6] = {0, 0, 0, 0, 0, 0};
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) {
-        const T d = df[i];
-        const T g = chi[i] * d + (chi[i] - c0) * T(wgt<L>(i));  // red part minus c0 w_i
+        const T d = p.df[i];
+        const bool fl = p.flag(i);
+        const T f36 = T(w36<L>(i)) + T(36) * d;
+        const T mu = p.mm[i] * f36;
+        // 36 x red part, less its integer weight share when red is the majority
+        const T r36 = fl ? T(36) * d - mu : mu;
         if (L::cx[i]) jx += L::cx[i] > 0 ? d : -d;
         if (L::cy[i]) jy += L::cy[i] > 0 ? d : -d;
         if (L::cz[i]) jz += L::cz[i] > 0 ? d : -d;
-        const T qxx = T(L::cx[i] * L::cx[i]) - T(1.0 / 3.0);
-        const T qyy = T(L::cy[i] * L::cy[i]) - T(1.0 / 3.0);
-        S[0] += qxx * d;
-        P[0] += qxx * g;
-        S[1] += qyy * d;
-        P[1] += qyy * g;
-        if (L::D == 3) {
-            const T qzz = T(L::cz[i] * L::cz[i]) - T(1.0 / 3.0);
-            S[2] += qzz * d;
-            P[2] += qzz * g;
+#pragma unroll
+        for (int a = 0; a < L::D; ++a) {
+            const int ca = a == 0 ? L::cx[i] : (a == 1 ? L::cy[i] : L::cz[i]);
+            S[a] += (T(ca * ca) - T(1.0 / 3.0)) * d;
+            const int q3 = 3 * ca * ca - 1;
+            P[a] += T(q3) * r36;
+            KQ[a] += fl ? w36<L>(i) * q3 : 0;
         }
-        const int xy = L::cx[i] * L::cy[i];
-        if (xy) { S[3] += xy > 0 ? d : -d; P[3] += xy > 0 ? g : -g; }
-        if (L::D == 3) {
-            const int xz = L::cx[i] * L::cz[i], yz = L::cy[i] * L::cz[i];
-            if (xz) { S[4] += xz > 0 ? d : -d; P[4] += xz > 0 ? g : -g; }
-            if (yz) { S[5] += yz > 0 ? d : -d; P[5] += yz > 0 ? g : -g; }
+        const int off[3] = {L::cx[i] * L::cy[i], L::cx[i] * L::cz[i], L::cy[i] * L::cz[i]};
+#pragma unroll
+        for (int b = 0; b < (L::D == 3 ? 3 : 1); ++b) {
+            if (off[b]) {
+                S[3 + b] += off[b] > 0 ? d : -d;
+                P[3 + b] += off[b] > 0 ? r36 : -r36;
+                KQ[3 + b] += fl ? off[b] * w36<L>(i) : 0;
+            }
         }
     }
-    m.drho = drho;
-    m.rhoR = rhoR;
     m.j[0] = jx;
     m.j[1] = jy;
     m.j[2] = jz;
 #pragma unroll
     for (int q = 0; q < 6; ++q) {
         m.S[q] = S[q];
-        m.PR[q] = P[q];
+        m.PR[q] = q < 3 ? (T(KQ[q]) + P[q]) / T(108) : (T(KQ[q]) + P[q]) / T(36);
     }
+}
+
+// phi_i(alpha) of Eq. (7): alpha at rest, the remainder shared among moving
+// directions in proportion to w_i.  The collision uses phi_i^k - w_i, formed
+// from alpha_k - w_0 so that it is exactly zero for equal densities (a
+// difference of two rounded constants would add a little mass every step).
+template <class L, typename T>
+__device__ __forceinline__ T phi(int i, T alpha) {
+    return i == 0 ? alpha : (T(1) - alpha) * T(wgt<L>(i) / (1.0 - wgt<L>(0)));
+}
+template <class L, typename T>
+__device__ __forceinline__ T dphi(int i, T d0, T k) {
+    return i == 0 ? d0 : T(wgt<L>(i)) * k;
+}
+// sum_i phi_i c_ix^2: (1 - alpha) * sum_{moving} w_i c_ix^2 / (1 - w_0)
+template <class L, typename T>
+__device__ __forceinline__ T phat(T alpha) {
+    return (T(1) - alpha) * T((1.0 / 3.0) / (1.0 - wgt<L>(0)));
 }
 
 // ---------------------------------------------------------------- pull
@@ -213,15 +367,15 @@ __device__ __forceinline__ void moments(const T *df, const T *chi, Mom<T> &m) {
 // stored state already is pre-collision and is read in place.
 template <class L, typename S, typename T>
 __device__ __forceinline__ void pull_node(const Geo &g, const Model<T> &mo, const S *__restrict__ st,
-                                          int x, int y, int z, int64_t n, bool pulled, T *df,
-                                          T *chi) {
+                                          int x, int y, int z, int64_t n, bool pulled, Pops<L, T> &p) {
+    p.red = 0;
     if (!pulled) {
 #pragma unroll
-        for (int i = 0; i < L::Q; ++i) load_raw<L, S, T>(st, g.pitch, n, i, df[i], chi[i]);
+        for (int i = 0; i < L::Q; ++i) load_raw<L, S, T>(st, g.pitch, n, i, p);
         return;
     }
     bool own = false;
-    T oR = 0, oRho = 0, oU[3] = {0, 0, 0};
+    T oRho = 0, oR = 0, oU[3] = {0, 0, 0};
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) {
         const int xs = wrap_m1(x - L::cx[i], g.nx);
@@ -230,38 +384,42 @@ __device__ __forceinline__ void pull_node(const Geo &g, const Model<T> &mo, cons
         const int64_t m = xs + int64_t(g.nx) * (ys + int64_t(g.ny) * zs);
         const uint8_t code = g.mask ? g.mask[m] : kFluid;
         if (code == kFluid) {
-            load_raw<L, S, T>(st, g.pitch, m, i, df[i], chi[i]);
+            load_raw<L, S, T>(st, g.pitch, m, i, p);
             continue;
         }
         const int io = L::opp[i];
-        T dfo, chio;
-        load_raw<L, S, T>(st, g.pitch, n, io, dfo, chio);
+        Pops<L, T> q;
+        q.red = 0;
+        load_raw<L, S, T>(st, g.pitch, n, io, q);
         if (code == kWall) {
-            df[i] = dfo;  // w_io == w_i
-            chi[i] = chio;
-        } else if (code < kOutlet0) {
+            p.set(i, q.df[io], q.mm[io], q.flag(io));  // w_io == w_i
+            continue;
+        }
+        const T fo = T(wgt<L>(io)) + q.df[io];
+        const T fRo = q.fred(io), fBo = fo - fRo;
+        T fR, fB;
+        if (code < kOutlet0) {
             const DevInlet in = g.inlets[code - kInlet0];
             const T cu = T(L::cx[io]) * T(in.u[0]) + T(L::cy[io]) * T(in.u[1]) + T(L::cz[io]) * T(in.u[2]);
             const T mom = T(6.0 * wgt<L>(io)) * cu;  // 2 w c.u / c_s^2
-            const T tot = T(wgt<L>(io)) + dfo - mom * T(in.rhoR + in.rhoB);
-            const T red = chio * (T(wgt<L>(io)) + dfo) - mom * T(in.rhoR);
-            df[i] = dfo - mom * T(in.rhoR + in.rhoB);
-            chi[i] = tot != T(0) ? red / tot : T(0);
+            fR = fRo - mom * T(in.rhoR);
+            fB = fBo - mom * T(in.rhoB);
         } else {
             if (!own) {
                 // moments of this node's own post-collision populations
-                T d[L::Q], c[L::Q];
+                Pops<L, T> c;
+                c.red = 0;
 #pragma unroll
-                for (int k = 0; k < L::Q; ++k) load_raw<L, S, T>(st, g.pitch, n, k, d[k], c[k]);
-                T odr;
-                densities<L, T>(d, c, odr, oR);
+                for (int k = 0; k < L::Q; ++k) load_raw<L, S, T>(st, g.pitch, n, k, c);
+                T odr, oB;
+                densities<L, T>(c, odr, oR, oB);
                 oRho = T(1) + odr;
                 T jx = 0, jy = 0, jz = 0;
 #pragma unroll
                 for (int k = 0; k < L::Q; ++k) {
-                    jx += T(L::cx[k]) * d[k];
-                    jy += T(L::cy[k]) * d[k];
-                    jz += T(L::cz[k]) * d[k];
+                    jx += T(L::cx[k]) * c.df[k];
+                    jy += T(L::cy[k]) * c.df[k];
+                    jz += T(L::cz[k]) * c.df[k];
                 }
                 oU[0] = jx / oRho;
                 oU[1] = jy / oRho;
@@ -273,41 +431,32 @@ __device__ __forceinline__ void pull_node(const Geo &g, const Model<T> &mo, cons
             const T cu = T(L::cx[io]) * oU[0] + T(L::cy[io]) * oU[1] + T(L::cz[io]) * oU[2];
             const T uu = oU[0] * oU[0] + oU[1] * oU[1] + oU[2] * oU[2];
             const T wv = T(wgt<L>(io)) * (T(4.5) * cu * cu - T(1.5) * uu);
-            const T phR = io == 0 ? mo.aR : (T(1) - mo.aR) * T(wgt<L>(io) / (1.0 - wgt<L>(0)));
-            const T phB = io == 0 ? mo.aB : (T(1) - mo.aB) * T(wgt<L>(io) / (1.0 - wgt<L>(0)));
-            const T evR = rwR * (phR + wv), evB = rwB * (phB + wv);
-            const T fo = T(wgt<L>(io)) + dfo;
-            const T tot = T(2) * (evR + evB) - fo;
-            const T red = T(2) * evR - chio * fo;
-            df[i] = tot - T(wgt<L>(i));
-            chi[i] = tot != T(0) ? red / tot : T(0);
+            const T phR = phi<L, T>(io, mo.aR), phB = phi<L, T>(io, mo.aB);
+            fR = T(2) * rwR * (phR + wv) - fRo;
+            fB = T(2) * rwB * (phB + wv) - fBo;
         }
+        const T f = fR + fB;
+        T mm;
+        bool fl;
+        split_shares<T>(f != T(0) ? fR / f : T(0), f != T(0) ? fB / f : T(0), mm, fl);
+        p.set(i, f - T(wgt<L>(i)), mm, fl);
     }
 }
 
 // ---------------------------------------------------------------- collide
-// phi_i(alpha) of Eq. (7): alpha at rest, the remainder shared among moving
-// directions in proportion to w_i.
-template <class L, typename T>
-__device__ __forceinline__ T phi(int i, T alpha) {
-    return i == 0 ? alpha : (T(1) - alpha) * T(wgt<L>(i) / (1.0 - wgt<L>(0)));
-}
-// sum_i phi_i c_ix^2: (1 - alpha) * sum_{moving} w_i c_ix^2 / (1 - w_0)
-template <class L, typename T>
-__device__ __forceinline__ T phat(T alpha) {
-    return (T(1) - alpha) * T((1.0 / 3.0) / (1.0 - wgt<L>(0)));
-}
-
-// Output of one node: the new (df, chi) of every direction.
+// Output of one node: new total deviation, minority share and majority flag
+// of every direction.
 template <class L, typename T>
 struct PostOut {
     T df[L::Q];
-    T chi[L::Q];
+    T mm[L::Q];
+    uint32_t red;
 };
 
 // The part of N = sum_k (1 - omega_k) Pi^{k,neq} that comes straight from
 // the populations: G = (1 - omega_B) sum_i f_i Q_i + (omega_B - omega_R)
-// sum_i f_i^R Q_i.  A node carries only (drho, rhoR, j, G) into collide.
+// sum_i f_i^R Q_i.  A node carries only (drho, rho^R, rho^B, j, G) into
+// collide.
 template <typename T>
 __device__ __forceinline__ void fold_flux(const Model<T> &mo, const Mom<T> &m, T G[6]) {
     const T gR = T(1) - mo.omR, gB = T(1) - mo.omB;
@@ -316,16 +465,16 @@ __device__ __forceinline__ void fold_flux(const Model<T> &mo, const Mom<T> &m, T
 }
 
 // Collision (Eq. (11), or Eq. (5) with bgk), perturbation (Eq. (9)) and
-// recolouring (Eq. (10)) from the node's density deviation, red density,
-// momentum, folded flux G, colour gradient F and - for plain BGK only - its
-// populations.
+// recolouring (Eq. (10)) from the node's density deviation, colour
+// densities, momentum, folded flux G, colour gradient F and - for plain BGK
+// only - its populations.  Opposite directions i and -i share every even term
+// (weights, Q_i, (c.u)^2, (F.c)^2, B_i, phi_i) and flip the odd ones (c.u,
+// cos), so the update is computed once per pair.
 template <class L, typename T>
-__device__ __forceinline__ void collide(const Model<T> &mo, T drho, T rR, const T j[3], const T G[6],
-                                        const T F[3], const T *dfin, const T *chiin,
-                                        PostOut<L, T> &o) {
+__device__ __forceinline__ void collide(const Model<T> &mo, T drho, T rR, T rB, const T j[3], const T G[6],
+                                        const T F[3], const Pops<L, T> *pin, PostOut<L, T> &o) {
     const T rho = T(1) + drho;
-    const T rB = rho - rR;
-    const T inv_rho = T(1) / rho;
+    const T inv_rho = rcp<T>(rho);
     const T ux = j[0] * inv_rho, uy = j[1] * inv_rho, uz = j[2] * inv_rho;
     const T usq = ux * ux + uy * uy + uz * uz;
     const T pR = phat<L, T>(mo.aR), pB = phat<L, T>(mo.aB);
@@ -344,45 +493,84 @@ __device__ __forceinline__ void collide(const Model<T> &mo, T drho, T rR, const 
 
     const T Fx = F[0], Fy = F[1], Fz = F[2];
     const T F2 = Fx * Fx + Fy * Fy + Fz * Fz;
-    const T Fn = sqrt(F2);
+    const T Fn = sqrt_<T>(F2);
     const bool hasF = Fn > mo.eps_F;
-    const T invFn = hasF ? T(1) / Fn : T(0);
+    const T invFn = hasF ? rcp<T>(Fn) : T(0);
     const T seg = mo.beta * rR * rB * inv_rho * inv_rho;
-    const T fracR = rR * inv_rho;
+    // colour shares rho^k / rho, the minority one formed directly (exactly 0 in
+    // the other colour's bulk).  Colour shares use correctly rounded division:
+    // an approximate reciprocal errs to one side and would bias colour mass
+    // through the recolouring.
+    const bool redmaj = rR >= rB;
+    const T sB = redmaj ? rB / rho : T(1) - rR / rho;
+    const T sR = redmaj ? T(1) - sB : rR / rho;
+    const T wrho = rho * T(1.5) * usq;  // rho u^2 / (2 c_s^2)
+    o.red = 0;
 
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) {
+        if (i != 0 && L::opp[i] < i) continue;  // handled with its partner
+        const int ib = L::opp[i];
         const T w = T(wgt<L>(i));
         const T cx = T(L::cx[i]), cy = T(L::cy[i]), cz = T(L::cz[i]);
         const T cu = cx * ux + cy * uy + cz * uz;
-        const T U = T(3) * cu + T(4.5) * cu * cu - T(1.5) * usq;
-        const T phR = phi<L, T>(i, mo.aR), phB = phi<L, T>(i, mo.aB);
-        T d;
+        const T dpR = dphi<L, T>(i, mo.dR0, mo.kR), dpB = dphi<L, T>(i, mo.dB0, mo.kB);
+        T ev, od;  // even and odd parts of the new total deviation of direction i
         if (!mo.bgk) {
             T qn = (cx * cx - T(1.0 / 3.0)) * N[0] + (cy * cy - T(1.0 / 3.0)) * N[1];
             if (L::D == 3) qn += (cz * cz - T(1.0 / 3.0)) * N[2];
             qn += T(2) * cx * cy * N[3];
             if (L::D == 3) qn += T(2) * (cx * cz * N[4] + cy * cz * N[5]);
             // sum_k rho^k phi_i^k - w_i  +  w_i rho U  +  w_i/(2 c_s^4) Q_i : N
-            d = w * drho + rR * (phR - w) + rB * (phB - w) + w * rho * U + T(4.5) * w * qn;
+            ev = w * drho + rR * dpR + rB * dpB + w * (T(4.5) * rho * cu * cu - wrho) + T(4.5) * w * qn;
+            od = T(3) * w * rho * cu;
         } else {
-            // sum_k [(1 - omega_k) f_i^k + omega_k f_i^{k,eq}] - w_i
-            const T fi = w + dfin[i];
-            const T fRi = chiin[i] * fi;
-            d = gB * dfin[i] + (gR - gB) * fRi - mo.omB * w + mo.omR * rR * (phR + w * U) +
-                mo.omB * rB * (phB + w * U);
+            // sum_k [(1 - omega_k) f_i^k + omega_k f_i^{k,eq}] - w_i, split into
+            // the parts even and odd under i <-> -i (the populations themselves
+            // have no symmetry, so both directions are formed here).
+            const T U2 = T(4.5) * cu * cu - T(1.5) * usq;
+            const T base = -mo.omB * w + mo.omR * rR * (w + dpR + w * U2) + mo.omB * rB * (w + dpB + w * U2);
+            const T lin = (mo.omR * rR + mo.omB * rB) * w * T(3) * cu;
+            const T di = gB * pin->df[i] + (gR - gB) * pin->fred(i);
+            const T db = gB * pin->df[ib] + (gR - gB) * pin->fred(ib);
+            ev = base + T(0.5) * (di + db);
+            od = lin + T(0.5) * (di - db);
         }
         T cosp = T(0);
         if (hasF) {
-            const T Fc = Fx * cx + Fy * cy + Fz * cz;
-            const T Fh = Fc * invFn;
-            d += mo.Abar * Fn * (w * Fh * Fh - T(bcoef<L>(i)));
+            const T Fh = (Fx * cx + Fy * cy + Fz * cz) * invFn;
+            ev += mo.Abar * Fn * (w * Fh * Fh - T(bcoef<L>(i)));
             cosp = Fh * T(inv_len<L>(i));
         }
-        const T f2 = w + d;
-        const T rec = seg * cosp * (rR * phR + rB * phB);
-        o.df[i] = d;
-        o.chi[i] = f2 != T(0) ? fracR + rec / f2 : fracR;
+        // recolouring, Eq. (10): f_i^R = (rho^R/rho) f_i + rec_i and
+        // f_i^B = (rho^B/rho) f_i - rec_i
+        const T rec = seg * cosp * (w * rho + rR * dpR + rB * dpB);
+        const T d_i = ev + od;
+        const T f_i = w + d_i;
+        T m;
+        bool fl;
+        split_shares<T>(f_i != T(0) ? sR + rec / f_i : sR, f_i != T(0) ? sB - rec / f_i : sB, m, fl);
+        o.df[i] = d_i;
+        o.mm[i] = m;
+        o.red |= fl ? (1u << i) : 0u;
+        if (i != 0) {
+            const T d_b = ev - od;
+            const T f_b = w + d_b;
+            split_shares<T>(f_b != T(0) ? sR - rec / f_b : sR, f_b != T(0) ? sB + rec / f_b : sB, m, fl);
+            o.df[ib] = d_b;
+            o.mm[ib] = m;
+            o.red |= fl ? (1u << ib) : 0u;
+        }
+    }
+}
+
+template <class L, typename S, typename T>
+__device__ __forceinline__ void store_out(S *__restrict__ st, int64_t pitch, int64_t node,
+                                          const PostOut<L, T> &o) {
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+        st[int64_t(i) * pitch + node] = Codec<S>::template enc_df<L, T>(o.df[i], i);
+        st[int64_t(L::Q + i) * pitch + node] = Codec<S>::template enc_col<T>(o.mm[i], (o.red >> i) & 1u);
     }
 }
 

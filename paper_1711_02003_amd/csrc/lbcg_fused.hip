@@ -10,19 +10,32 @@
 // momentum flux G), and writes psi of the tile plus a one-node ring (the
 // ring recomputes the neighbours' densities from cache) into a 4-slot LDS
 // ring buffer.  After one barrier it collides plane z with the gradient taken
-// from the LDS planes z-1, z, z+1 and stores the 38 new values coalesced.
+// from the LDS planes z-1, z, z+1 and stores the 38 new values coalesced,
+// with non-temporal stores (the new state is not read again in this step).
+// The populations of plane z+2 are loaded one iteration ahead, so their HBM
+// latency overlaps the barrier, the collision and the stores; the barrier
+// orders only LDS traffic and leaves those loads in flight.
+//
 // Every stored population is read from HBM once and written once: the
 // algorithmic traffic is 2 x 38 x sizeof(storage) bytes per node.
 //
-// Block -> tile mapping: block b takes z chunk b % zchunks and column tile
-// b / zchunks, so with zchunks a multiple of 8 all tiles of one chunk land on
-// the same XCD (blocks are dealt round-robin over the 8 XCDs) and the ring
-// re-reads hit that XCD's L2.
+// Block -> work mapping: work items (tile, z chunk) are numbered tile-major
+// and dealt to the 8 XCDs in contiguous bands matching the round-robin
+// dispatch of blocks to XCDs, so each XCD sweeps a compact band of tiles and
+// the ring re-reads mostly hit that XCD's L2.
 #include "lbcg_internal.h"
 
 namespace lbcg {
 
 constexpr int kTX = 64;
+constexpr int kXCD = 8;
+
+#ifndef LBCG_PREFETCH
+#define LBCG_PREFETCH 1
+#endif
+#ifndef LBCG_NT_STORE
+#define LBCG_NT_STORE 1
+#endif
 
 template <typename S>
 struct FusedArgs {
@@ -33,11 +46,27 @@ struct FusedArgs {
     int ntx, nty, zchunks;
 };
 
+template <typename S>
+__device__ __forceinline__ void put(S *p, S v) {
+#if LBCG_NT_STORE
+    __builtin_nontemporal_store(v, p);
+#else
+    *p = v;
+#endif
+}
+
+// Barrier that orders LDS accesses only; global loads stay in flight.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Pull the 38 values of node (x, y, z) (periodic).  Addresses are 32-bit
 // byte offsets from the uniform state base (the host checks that a state
 // buffer is below 4 GiB), which keeps one VGPR per load instead of two.
 template <typename S, typename T>
-__device__ __forceinline__ void pull_periodic(const FusedArgs<S> &a, int x, int y, int z, T *df, T *chi) {
+__device__ __forceinline__ void pull_periodic(const FusedArgs<S> &a, int x, int y, int z, Pops<D3Q19, T> &p) {
     using L = D3Q19;
     const int xm = x == 0 ? a.nx - 1 : x - 1, xp = x == a.nx - 1 ? 0 : x + 1;
     const int ym = y == 0 ? a.ny - 1 : y - 1, yp = y == a.ny - 1 ? 0 : y + 1;
@@ -50,24 +79,31 @@ __device__ __forceinline__ void pull_periodic(const FusedArgs<S> &a, int x, int 
         const int xs = L::cx[i] > 0 ? xm : (L::cx[i] < 0 ? xp : x);
         const int ys = L::cy[i] > 0 ? ym : (L::cy[i] < 0 ? yp : y);
         const int zs = L::cz[i] > 0 ? zm : (L::cz[i] < 0 ? zp : z);
-        const uint32_t m = uint32_t(xs) + uint32_t(a.nx) * (uint32_t(ys) + uint32_t(a.ny) * uint32_t(zs));
-        const uint32_t o1 = uint32_t(i) * cstride + m * uint32_t(sizeof(S));
+        const uint32_t nd = uint32_t(xs) + uint32_t(a.nx) * (uint32_t(ys) + uint32_t(a.ny) * uint32_t(zs));
+        const uint32_t o1 = uint32_t(i) * cstride + nd * uint32_t(sizeof(S));
         const uint32_t o2 = o1 + uint32_t(L::Q) * cstride;
-        df[i] = Codec<S>::template df<L, T>(*reinterpret_cast<const S *>(base + o1), i);
-        chi[i] = T(*reinterpret_cast<const S *>(base + o2));
+        bool fl;
+        const T d = Codec<S>::template df<L, T>(*reinterpret_cast<const S *>(base + o1), i);
+        const T m = Codec<S>::template col<T>(*reinterpret_cast<const S *>(base + o2), fl);
+        p.set(i, d, m, fl);
     }
 }
+
+__device__ __forceinline__ int wrapz(int z, int nz) { return z < 0 ? z + nz : (z >= nz ? z - nz : z); }
 
 template <typename S, typename T, int R>
 __global__ void __launch_bounds__(kTX * R) k_step_fused(FusedArgs<S> a, Model<T> mo) {
     using L = D3Q19;
     extern __shared__ float lds[];
-    const int W = kTX + 2, H = R + 2;  // LDS plane: (R+2) x 66
+    constexpr int W = kTX + 2, H = R + 2, PL = W * H;  // LDS plane: (R+2) x 66
     const int lane = threadIdx.x % kTX, row = threadIdx.x / kTX;
 
-    const int b = blockIdx.x;
-    const int chunk = b % a.zchunks;
-    const int tile = b / a.zchunks;
+    // work item of this block (see the file comment)
+    const int total = a.ntx * a.nty * a.zchunks;
+    const int xcd = blockIdx.x % kXCD, l = blockIdx.x / kXCD;
+    const int item = xcd * (total / kXCD) + min(xcd, total % kXCD) + l;
+    const int chunk = item % a.zchunks;
+    const int tile = item / a.zchunks;
     const int tx = tile % a.ntx, ty = tile / a.ntx;
     const int x0 = tx * kTX, y0 = ty * R;
     const int tw = min(kTX, a.nx - x0), th = min(R, a.ny - y0);
@@ -98,53 +134,84 @@ __global__ void __launch_bounds__(kTX * R) k_step_fused(FusedArgs<S> a, Model<T>
         }
     }
     const int gx = wrap_m1(x0 + rx, a.nx), gy = wrap_m1(y0 + ry, a.ny);
+    auto slot_of = [&](int zp) { return lds + ((zp - z0 + 1) & 3) * PL; };
 
-    // psi of plane zp into LDS slot; interior nodes also return their moments
-    auto plane = [&](int zp, bool carry, T &drho, T &rR, T *j, T *G) {
-        const int zz = zp < 0 ? zp + a.nz : (zp >= a.nz ? zp - a.nz : zp);
-        float *slot = lds + ((zp - z0 + 1) & 3) * (W * H);
-        if (active) {
-            T df[L::Q], chi[L::Q];
-            pull_periodic<S, T>(a, x, y, zz, df, chi);
-            T ps;
-            if (carry) {
-                Mom<T> m;
-                moments<L, T>(df, chi, m);
-                drho = m.drho;
-                rR = m.rhoR;
-                j[0] = m.j[0];
-                j[1] = m.j[1];
-                j[2] = m.j[2];
-                fold_flux<T>(mo, m, G);
-                ps = psi_of<T>(m.drho, m.rhoR);
-            } else {
-                T dr, rhoR;
-                densities<L, T>(df, chi, dr, rhoR);
-                ps = psi_of<T>(dr, rhoR);
-            }
-            slot[(row + 1) * W + lane + 1] = float(ps);
-        }
+    // psi of the ring nodes of plane zp, in two halves: issue the loads, then
+    // (after other work) reduce them and write LDS.  Loads retire in order, so
+    // ring loads are issued before the interior prefetch; waiting for them then
+    // leaves the prefetch in flight.
+    Pops<L, T> rp;
+    rp.red = 0;
+    auto ring_issue = [&](int zp) {
+        if (has_ring) pull_periodic<S, T>(a, gx, gy, wrapz(zp, a.nz), rp);
+    };
+    auto ring_finish = [&](int zp) {
         if (has_ring) {
-            T df[L::Q], chi[L::Q];
-            pull_periodic<S, T>(a, gx, gy, zz, df, chi);
-            T dr, rhoR;
-            densities<L, T>(df, chi, dr, rhoR);
-            slot[(ry + 1) * W + rx + 1] = float(psi_of<T>(dr, rhoR));
+            T dr, rR, rB;
+            densities<L, T>(rp, dr, rR, rB);
+            slot_of(zp)[(ry + 1) * W + rx + 1] = float(psi_of<T>(dr, rR, rB));
         }
     };
 
-    T cd = 0, cR = 0, cj[3] = {0, 0, 0}, cG[6] = {0, 0, 0, 0, 0, 0};
-    T nd = 0, nR = 0, nj[3] = {0, 0, 0}, nG[6] = {0, 0, 0, 0, 0, 0};
-    plane(z0 - 1, false, nd, nR, nj, nG);
-    plane(z0, true, cd, cR, cj, cG);
+    T cd = 0, cR = 0, cB = 0, cj[3] = {0, 0, 0}, cG[6] = {0, 0, 0, 0, 0, 0};
+    Pops<L, T> pp;  // populations of the next interior plane
+    pp.red = 0;
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) pp.df[i] = pp.mm[i] = T(0);
+
+    // prologue: psi of plane z0-1, moments and psi of plane z0
+    ring_issue(z0 - 1);
+    if (active) {
+        pull_periodic<S, T>(a, x, y, wrapz(z0 - 1, a.nz), pp);
+        T dr, rR, rB;
+        densities<L, T>(pp, dr, rR, rB);
+        slot_of(z0 - 1)[(row + 1) * W + lane + 1] = float(psi_of<T>(dr, rR, rB));
+    }
+    ring_finish(z0 - 1);
+    ring_issue(z0);
+    if (active) {
+        pull_periodic<S, T>(a, x, y, z0, pp);
+        Mom<T> m;
+        moments<L, T>(pp, m);
+        cd = m.drho;
+        cR = m.rhoR;
+        cB = m.rhoB;
+        cj[0] = m.j[0];
+        cj[1] = m.j[1];
+        cj[2] = m.j[2];
+        fold_flux<T>(mo, m, cG);
+        slot_of(z0)[(row + 1) * W + lane + 1] = float(psi_of<T>(m.drho, m.rhoR, m.rhoB));
+    }
+    ring_finish(z0);
+#if LBCG_PREFETCH
+    if (active) pull_periodic<S, T>(a, x, y, wrapz(z0 + 1, a.nz), pp);
+#endif
 
     for (int z = z0; z < z1; ++z) {
-        plane(z + 1, true, nd, nR, nj, nG);
-        __syncthreads();
+        T nd = 0, nR = 0, nB = 0, nj[3] = {0, 0, 0}, nG[6] = {0, 0, 0, 0, 0, 0};
+        ring_issue(z + 1);
+#if !LBCG_PREFETCH
+        if (active) pull_periodic<S, T>(a, x, y, wrapz(z + 1, a.nz), pp);
+#endif
         if (active) {
-            const float *sm = lds + ((z - 1 - z0 + 1) & 3) * (W * H);
-            const float *s0 = lds + ((z - z0 + 1) & 3) * (W * H);
-            const float *sp = lds + ((z + 1 - z0 + 1) & 3) * (W * H);
+            Mom<T> m;
+            moments<L, T>(pp, m);
+            nd = m.drho;
+            nR = m.rhoR;
+            nB = m.rhoB;
+            nj[0] = m.j[0];
+            nj[1] = m.j[1];
+            nj[2] = m.j[2];
+            fold_flux<T>(mo, m, nG);
+            slot_of(z + 1)[(row + 1) * W + lane + 1] = float(psi_of<T>(m.drho, m.rhoR, m.rhoB));
+        }
+#if LBCG_PREFETCH
+        if (active && z + 2 <= z1) pull_periodic<S, T>(a, x, y, wrapz(z + 2, a.nz), pp);
+#endif
+        ring_finish(z + 1);
+        lds_barrier();
+        if (active) {
+            const float *sm = slot_of(z - 1), *s0 = slot_of(z), *sp = slot_of(z + 1);
             const int c = (row + 1) * W + lane + 1;
             T fx = 0, fy = 0, fz = 0;
 #pragma unroll
@@ -158,19 +225,21 @@ __global__ void __launch_bounds__(kTX * R) k_step_fused(FusedArgs<S> a, Model<T>
             }
             const T F[3] = {fx, fy, fz};
             PostOut<L, T> o;
-            collide<L, T>(mo, cd, cR, cj, cG, F, nullptr, nullptr, o);
+            collide<L, T>(mo, cd, cR, cB, cj, cG, F, nullptr, o);
             const uint32_t n = uint32_t(x) + uint32_t(a.nx) * (uint32_t(y) + uint32_t(a.ny) * uint32_t(z));
             char *ob = reinterpret_cast<char *>(a.out);
             const uint32_t cstride = uint32_t(a.pitch) * uint32_t(sizeof(S));
 #pragma unroll
             for (int i = 0; i < L::Q; ++i) {
                 const uint32_t o1 = uint32_t(i) * cstride + n * uint32_t(sizeof(S));
-                *reinterpret_cast<S *>(ob + o1) = Codec<S>::template enc_df<L, T>(o.df[i], i);
-                *reinterpret_cast<S *>(ob + o1 + uint32_t(L::Q) * cstride) = S(o.chi[i]);
+                put(reinterpret_cast<S *>(ob + o1), Codec<S>::template enc_df<L, T>(o.df[i], i));
+                put(reinterpret_cast<S *>(ob + o1 + uint32_t(L::Q) * cstride),
+                    Codec<S>::template enc_col<T>(o.mm[i], (o.red >> i) & 1u));
             }
         }
         cd = nd;
         cR = nR;
+        cB = nB;
 #pragma unroll
         for (int q = 0; q < 3; ++q) cj[q] = nj[q];
 #pragma unroll
@@ -182,6 +251,27 @@ bool fused_supported(int lattice, int prec, const Geo &g) {
     const uint64_t elem = prec == 1 ? 4 : 2;
     return lattice == 1 && (prec == 1 || prec == 2) && g.mask == nullptr &&
            uint64_t(2 * D3Q19::Q) * uint64_t(g.pitch) * elem < (uint64_t(1) << 32);
+}
+
+template <typename S>
+static const void *fused_fn(int R) {
+    return R == 4 ? reinterpret_cast<const void *>(&k_step_fused<S, float, 4>)
+                  : reinterpret_cast<const void *>(&k_step_fused<S, float, 8>);
+}
+
+static size_t fused_lds(int R) { return size_t(4) * (R + 2) * (kTX + 2) * sizeof(float); }
+
+int fused_resident_blocks(int prec, int rows) {
+    int per_cu = 0;
+    const void *fn = prec == 2 ? fused_fn<_Float16>(rows) : fused_fn<float>(rows);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kTX * rows, fused_lds(rows)) != hipSuccess) {
+        (void)hipGetLastError();
+        per_cu = 1;
+    }
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess)
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    return (per_cu > 0 ? per_cu : 1) * cus;
 }
 
 template <typename S>
@@ -206,12 +296,13 @@ static hipError_t run_fused(const Geo &g, const ModelD &md, const void *in, void
     a.zchunks = sh.zchunks < 1 ? 1 : (sh.zchunks > g.nz ? g.nz : sh.zchunks);
     const int64_t nblocks = int64_t(a.ntx) * a.nty * a.zchunks;
     if (nblocks > 0x7fffffff) return hipErrorInvalidValue;
-    const size_t shmem = size_t(4) * (R + 2) * (kTX + 2) * sizeof(float);
     const Model<float> mo = to_model<float>(md);
     if (R == 4)
-        hipLaunchKernelGGL((k_step_fused<S, float, 4>), dim3(unsigned(nblocks)), dim3(kTX * 4), shmem, s, a, mo);
+        hipLaunchKernelGGL((k_step_fused<S, float, 4>), dim3(unsigned(nblocks)), dim3(kTX * 4), fused_lds(4), s,
+                           a, mo);
     else
-        hipLaunchKernelGGL((k_step_fused<S, float, 8>), dim3(unsigned(nblocks)), dim3(kTX * 8), shmem, s, a, mo);
+        hipLaunchKernelGGL((k_step_fused<S, float, 8>), dim3(unsigned(nblocks)), dim3(kTX * 8), fused_lds(8), s,
+                           a, mo);
     return hipGetLastError();
 }
 

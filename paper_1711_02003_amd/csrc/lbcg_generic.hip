@@ -47,8 +47,11 @@ __global__ void __launch_bounds__(kBlock) k_init(Geo g, Model<T> mo, int64_t n0,
         const double phB = i == 0 ? aB : (1.0 - aB) * w / (1.0 - wgt<L>(0));
         const double fR = r0 * (phR + U), fB = r1 * (phB + U);  // Eq. (6)
         const double f = fR + fB;
+        double m;
+        bool redmaj;
+        split_shares<double>(f != 0.0 ? fR / f : 0.0, f != 0.0 ? fB / f : 0.0, m, redmaj);
         st[int64_t(i) * g.pitch + n] = Codec<S>::template enc_df<L, double>(f - w, i);
-        st[int64_t(L::Q + i) * g.pitch + n] = S(f != 0.0 ? fR / f : 0.0);
+        st[int64_t(L::Q + i) * g.pitch + n] = Codec<S>::template enc_col<double>(m, redmaj);
     }
 }
 
@@ -63,11 +66,11 @@ __global__ void __launch_bounds__(kBlock) k_psi(Geo g, Model<T> mo, const S *__r
     }
     int x, y, z;
     node_xyz(g, n, x, y, z);
-    T df[L::Q], chi[L::Q];
-    pull_node<L, S, T>(g, mo, st, x, y, z, n, pulled, df, chi);
-    T drho, rhoR;
-    densities<L, T>(df, chi, drho, rhoR);
-    psi[n] = psi_of<T>(drho, rhoR);
+    Pops<L, T> p;
+    pull_node<L, S, T>(g, mo, st, x, y, z, n, pulled, p);
+    T drho, rR, rB;
+    densities<L, T>(p, drho, rR, rB);
+    psi[n] = psi_of<T>(drho, rR, rB);
 }
 
 // Colour gradient F = (1/c_s^2) sum_i w_i c_i psi~(x + c_i), psi~ = psi at fluid
@@ -111,21 +114,17 @@ __global__ void __launch_bounds__(kBlock) k_step_generic(Geo g, Model<T> mo, con
     if (code_at(g, n) != kFluid) return;
     int x, y, z;
     node_xyz(g, n, x, y, z);
-    T df[L::Q], chi[L::Q];
-    pull_node<L, S, T>(g, mo, in, x, y, z, n, pulled, df, chi);
+    Pops<L, T> p;
+    pull_node<L, S, T>(g, mo, in, x, y, z, n, pulled, p);
     Mom<T> m;
-    moments<L, T>(df, chi, m);
+    moments<L, T>(p, m);
     T G[6];
     fold_flux<T>(mo, m, G);
     T F[3];
     gradient<L, T>(g, psi, x, y, z, n, F);
     PostOut<L, T> o;
-    collide<L, T>(mo, m.drho, m.rhoR, m.j, G, F, df, chi, o);
-#pragma unroll
-    for (int i = 0; i < L::Q; ++i) {
-        out[int64_t(i) * g.pitch + n] = Codec<S>::template enc_df<L, T>(o.df[i], i);
-        out[int64_t(L::Q + i) * g.pitch + n] = S(o.chi[i]);
-    }
+    collide<L, T>(mo, m.drho, m.rhoR, m.rhoB, m.j, G, F, &p, o);
+    store_out<L, S, T>(out, g.pitch, n, o);
 }
 
 template <class L, typename S, typename T>
@@ -138,17 +137,17 @@ __global__ void __launch_bounds__(kBlock) k_fields(Geo g, Model<T> mo, const S *
     if (code_at(g, n) == kFluid) {
         int x, y, z;
         node_xyz(g, n, x, y, z);
-        T df[L::Q], chi[L::Q];
-        pull_node<L, S, T>(g, mo, st, x, y, z, n, pulled, df, chi);
+        Pops<L, T> p;
+        pull_node<L, S, T>(g, mo, st, x, y, z, n, pulled, p);
         Mom<T> m;
-        moments<L, T>(df, chi, m);
+        moments<L, T>(p, m);
         const T rho = T(1) + m.drho;
         v[0] = double(m.rhoR);
-        v[1] = double(rho - m.rhoR);
+        v[1] = double(m.rhoB);
         v[2] = double(m.j[0] / rho);
         v[3] = double(m.j[1] / rho);
         v[4] = double(m.j[2] / rho);
-        v[5] = double(psi_of<T>(m.drho, m.rhoR));
+        v[5] = double(psi_of<T>(m.drho, m.rhoR, m.rhoB));
     }
 #pragma unroll
     for (int q = 0; q < 6; ++q) out[q * cnt + k] = v[q];
@@ -160,19 +159,19 @@ __global__ void __launch_bounds__(kBlock) k_pops(Geo g, Model<T> mo, const S *__
     const int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x;
     if (k >= cnt) return;
     const int64_t n = n0 + k;
-    T df[L::Q], chi[L::Q];
+    Pops<L, T> p;
     const bool fl = code_at(g, n) == kFluid;
     if (fl) {
         int x, y, z;
         node_xyz(g, n, x, y, z);
-        pull_node<L, S, T>(g, mo, st, x, y, z, n, pulled, df, chi);
+        pull_node<L, S, T>(g, mo, st, x, y, z, n, pulled, p);
     }
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) {
         double fR = 0, fB = 0;
         if (fl) {
-            const T f = T(wgt<L>(i)) + df[i];
-            const T r = chi[i] * f;
+            const T f = T(wgt<L>(i)) + p.df[i];
+            const T r = p.fred(i);
             fR = double(r);
             fB = double(f - r);
         }
@@ -196,12 +195,12 @@ __global__ void __launch_bounds__(kBlock) k_pops_at(Geo g, Model<T> mo, const S 
     }
     int x, y, z;
     node_xyz(g, n, x, y, z);
-    T df[L::Q], chi[L::Q];
-    pull_node<L, S, T>(g, mo, st, x, y, z, n, pulled, df, chi);
+    Pops<L, T> p;
+    pull_node<L, S, T>(g, mo, st, x, y, z, n, pulled, p);
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) {
-        const T f = T(wgt<L>(i)) + df[i];
-        const T r = chi[i] * f;
+        const T f = T(wgt<L>(i)) + p.df[i];
+        const T r = p.fred(i);
         o[i] = double(r);
         o[L::Q + i] = double(f - r);
     }
@@ -224,20 +223,20 @@ __global__ void __launch_bounds__(kBlock) k_diag(Geo g, Model<T> mo, const S *__
         if (code_at(g, n) != kFluid) continue;
         int x, y, z;
         node_xyz(g, n, x, y, z);
-        T df[L::Q], chi[L::Q];
-        pull_node<L, S, T>(g, mo, st, x, y, z, n, pulled, df, chi);
+        Pops<L, T> p;
+        pull_node<L, S, T>(g, mo, st, x, y, z, n, pulled, p);
         Mom<T> m;
-        moments<L, T>(df, chi, m);
+        moments<L, T>(p, m);
         const double rho = 1.0 + double(m.drho);
-        const double r0 = double(m.rhoR), r1 = rho - r0;
+        const double r0 = double(m.rhoR), r1 = double(m.rhoB);
         const double jx = double(m.j[0]), jy = double(m.j[1]), jz = double(m.j[2]);
         acc[12] += 1.0;
-        if (!(isfinite(rho) && isfinite(r0) && isfinite(jx) && isfinite(jy) && isfinite(jz))) {
+        if (!(isfinite(rho) && isfinite(r0) && isfinite(r1) && isfinite(jx) && isfinite(jy) && isfinite(jz))) {
             acc[11] += 1.0;
             continue;
         }
-        const double psi = (r0 - r1) / rho;
-        const double p = pR * r0 + pB * r1;  // Eq. (8)
+        const double psi = double(psi_of<T>(m.drho, m.rhoR, m.rhoB));
+        const double pres = pR * r0 + pB * r1;  // Eq. (8)
         acc[0] += r0;
         acc[1] += r1;
         acc[2] += jx;
@@ -245,10 +244,10 @@ __global__ void __launch_bounds__(kBlock) k_diag(Geo g, Model<T> mo, const S *__
         acc[4] += jz;
         acc[5] = fmax(acc[5], sqrt(jx * jx + jy * jy + jz * jz) / rho);
         if (psi > 0.99) {
-            acc[6] += p;
+            acc[6] += pres;
             acc[7] += 1.0;
         } else if (psi < -0.99) {
-            acc[8] += p;
+            acc[8] += pres;
             acc[9] += 1.0;
         }
         acc[10] += 0.5 * (1.0 + psi);

@@ -11,6 +11,7 @@ namespace lbcg {
 // Model parameters in double; launchers convert to the compute type.
 struct ModelD {
     double omR, omB, Abar, beta, aR, aB, eps_F;
+    double w0;  // rest weight of the lattice
     int bgk;
 };
 
@@ -23,6 +24,10 @@ inline Model<T> to_model(const ModelD &m) {
     r.beta = T(m.beta);
     r.aR = T(m.aR);
     r.aB = T(m.aB);
+    r.dR0 = T(m.aR - m.w0);
+    r.dB0 = T(m.aB - m.w0);
+    r.kR = T((m.w0 - m.aR) / (1.0 - m.w0));
+    r.kB = T((m.w0 - m.aB) / (1.0 - m.w0));
     r.eps_F = T(m.eps_F);
     r.bgk = m.bgk;
     return r;
@@ -64,6 +69,8 @@ struct FusedShape {
 hipError_t launch_step_fused(int prec, const Geo &g, const ModelD &md, const void *in, void *out,
                              FusedShape shape, hipStream_t s);
 bool fused_supported(int lattice, int prec, const Geo &g);
+// Blocks of the fused kernel that fit on the device at once.
+int fused_resident_blocks(int prec, int rows);
 
 // Batched fused step: one launch over many lattices (see lbcg_batch.hip).
 struct BatchItem {

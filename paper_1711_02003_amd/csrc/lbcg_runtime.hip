@@ -146,16 +146,18 @@ int check_device() {
 
 FusedShape pick_shape(const lbcg_sim *s, const lbcg_params *p) {
     FusedShape sh;
-    sh.rows = p->tile[0] ? p->tile[0] : 8;
+    sh.rows = p->tile[0] ? p->tile[0] : 4;
     int zc = p->tile[1];
-    if (!zc) {
-        // enough blocks to fill 256 CUs a few times over, chunks a multiple of 8
-        const int64_t tiles = ((s->g.nx + 63) / 64) * ((s->g.ny + sh.rows - 1) / sh.rows);
-        zc = 8;
-        while (zc < 64 && tiles * zc < 1024 && s->g.nz / (zc * 2) >= 8) zc *= 2;
-        if (zc > s->g.nz) zc = s->g.nz;
+    if (!zc && s->kernel == LBCG_KERNEL_FUSED) {
+        // One wave of resident blocks: each z chunk re-reads two planes, so use
+        // as few (long) chunks as fill the device, but keep chunks >= 8 planes.
+        const int64_t tiles = int64_t((s->g.nx + 63) / 64) * ((s->g.ny + sh.rows - 1) / sh.rows);
+        const int64_t resident = fused_resident_blocks(s->prec, sh.rows);
+        int64_t want = (resident + tiles - 1) / tiles;
+        const int64_t cap = s->g.nz / 8 > 1 ? s->g.nz / 8 : 1;
+        zc = int(want < 1 ? 1 : (want > cap ? cap : want));
     }
-    sh.zchunks = zc;
+    sh.zchunks = zc < 1 ? 1 : zc;
     return sh;
 }
 
@@ -268,6 +270,7 @@ int lbcg_create(const lbcg_params *p, void *dev_buf, size_t bytes, void *hip_str
     s->md.aR = p->alpha_R > 0.0 ? p->alpha_R : w0;
     s->md.aB = p->alpha_B > 0.0 ? p->alpha_B : w0;
     s->md.eps_F = p->eps_F < 0.0 ? 1e-8 : p->eps_F;
+    s->md.w0 = w0;
     s->md.bgk = p->collision == LBCG_BGK;
 
     if (dev_buf) {

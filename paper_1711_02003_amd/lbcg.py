@@ -16,7 +16,7 @@ from typing import Optional, Sequence
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liblbcg.so")
+LIB_PATH = os.environ.get("LBCG_LIBRARY", os.path.join(HERE, "liblbcg.so"))
 
 OK, E_INVAL, E_NOMEM, E_DEVICE, E_UNSTABLE, E_STATE = 0, -1, -2, -3, -4, -5
 D2Q9, D3Q19 = 0, 1

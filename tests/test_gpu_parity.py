@@ -122,8 +122,14 @@ def test_fused_f32_config2_recipe_1000_steps(L, orc):
     _say("fused f32 48^3 x1000")
     s = L.Sim.from_workload(w, precision="f32", kernel=L.KERNEL_FUSED)
     assert s.launch_info()["kernel"] == L.KERNEL_FUSED
+    d0 = s.diagnostics()
     s.step(1000)
     g = s.fields()
+    d1 = s.diagnostics(check=True)
+    # per-colour mass: FP32 rounding is unbiased, so the drift stays far below
+    # one FP32 ulp per node-step (a biased reciprocal or codec would not)
+    drifts = {k: abs(d1[k] - d0[k]) / d0[k] for k in ("mass_R", "mass_B")}
+    _say(f"  mass drift R {drifts['mass_R']:.2e} B {drifts['mass_B']:.2e}")
     o = oracle_for(orc, w, threads=16).step(1000)
     f = o.fields()
     eu, ep = rel_l2(g["u"], f["u"]), rel_l2(g["psi"], f["psi"])
@@ -131,6 +137,8 @@ def test_fused_f32_config2_recipe_1000_steps(L, orc):
     _say(f"  relL2 u {eu:.3e} (floored {euf:.3e}) psi {ep:.3e} |u|rms {np.sqrt((f['u']**2).mean()):.2e}")
     assert eu < 1e-5
     assert ep < 1e-5
+    for k, v in drifts.items():
+        assert v < 1e-6, (k, v)
 
 
 def test_fused_matches_generic_ragged(L):
