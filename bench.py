@@ -19,7 +19,6 @@ colours).  Prints one JSON line:
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -31,15 +30,6 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fused_d3q19_f32_256_traffic.txt")
-KERNEL_SOURCES = ["paper_1711_02003_amd/csrc/lbcg_fused.hip", "paper_1711_02003_amd/csrc/lbcg_device.h"]
-
-
-def kernel_hash() -> str:
-    h = hashlib.sha256()
-    for p in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, p), "rb") as f:
-            h.update(f.read())
-    return h.hexdigest()[:16]
 
 
 def read_traffic():
@@ -51,6 +41,7 @@ def read_traffic():
         if ":" in line:
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
+    from paper_1711_02003_amd.profiling import kernel_hash
     if vals.get("kernel_hash") != kernel_hash():
         return None
     try:

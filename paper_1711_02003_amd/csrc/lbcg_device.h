@@ -63,15 +63,10 @@ template <class L>
 __host__ __device__ constexpr double wgt(int i) {
     return L::wc[csq<L>(i)];
 }
-// 36 w_i (an integer) and 108 w_i (c_ia^2 - 1/3) = 3 * 36 w_i c_ia^2 - 36 w_i
+// 36 w_i (an integer)
 template <class L>
 __host__ __device__ constexpr int w36(int i) {
     return L::w36[csq<L>(i)];
-}
-template <class L>
-__host__ __device__ constexpr int wq108(int i, int a) {
-    return 3 * w36<L>(i) * (a == 0 ? L::cx[i] * L::cx[i] : (a == 1 ? L::cy[i] * L::cy[i] : L::cz[i] * L::cz[i])) -
-           w36<L>(i);
 }
 // Perturbation constants B_i = w_i (|c_i|^2 - (D - 1) c_s^2): the choice with
 // sum_i B_i = c_s^2 (mass kept) and sum_i B_i c_i c_i = 3 c_s^4 I.
@@ -227,13 +222,46 @@ struct Pops {
     }
 };
 
+// The two stored values of a population travel together: the state is Q
+// arrays (one per direction) of value pairs (df_i, m_i), element n of array i
+// at pair index i * pitch + n.  A pull then moves one 2-wide element per
+// population, half the memory instructions of separate arrays.
+template <typename S>
+struct PairOf;
+template <>
+struct PairOf<double> {
+    typedef double type __attribute__((ext_vector_type(2)));
+};
+template <>
+struct PairOf<float> {
+    typedef float type __attribute__((ext_vector_type(2)));
+};
+template <>
+struct PairOf<_Float16> {
+    typedef _Float16 type __attribute__((ext_vector_type(2)));
+};
+
+template <class L, typename S, typename T>
+__device__ __forceinline__ void decode_pair(typename PairOf<S>::type v, int i, Pops<L, T> &p) {
+    bool fl;
+    const T d = Codec<S>::template df<L, T>(v.x, i);
+    const T m = Codec<S>::template col<T>(v.y, fl);
+    p.set(i, d, m, fl);
+}
+
+template <class L, typename S, typename T>
+__device__ __forceinline__ typename PairOf<S>::type encode_pair(T df, T m, bool redmaj, int i) {
+    typename PairOf<S>::type v;
+    v.x = Codec<S>::template enc_df<L, T>(df, i);
+    v.y = Codec<S>::template enc_col<T>(m, redmaj);
+    return v;
+}
+
 template <class L, typename S, typename T>
 __device__ __forceinline__ void load_raw(const S *__restrict__ st, int64_t pitch, int64_t node, int i,
                                          Pops<L, T> &p) {
-    bool fl;
-    const T d = Codec<S>::template df<L, T>(st[int64_t(i) * pitch + node], i);
-    const T m = Codec<S>::template col<T>(st[int64_t(L::Q + i) * pitch + node], fl);
-    p.set(i, d, m, fl);
+    const typename PairOf<S>::type *a = reinterpret_cast<const typename PairOf<S>::type *>(st);
+    decode_pair<L, S, T>(a[int64_t(i) * pitch + node], i, p);
 }
 
 // Minority share and majority flag from the red and blue shares of a
@@ -245,49 +273,109 @@ __device__ __forceinline__ void split_shares(T shareR, T shareB, T &m, bool &red
 }
 
 // ---------------------------------------------------------------- moments
-// Densities (Eq. (2)): the deviation of the total density, and the red and
-// blue densities, each accumulated so that a node's minority colour is summed
-// directly from its small shares (precise in the other colour's bulk).  Every
-// path computes psi through this one expression sequence, so psi is bitwise
-// the same whichever kernel or tile shape produced it.
-template <class L, typename T>
-__device__ __forceinline__ void densities(const Pops<L, T> &p, T &drho_out, T &rR, T &rB) {
-    // Colour sums are kept in units of 1/36 (the weights are then the integers
-    // 36 w_i) and rounded once at the end: a rounded weight constant would
-    // shift every mixed node's colour mass the same way, step after step.
-    T drho = 0, A = 0, Mu = 0;
-    int K = 0;
-#pragma unroll
-    for (int i = 0; i < L::Q; ++i) {
-        const T d = p.df[i];
-        const bool fl = p.flag(i);
-        const T mu = p.mm[i] * (T(w36<L>(i)) + T(36) * d);  // 36 x minority part
-        drho += d;
-        A += fl ? d : T(0);
-        K += fl ? w36<L>(i) : 0;
-        Mu += fl ? -mu : mu;
+// Colour sums are kept in units of 1/36 (the weights are then the integers
+// 36 w_i) and rounded once at the end: a rounded weight constant would shift
+// every mixed node's colour mass the same way, step after step.  Per
+// population, 36 f_i^R and 36 f_i^B are split into an integer weight part
+// (counted from the majority flags) and a small floating part:
+//   red majority:  36 f^R = 36 w + (36 df - mu),  36 f^B = mu,
+//   blue majority: 36 f^R = mu,  36 f^B = 36 w + (36 df - mu),
+// with mu = m (36 w + 36 df) the minority colour in units of 1/36.
+
+// Direction masks of a lattice (bit i = direction i), built at compile time.
+template <class L>
+__host__ __device__ constexpr uint32_t dir_mask(int a, int kind) {
+    // kind 0: axis directions along a; 1: diagonals with c_a != 0;
+    // 2: diagonals in the plane of pair a with c_p c_q > 0; 3: ... < 0
+    uint32_t m = 0;
+    for (int i = 1; i < L::Q; ++i) {
+        const int c[3] = {L::cx[i], L::cy[i], L::cz[i]};
+        const int n2 = c[0] * c[0] + c[1] * c[1] + c[2] * c[2];
+        const int pq[3][2] = {{0, 1}, {0, 2}, {1, 2}};
+        if (kind == 0 && n2 == 1 && c[a] != 0) m |= 1u << i;
+        if (kind == 1 && n2 == 2 && c[a] != 0) m |= 1u << i;
+        if (kind >= 2 && n2 == 2) {
+            const int pr = c[pq[a][0]] * c[pq[a][1]];
+            if ((kind == 2 && pr > 0) || (kind == 3 && pr < 0)) m |= 1u << i;
+        }
     }
-    drho_out = drho;
-    // red: f_i of the red-majority populations less their blue parts, plus the
-    // red parts of the others; blue alike.
-    rR = ((T(K) + T(36) * A) + Mu) / T(36);
-    rB = ((T(36 - K) + T(36) * (drho - A)) - Mu) / T(36);
+    return m;
 }
 
-// Phase field psi = (rho^R - rho^B) / rho, from the minority colour's density
-// so that it is exactly +1 or -1 in the bulk of either colour.
+__device__ __forceinline__ int popc(uint32_t x) { return __builtin_popcount(x); }
+
+// all diagonal directions
+template <class L>
+__host__ __device__ constexpr uint32_t dir_mask_diag() {
+    uint32_t m = 0;
+    for (int i = 1; i < L::Q; ++i)
+        if (csq<L>(i) == 2) m |= 1u << i;
+    return m;
+}
+
+// sum of 36 w_i over the red-majority directions among the given axis and
+// diagonal directions (and the rest direction if asked)
+template <class L>
+__device__ __forceinline__ int w36_sum(uint32_t red, uint32_t axes, uint32_t diags, bool rest) {
+    return (rest ? int(red & 1u) * L::w36[0] : 0) + L::w36[1] * popc(red & axes) + L::w36[2] * popc(red & diags);
+}
+
+// 36 x red and 36 x blue floating parts of population i
+template <class L, typename T>
+__device__ __forceinline__ void colour_parts(const Pops<L, T> &p, int i, T &r36, T &b36) {
+    const T d = p.df[i];
+    const T mu = p.mm[i] * (T(w36<L>(i)) + T(36) * d);
+    const T t = T(36) * d - mu;
+    const bool fl = p.flag(i);
+    r36 = fl ? t : mu;
+    b36 = fl ? mu : t;
+}
+
+// Densities (Eq. (2)): the deviation of the total density and 36 x the red
+// and blue densities (each exact in the other colour's bulk).  Every path
+// computes psi through this one expression sequence, so psi is bitwise the
+// same whichever kernel or tile shape produced it.
+template <class L, typename T>
+__device__ __forceinline__ void densities(const Pops<L, T> &p, T &drho_out, T &r36R, T &r36B) {
+    T drho = 0, Ra = 0, Ba = 0;
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+        T r36, b36;
+        colour_parts<L, T>(p, i, r36, b36);
+        drho += p.df[i];
+        Ra += r36;
+        Ba += b36;
+    }
+    const uint32_t all = (1u << L::Q) - 2u;
+    const int K = w36_sum<L>(p.red, all & ~dir_mask_diag<L>(), dir_mask_diag<L>(), true);
+    drho_out = drho;
+    r36R = T(K) + Ra;
+    r36B = T(36 - K) + Ba;
+}
+
+// 36 x the total density
 template <typename T>
-__device__ __forceinline__ T psi_of(T drho, T rR, T rB) {
-    const T rho = T(1) + drho;
-    return rR >= rB ? T(1) - T(2) * rB / rho : T(2) * rR / rho - T(1);
+__device__ __forceinline__ T rho36(T drho) {
+    return T(36) + T(36) * drho;
+}
+
+// Phase field psi = (rho^R - rho^B) / rho from 36 x the colour densities,
+// with the minority colour's share formed directly so that psi is exactly +1
+// or -1 in the bulk of either colour.
+template <typename T>
+__device__ __forceinline__ T psi_of(T drho, T r36R, T r36B) {
+    const T r36 = rho36<T>(drho);
+    return r36R >= r36B ? T(1) - T(2) * r36B / r36 : T(2) * r36R / r36 - T(1);
 }
 
 // Moments of one node: densities, total momentum (Eq. (3)) and the
 // trace-adjusted momentum fluxes sum_i f_i Q_i and sum_i f_i^R Q_i with
-// Q_i = c_i c_i - I/3 (components xx, yy, zz, xy, xz, yz).
+// Q_i = c_i c_i - I/3 (components xx, yy, zz, xy, xz, yz).  The flux sums use
+// sum_i g_i (c_ia^2 - 1/3) = sum_{c_ia != 0} g_i - (1/3) sum_i g_i.
 template <typename T>
 struct Mom {
-    T drho, rhoR, rhoB;
+    T drho;
+    T r36R, r36B;  // 36 x rho^R, 36 x rho^B
     T j[3];
     T S[6];
     T PR[6];
@@ -295,48 +383,63 @@ struct Mom {
 
 template <class L, typename T>
 __device__ __forceinline__ void moments(const Pops<L, T> &p, Mom<T> &m) {
-    densities<L, T>(p, m.drho, m.rhoR, m.rhoB);
-    // sum_i f_i^R Q_i in units of 1/108 (diagonal: 108 w_i (c_a^2 - 1/3) is
-    // the integer 36 w_i (3 c_a^2 - 1)) and 1/36 (off-diagonal), as above.
-    T jx = 0, jy = 0, jz = 0;
-    T S[6] = {0, 0, 0, 0, 0, 0}, P[6] = {0, 0, 0, 0, 0, 0};
-    int KQ[6] = {0, 0, 0, 0, 0, 0};
+    T drho = 0, Ra = 0, Ba = 0;
+    T jd[3] = {0, 0, 0}, Sd[3] = {0, 0, 0}, So[3] = {0, 0, 0}, Rd[3] = {0, 0, 0}, Ro[3] = {0, 0, 0};
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) {
+        T r36, b36;
+        colour_parts<L, T>(p, i, r36, b36);
         const T d = p.df[i];
-        const bool fl = p.flag(i);
-        const T f36 = T(w36<L>(i)) + T(36) * d;
-        const T mu = p.mm[i] * f36;
-        // 36 x red part, less its integer weight share when red is the majority
-        const T r36 = fl ? T(36) * d - mu : mu;
-        if (L::cx[i]) jx += L::cx[i] > 0 ? d : -d;
-        if (L::cy[i]) jy += L::cy[i] > 0 ? d : -d;
-        if (L::cz[i]) jz += L::cz[i] > 0 ? d : -d;
+        drho += d;
+        Ra += r36;
+        Ba += b36;
+        const int c[3] = {L::cx[i], L::cy[i], L::cz[i]};
 #pragma unroll
         for (int a = 0; a < L::D; ++a) {
-            const int ca = a == 0 ? L::cx[i] : (a == 1 ? L::cy[i] : L::cz[i]);
-            S[a] += (T(ca * ca) - T(1.0 / 3.0)) * d;
-            const int q3 = 3 * ca * ca - 1;
-            P[a] += T(q3) * r36;
-            KQ[a] += fl ? w36<L>(i) * q3 : 0;
+            if (c[a]) {
+                jd[a] += c[a] > 0 ? d : -d;
+                Sd[a] += d;
+                Rd[a] += r36;
+            }
         }
-        const int off[3] = {L::cx[i] * L::cy[i], L::cx[i] * L::cz[i], L::cy[i] * L::cz[i]};
+        const int off[3] = {c[0] * c[1], c[0] * c[2], c[1] * c[2]};
 #pragma unroll
         for (int b = 0; b < (L::D == 3 ? 3 : 1); ++b) {
             if (off[b]) {
-                S[3 + b] += off[b] > 0 ? d : -d;
-                P[3 + b] += off[b] > 0 ? r36 : -r36;
-                KQ[3 + b] += fl ? off[b] * w36<L>(i) : 0;
+                So[b] += off[b] > 0 ? d : -d;
+                Ro[b] += off[b] > 0 ? r36 : -r36;
             }
         }
     }
-    m.j[0] = jx;
-    m.j[1] = jy;
-    m.j[2] = jz;
+    const uint32_t all = (1u << L::Q) - 2u;
+    const int K = w36_sum<L>(p.red, all & ~dir_mask_diag<L>(), dir_mask_diag<L>(), true);
+    m.drho = drho;
+    m.r36R = T(K) + Ra;
+    m.r36B = T(36 - K) + Ba;
 #pragma unroll
-    for (int q = 0; q < 6; ++q) {
-        m.S[q] = S[q];
-        m.PR[q] = q < 3 ? (T(KQ[q]) + P[q]) / T(108) : (T(KQ[q]) + P[q]) / T(36);
+    for (int a = 0; a < 3; ++a) m.j[a] = jd[a];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (a < L::D) {
+            // sum_{red} 36 w (3 c_a^2 - 1) = 3 sum_{red, c_a != 0} 36 w - K
+            const int Ka = 3 * w36_sum<L>(p.red, dir_mask<L>(a, 0), dir_mask<L>(a, 1), false) - K;
+            m.S[a] = Sd[a] - drho * T(1.0 / 3.0);
+            m.PR[a] = (T(Ka) + (T(3) * Rd[a] - Ra)) * T(1.0 / 108.0);
+        } else {
+            m.S[a] = T(0);
+            m.PR[a] = T(0);
+        }
+    }
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        if (b == 0 || L::D == 3) {
+            const int Kb = popc(p.red & dir_mask<L>(b, 2)) - popc(p.red & dir_mask<L>(b, 3));
+            m.S[3 + b] = So[b];
+            m.PR[3 + b] = (T(Kb) + Ro[b]) * T(1.0 / 36.0);
+        } else {
+            m.S[3 + b] = T(0);
+            m.PR[3 + b] = T(0);
+        }
     }
 }
 
@@ -411,9 +514,10 @@ __device__ __forceinline__ void pull_node(const Geo &g, const Model<T> &mo, cons
                 c.red = 0;
 #pragma unroll
                 for (int k = 0; k < L::Q; ++k) load_raw<L, S, T>(st, g.pitch, n, k, c);
-                T odr, oB;
-                densities<L, T>(c, odr, oR, oB);
+                T odr, oR36, oB36;
+                densities<L, T>(c, odr, oR36, oB36);
                 oRho = T(1) + odr;
+                oR = oR36 / T(36);
                 T jx = 0, jy = 0, jz = 0;
 #pragma unroll
                 for (int k = 0; k < L::Q; ++k) {
@@ -471,9 +575,10 @@ __device__ __forceinline__ void fold_flux(const Model<T> &mo, const Mom<T> &m, T
 // (weights, Q_i, (c.u)^2, (F.c)^2, B_i, phi_i) and flip the odd ones (c.u,
 // cos), so the update is computed once per pair.
 template <class L, typename T>
-__device__ __forceinline__ void collide(const Model<T> &mo, T drho, T rR, T rB, const T j[3], const T G[6],
+__device__ __forceinline__ void collide(const Model<T> &mo, T drho, T r36R, T r36B, const T j[3], const T G[6],
                                         const T F[3], const Pops<L, T> *pin, PostOut<L, T> &o) {
     const T rho = T(1) + drho;
+    const T rR = r36R * T(1.0 / 36.0), rB = r36B * T(1.0 / 36.0);
     const T inv_rho = rcp<T>(rho);
     const T ux = j[0] * inv_rho, uy = j[1] * inv_rho, uz = j[2] * inv_rho;
     const T usq = ux * ux + uy * uy + uz * uz;
@@ -498,12 +603,14 @@ __device__ __forceinline__ void collide(const Model<T> &mo, T drho, T rR, T rB, 
     const T invFn = hasF ? rcp<T>(Fn) : T(0);
     const T seg = mo.beta * rR * rB * inv_rho * inv_rho;
     // colour shares rho^k / rho, the minority one formed directly (exactly 0 in
-    // the other colour's bulk).  Colour shares use correctly rounded division:
-    // an approximate reciprocal errs to one side and would bias colour mass
-    // through the recolouring.
-    const bool redmaj = rR >= rB;
-    const T sB = redmaj ? rB / rho : T(1) - rR / rho;
-    const T sR = redmaj ? T(1) - sB : rR / rho;
+    // the other colour's bulk) with one correctly rounded division: a rounded
+    // constant or an approximate reciprocal would err to one side and bias
+    // colour mass through the recolouring.  rec_i / f_i may use the refined
+    // reciprocal: rec is odd in i, so a common error cancels between i and -i.
+    const T r36 = rho36<T>(drho);
+    const bool redmaj = r36R >= r36B;
+    const T sB = redmaj ? r36B / r36 : T(1) - r36R / r36;
+    const T sR = redmaj ? T(1) - sB : r36R / r36;
     const T wrho = rho * T(1.5) * usq;  // rho u^2 / (2 c_s^2)
     o.red = 0;
 
@@ -549,14 +656,16 @@ __device__ __forceinline__ void collide(const Model<T> &mo, T drho, T rR, T rB, 
         const T f_i = w + d_i;
         T m;
         bool fl;
-        split_shares<T>(f_i != T(0) ? sR + rec / f_i : sR, f_i != T(0) ? sB - rec / f_i : sB, m, fl);
+        const T q_i = f_i != T(0) ? rec * rcp<T>(f_i) : T(0);
+        split_shares<T>(sR + q_i, sB - q_i, m, fl);
         o.df[i] = d_i;
         o.mm[i] = m;
         o.red |= fl ? (1u << i) : 0u;
         if (i != 0) {
             const T d_b = ev - od;
             const T f_b = w + d_b;
-            split_shares<T>(f_b != T(0) ? sR - rec / f_b : sR, f_b != T(0) ? sB + rec / f_b : sB, m, fl);
+            const T q_b = f_b != T(0) ? rec * rcp<T>(f_b) : T(0);
+            split_shares<T>(sR - q_b, sB + q_b, m, fl);
             o.df[ib] = d_b;
             o.mm[ib] = m;
             o.red |= fl ? (1u << ib) : 0u;
@@ -567,11 +676,10 @@ __device__ __forceinline__ void collide(const Model<T> &mo, T drho, T rR, T rB, 
 template <class L, typename S, typename T>
 __device__ __forceinline__ void store_out(S *__restrict__ st, int64_t pitch, int64_t node,
                                           const PostOut<L, T> &o) {
+    typename PairOf<S>::type *a = reinterpret_cast<typename PairOf<S>::type *>(st);
 #pragma unroll
-    for (int i = 0; i < L::Q; ++i) {
-        st[int64_t(i) * pitch + node] = Codec<S>::template enc_df<L, T>(o.df[i], i);
-        st[int64_t(L::Q + i) * pitch + node] = Codec<S>::template enc_col<T>(o.mm[i], (o.red >> i) & 1u);
-    }
+    for (int i = 0; i < L::Q; ++i)
+        a[int64_t(i) * pitch + node] = encode_pair<L, S, T>(o.df[i], o.mm[i], (o.red >> i) & 1u, i);
 }
 
 }  // namespace lbcg

@@ -8,7 +8,7 @@
 // planes.  For plane z+1 it pulls the 38 populations of its nodes (Eq. (1)),
 // keeps only the 11 scalars the collision needs (drho, rho^R, j, folded
 // momentum flux G), and writes psi of the tile plus a one-node ring (the
-// ring recomputes the neighbours' densities from cache) into a 4-slot LDS
+// ring recomputes the neighbours' densities from cache) into a 5-slot LDS
 // ring buffer.  After one barrier it collides plane z with the gradient taken
 // from the LDS planes z-1, z, z+1 and stores the 38 new values coalesced,
 // with non-temporal stores (the new state is not read again in this step).
@@ -30,9 +30,6 @@ namespace lbcg {
 constexpr int kTX = 64;
 constexpr int kXCD = 8;
 
-#ifndef LBCG_PREFETCH
-#define LBCG_PREFETCH 1
-#endif
 #ifndef LBCG_NT_STORE
 #define LBCG_NT_STORE 1
 #endif
@@ -46,8 +43,8 @@ struct FusedArgs {
     int ntx, nty, zchunks;
 };
 
-template <typename S>
-__device__ __forceinline__ void put(S *p, S v) {
+template <typename V>
+__device__ __forceinline__ void put(V *p, V v) {
 #if LBCG_NT_STORE
     __builtin_nontemporal_store(v, p);
 #else
@@ -71,8 +68,9 @@ __device__ __forceinline__ void pull_periodic(const FusedArgs<S> &a, int x, int 
     const int xm = x == 0 ? a.nx - 1 : x - 1, xp = x == a.nx - 1 ? 0 : x + 1;
     const int ym = y == 0 ? a.ny - 1 : y - 1, yp = y == a.ny - 1 ? 0 : y + 1;
     const int zm = z == 0 ? a.nz - 1 : z - 1, zp = z == a.nz - 1 ? 0 : z + 1;
+    typedef typename PairOf<S>::type P2;
     const char *base = reinterpret_cast<const char *>(a.in);
-    const uint32_t cstride = uint32_t(a.pitch) * uint32_t(sizeof(S));
+    const uint32_t cstride = uint32_t(a.pitch) * uint32_t(sizeof(P2));
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) {
         // source = x - c_i
@@ -80,12 +78,8 @@ __device__ __forceinline__ void pull_periodic(const FusedArgs<S> &a, int x, int 
         const int ys = L::cy[i] > 0 ? ym : (L::cy[i] < 0 ? yp : y);
         const int zs = L::cz[i] > 0 ? zm : (L::cz[i] < 0 ? zp : z);
         const uint32_t nd = uint32_t(xs) + uint32_t(a.nx) * (uint32_t(ys) + uint32_t(a.ny) * uint32_t(zs));
-        const uint32_t o1 = uint32_t(i) * cstride + nd * uint32_t(sizeof(S));
-        const uint32_t o2 = o1 + uint32_t(L::Q) * cstride;
-        bool fl;
-        const T d = Codec<S>::template df<L, T>(*reinterpret_cast<const S *>(base + o1), i);
-        const T m = Codec<S>::template col<T>(*reinterpret_cast<const S *>(base + o2), fl);
-        p.set(i, d, m, fl);
+        const uint32_t off = uint32_t(i) * cstride + nd * uint32_t(sizeof(P2));
+        decode_pair<L, S, T>(*reinterpret_cast<const P2 *>(base + off), i, p);
     }
 }
 
@@ -134,12 +128,17 @@ __global__ void __launch_bounds__(kTX * R) k_step_fused(FusedArgs<S> a, Model<T>
         }
     }
     const int gx = wrap_m1(x0 + rx, a.nx), gy = wrap_m1(y0 + ry, a.ny);
-    auto slot_of = [&](int zp) { return lds + ((zp - z0 + 1) & 3) * PL; };
+    // psi planes live in a 5-slot LDS ring: iteration z writes the interior of
+    // plane z+1 and the ring of plane z+2 while the collision reads planes
+    // z-1..z+1, so a slot is rewritten only after every wave has passed the
+    // barrier that follows its last read.
+    auto slot_of = [&](int zp) { return lds + ((zp - z0 + 1) % 5) * PL; };
 
-    // psi of the ring nodes of plane zp, in two halves: issue the loads, then
-    // (after other work) reduce them and write LDS.  Loads retire in order, so
-    // ring loads are issued before the interior prefetch; waiting for them then
-    // leaves the prefetch in flight.
+    // Ring nodes: psi of the one-node ring around the tile.  Their loads are
+    // issued one plane ahead, together with the interior prefetch, so the
+    // neighbour tiles' rows are requested while those tiles load them too
+    // (L2 hits), and before the interior prefetch so that waiting for them
+    // (loads retire in order) leaves the prefetch in flight.
     Pops<L, T> rp;
     rp.red = 0;
     auto ring_issue = [&](int zp) {
@@ -159,7 +158,8 @@ __global__ void __launch_bounds__(kTX * R) k_step_fused(FusedArgs<S> a, Model<T>
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) pp.df[i] = pp.mm[i] = T(0);
 
-    // prologue: psi of plane z0-1, moments and psi of plane z0
+    // prologue: psi of planes z0-1 and z0, moments of z0, ring of z0+1 and
+    // the interior loads of z0+1
     ring_issue(z0 - 1);
     if (active) {
         pull_periodic<S, T>(a, x, y, wrapz(z0 - 1, a.nz), pp);
@@ -174,41 +174,37 @@ __global__ void __launch_bounds__(kTX * R) k_step_fused(FusedArgs<S> a, Model<T>
         Mom<T> m;
         moments<L, T>(pp, m);
         cd = m.drho;
-        cR = m.rhoR;
-        cB = m.rhoB;
+        cR = m.r36R;
+        cB = m.r36B;
         cj[0] = m.j[0];
         cj[1] = m.j[1];
         cj[2] = m.j[2];
         fold_flux<T>(mo, m, cG);
-        slot_of(z0)[(row + 1) * W + lane + 1] = float(psi_of<T>(m.drho, m.rhoR, m.rhoB));
+        slot_of(z0)[(row + 1) * W + lane + 1] = float(psi_of<T>(m.drho, m.r36R, m.r36B));
     }
     ring_finish(z0);
-#if LBCG_PREFETCH
+    ring_issue(z0 + 1);
     if (active) pull_periodic<S, T>(a, x, y, wrapz(z0 + 1, a.nz), pp);
-#endif
+    ring_finish(z0 + 1);
 
     for (int z = z0; z < z1; ++z) {
+        const bool more = z + 2 <= z1;  // uniform over the block
         T nd = 0, nR = 0, nB = 0, nj[3] = {0, 0, 0}, nG[6] = {0, 0, 0, 0, 0, 0};
-        ring_issue(z + 1);
-#if !LBCG_PREFETCH
-        if (active) pull_periodic<S, T>(a, x, y, wrapz(z + 1, a.nz), pp);
-#endif
+        if (more) ring_issue(z + 2);
         if (active) {
             Mom<T> m;
             moments<L, T>(pp, m);
             nd = m.drho;
-            nR = m.rhoR;
-            nB = m.rhoB;
+            nR = m.r36R;
+            nB = m.r36B;
             nj[0] = m.j[0];
             nj[1] = m.j[1];
             nj[2] = m.j[2];
             fold_flux<T>(mo, m, nG);
-            slot_of(z + 1)[(row + 1) * W + lane + 1] = float(psi_of<T>(m.drho, m.rhoR, m.rhoB));
+            slot_of(z + 1)[(row + 1) * W + lane + 1] = float(psi_of<T>(m.drho, m.r36R, m.r36B));
         }
-#if LBCG_PREFETCH
-        if (active && z + 2 <= z1) pull_periodic<S, T>(a, x, y, wrapz(z + 2, a.nz), pp);
-#endif
-        ring_finish(z + 1);
+        if (more && active) pull_periodic<S, T>(a, x, y, wrapz(z + 2, a.nz), pp);
+        if (more) ring_finish(z + 2);
         lds_barrier();
         if (active) {
             const float *sm = slot_of(z - 1), *s0 = slot_of(z), *sp = slot_of(z + 1);
@@ -226,15 +222,14 @@ __global__ void __launch_bounds__(kTX * R) k_step_fused(FusedArgs<S> a, Model<T>
             const T F[3] = {fx, fy, fz};
             PostOut<L, T> o;
             collide<L, T>(mo, cd, cR, cB, cj, cG, F, nullptr, o);
+            typedef typename PairOf<S>::type P2;
             const uint32_t n = uint32_t(x) + uint32_t(a.nx) * (uint32_t(y) + uint32_t(a.ny) * uint32_t(z));
             char *ob = reinterpret_cast<char *>(a.out);
-            const uint32_t cstride = uint32_t(a.pitch) * uint32_t(sizeof(S));
+            const uint32_t cstride = uint32_t(a.pitch) * uint32_t(sizeof(P2));
 #pragma unroll
             for (int i = 0; i < L::Q; ++i) {
-                const uint32_t o1 = uint32_t(i) * cstride + n * uint32_t(sizeof(S));
-                put(reinterpret_cast<S *>(ob + o1), Codec<S>::template enc_df<L, T>(o.df[i], i));
-                put(reinterpret_cast<S *>(ob + o1 + uint32_t(L::Q) * cstride),
-                    Codec<S>::template enc_col<T>(o.mm[i], (o.red >> i) & 1u));
+                const uint32_t off = uint32_t(i) * cstride + n * uint32_t(sizeof(P2));
+                put(reinterpret_cast<P2 *>(ob + off), encode_pair<L, S, T>(o.df[i], o.mm[i], (o.red >> i) & 1u, i));
             }
         }
         cd = nd;
@@ -259,7 +254,7 @@ static const void *fused_fn(int R) {
                   : reinterpret_cast<const void *>(&k_step_fused<S, float, 8>);
 }
 
-static size_t fused_lds(int R) { return size_t(4) * (R + 2) * (kTX + 2) * sizeof(float); }
+static size_t fused_lds(int R) { return size_t(5) * (R + 2) * (kTX + 2) * sizeof(float); }
 
 int fused_resident_blocks(int prec, int rows) {
     int per_cu = 0;

@@ -50,8 +50,8 @@ __global__ void __launch_bounds__(kBlock) k_init(Geo g, Model<T> mo, int64_t n0,
         double m;
         bool redmaj;
         split_shares<double>(f != 0.0 ? fR / f : 0.0, f != 0.0 ? fB / f : 0.0, m, redmaj);
-        st[int64_t(i) * g.pitch + n] = Codec<S>::template enc_df<L, double>(f - w, i);
-        st[int64_t(L::Q + i) * g.pitch + n] = Codec<S>::template enc_col<double>(m, redmaj);
+        reinterpret_cast<typename PairOf<S>::type *>(st)[int64_t(i) * g.pitch + n] =
+            encode_pair<L, S, double>(f - w, m, redmaj, i);
     }
 }
 
@@ -123,7 +123,7 @@ __global__ void __launch_bounds__(kBlock) k_step_generic(Geo g, Model<T> mo, con
     T F[3];
     gradient<L, T>(g, psi, x, y, z, n, F);
     PostOut<L, T> o;
-    collide<L, T>(mo, m.drho, m.rhoR, m.rhoB, m.j, G, F, &p, o);
+    collide<L, T>(mo, m.drho, m.r36R, m.r36B, m.j, G, F, &p, o);
     store_out<L, S, T>(out, g.pitch, n, o);
 }
 
@@ -142,12 +142,12 @@ __global__ void __launch_bounds__(kBlock) k_fields(Geo g, Model<T> mo, const S *
         Mom<T> m;
         moments<L, T>(p, m);
         const T rho = T(1) + m.drho;
-        v[0] = double(m.rhoR);
-        v[1] = double(m.rhoB);
+        v[0] = double(m.r36R / T(36));
+        v[1] = double(m.r36B / T(36));
         v[2] = double(m.j[0] / rho);
         v[3] = double(m.j[1] / rho);
         v[4] = double(m.j[2] / rho);
-        v[5] = double(psi_of<T>(m.drho, m.rhoR, m.rhoB));
+        v[5] = double(psi_of<T>(m.drho, m.r36R, m.r36B));
     }
 #pragma unroll
     for (int q = 0; q < 6; ++q) out[q * cnt + k] = v[q];
@@ -228,14 +228,14 @@ __global__ void __launch_bounds__(kBlock) k_diag(Geo g, Model<T> mo, const S *__
         Mom<T> m;
         moments<L, T>(p, m);
         const double rho = 1.0 + double(m.drho);
-        const double r0 = double(m.rhoR), r1 = double(m.rhoB);
+        const double r0 = double(m.r36R / T(36)), r1 = double(m.r36B / T(36));
         const double jx = double(m.j[0]), jy = double(m.j[1]), jz = double(m.j[2]);
         acc[12] += 1.0;
         if (!(isfinite(rho) && isfinite(r0) && isfinite(r1) && isfinite(jx) && isfinite(jy) && isfinite(jz))) {
             acc[11] += 1.0;
             continue;
         }
-        const double psi = double(psi_of<T>(m.drho, m.rhoR, m.rhoB));
+        const double psi = double(psi_of<T>(m.drho, m.r36R, m.r36B));
         const double pres = pR * r0 + pB * r1;  // Eq. (8)
         acc[0] += r0;
         acc[1] += r1;

@@ -146,7 +146,7 @@ int check_device() {
 
 FusedShape pick_shape(const lbcg_sim *s, const lbcg_params *p) {
     FusedShape sh;
-    sh.rows = p->tile[0] ? p->tile[0] : 4;
+    sh.rows = p->tile[0] ? p->tile[0] : 8;
     int zc = p->tile[1];
     if (!zc && s->kernel == LBCG_KERNEL_FUSED) {
         // One wave of resident blocks: each z chunk re-reads two planes, so use
@@ -512,7 +512,7 @@ int lbcg_diagnostics(lbcg_sim *s, lbcg_diag *out) {
     return d.nonfinite ? LBCG_E_UNSTABLE : LBCG_OK;
 }
 
-// Checkpoint layout: 8 int64 header words, then 2Q component arrays of N values.
+// Checkpoint layout: 8 int64 header words, then Q arrays of N (df, m) value pairs.
 static const int64_t kMagic = 0x4c42434731LL;  // "LBCG1"
 
 int lbcg_state_bytes(lbcg_sim *s, size_t *bytes) {
@@ -538,10 +538,11 @@ int lbcg_get_state(lbcg_sim *s, void *host, size_t bytes) {
     h[6] = s->pulled ? 1 : 0;
     h[7] = s->step;
     char *dst = reinterpret_cast<char *>(h + 8);
-    const size_t comp = size_t(s->g.N) * s->elem;
+    // one array of (df, m) pairs per direction
+    const size_t comp = 2 * size_t(s->g.N) * s->elem;
     const char *src = static_cast<const char *>(s->buf[s->cur]);
-    for (int c = 0; c < 2 * s->Q; ++c)
-        HIP_TRY(hipMemcpyAsync(dst + c * comp, src + size_t(c) * size_t(s->g.pitch) * s->elem, comp,
+    for (int c = 0; c < s->Q; ++c)
+        HIP_TRY(hipMemcpyAsync(dst + c * comp, src + 2 * size_t(c) * size_t(s->g.pitch) * s->elem, comp,
                                hipMemcpyDeviceToHost, s->stream));
     HIP_TRY(hipStreamSynchronize(s->stream));
     return LBCG_OK;
@@ -558,10 +559,10 @@ int lbcg_set_state(lbcg_sim *s, const void *host, size_t bytes) {
         h[5] != s->g.nz || (h[6] != 0 && h[6] != 1) || h[7] < 0)
         return LBCG_E_INVAL;
     const char *src = reinterpret_cast<const char *>(h + 8);
-    const size_t comp = size_t(s->g.N) * s->elem;
+    const size_t comp = 2 * size_t(s->g.N) * s->elem;
     char *dst = static_cast<char *>(s->buf[s->cur]);
-    for (int c = 0; c < 2 * s->Q; ++c)
-        HIP_TRY(hipMemcpyAsync(dst + size_t(c) * size_t(s->g.pitch) * s->elem, src + c * comp, comp,
+    for (int c = 0; c < s->Q; ++c)
+        HIP_TRY(hipMemcpyAsync(dst + 2 * size_t(c) * size_t(s->g.pitch) * s->elem, src + c * comp, comp,
                                hipMemcpyHostToDevice, s->stream));
     HIP_TRY(hipStreamSynchronize(s->stream));
     s->pulled = h[6] == 1;
