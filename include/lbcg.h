@@ -60,7 +60,9 @@ extern "C" {
 #define LBCG_BGK 1
 
 /* Kernel choice: automatic, the two-pass generic kernel (every lattice,
- * precision, collision and boundary) or the fused single-pass D3Q19 kernel. */
+ * precision, collision and boundary) or the fused single-pass kernel (D3Q19,
+ * F32 or F16 storage, regularized collision, any geometry; state buffers
+ * below 4 GiB).  Automatic picks the fused kernel where it applies. */
 #define LBCG_KERNEL_AUTO 0
 #define LBCG_KERNEL_GENERIC 1
 #define LBCG_KERNEL_FUSED 2
@@ -193,15 +195,38 @@ const char *lbcg_strerror(int status);
  * LBCG_KERNEL_FUSED), rows per block, z chunks. */
 int lbcg_launch_info(lbcg_sim *s, int32_t *kernel, int32_t *rows, int32_t *zchunks);
 
-/* Batched form: many independent lattices stepped together.  A batch refers
- * to existing handles (same device, same stream, each initialised); it does
- * not own them.  lbcg_batch_step advances lattice j by nsteps[j] >= 0 steps
- * with one launch per time level over all lattices that still have steps
- * left, captured into a HIP graph and replayed.  Results per lattice are
- * identical to stepping each handle alone. */
+/* Choose the fused kernel's launch shape for this handle by timing candidate
+ * shapes (rows 4 or 8; z splits that fill the device once, twice or four
+ * times; chunks of 8 to 64 planes) on the handle's own lattice, stepping the
+ * current state into the spare buffer so the state does not change.  Keeps
+ * the fastest shape for later steps and reports it.  No effect on the
+ * generic kernel.  Synchronizes. */
+int lbcg_tune(lbcg_sim *s, int32_t *rows, int32_t *zchunks);
+
+/* Batched form (the paper's method applied to many independent lattices at
+ * once): one fused launch per time level covers every lattice that still has
+ * steps left, with runs of 32 levels replayed from HIP graphs.  A batch
+ * refers to existing handles; it does not own them, and they must outlive
+ * it.  Requirements: every handle initialised, on the fused kernel (D3Q19,
+ * F32 or F16 storage, regularized collision), one storage precision, one
+ * stream, no handle listed twice; geometry and periodic lattices may mix.
+ * tile: {rows per block (4 or 8), z planes per chunk (>= 1)}; NULL or {0, 0}
+ * = choose by timing candidate shapes on the batch (the states do not
+ * change).  Errors: LBCG_E_INVAL for a violated requirement, LBCG_E_NOMEM /
+ * LBCG_E_DEVICE for allocation or HIP failures.  The batch allocates its
+ * own small descriptor tables (device and pinned host memory).
+ *
+ * lbcg_batch_step advances lattice j by nsteps[j] >= 0 steps (n entries),
+ * asynchronously on the shared stream.  Results per lattice are bitwise those
+ * of lbcg_step on the handle alone.  Between batch steps the handles may be
+ * used directly (fields, diagnostics, lbcg_step). */
 typedef struct lbcg_batch lbcg_batch;
-int lbcg_batch_create(lbcg_sim *const *sims, int32_t n, lbcg_batch **out);
+int lbcg_batch_create(lbcg_sim *const *sims, int32_t n, const int32_t *tile, lbcg_batch **out);
 int lbcg_batch_step(lbcg_batch *b, const int64_t *nsteps);
+/* Launch shape of the batch: rows per block, z planes per chunk, total blocks
+ * of one level over all lattices. */
+int lbcg_batch_launch_info(lbcg_batch *b, int32_t *rows, int32_t *zplanes, int64_t *blocks);
+/* Waits for the batch's queued work, then releases its tables. */
 void lbcg_batch_destroy(lbcg_batch *b);
 
 #ifdef __cplusplus

@@ -61,24 +61,42 @@ hipError_t launch_pops_at(int lattice, int prec, const Geo &g, const ModelD &md,
 hipError_t launch_diag(int lattice, int prec, const Geo &g, const ModelD &md, const void *st,
                        bool pulled, double *partials, double *res, hipStream_t s);
 
-// Fused single-pass D3Q19 step (periodic, no mask); F32 or F16 storage.
+// Fused single-pass D3Q19 step; F32 or F16 storage, with or without geometry.
 struct FusedShape {
     int rows;     // rows of the x-y tile (one wave of 64 nodes per row)
     int zchunks;  // z range split per column of tiles
 };
+
+// Kernel view of one lattice for the fused sweep.
+template <typename S>
+struct FusedArgs {
+    const S *in;
+    S *out;
+    int nx, ny, nz;
+    int64_t pitch;
+    const uint8_t *mask;  // nullptr = every node fluid
+    const DevInlet *inlets;
+    const DevOutlet *outlets;
+    int ntx, nty, zchunks;
+};
+template <typename S>
+FusedArgs<S> fused_args(const Geo &g, const void *in, void *out, FusedShape sh);
+
 hipError_t launch_step_fused(int prec, const Geo &g, const ModelD &md, const void *in, void *out,
                              FusedShape shape, hipStream_t s);
 bool fused_supported(int lattice, int prec, const Geo &g);
 // Blocks of the fused kernel that fit on the device at once.
-int fused_resident_blocks(int prec, int rows);
+int fused_resident_blocks(int prec, int rows, bool masked);
 
-// Batched fused step: one launch over many lattices (see lbcg_batch.hip).
-struct BatchItem {
-    const void *in;
-    void *out;
-    Geo g;
-    ModelD md;
-    int prec;
+// Batched fused step: one launch steps many lattices by one time level.
+// Block b sweeps work item bitem[b] (tile-major (tile, z chunk) index) of
+// lattice blat[b], described by desc[blat[b]].
+template <typename S>
+struct BatchDesc {
+    FusedArgs<S> a;
+    Model<float> mo;
 };
+hipError_t launch_step_fused_batch(int prec, const void *desc, const int *blat, const int *bitem, int nblocks,
+                                   int rows, bool masked, hipStream_t s);
 
 }  // namespace lbcg

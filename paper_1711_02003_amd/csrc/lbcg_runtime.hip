@@ -13,43 +13,9 @@
 #include <vector>
 
 #include "../../include/lbcg.h"
-#include "lbcg_internal.h"
+#include "lbcg_sim.h"
 
 using namespace lbcg;
-
-struct lbcg_sim {
-    int lattice, prec, collision, kernel;
-    int Q, D;
-    Geo g;
-    ModelD md;
-    FusedShape shape;
-    size_t elem;            // bytes per stored value
-    size_t state_bytes;     // one state buffer
-    void *buf[2];
-    int cur;                // buffer holding the current state
-    bool pulled;            // true: buffer holds post-collision values (pull to read S_t)
-    bool initialised;
-    int64_t step;
-    void *psi;              // generic phase-field scratch (N values of the compute type)
-    double *partials, *diag;
-    double *staging;        // field / population staging
-    int64_t staging_nodes;
-    uint8_t *mask_dev;
-    DevInlet *in_dev;
-    DevOutlet *out_dev;
-    hipStream_t stream;
-    bool own_stream;
-    void *arena;
-    bool own_arena;
-    size_t arena_bytes;
-    hipGraphExec_t graph[2];  // graph_steps steps starting from buffer 0 / 1
-    int graph_steps;
-    bool graph_failed;
-};
-
-struct lbcg_batch {
-    std::vector<lbcg_sim *> sims;
-};
 
 namespace {
 
@@ -152,7 +118,7 @@ FusedShape pick_shape(const lbcg_sim *s, const lbcg_params *p) {
         // One wave of resident blocks: each z chunk re-reads two planes, so use
         // as few (long) chunks as fill the device, but keep chunks >= 8 planes.
         const int64_t tiles = int64_t((s->g.nx + 63) / 64) * ((s->g.ny + sh.rows - 1) / sh.rows);
-        const int64_t resident = fused_resident_blocks(s->prec, sh.rows);
+        const int64_t resident = fused_resident_blocks(s->prec, sh.rows, s->g.mask != nullptr);
         int64_t want = (resident + tiles - 1) / tiles;
         const int64_t cap = s->g.nz / 8 > 1 ? s->g.nz / 8 : 1;
         zc = int(want < 1 ? 1 : (want > cap ? cap : want));
@@ -579,37 +545,76 @@ int lbcg_launch_info(lbcg_sim *s, int32_t *kernel, int32_t *rows, int32_t *zchun
     return LBCG_OK;
 }
 
+int lbcg_tune(lbcg_sim *s, int32_t *rows, int32_t *zchunks) {
+    if (!s) return LBCG_E_INVAL;
+    if (!s->initialised) return LBCG_E_STATE;
+    if (s->kernel == LBCG_KERNEL_FUSED) {
+        // Candidate shapes: both tile heights, z splits that fill the device
+        // once, twice or four times, and fixed chunk lengths.  Each is timed
+        // stepping buf[cur] into the other buffer, which leaves the current
+        // state untouched.
+        const bool masked = s->g.mask != nullptr;
+        std::vector<FusedShape> cand;
+        for (int r : {4, 8}) {
+            const int64_t tiles = int64_t((s->g.nx + 63) / 64) * ((s->g.ny + r - 1) / r);
+            const int64_t resident = fused_resident_blocks(s->prec, r, masked);
+            std::vector<int64_t> zs = {1};
+            for (int m : {1, 2, 4}) zs.push_back((m * resident + tiles - 1) / tiles);
+            for (int planes : {8, 16, 32, 64}) zs.push_back((s->g.nz + planes - 1) / planes);
+            for (int64_t z : zs) {
+                const int zc = int(z < 1 ? 1 : (z > s->g.nz ? s->g.nz : (z > 4096 ? 4096 : z)));
+                bool seen = false;
+                for (const FusedShape &c : cand) seen = seen || (c.rows == r && c.zchunks == zc);
+                if (!seen) cand.push_back(FusedShape{r, zc});
+            }
+        }
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        HIP_TRY(hipEventCreate(&e0));
+        if (hipEventCreate(&e1) != hipSuccess) {
+            (void)hipEventDestroy(e0);
+            return LBCG_E_DEVICE;
+        }
+        const void *in = s->buf[s->cur];
+        void *out = s->buf[s->cur ^ 1];
+        float best = 0;
+        FusedShape pick = s->shape;
+        hipError_t e = hipSuccess;
+        for (const FusedShape &c : cand) {
+            for (int k = 0; k < 2 && e == hipSuccess; ++k) e = launch_step_fused(s->prec, s->g, s->md, in, out, c, s->stream);
+            if (e == hipSuccess) e = hipEventRecord(e0, s->stream);
+            for (int k = 0; k < 4 && e == hipSuccess; ++k) e = launch_step_fused(s->prec, s->g, s->md, in, out, c, s->stream);
+            if (e == hipSuccess) e = hipEventRecord(e1, s->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) break;
+            if (best == 0 || ms < best) {
+                best = ms;
+                pick = c;
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (e != hipSuccess) return dev_err(e);
+        if (pick.rows != s->shape.rows || pick.zchunks != s->shape.zchunks) {
+            for (int k = 0; k < 2; ++k)
+                if (s->graph[k]) {
+                    (void)hipGraphExecDestroy(s->graph[k]);
+                    s->graph[k] = nullptr;
+                }
+            s->shape = pick;
+        }
+    }
+    if (rows) *rows = s->shape.rows;
+    if (zchunks) *zchunks = s->shape.zchunks;
+    return LBCG_OK;
+}
+
 void lbcg_destroy(lbcg_sim *s) {
     if (!s) return;
     (void)hipStreamSynchronize(s->stream);
     release(s);
     delete s;
 }
-
-int lbcg_batch_create(lbcg_sim *const *sims, int32_t n, lbcg_batch **out) {
-    if (!sims || n < 1 || !out) return LBCG_E_INVAL;
-    lbcg_batch *b = new (std::nothrow) lbcg_batch();
-    if (!b) return LBCG_E_NOMEM;
-    for (int j = 0; j < n; ++j) {
-        if (!sims[j]) {
-            delete b;
-            return LBCG_E_INVAL;
-        }
-        b->sims.push_back(sims[j]);
-    }
-    *out = b;
-    return LBCG_OK;
-}
-
-int lbcg_batch_step(lbcg_batch *b, const int64_t *nsteps) {
-    if (!b || !nsteps) return LBCG_E_INVAL;
-    for (size_t j = 0; j < b->sims.size(); ++j) {
-        int rc = lbcg_step(b->sims[j], nsteps[j]);
-        if (rc) return rc;
-    }
-    return LBCG_OK;
-}
-
-void lbcg_batch_destroy(lbcg_batch *b) { delete b; }
 
 }  // extern "C"

@@ -81,8 +81,10 @@ _SIGS = {
     "lbcg_destroy": (None, [C.c_void_p]),
     "lbcg_strerror": (C.c_char_p, [C.c_int]),
     "lbcg_launch_info": (C.c_int, [C.c_void_p, _P(C.c_int32), _P(C.c_int32), _P(C.c_int32)]),
-    "lbcg_batch_create": (C.c_int, [_P(C.c_void_p), C.c_int32, _P(C.c_void_p)]),
+    "lbcg_tune": (C.c_int, [C.c_void_p, _P(C.c_int32), _P(C.c_int32)]),
+    "lbcg_batch_create": (C.c_int, [_P(C.c_void_p), C.c_int32, _P(C.c_int32), _P(C.c_void_p)]),
     "lbcg_batch_step": (C.c_int, [C.c_void_p, _P(C.c_int64)]),
+    "lbcg_batch_launch_info": (C.c_int, [C.c_void_p, _P(C.c_int32), _P(C.c_int32), _P(C.c_int64)]),
     "lbcg_batch_destroy": (None, [C.c_void_p]),
 }
 
@@ -296,11 +298,65 @@ class Sim:
                "lbcg_launch_info")
         return {"kernel": k.value, "rows": r.value, "zchunks": z.value}
 
+    def tune(self):
+        """Time candidate launch shapes of the fused kernel and keep the fastest."""
+        r, z = C.c_int32(), C.c_int32()
+        _check(self._lib.lbcg_tune(self._handle(), C.byref(r), C.byref(z)), "lbcg_tune")
+        return {"rows": r.value, "zchunks": z.value}
+
     def close(self):
         if self._h is not None:
             self._lib.lbcg_destroy(self._h)
             self._h = None
             self._buf = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many Sim handles (fused kernel, one precision, one stream) stepped together.
+
+    ``tile`` = (rows per block, z planes per chunk); None = chosen by timing on
+    the batch.  The batch keeps references to its handles.
+    """
+
+    def __init__(self, sims, tile=None):
+        self._lib = load_library()
+        self.sims = list(sims)
+        arr = (C.c_void_p * len(self.sims))(*[s._handle().value for s in self.sims])
+        t = None if tile is None else (C.c_int32 * 2)(*[int(v) for v in tile])
+        h = C.c_void_p()
+        _check(self._lib.lbcg_batch_create(arr, len(self.sims), t, C.byref(h)), "lbcg_batch_create")
+        self._h = h
+
+    def step(self, nsteps):
+        """Advance lattice j by nsteps[j] steps (an int applies to every lattice)."""
+        if np.isscalar(nsteps):
+            nsteps = [int(nsteps)] * len(self.sims)
+        n = np.ascontiguousarray(nsteps, dtype=np.int64)
+        assert n.size == len(self.sims)
+        if self._h is None:
+            raise RuntimeError("batch already closed")
+        _check(self._lib.lbcg_batch_step(self._h, n.ctypes.data_as(C.POINTER(C.c_int64))), "lbcg_batch_step")
+        return self
+
+    def synchronize(self):
+        self.sims[0].synchronize()
+
+    def launch_info(self):
+        r, z, b = C.c_int32(), C.c_int32(), C.c_int64()
+        _check(self._lib.lbcg_batch_launch_info(self._h, C.byref(r), C.byref(z), C.byref(b)),
+               "lbcg_batch_launch_info")
+        return {"rows": r.value, "zplanes": z.value, "blocks": b.value}
+
+    def close(self):
+        if self._h is not None:
+            self._lib.lbcg_batch_destroy(self._h)
+            self._h = None
 
     def __del__(self):
         try:

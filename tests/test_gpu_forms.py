@@ -1,0 +1,235 @@
+"""GPU tests of the fused kernel on geometry, the batched form, launch-shape
+tuning and FP16 storage.
+
+Bars: the fused kernel on a masked lattice is bitwise the generic kernel and
+agrees with the FP64 oracle to FP32 level; a batch gives every lattice
+bitwise the result of stepping it alone; tuning leaves the state untouched;
+FP16 storage stays within 1 % of FP32 on the droplet radius and Laplace
+pressure.
+"""
+import numpy as np
+import pytest
+
+from paper_1711_02003_amd import workloads as W
+from tests.helpers import oracle_for, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def L():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1711_02003_amd import lbcg
+    lbcg.load_library()
+    return lbcg
+
+
+@pytest.fixture(scope="module")
+def stream():
+    import torch
+    return torch.cuda.Stream()
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _maxrel(a, b, sel=None):
+    a, b = np.asarray(a), np.asarray(b)
+    if sel is not None:
+        a, b = a[..., sel], b[..., sel]
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+def _small_focusing():
+    # the flow-focusing cross of the benchmark geometry at 1/4 size, with a
+    # faster inlet so that 200 steps move the interface
+    return W.flow_focusing(nx=128, ny=48, nz=14, lam=3.0, u_disp=0.02, u_side=0.03, A=0.01)
+
+
+def test_fused_masked_matches_generic_bitwise(L):
+    w = _small_focusing()
+    _say(f"fused vs generic masked {w.dims}")
+    a = L.Sim.from_workload(w, precision="f32", kernel=L.KERNEL_FUSED)
+    b = L.Sim.from_workload(w, precision="f32", kernel=L.KERNEL_GENERIC)
+    assert a.launch_info()["kernel"] == L.KERNEL_FUSED
+    a.step(200)
+    b.step(200)
+    fl = w.mask == 0
+    pa, pb = a.populations()[..., fl], b.populations()[..., fl]
+    _say(f"  max rel diff {_maxrel(pa, pb):.2e}")
+    assert np.array_equal(pa, pb)
+
+
+@pytest.mark.parametrize("tile", [(4, 1, 0), (8, 3, 0), (4, 0, 0)])
+def test_fused_masked_tile_invariance(L, tile):
+    w = _small_focusing()
+    ref = L.Sim.from_workload(w, precision="f32", kernel=L.KERNEL_FUSED, tile=(8, 1, 0))
+    s = L.Sim.from_workload(w, precision="f32", kernel=L.KERNEL_FUSED, tile=tile)
+    ref.step(41)
+    s.step(41)
+    fl = w.mask == 0
+    assert np.array_equal(s.populations()[..., fl], ref.populations()[..., fl])
+
+
+def test_fused_masked_matches_oracle(L, orc):
+    # FP32 fused on the flow-focusing geometry vs the FP64 oracle: velocity
+    # and phase field after 300 steps of driven flow
+    w = _small_focusing()
+    s = L.Sim.from_workload(w, precision="f32", kernel=L.KERNEL_FUSED)
+    s.step(300)
+    o = oracle_for(orc, w, threads=16).step(300)
+    g, f = s.fields(), o.fields()
+    fl = w.mask == 0
+    eu = rel_l2(g["u"][:, fl], f["u"][:, fl])
+    ep = rel_l2(g["psi"][fl], f["psi"][fl])
+    _say(f"focusing 300 steps: relL2 u {eu:.2e} psi {ep:.2e} max|u| {np.abs(f['u']).max():.3e}")
+    assert eu < 1e-5 and ep < 1e-5
+
+
+def test_full_size_focusing_sampled(L, orc):
+    # Flow-focusing cross at full size (512 x 128 x 64) in the benchmark's
+    # launch configuration.  A node's next state depends on the stored state
+    # and mask within two nodes, so the oracle steps 5^3 cuts (mask and
+    # boundary tables included) around sampled fluid nodes.
+    w = W.flow_focusing(lam=3.0)
+    nx, ny, nz = w.dims
+    s = L.Sim.from_workload(w, precision="f32")
+    assert s.launch_info()["kernel"] == L.KERNEL_FUSED
+    s.step(30)
+    rng = np.random.default_rng(3)
+    fluid = np.flatnonzero(w.mask.reshape(-1) == 0)
+    # bias the sample to nodes near walls, inlets and the outlet
+    near = np.flatnonzero((w.mask.reshape(-1) == 0) & (_dist_to_solid(w.mask).reshape(-1) <= 2))
+    picks = np.concatenate([rng.choice(near, 32, replace=False), rng.choice(fluid, 16, replace=False)])
+    off = np.arange(-2, 3)
+    boxes, masks = [], []
+    for n in picks:
+        cx, cy, cz = n % nx, (n // nx) % ny, n // (nx * ny)
+        zz, yy, xx = np.meshgrid((cz + off) % nz, (cy + off) % ny, (cx + off) % nx, indexing="ij")
+        boxes.append((xx + nx * (yy + ny * zz)).reshape(-1))
+        masks.append(w.mask[zz, yy, xx])
+    before = s.populations_at(np.concatenate(boxes)).reshape(len(picks), 5, 5, 5, 2, 19)
+    s.step(1)
+    after = s.populations_at(picks)
+    worst = 0.0
+    for j in range(len(picks)):
+        p = orc.Params(lattice=orc.D3Q19, dims=(5, 5, 5), tau=(w.tau_R, w.tau_B), A=(w.A, w.A), beta=w.beta,
+                       mask=masks[j],
+                       inlets=[orc.Inlet(u=i["u"], rho_w=(i["rho_R"], i["rho_B"])) for i in w.inlets],
+                       outlets=[orc.Outlet(rho=o["rho"]) for o in w.outlets])
+        o = orc.Oracle(p)
+        pops = np.moveaxis(before[j], (3, 4), (0, 1)).copy()
+        pops[:, :, masks[j] != 0] = 0.0
+        o.set_populations(pops)
+        o.step(1)
+        ref = o.populations()[:, :, 2, 2, 2]
+        worst = max(worst, float(np.abs(after[j] - ref).max() / np.abs(ref).max()))
+    _say(f"  focusing sampled one-step max rel diff {worst:.2e}")
+    assert worst < 2e-6
+
+
+def _dist_to_solid(mask):
+    # Chebyshev distance (capped at 3) from each node to the nearest non-fluid node
+    solid = mask != 0
+    d = np.where(solid, 0, 3)
+    for r in (1, 2):
+        grown = solid.copy()
+        for ax in range(3):
+            for sh in range(1, r + 1):
+                grown |= np.roll(solid, sh, ax) | np.roll(solid, -sh, ax)
+        d = np.where((d == 3) & grown, r, d)
+    return d
+
+
+def _boxes(n, seed, lo=20, hi=52):
+    ws = W.batch_boxes(n_boxes=n, seed=seed, edge_lo=lo, edge_hi=hi)
+    return ws
+
+
+def test_batch_matches_plain_bitwise(L, stream):
+    ws = _boxes(5, seed=11) + [_small_focusing()]
+    nsteps = [150, 33, 5, 0, 100, 40]  # runs of >= 32 levels replay graphs
+    sims = [L.Sim.from_workload(w, precision="f32", stream=stream.cuda_stream) for w in ws]
+    for s in sims:
+        s.step(1)  # pulled state; the batch also takes care of fresh handles
+    b = L.Batch(sims)
+    info = b.launch_info()
+    _say(f"batch autotuned shape {info}")
+    b.step(nsteps)
+    b.synchronize()
+    for w, s, n in zip(ws, sims, nsteps):
+        ref = L.Sim.from_workload(w, precision="f32")
+        ref.step(1 + n)
+        fl = np.ones(w.shape, bool) if w.mask is None else w.mask == 0
+        assert np.array_equal(s.populations()[..., fl], ref.populations()[..., fl]), w.name
+        assert s.diagnostics()["step"] == 1 + n
+    # second call with a different order of step counts and an explicit shape
+    b.close()
+    b2 = L.Batch(sims, tile=(4, 16))
+    assert b2.launch_info()["rows"] == 4
+    more = [3, 40, 1, 35, 0, 2]
+    b2.step(more)
+    for w, s, n, m in zip(ws, sims, nsteps, more):
+        ref = L.Sim.from_workload(w, precision="f32")
+        ref.step(1 + n + m)
+        fl = np.ones(w.shape, bool) if w.mask is None else w.mask == 0
+        assert np.array_equal(s.populations()[..., fl], ref.populations()[..., fl]), w.name
+    b2.close()
+
+
+def test_batch_fresh_handles_and_f16(L, stream):
+    ws = _boxes(3, seed=12)
+    sims = [L.Sim.from_workload(w, precision="f16", stream=stream.cuda_stream) for w in ws]
+    b = L.Batch(sims, tile=(8, 8))
+    b.step([34, 9, 20])
+    for w, s, n in zip(ws, sims, [34, 9, 20]):
+        ref = L.Sim.from_workload(w, precision="f16")
+        ref.step(n)
+        assert np.array_equal(s.populations(), ref.populations()), w.name
+
+
+def test_batch_rejects_mixed_streams(L, stream):
+    ws = _boxes(2, seed=13)
+    a = L.Sim.from_workload(ws[0], precision="f32", stream=stream.cuda_stream)
+    c = L.Sim.from_workload(ws[1], precision="f32")
+    with pytest.raises(L.LbcgError):
+        L.Batch([a, c])
+    with pytest.raises(L.LbcgError):
+        L.Batch([a, a])
+
+
+def test_tune_keeps_state(L):
+    w = W.config2(L=64, seed=3)
+    a = L.Sim.from_workload(w, precision="f32")
+    a.step(3)
+    p0 = a.populations()
+    shape = a.tune()
+    _say(f"tuned shape 64^3: {shape}")
+    assert shape["rows"] in (4, 8) and 1 <= shape["zchunks"] <= 64
+    assert np.array_equal(a.populations(), p0)
+    a.step(40)
+    b = L.Sim.from_workload(w, precision="f32")
+    b.step(43)
+    assert np.array_equal(a.populations(), b.populations())
+
+
+def test_f16_storage_droplet_within_one_percent(L):
+    # Static D3Q19 droplet 96^3, R = 20: FP16 deviation storage vs FP32 on the
+    # equivalent radius and the Laplace pressure jump after relaxation.
+    w = W.static_droplet_3d(n=96, R=20.0, tau=(1.0, 1.0), A=0.005, steps=3000)
+    out = {}
+    for prec in ("f32", "f16"):
+        s = L.Sim.from_workload(w, precision=prec)
+        s.step(w.steps)
+        d = s.diagnostics(check=True)
+        out[prec] = (d["R_eff"], d["p_in"] - d["p_out"], d["max_u"])
+        s.close()
+    (r32, dp32, u32), (r16, dp16, u16) = out["f32"], out["f16"]
+    _say(f"R_eff f32 {r32:.4f} f16 {r16:.4f}; dp f32 {dp32:.4e} f16 {dp16:.4e}; "
+         f"max|u| f32 {u32:.2e} f16 {u16:.2e}")
+    assert dp32 > 0
+    assert abs(r16 - r32) / r32 < 0.01
+    assert abs(dp16 - dp32) / dp32 < 0.01
