@@ -14,7 +14,13 @@ colours).  Prints one JSON line:
              counters scaled by a copy-kernel calibration (null when the
              kernel source changed since the counters were taken);
   cpu_baseline  the FP64 CPU oracle timed on this host on a bounded sample;
-  copy_probe achieved bandwidth of a plain device-to-device copy (context).
+  copy_probe achieved bandwidth of a plain device-to-device copy (context);
+  forms      the other forms of the step, each measured on its own workload:
+             f16 (the same lattice with FP16 deviation storage), batched (64
+             uneven periodic boxes in one launch per time level vs the same
+             boxes stepped one after another) and served (a Poisson stream of
+             step-emulsifier requests through the continuous-batching server
+             vs one request at a time; p50 / p99 time to result).
 """
 from __future__ import annotations
 
@@ -30,6 +36,11 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fused_d3q19_f32_256_traffic.txt")
+
+
+def log(msg):
+    """Progress on stderr (stdout carries only the JSON line)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def read_traffic():
@@ -67,7 +78,7 @@ def copy_probe(torch, nbytes=2 << 30, reps=10):
     return {"gbps": round(2 * nbytes / ms / 1e6, 1), "bytes_per_copy": 2 * nbytes}
 
 
-def cpu_baseline(w, steps=2, threads=16):
+def cpu_baseline(w, steps=16, threads=16):
     import oracle
     from tests.helpers import oracle_for
     oracle.build(force=False)
@@ -81,6 +92,106 @@ def cpu_baseline(w, steps=2, threads=16):
                       f"FP64, OpenMP over nodes"}
 
 
+def time_sim(torch, sim, stream, steps, warmup):
+    sim.step(warmup)
+    sim.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    sim.step(steps)
+    e1.record(stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1)
+
+
+def f16_form(torch, lbcg, W, size, steps=200, warmup=10):
+    w = W.config2(L=size, seed=2)
+    stream = torch.cuda.Stream()
+    sim = lbcg.Sim.from_workload(w, precision="f16", stream=stream.cuda_stream)
+    sim.step(1)
+    shape = sim.tune()
+    ms = time_sim(torch, sim, stream, steps, warmup)
+    sim.close()
+    mlups = w.fluid_nodes * steps / (ms / 1e3) / 1e6
+    gbs = 152 * w.fluid_nodes * steps / (ms / 1e3) / 1e9
+    return {"workload": w.name, "storage": "f16", "mlups": round(mlups, 1),
+            "ms_per_step": round(ms / steps, 4), "achieved_gbs": round(gbs, 1),
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "bytes_per_node": 152, "rows": shape["rows"],
+            "zchunks": shape["zchunks"], "steps": steps}
+
+
+def batched_form(torch, lbcg, W, steps=200, warmup=10):
+    ws = W.batch_boxes(n_boxes=64, seed=4)
+    nodes = sum(w.fluid_nodes for w in ws)
+    stream = torch.cuda.Stream()
+    sims = [lbcg.Sim.from_workload(w, precision="f32", stream=stream.cuda_stream) for w in ws]
+    for s in sims:
+        s.step(1)
+    b = lbcg.Batch(sims)
+    info = b.launch_info()
+    b.step(warmup)
+    stream.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    b.step(steps)
+    e1.record(stream)
+    e1.synchronize()
+    ms_b = e0.elapsed_time(e1)
+    b.close()
+    # the same boxes stepped one after another, each in its own tuned shape
+    for s in sims:
+        s.tune()
+        s.step(warmup)
+    stream.synchronize()
+    e0.record(stream)
+    for s in sims:
+        s.step(steps)
+    e1.record(stream)
+    e1.synchronize()
+    ms_p = e0.elapsed_time(e1)
+    for s in sims:
+        s.close()
+    mb = nodes * steps / (ms_b / 1e3) / 1e6
+    mp = nodes * steps / (ms_p / 1e3) / 1e6
+    return {"workload": "64 periodic D3Q19 boxes, edges U{32..96}, seed 4", "nodes": nodes,
+            "steps": steps, "batched_mlups": round(mb, 1), "plain_mlups": round(mp, 1),
+            "speedup": round(mb / mp, 3), "frac": round(mb * 304 / 1e3 / HBM_PEAK_GBS, 4),
+            "rows": info["rows"], "zplanes": info["zplanes"], "blocks": info["blocks"]}
+
+
+def served_form(torch, lbcg, W, n=32, steps_scale=0.1, load=0.8):
+    from paper_1711_02003_amd import serve
+    lo, hi = int(5000 * steps_scale), int(20000 * steps_scale)
+
+    def reqs(rate):
+        return serve.requests_from_stream(
+            W.served_requests(n=n, seed=5, rate=rate, steps_lo=lo, steps_hi=hi), W.step_emulsifier)
+
+    probe = reqs(1.0)
+    fps = []
+    for r in probe:
+        w = r.make()
+        p, _k = lbcg.make_params(w.lattice, w.dims, w.tau_R, w.tau_B, w.A, w.A, w.beta, "f32",
+                                 mask=w.mask, inlets=w.inlets, outlets=w.outlets)
+        fps.append(lbcg.footprint(p))
+    cap = int(sum(sorted(fps)[-8:]) * 1.05)  # room for about eight requests at once
+    # plain: one request at a time (its own tuned-once shape); capacity
+    # measured with every request queued at t = 0
+    one = serve.LbcgBackend(cap, precision="f32", fields=False, tune_min=1)
+    sat = serve.requests_from_stream(
+        [dict(r, arrival=0.0) for r in W.served_requests(n=n, seed=5, rate=1.0, steps_lo=lo,
+                                                          steps_hi=hi)], W.step_emulsifier)
+    st0 = serve.Server(one, cap, slice_steps=256, max_running=1, keep_results=False).run(sat)
+    rate = load * st0.completed / st0.makespan_s
+    plain = serve.Server(one, cap, slice_steps=256, max_running=1, keep_results=False).run(reqs(rate))
+    del one
+    be = serve.LbcgBackend(cap, precision="f32", fields=False)
+    served = serve.Server(be, cap, slice_steps=256, keep_results=False).run(reqs(rate))
+    return {"workload": f"{n} step-emulsifier requests (Poisson), steps U{{{lo}..{hi}}}, seed 5",
+            "arrival_rate_per_s": round(rate, 3), "offered_load": load,
+            "arena_bytes": cap, "served": served.as_dict(), "plain": plain.as_dict(),
+            "tile": list(be.tile) if be.tile else None}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -92,6 +203,9 @@ def main():
     ap.add_argument("--zchunks", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-copy-probe", action="store_true")
+    ap.add_argument("--no-forms", action="store_true", help="skip the f16 / batched / served forms")
+    ap.add_argument("--served-requests", type=int, default=32)
+    ap.add_argument("--served-steps-scale", type=float, default=0.1)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
@@ -108,6 +222,9 @@ def main():
     with torch.cuda.stream(stream):
         sim = lbcg.Sim.from_workload(w, precision=args.precision, kernel=lbcg.KERNEL_FUSED,
                                      tile=(args.rows, args.zchunks, 0))
+    if not (args.rows or args.zchunks):
+        sim.step(1)
+        sim.tune()  # launch shape chosen by timing candidates on this lattice
     info = sim.launch_info()
     sim.step(args.warmup)
     sim.synchronize()
@@ -157,9 +274,20 @@ def main():
                      "traffic": traffic, "bytes_per_node": bytes_node},
         "wall_s": round(wall, 3),
     }
+    log(f"headline {out['value']} MLUPS, {out['ms_per_step']} ms/step, shape {info}")
     if not args.no_copy_probe:
         out["copy_probe"] = copy_probe(torch)
+    if not args.no_forms:
+        forms = {"f16": f16_form(torch, lbcg, W, args.size)}
+        log(f"f16 {forms['f16']}")
+        forms["batched"] = batched_form(torch, lbcg, W)
+        log(f"batched {forms['batched']}")
+        forms["served"] = served_form(torch, lbcg, W, n=args.served_requests,
+                                      steps_scale=args.served_steps_scale)
+        log(f"served {forms['served']}")
+        out["forms"] = forms
     if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)
 

@@ -12,9 +12,10 @@
 // buffer.  After one barrier it collides plane z with the gradient taken from
 // the LDS planes z-1, z, z+1 and stores the 19 new pairs coalesced, with
 // non-temporal stores (the new state is not read again in this step).  The
-// populations of plane z+2 (interior and ring) are loaded one iteration
-// ahead, so their latency overlaps the barrier, the collision and the stores;
-// the barrier orders only LDS traffic and leaves those loads in flight.
+// populations of a plane (interior and ring) are loaded one iteration ahead
+// of their use, so their latency overlaps the moments, the barrier, the
+// collision and the stores; the barrier orders only LDS traffic and leaves
+// those loads in flight.
 //
 // Every stored population is read from HBM once and written once: the
 // algorithmic traffic is 2 x 38 x sizeof(storage) bytes per node.
@@ -37,19 +38,6 @@ constexpr int kTX = 64;
 constexpr int kXCD = 8;
 constexpr float kSentinel = 1e30f;  // LDS psi of a wall or outlet node
 
-#ifndef LBCG_NT_STORE
-#define LBCG_NT_STORE 1
-#endif
-
-template <typename V>
-__device__ __forceinline__ void put(V *p, V v) {
-#if LBCG_NT_STORE
-    __builtin_nontemporal_store(v, p);
-#else
-    *p = v;
-#endif
-}
-
 // Barrier that orders LDS accesses only; global loads stay in flight.
 __device__ __forceinline__ void lds_barrier() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
@@ -57,29 +45,97 @@ __device__ __forceinline__ void lds_barrier() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-// Pull the 19 population pairs of node (x, y, z) of a lattice without
-// geometry.  Addresses are 32-bit byte offsets from the uniform state base
-// (the host checks that a state buffer is below 4 GiB), which keeps one VGPR
-// per load instead of two.
+// State buffers are read and written with buffer instructions: the byte
+// offset of pair (i, x, y, z) splits into a per-thread part (x + nx y), fixed
+// over the sweep, and a part uniform over the block (z plane, direction i)
+// that travels in a scalar register, so a population costs no address
+// arithmetic.  The host keeps a state buffer below 4 GiB; the resource's
+// size also bounds every access (an offset past it reads 0 and drops a
+// write).
+constexpr int kRsrcWord3 = 0x00020000;  // raw 32-bit dword buffer (gfx9 family)
+constexpr int kNonTemporal = 2;         // cache-policy bit of a streaming store
+
+template <typename S>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t state_rsrc(const S *p, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<S *>(p), (short)0, int(bytes), kRsrcWord3);
+}
+
+
+template <typename P2>
+__device__ __forceinline__ P2 load_pair(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    if constexpr (sizeof(P2) == 8)
+        return __builtin_bit_cast(P2, __builtin_amdgcn_raw_buffer_load_b64(r, int(voff), int(soff), 0));
+    else
+        return __builtin_bit_cast(P2, __builtin_amdgcn_raw_buffer_load_b32(r, int(voff), int(soff), 0));
+}
+
+template <typename P2>
+__device__ __forceinline__ void store_pair(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, P2 v) {
+    constexpr int pol = kNonTemporal;  // the new state is not read again in this step
+    typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+    if constexpr (sizeof(P2) == 8)
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, int(voff), int(soff), pol);
+    else
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, int(voff), int(soff), pol);
+}
+
+// Wait until every vector memory operation of the wave has completed
+// (s_waitcnt vmcnt(0); the export and LDS/scalar counters are left alone).
+__device__ __forceinline__ void wait_memory() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
+// A value the caller knows to be the same in every lane (a z plane of the
+// block's sweep), marked so for the compiler: buffer offsets derived from it
+// then stay in scalar registers.
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Byte offsets (x' + nx y') * sizeof(pair) of the 9 source columns
+// x' = x - c_x, y' = y - c_y of node (x, y), periodic; entry (1 - c_x) +
+// 3 (1 - c_y).
+template <typename S>
+__device__ __forceinline__ void column_offsets(const FusedArgs<S> &a, int x, int y, uint32_t t[9]) {
+    constexpr uint32_t E = sizeof(typename PairOf<S>::type);
+    const uint32_t xs[3] = {uint32_t(x == 0 ? a.nx - 1 : x - 1), uint32_t(x), uint32_t(x == a.nx - 1 ? 0 : x + 1)};
+    const uint32_t ys[3] = {uint32_t(y == 0 ? a.ny - 1 : y - 1), uint32_t(y), uint32_t(y == a.ny - 1 ? 0 : y + 1)};
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) t[c + 3 * b] = (xs[c] + uint32_t(a.nx) * ys[b]) * E;
+}
+
+// Populations requested but not yet used.  Without geometry they stay as the
+// loaded pairs and are decoded only where they are consumed, so nothing
+// waits on a load before then; the boundary rules of the geometry path need
+// the values at once and keep them decoded.
+template <typename S, typename T, bool MASKED>
+struct Pending {
+    typename PairOf<S>::type v[D3Q19::Q];
+    __device__ __forceinline__ void take(Pops<D3Q19, T> &p) const {
+        p.red = 0;
+#pragma unroll
+        for (int i = 0; i < D3Q19::Q; ++i) decode_pair<D3Q19, S, T>(v[i], i, p);
+    }
+};
 template <typename S, typename T>
-__device__ __forceinline__ void pull_periodic(const FusedArgs<S> &a, int x, int y, int z, Pops<D3Q19, T> &p) {
+struct Pending<S, T, true> {
+    Pops<D3Q19, T> p;
+    __device__ __forceinline__ void take(Pops<D3Q19, T> &q) const { q = p; }
+};
+
+// Request the 19 population pairs of a node without geometry at plane z,
+// from its column offsets t.
+template <typename S, typename T>
+__device__ __forceinline__ void pull_periodic(const FusedArgs<S> &a, __amdgpu_buffer_rsrc_t r, const uint32_t t[9],
+                                              int z, Pending<S, T, false> &pend) {
     using L = D3Q19;
     typedef typename PairOf<S>::type P2;
-    const int xm = x == 0 ? a.nx - 1 : x - 1, xp = x == a.nx - 1 ? 0 : x + 1;
-    const int ym = y == 0 ? a.ny - 1 : y - 1, yp = y == a.ny - 1 ? 0 : y + 1;
-    const int zm = z == 0 ? a.nz - 1 : z - 1, zp = z == a.nz - 1 ? 0 : z + 1;
-    const char *base = reinterpret_cast<const char *>(a.in);
-    const uint32_t cstride = uint32_t(a.pitch) * uint32_t(sizeof(P2));
+    constexpr uint32_t E = sizeof(P2);
+    const uint32_t plane = uniform(int(uint32_t(a.nx) * uint32_t(a.ny) * E));
+    const uint32_t cstride = uniform(int(uint32_t(a.pitch) * E));
+    const uint32_t zo[3] = {uint32_t(uniform(z == 0 ? a.nz - 1 : z - 1)) * plane, uint32_t(uniform(z)) * plane,
+                            uint32_t(uniform(z == a.nz - 1 ? 0 : z + 1)) * plane};
 #pragma unroll
-    for (int i = 0; i < L::Q; ++i) {
-        // source = x - c_i
-        const int xs = L::cx[i] > 0 ? xm : (L::cx[i] < 0 ? xp : x);
-        const int ys = L::cy[i] > 0 ? ym : (L::cy[i] < 0 ? yp : y);
-        const int zs = L::cz[i] > 0 ? zm : (L::cz[i] < 0 ? zp : z);
-        const uint32_t nd = uint32_t(xs) + uint32_t(a.nx) * (uint32_t(ys) + uint32_t(a.ny) * uint32_t(zs));
-        const uint32_t off = uint32_t(i) * cstride + nd * uint32_t(sizeof(P2));
-        decode_pair<L, S, T>(*reinterpret_cast<const P2 *>(base + off), i, p);
-    }
+    for (int i = 0; i < L::Q; ++i)
+        pend.v[i] = load_pair<P2>(r, t[(1 - L::cx[i]) + 3 * (1 - L::cy[i])], uint32_t(i) * cstride + zo[1 - L::cz[i]]);
 }
 
 __device__ __forceinline__ int wrapz(int z, int nz) { return z < 0 ? z + nz : (z >= nz ? z - nz : z); }
@@ -136,6 +192,18 @@ __device__ __forceinline__ void sweep(const FusedArgs<S> &a, const Model<T> &mo,
     }
     const int gx = wrap_m1(x0 + rx, a.nx), gy = wrap_m1(y0 + ry, a.ny);
 
+    typedef typename PairOf<S>::type P2;
+    constexpr uint32_t E = sizeof(P2);
+    const uint32_t cstride = uniform(int(uint32_t(a.pitch) * E));
+    const uint32_t plane = uniform(int(uint32_t(a.nx) * uint32_t(a.ny) * E));
+    const __amdgpu_buffer_rsrc_t rin = state_rsrc(a.in, uint32_t(L::Q) * cstride);
+    const __amdgpu_buffer_rsrc_t rout = state_rsrc(a.out, uint32_t(L::Q) * cstride);
+    // column offsets of the interior node and of the ring node (unused
+    // entries of threads outside the tile stay in range)
+    uint32_t ixy[9], rxy[9];
+    column_offsets(a, intile ? x : 0, intile ? y : 0, ixy);
+    column_offsets(a, gx, gy, rxy);
+
     auto node = [&](int xx, int yy, int zz) {
         return int64_t(xx) + int64_t(a.nx) * (int64_t(yy) + int64_t(a.ny) * zz);
     };
@@ -152,42 +220,43 @@ __device__ __forceinline__ void sweep(const FusedArgs<S> &a, const Model<T> &mo,
         }
         return kSentinel;
     };
-    auto pull = [&](int xx, int yy, int zz, Pops<L, T> &p) {
-        if (MASKED) {
+    auto pull = [&](int xx, int yy, int zz, const uint32_t t[9], Pending<S, T, MASKED> &pend) {
+        if constexpr (MASKED) {
             const Geo g = geo_of(a);
-            pull_node<L, S, T>(g, mo, a.in, xx, yy, zz, node(xx, yy, zz), true, p);
+            pull_node<L, S, T>(g, mo, a.in, xx, yy, zz, node(xx, yy, zz), true, pend.p);
         } else {
-            pull_periodic<S, T>(a, xx, yy, zz, p);
+            pull_periodic<S, T>(a, rin, t, zz, pend);
         }
     };
 
-    // psi planes live in a 5-slot LDS ring: iteration z writes the interior of
-    // plane z+1 and the ring of plane z+2 while the collision reads planes
-    // z-1..z+1, so a slot is rewritten only after every wave has passed the
-    // barrier that follows its last read.
+    // psi planes live in a 5-slot LDS ring: iteration z writes plane z+1
+    // (interior and ring) and then collides plane z from planes z-1..z+1; the
+    // barrier keeps the waves within one iteration of each other, so a slot
+    // is rewritten only after every wave has passed its last read.
     auto slot_of = [&](int zp) { return lds + ((zp - z0 + 1) % 5) * PL; };
 
-    // Ring nodes: psi of the one-node ring around the tile.  Their loads are
-    // issued one plane ahead, together with the interior prefetch, so the
-    // neighbour tiles' rows are requested while those tiles load them too,
-    // and before the interior prefetch so that waiting for them (loads retire
-    // in order) leaves the prefetch in flight.
-    Pops<L, T> rp;
-    rp.red = 0;
+    // Ring nodes: psi of the one-node ring around the tile.  Ring and
+    // interior populations of a plane are requested one iteration before
+    // they are used, ring first: the neighbour tiles' rows are then requested
+    // while those tiles load them too, and waiting for the ring (loads retire
+    // in order) leaves the interior loads in flight.
+    Pending<S, T, MASKED> rp;
     uint8_t rcode = kFluid;
     auto ring_issue = [&](int zp) {
         if (has_ring) {
             const int zz = wrapz(zp, a.nz);
             rcode = code(gx, gy, zz);
-            if (rcode == kFluid) pull(gx, gy, zz, rp);
+            if (rcode == kFluid) pull(gx, gy, zz, rxy, rp);
         }
     };
     auto ring_finish = [&](int zp) {
         if (has_ring) {
             float v;
             if (rcode == kFluid) {
+                Pops<L, T> q;
+                rp.take(q);
                 T dr, rR, rB;
-                densities<L, T>(rp, dr, rR, rB);
+                densities<L, T>(q, dr, rR, rB);
                 v = float(psi_of<T>(dr, rR, rB));
             } else {
                 v = solid_psi(rcode);
@@ -200,24 +269,23 @@ __device__ __forceinline__ void sweep(const FusedArgs<S> &a, const Model<T> &mo,
     // of plane z+1 are in flight.
     T cd = 0, cR = 0, cB = 0, cj[3] = {0, 0, 0}, cG[6] = {0, 0, 0, 0, 0, 0};
     bool cfl = false;
-    Pops<L, T> pp;
-    pp.red = 0;
-#pragma unroll
-    for (int i = 0; i < L::Q; ++i) pp.df[i] = pp.mm[i] = T(0);
+    Pending<S, T, MASKED> pp;
     uint8_t pcode = kFluid;
     auto interior_issue = [&](int zp) {
         if (intile) {
             const int zz = wrapz(zp, a.nz);
             pcode = code(x, y, zz);
-            if (pcode == kFluid) pull(x, y, zz, pp);
+            if (pcode == kFluid) pull(x, y, zz, ixy, pp);
         }
     };
     // moments of the pulled interior plane into (d, r36R, r36B, j, G); returns psi
     auto interior_moments = [&](T &d, T &r36R, T &r36B, T j[3], T G[6], bool &fl) -> float {
         fl = pcode == kFluid;
         if (!fl) return solid_psi(pcode);
+        Pops<L, T> q;
+        pp.take(q);
         Mom<T> m;
-        moments<L, T>(pp, m);
+        moments<L, T>(q, m);
         d = m.drho;
         r36R = m.r36R;
         r36B = m.r36B;
@@ -235,8 +303,10 @@ __device__ __forceinline__ void sweep(const FusedArgs<S> &a, const Model<T> &mo,
     if (intile) {
         float v;
         if (pcode == kFluid) {
+            Pops<L, T> q;
+            pp.take(q);
             T dr, rR, rB;
-            densities<L, T>(pp, dr, rR, rB);
+            densities<L, T>(q, dr, rR, rB);
             v = float(psi_of<T>(dr, rR, rB));
         } else {
             v = solid_psi(pcode);
@@ -250,18 +320,47 @@ __device__ __forceinline__ void sweep(const FusedArgs<S> &a, const Model<T> &mo,
     ring_finish(z0);
     ring_issue(z0 + 1);
     interior_issue(z0 + 1);
-    ring_finish(z0 + 1);
+
+    // Output pairs of the last collided plane.  Loads and stores share one
+    // completion counter that the compiler cannot treat as ordered while both
+    // are pending, so every use of a requested value waits for all
+    // outstanding memory operations (the explicit wait at the top of the
+    // sweep makes that wait one, on every path).  With 16-bit storage the
+    // sweep is bound by arithmetic, and the stores are held one iteration
+    // and issued right after the next plane is requested, so that wait finds
+    // them complete; with 32-bit storage the sweep is bound by memory
+    // traffic, and storing at once (measured faster) keeps more writes in
+    // flight.
+    constexpr bool kDelayStores = !MASKED && sizeof(P2) == 4;
+    P2 ov[L::Q];
+    bool ovalid = false;
+    uint32_t ozoff = 0;
+    auto flush = [&]() {
+        if (ovalid) {
+            const uint32_t zoff = uint32_t(uniform(int(ozoff)));
+#pragma unroll
+            for (int i = 0; i < L::Q; ++i) store_pair<P2>(rout, ixy[4], uint32_t(i) * cstride + zoff, ov[i]);
+        }
+    };
 
     for (int z = z0; z < z1; ++z) {
         const bool more = z + 2 <= z1;  // uniform over the block
         T nd = 0, nR = 0, nB = 0, nj[3] = {0, 0, 0}, nG[6] = {0, 0, 0, 0, 0, 0};
         bool nfl = false;
-        if (more) ring_issue(z + 2);
+        // plane z+1: its ring and interior populations were requested one
+        // iteration ago.  Wait for everything outstanding here, on every
+        // path, so that no later use waits for the loads issued below.
+        wait_memory();
+        ring_finish(z + 1);
         if (intile) slot_of(z + 1)[(row + 1) * W + lane + 1] = interior_moments(nd, nR, nB, nj, nG, nfl);
-        if (more) interior_issue(z + 2);
-        if (more) ring_finish(z + 2);
+        if (more) {
+            ring_issue(z + 2);
+            interior_issue(z + 2);
+        }
+        if (kDelayStores) flush();
         lds_barrier();
-        if (intile && (!MASKED || cfl)) {
+        ovalid = intile && (!MASKED || cfl);
+        if (ovalid) {
             const float *sm = slot_of(z - 1), *s0 = slot_of(z), *sp = slot_of(z + 1);
             const int c = (row + 1) * W + lane + 1;
             const float pc = s0[c];
@@ -279,16 +378,11 @@ __device__ __forceinline__ void sweep(const FusedArgs<S> &a, const Model<T> &mo,
             const T F[3] = {fx, fy, fz};
             PostOut<L, T> o;
             collide<L, T>(mo, cd, cR, cB, cj, cG, F, nullptr, o);
-            typedef typename PairOf<S>::type P2;
-            const uint32_t n = uint32_t(x) + uint32_t(a.nx) * (uint32_t(y) + uint32_t(a.ny) * uint32_t(z));
-            char *ob = reinterpret_cast<char *>(a.out);
-            const uint32_t cstride = uint32_t(a.pitch) * uint32_t(sizeof(P2));
 #pragma unroll
-            for (int i = 0; i < L::Q; ++i) {
-                const uint32_t off = uint32_t(i) * cstride + n * uint32_t(sizeof(P2));
-                put(reinterpret_cast<P2 *>(ob + off), encode_pair<L, S, T>(o.df[i], o.mm[i], (o.red >> i) & 1u, i));
-            }
+            for (int i = 0; i < L::Q; ++i) ov[i] = encode_pair<L, S, T>(o.df[i], o.mm[i], (o.red >> i) & 1u, i);
         }
+        ozoff = uint32_t(uniform(z)) * plane;
+        if (!kDelayStores) flush();
         cfl = nfl;
         cd = nd;
         cR = nR;
@@ -298,6 +392,7 @@ __device__ __forceinline__ void sweep(const FusedArgs<S> &a, const Model<T> &mo,
 #pragma unroll
         for (int q = 0; q < 6; ++q) cG[q] = nG[q];
     }
+    if (kDelayStores) flush();
 }
 
 // Single lattice, XCD-banded work mapping (see the file comment).

@@ -192,7 +192,7 @@ class Sim:
     def __init__(self, lattice="D3Q19", dims=(64, 64, 64), tau_R=1.0, tau_B=1.0, A=0.01,
                  beta=0.7, precision="f32", collision=REGULARIZED, kernel=KERNEL_AUTO, mask=None,
                  inlets=(), outlets=(), alpha_R=0.0, alpha_B=0.0, eps_F=-1.0, A_B=None,
-                 tile=(0, 0, 0), use_torch=True, stream=None):
+                 tile=(0, 0, 0), use_torch=True, stream=None, dev_buf=None):
         self._lib = load_library()
         self.lattice = LATTICES.get(lattice, lattice)
         self.Q = 9 if self.lattice == D2Q9 else 19
@@ -205,7 +205,12 @@ class Sim:
         self.footprint = footprint(self.params)
         self._buf = None
         dev_ptr, strm = None, stream
-        if use_torch:
+        if dev_buf is not None:
+            # caller-owned device memory: (address, bytes), at least the footprint
+            dev_ptr, nbytes = int(dev_buf[0]), int(dev_buf[1])
+            if nbytes < self.footprint:
+                raise ValueError(f"device buffer of {nbytes} bytes < footprint {self.footprint}")
+        elif use_torch:
             self._buf, tstream = _torch_device_buffer(self.footprint)
             if self._buf is not None:
                 dev_ptr = self._buf.data_ptr()

@@ -1,15 +1,22 @@
 """Summaries of rocprofv3 output for the profiles/ folder.
 
-    python -m paper_1711_02003_amd.profiling trace <kernel_stats.csv> <out.md> "<command>"
+    python -m paper_1711_02003_amd.profiling trace <kernel_trace.csv> <out.md> <kernel substring>
+        <timed dispatches> "<command>"
     python -m paper_1711_02003_amd.profiling traffic <fetch counter_collection.csv>
-        <write counter_collection.csv> <kernel substring> <nodes> <out.txt> "<commands>"
+        <write counter_collection.csv> <kernel substring> <timed dispatches> <nodes> <out.txt>
+        "<commands>"
+
+The benchmark first times candidate launch shapes of the kernel (same kernel
+name), then runs the timed region; both summaries therefore report the last
+<timed dispatches> dispatches of the named kernel (the timed region) besides
+the per-kernel totals.
 
 The traffic summary scales FETCH_SIZE and WRITE_SIZE (KiB per dispatch) by
 what the same counters read for a plain device copy of known size (the
 benchmark's 2 GiB copy probe): on this hardware FETCH_SIZE counts half of
-the bytes such a copy reads.  The result is HBM bytes per launch of the named
-kernel, tagged with a hash of the kernel sources so a stale figure is never
-reported for changed code.
+the bytes such a copy reads.  The result is bytes per launch of the named
+kernel that leave the L2 towards memory, tagged with a hash of the kernel
+sources so that a stale figure is never reported for changed code.
 """
 from __future__ import annotations
 
@@ -22,6 +29,7 @@ import sys
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 KERNEL_SOURCES = ["paper_1711_02003_amd/csrc/lbcg_fused.hip", "paper_1711_02003_amd/csrc/lbcg_device.h"]
 COPY_BYTES = 2 << 30  # the copy probe moves 2 GiB in and 2 GiB out per dispatch
+BYTES_PER_NODE = 2 * 38 * 4  # FP32: every population pair read once and written once
 
 
 def kernel_hash() -> str:
@@ -32,56 +40,61 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def trace_summary(stats_csv: str, out_md: str, command: str) -> str:
-    rows = list(csv.DictReader(open(stats_csv)))
-    lines = [f"# rocprofv3 kernel trace: {os.path.basename(out_md)[:-3]}", "",
-             f"Command: `{command}`", "",
-             "| kernel | calls | avg us | min us | max us | share % |",
-             "|---|---|---|---|---|---|"]
+def _short(name: str, n: int = 90) -> str:
+    return name if len(name) <= n else name[:n - 3] + "..."
+
+
+def trace_summary(trace_csv, out_md, kernel_sub, timed, command):
+    rows = list(csv.DictReader(open(trace_csv)))
+    per = collections.defaultdict(list)
     for r in rows:
-        name = r["Name"]
-        if len(name) > 90:
-            name = name[:87] + "..."
-        lines.append(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
-                     f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | "
-                     f"{float(r['Percentage']):.1f} |")
+        per[r["Kernel_Name"]].append(r)
+    total = sum(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in rows) or 1
+    lines = [f"# rocprofv3 kernel trace: {os.path.basename(out_md).rsplit('.', 1)[0]}", "",
+             f"Command: `{command}`", "", "All dispatches per kernel:", "",
+             "| kernel | calls | avg us | min us | max us | share % |", "|---|---|---|---|---|---|"]
+    for name, rs in sorted(per.items(), key=lambda kv: -sum(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+                                                            for r in kv[1])):
+        d = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in rs]
+        lines.append(f"| `{_short(name)}` | {len(d)} | {sum(d) / len(d):.1f} | {min(d):.1f} | {max(d):.1f} | "
+                     f"{100 * sum(d) * 1e3 / total:.1f} |")
+    ks = [r for r in rows if kernel_sub in r["Kernel_Name"]]
+    ks.sort(key=lambda r: int(r["Start_Timestamp"]))
+    tail = ks[-timed:]
+    d = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in tail]
+    span = (int(tail[-1]["End_Timestamp"]) - int(tail[0]["Start_Timestamp"])) / 1e3
+    grid = {(r["Grid_Size_X"], r["Workgroup_Size_X"]) for r in tail}
+    lines += ["", f"Timed region: the last {len(tail)} dispatches of `{kernel_sub}` "
+                  f"(grid, workgroup = {sorted(grid)}):", "",
+              f"- average duration: {sum(d) / len(d):.1f} us (min {min(d):.1f}, max {max(d):.1f})",
+              f"- first start to last end: {span:.1f} us = {span / len(d):.1f} us per dispatch"]
     txt = "\n".join(lines) + "\n"
     with open(out_md, "w") as f:
         f.write(txt)
     return txt
 
 
-def _per_kernel(counter_csv: str, counter: str):
-    agg = collections.defaultdict(list)
-    for r in csv.DictReader(open(counter_csv)):
-        if r["Counter_Name"] == counter:
-            agg[r["Kernel_Name"]].append(float(r["Counter_Value"]))
-    return agg
+def _kernel_values(counter_csv, counter, kernel_sub, timed):
+    rows = [r for r in csv.DictReader(open(counter_csv)) if r["Counter_Name"] == counter]
+    copy = [float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"]]
+    ks = [r for r in rows if kernel_sub in r["Kernel_Name"]]
+    ks.sort(key=lambda r: int(r["Dispatch_Id"]))
+    return [float(r["Counter_Value"]) for r in ks[-timed:]], (max(copy) if copy else None)
 
 
-def traffic_summary(fetch_csv, write_csv, kernel_sub, nodes, out_txt, commands):
-    fetch = _per_kernel(fetch_csv, "FETCH_SIZE")
-    write = _per_kernel(write_csv, "WRITE_SIZE")
-
-    def copy_kib(agg):
-        vals = [v for k, vs in agg.items() if "copyBuffer" in k or "copy" in k.lower() for v in vs]
-        return max(vals) if vals else None
-
-    fc, wc = copy_kib(fetch), copy_kib(write)
-    f_fac = COPY_BYTES / (fc * 1024) if fc else None
-    w_fac = COPY_BYTES / (wc * 1024) if wc else None
-    kf = [v for k, vs in fetch.items() if kernel_sub in k for v in vs]
-    kw = [v for k, vs in write.items() if kernel_sub in k for v in vs]
-    fkib = sum(kf) / len(kf)
-    wkib = sum(kw) / len(kw)
-    fb = fkib * 1024 * f_fac
-    wb = wkib * 1024 * w_fac
-    alg = 2 * 38 * 4 * nodes / 2  # read (or write) bytes of the algorithm
+def traffic_summary(fetch_csv, write_csv, kernel_sub, timed, nodes, out_txt, commands):
+    kf, fc = _kernel_values(fetch_csv, "FETCH_SIZE", kernel_sub, timed)
+    kw, wc = _kernel_values(write_csv, "WRITE_SIZE", kernel_sub, timed)
+    f_fac = COPY_BYTES / (fc * 1024)
+    w_fac = COPY_BYTES / (wc * 1024)
+    fkib, wkib = sum(kf) / len(kf), sum(kw) / len(kw)
+    fb, wb = fkib * 1024 * f_fac, wkib * 1024 * w_fac
+    alg = BYTES_PER_NODE * nodes / 2  # read (or write) bytes of the algorithm
     lines = [
         f"kernel: {kernel_sub}",
         f"kernel_hash: {kernel_hash()}",
         f"commands: {commands}",
-        f"dispatches: {len(kf)} fetch, {len(kw)} write",
+        f"timed_dispatches: {len(kf)} fetch, {len(kw)} write",
         f"fetch_kib_per_dispatch: {fkib:.1f}",
         f"write_kib_per_dispatch: {wkib:.1f}",
         f"copy_probe_fetch_kib: {fc}",
@@ -104,9 +117,9 @@ def traffic_summary(fetch_csv, write_csv, kernel_sub, nodes, out_txt, commands):
 if __name__ == "__main__":
     mode = sys.argv[1]
     if mode == "trace":
-        print(trace_summary(sys.argv[2], sys.argv[3], sys.argv[4]))
+        print(trace_summary(sys.argv[2], sys.argv[3], sys.argv[4], int(sys.argv[5]), sys.argv[6]))
     elif mode == "traffic":
-        print(traffic_summary(sys.argv[2], sys.argv[3], sys.argv[4], int(sys.argv[5]), sys.argv[6],
-                              sys.argv[7]))
+        print(traffic_summary(sys.argv[2], sys.argv[3], sys.argv[4], int(sys.argv[5]), int(sys.argv[6]),
+                              sys.argv[7], sys.argv[8]))
     else:
         raise SystemExit(__doc__)
