@@ -16,7 +16,8 @@ colours).  Prints one JSON line:
   cpu_baseline  the FP64 CPU oracle timed on this host on a bounded sample;
   copy_probe achieved bandwidth of a plain device-to-device copy (context);
   forms      the other forms of the step, each measured on its own workload:
-             f16 (the same lattice with FP16 deviation storage), batched (64
+             f16 (the same lattice with FP16 deviation storage), focusing (the
+             512 x 128 x 64 flow-focusing junction, FP32 and FP16), batched (64
              uneven periodic boxes in one launch per time level vs the same
              boxes stepped one after another) and served (a Poisson stream of
              step-emulsifier requests through the continuous-batching server
@@ -117,6 +118,27 @@ def f16_form(torch, lbcg, W, size, steps=200, warmup=10):
             "ms_per_step": round(ms / steps, 4), "achieved_gbs": round(gbs, 1),
             "frac": round(gbs / HBM_PEAK_GBS, 4), "bytes_per_node": 152, "rows": shape["rows"],
             "zchunks": shape["zchunks"], "steps": steps}
+
+
+def focusing_form(torch, lbcg, W, steps=200, warmup=10):
+    """Flow-focusing cross junction 512 x 128 x 64 (walls, inlets, outlet):
+    FP32 and FP16 storage, fluid-node MLUPS and all-node MLUPS."""
+    w = W.flow_focusing(lam=3.0)
+    out = {"workload": w.name, "fluid_nodes": w.fluid_nodes, "nodes": w.nodes, "steps": steps}
+    for prec in ("f32", "f16"):
+        stream = torch.cuda.Stream()
+        sim = lbcg.Sim.from_workload(w, precision=prec, stream=stream.cuda_stream)
+        sim.step(1)
+        shape = sim.tune()
+        ms = time_sim(torch, sim, stream, steps, warmup)
+        sim.close()
+        elem = 4 if prec == "f32" else 2
+        out[prec] = {"mlups": round(w.fluid_nodes * steps / (ms / 1e3) / 1e6, 1),
+                     "lattice_mlups": round(w.nodes * steps / (ms / 1e3) / 1e6, 1),
+                     "ms_per_step": round(ms / steps, 4),
+                     "frac": round((2 * 38 * elem + 1) * w.fluid_nodes * steps / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "rows": shape["rows"], "zchunks": shape["zchunks"]}
+    return out
 
 
 def batched_form(torch, lbcg, W, steps=200, warmup=10):
@@ -280,6 +302,8 @@ def main():
     if not args.no_forms:
         forms = {"f16": f16_form(torch, lbcg, W, args.size)}
         log(f"f16 {forms['f16']}")
+        forms["focusing"] = focusing_form(torch, lbcg, W)
+        log(f"focusing {forms['focusing']}")
         forms["batched"] = batched_form(torch, lbcg, W)
         log(f"batched {forms['batched']}")
         forms["served"] = served_form(torch, lbcg, W, n=args.served_requests,

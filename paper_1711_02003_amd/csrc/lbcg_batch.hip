@@ -119,7 +119,7 @@ int stage(lbcg_batch *b, const std::vector<int> &order) {
             const void *in = s->buf[s->cur ^ par];
             void *out = s->buf[s->cur ^ par ^ 1];
             std::memset(&d[j], 0, sizeof(Desc));
-            d[j].a = fused_args<float>(s->g, in, out, sh);
+            d[j].a = fused_args<float>(s->g, in, out, s->ctr + (s->cur ^ par), s->ctr + (s->cur ^ par ^ 1), sh);
             d[j].mo = to_model<float>(s->md);
         }
     }

@@ -188,16 +188,63 @@ struct Codec<_Float16> {
     __device__ static __forceinline__ _Float16 enc_df(T v, int i) {
         return _Float16(float(v * T(1.0 / wgt<L>(i))));
     }
+    // The minority share is stored times 2^14 (exact): the shares in an
+    // interface's exponential tail would otherwise fall below FP16's normal
+    // range (6.1e-5) and round to zero, which drains the thinner colour a
+    // little every step; scaled, they stay representable down to ~1e-11.
+    // |m| up to 4 fits.
     template <typename T>
     __device__ static __forceinline__ T col(_Float16 v, bool &flag) {
         const uint16_t b = __builtin_bit_cast(uint16_t, v);
         flag = b & 1u;
-        return T(float(__builtin_bit_cast(_Float16, uint16_t(b & ~1u))));
+        return T(float(__builtin_bit_cast(_Float16, uint16_t(b & ~1u))) * (1.0f / 16384.0f));
     }
     template <typename T>
     __device__ static __forceinline__ _Float16 enc_col(T m, bool flag) {
-        const uint16_t b = __builtin_bit_cast(uint16_t, _Float16(float(m)));
+        const uint16_t b = __builtin_bit_cast(uint16_t, _Float16(float(m) * 16384.0f));
         return __builtin_bit_cast(_Float16, pack_flag<uint16_t>(b, flag));
+    }
+    // Stochastic rounding of the scaled share to the 9 stored mantissa bits,
+    // driven by 8 random bits r: the float's 14 discarded bits plus r placed
+    // on their top 8 (and half a step) carry into the kept bits with
+    // probability equal to the discarded fraction, to 1/256.  Round to nearest
+    // would repeat the same error every step in a steady interface and drift
+    // the colour mass linearly in time; these errors are independent from
+    // step to step.  Values below FP16's normal range (the far tail, shares
+    // below ~4e-9) end up rounded to nearest by the conversion.
+    template <typename T>
+    __device__ static __forceinline__ _Float16 enc_col_sr(T m, bool flag, uint32_t r) {
+        const uint32_t t = (__float_as_uint(float(m) * 16384.0f) + ((r & 0xffu) << 6) + 32u) & ~0x3fffu;
+        const uint16_t h = __builtin_bit_cast(uint16_t, _Float16(__uint_as_float(t)));
+        return __builtin_bit_cast(_Float16, uint16_t((h & ~1u) | (flag ? 1u : 0u)));
+    }
+    // The deviation likewise (13 discarded bits, 10 kept): in a steady flow
+    // its round-to-nearest error would also repeat every step.
+    template <class L, typename T>
+    __device__ static __forceinline__ _Float16 enc_df_sr(T v, int i, uint32_t r) {
+        const float x = float(v * T(1.0 / wgt<L>(i)));
+        const uint32_t t = (__float_as_uint(x) + ((r & 0xffu) << 5) + 16u) & ~0x1fffu;
+        return _Float16(__uint_as_float(t));
+    }
+};
+
+// Random bits for the stochastic rounding of stored colour shares: the PCG
+// hash of Jarzynski and Olano (J. Computer Graphics Techniques 9(3), 2020)
+// seeds one generator per node and time step, and Marsaglia's xorshift32
+// (J. Stat. Software 8(14), 2003) draws one word per population.
+__device__ __forceinline__ uint32_t pcg_hash(uint32_t v) {
+    const uint32_t state = v * 747796405u + 2891336453u;
+    const uint32_t word = ((state >> ((state >> 28u) + 4u)) ^ state) * 277803737u;
+    return (word >> 22u) ^ word;
+}
+struct Dither {
+    uint32_t x, word = 0;
+    __device__ __forceinline__ Dither(uint32_t step, uint32_t node) : x(pcg_hash(node ^ pcg_hash(step)) | 1u) {}
+    __device__ __forceinline__ uint32_t next() {
+        x ^= x << 13;
+        x ^= x >> 17;
+        x ^= x << 5;
+        return x;
     }
 };
 
@@ -255,6 +302,24 @@ __device__ __forceinline__ typename PairOf<S>::type encode_pair(T df, T m, bool 
     v.x = Codec<S>::template enc_df<L, T>(df, i);
     v.y = Codec<S>::template enc_col<T>(m, redmaj);
     return v;
+}
+
+// Encoding of a time step's output: 16-bit shares are rounded
+// stochastically with the node's generator, wider ones to nearest.
+template <class L, typename S, typename T>
+__device__ __forceinline__ typename PairOf<S>::type encode_step(T df, T m, bool redmaj, int i, Dither &dz) {
+    if constexpr (sizeof(S) == 2) {
+        // one 32-bit draw serves two populations (8 bits each for the share
+        // and the deviation)
+        if ((i & 1) == 0) dz.word = dz.next();
+        const uint32_t r = (i & 1) ? dz.word >> 16 : dz.word;
+        typename PairOf<S>::type v;
+        v.x = Codec<S>::template enc_df_sr<L, T>(df, i, r >> 8);
+        v.y = Codec<S>::template enc_col_sr<T>(m, redmaj, r);
+        return v;
+    } else {
+        return encode_pair<L, S, T>(df, m, redmaj, i);
+    }
 }
 
 template <class L, typename S, typename T>
@@ -675,11 +740,12 @@ __device__ __forceinline__ void collide(const Model<T> &mo, T drho, T r36R, T r3
 
 template <class L, typename S, typename T>
 __device__ __forceinline__ void store_out(S *__restrict__ st, int64_t pitch, int64_t node,
-                                          const PostOut<L, T> &o) {
+                                          const PostOut<L, T> &o, uint32_t step) {
     typename PairOf<S>::type *a = reinterpret_cast<typename PairOf<S>::type *>(st);
+    Dither dz(step, uint32_t(node));
 #pragma unroll
     for (int i = 0; i < L::Q; ++i)
-        a[int64_t(i) * pitch + node] = encode_pair<L, S, T>(o.df[i], o.mm[i], (o.red >> i) & 1u, i);
+        a[int64_t(i) * pitch + node] = encode_step<L, S, T>(o.df[i], o.mm[i], (o.red >> i) & 1u, i, dz);
 }
 
 }  // namespace lbcg

@@ -170,6 +170,7 @@ __device__ __forceinline__ void sweep(const FusedArgs<S> &a, const Model<T> &mo,
 
     const bool intile = lane < tw && row < th;
     const int x = x0 + lane, y = y0 + row;
+    const uint32_t step = *a.ctr_in;  // seeds the stochastic rounding of 16-bit shares
 
     // ring node of this thread (at most one): rows -1 and th over x in [-1, tw],
     // then columns -1 and tw over y in [0, th)
@@ -378,8 +379,9 @@ __device__ __forceinline__ void sweep(const FusedArgs<S> &a, const Model<T> &mo,
             const T F[3] = {fx, fy, fz};
             PostOut<L, T> o;
             collide<L, T>(mo, cd, cR, cB, cj, cG, F, nullptr, o);
+            Dither dz(step, uint32_t(x) + uint32_t(a.nx) * (uint32_t(y) + uint32_t(a.ny) * uint32_t(z)));
 #pragma unroll
-            for (int i = 0; i < L::Q; ++i) ov[i] = encode_pair<L, S, T>(o.df[i], o.mm[i], (o.red >> i) & 1u, i);
+            for (int i = 0; i < L::Q; ++i) ov[i] = encode_step<L, S, T>(o.df[i], o.mm[i], (o.red >> i) & 1u, i, dz);
         }
         ozoff = uint32_t(uniform(z)) * plane;
         if (!kDelayStores) flush();
@@ -402,6 +404,7 @@ __global__ void __launch_bounds__(kTX * R) k_step_fused(FusedArgs<S> a, Model<T>
     const int total = a.ntx * a.nty * a.zchunks;
     const int xcd = blockIdx.x % kXCD, l = blockIdx.x / kXCD;
     const int item = xcd * (total / kXCD) + min(xcd, total % kXCD) + l;
+    if (item == 0 && threadIdx.x == 0) *a.ctr_out = *a.ctr_in + 1u;
     sweep<S, T, R, MASKED>(a, mo, item / a.zchunks, item % a.zchunks, lds);
 }
 
@@ -418,6 +421,7 @@ __global__ void __launch_bounds__(kTX * R)
     const int k = xcd * (total / kXCD) + min(xcd, total % kXCD) + l;
     const int item = bitem[k];
     const BatchDesc<S> d = desc[blat[k]];
+    if (item == 0 && threadIdx.x == 0) *d.a.ctr_out = *d.a.ctr_in + 1u;
     sweep<S, T, R, MASKED>(d.a, d.mo, item / d.a.zchunks, item % d.a.zchunks, lds);
 }
 
@@ -450,10 +454,13 @@ int fused_resident_blocks(int prec, int rows, bool masked) {
 }
 
 template <typename S>
-FusedArgs<S> fused_args(const Geo &g, const void *in, void *out, FusedShape sh) {
+FusedArgs<S> fused_args(const Geo &g, const void *in, void *out, const uint32_t *ctr_in, uint32_t *ctr_out,
+                        FusedShape sh) {
     FusedArgs<S> a;
     a.in = static_cast<const S *>(in);
     a.out = static_cast<S *>(out);
+    a.ctr_in = ctr_in;
+    a.ctr_out = ctr_out;
     a.nx = g.nx;
     a.ny = g.ny;
     a.nz = g.nz;
@@ -466,8 +473,10 @@ FusedArgs<S> fused_args(const Geo &g, const void *in, void *out, FusedShape sh) 
     a.zchunks = sh.zchunks < 1 ? 1 : (sh.zchunks > g.nz ? g.nz : sh.zchunks);
     return a;
 }
-template FusedArgs<float> fused_args<float>(const Geo &, const void *, void *, FusedShape);
-template FusedArgs<_Float16> fused_args<_Float16>(const Geo &, const void *, void *, FusedShape);
+template FusedArgs<float> fused_args<float>(const Geo &, const void *, void *, const uint32_t *, uint32_t *,
+                                            FusedShape);
+template FusedArgs<_Float16> fused_args<_Float16>(const Geo &, const void *, void *, const uint32_t *, uint32_t *,
+                                                  FusedShape);
 
 template <typename S, int R, bool MASKED>
 static void launch_one(const FusedArgs<S> &a, const Model<float> &mo, unsigned nblocks, hipStream_t s) {
@@ -475,8 +484,8 @@ static void launch_one(const FusedArgs<S> &a, const Model<float> &mo, unsigned n
 }
 
 template <typename S>
-static hipError_t run_fused(const Geo &g, const ModelD &md, const void *in, void *out, FusedShape sh,
-                            hipStream_t s) {
+static hipError_t run_fused(const Geo &g, const ModelD &md, const void *in, void *out, const uint32_t *ctr_in,
+                            uint32_t *ctr_out, FusedShape sh, hipStream_t s) {
     const int R = sh.rows;
     // Rows 4 and 8 only: a 1024-thread block (16 rows) caps the kernel at 128
     // VGPRs, where it spills.
@@ -484,7 +493,7 @@ static hipError_t run_fused(const Geo &g, const ModelD &md, const void *in, void
     typedef typename PairOf<S>::type P2;
     // 32-bit byte offsets must cover a state buffer
     if (uint64_t(D3Q19::Q) * uint64_t(g.pitch) * sizeof(P2) >= (uint64_t(1) << 32)) return hipErrorInvalidValue;
-    const FusedArgs<S> a = fused_args<S>(g, in, out, sh);
+    const FusedArgs<S> a = fused_args<S>(g, in, out, ctr_in, ctr_out, sh);
     const int64_t nblocks = int64_t(a.ntx) * a.nty * a.zchunks;
     if (nblocks > 0x7fffffff) return hipErrorInvalidValue;
     const Model<float> mo = to_model<float>(md);
@@ -498,9 +507,9 @@ static hipError_t run_fused(const Geo &g, const ModelD &md, const void *in, void
 }
 
 hipError_t launch_step_fused(int prec, const Geo &g, const ModelD &md, const void *in, void *out,
-                             FusedShape shape, hipStream_t s) {
-    if (prec == 1) return run_fused<float>(g, md, in, out, shape, s);
-    if (prec == 2) return run_fused<_Float16>(g, md, in, out, shape, s);
+                             const uint32_t *ctr_in, uint32_t *ctr_out, FusedShape shape, hipStream_t s) {
+    if (prec == 1) return run_fused<float>(g, md, in, out, ctr_in, ctr_out, shape, s);
+    if (prec == 2) return run_fused<_Float16>(g, md, in, out, ctr_in, ctr_out, shape, s);
     return hipErrorInvalidValue;
 }
 

@@ -108,8 +108,12 @@ __device__ __forceinline__ void gradient(const Geo &g, const T *__restrict__ psi
 template <class L, typename S, typename T>
 __global__ void __launch_bounds__(kBlock) k_step_generic(Geo g, Model<T> mo, const S *__restrict__ in,
                                                          bool pulled, const T *__restrict__ psi,
-                                                         S *__restrict__ out) {
+                                                         S *__restrict__ out, const uint32_t *__restrict__ ctr_in,
+                                                         uint32_t *__restrict__ ctr_out) {
     const int64_t n = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+    // time-step counter (seeds the stochastic rounding of 16-bit shares)
+    const uint32_t step = *ctr_in;
+    if (n == 0) *ctr_out = step + 1u;
     if (n >= g.N) return;
     if (code_at(g, n) != kFluid) return;
     int x, y, z;
@@ -124,7 +128,7 @@ __global__ void __launch_bounds__(kBlock) k_step_generic(Geo g, Model<T> mo, con
     gradient<L, T>(g, psi, x, y, z, n, F);
     PostOut<L, T> o;
     collide<L, T>(mo, m.drho, m.r36R, m.r36B, m.j, G, F, &p, o);
-    store_out<L, S, T>(out, g.pitch, n, o);
+    store_out<L, S, T>(out, g.pitch, n, o, step);
 }
 
 template <class L, typename S, typename T>
@@ -314,10 +318,10 @@ struct RunPsi {
 template <class L, typename S, typename T>
 struct RunStep {
     static hipError_t run(const Geo &g, const ModelD &md, const void *in, bool pulled, const void *psi, void *out,
-                          hipStream_t s) {
+                          const uint32_t *ctr_in, uint32_t *ctr_out, hipStream_t s) {
         hipLaunchKernelGGL((k_step_generic<L, S, T>), dim3(blocks_for(g.N)), dim3(kBlock), 0, s, g,
                            to_model<T>(md), static_cast<const S *>(in), pulled, static_cast<const T *>(psi),
-                           static_cast<S *>(out));
+                           static_cast<S *>(out), ctr_in, ctr_out);
         return hipGetLastError();
     }
 };
@@ -370,8 +374,9 @@ hipError_t launch_psi(int lattice, int prec, const Geo &g, const ModelD &md, con
     return dispatch<RunPsi>(lattice, prec, g, md, st, pulled, psi, s);
 }
 hipError_t launch_step_generic(int lattice, int prec, const Geo &g, const ModelD &md, const void *in,
-                               bool pulled, const void *psi, void *out, hipStream_t s) {
-    return dispatch<RunStep>(lattice, prec, g, md, in, pulled, psi, out, s);
+                               bool pulled, const void *psi, void *out, const uint32_t *ctr_in, uint32_t *ctr_out,
+                               hipStream_t s) {
+    return dispatch<RunStep>(lattice, prec, g, md, in, pulled, psi, out, ctr_in, ctr_out, s);
 }
 hipError_t launch_fields(int lattice, int prec, const Geo &g, const ModelD &md, const void *st, bool pulled,
                          int64_t n0, int64_t cnt, double *out, hipStream_t s) {

@@ -45,9 +45,11 @@ hipError_t launch_init(int lattice, int prec, const Geo &g, const ModelD &md, in
                        const double *rhoR, const double *rhoB, const double *u, void *st, hipStream_t s);
 hipError_t launch_psi(int lattice, int prec, const Geo &g, const ModelD &md, const void *st,
                       bool pulled, void *psi, hipStream_t s);
+// ctr_in / ctr_out: the time-step counter read by this step and the slot
+// that receives its successor (device memory, one uint32 each).
 hipError_t launch_step_generic(int lattice, int prec, const Geo &g, const ModelD &md,
                                const void *in, bool pulled, const void *psi, void *out,
-                               hipStream_t s);
+                               const uint32_t *ctr_in, uint32_t *ctr_out, hipStream_t s);
 // Fields of nodes [n0, n0 + cnt): out = rhoR | rhoB | ux | uy | uz | psi (cnt each).
 hipError_t launch_fields(int lattice, int prec, const Geo &g, const ModelD &md, const void *st,
                          bool pulled, int64_t n0, int64_t cnt, double *out, hipStream_t s);
@@ -77,13 +79,16 @@ struct FusedArgs {
     const uint8_t *mask;  // nullptr = every node fluid
     const DevInlet *inlets;
     const DevOutlet *outlets;
+    const uint32_t *ctr_in;  // time-step counter of this step
+    uint32_t *ctr_out;       // receives ctr_in + 1
     int ntx, nty, zchunks;
 };
 template <typename S>
-FusedArgs<S> fused_args(const Geo &g, const void *in, void *out, FusedShape sh);
+FusedArgs<S> fused_args(const Geo &g, const void *in, void *out, const uint32_t *ctr_in, uint32_t *ctr_out,
+                        FusedShape sh);
 
 hipError_t launch_step_fused(int prec, const Geo &g, const ModelD &md, const void *in, void *out,
-                             FusedShape shape, hipStream_t s);
+                             const uint32_t *ctr_in, uint32_t *ctr_out, FusedShape shape, hipStream_t s);
 bool fused_supported(int lattice, int prec, const Geo &g);
 // Blocks of the fused kernel that fit on the device at once.
 int fused_resident_blocks(int prec, int rows, bool masked);

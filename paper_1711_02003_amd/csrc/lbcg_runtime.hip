@@ -28,7 +28,7 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 struct Plan {
     int Q;
     int64_t N, pitch, staging_nodes;
-    size_t elem, tsize, state, psi, mask, inl, outl, partials, diag, staging, total;
+    size_t elem, tsize, state, psi, mask, inl, outl, partials, diag, ctr, staging, total;
 };
 
 int validate(const lbcg_params *p) {
@@ -88,8 +88,10 @@ Plan make_plan(const lbcg_params *p) {
     pl.outl = align_up(sizeof(DevOutlet) * size_t(p->n_outlets > 0 ? p->n_outlets : 1), kAlign);
     pl.partials = align_up(sizeof(double) * kDiagBlocks * kDiagVals, kAlign);
     pl.diag = align_up(sizeof(double) * 16, kAlign);
+    pl.ctr = kAlign;
     pl.staging = align_up(sizeof(double) * size_t(per) * size_t(pl.staging_nodes), kAlign);
-    pl.total = 2 * pl.state + pl.psi + pl.mask + pl.inl + pl.outl + pl.partials + pl.diag + pl.staging + kAlign;
+    pl.total = 2 * pl.state + pl.psi + pl.mask + pl.inl + pl.outl + pl.partials + pl.diag + pl.ctr + pl.staging +
+               kAlign;
     return pl;
 }
 
@@ -131,11 +133,14 @@ FusedShape pick_shape(const lbcg_sim *s, const lbcg_params *p) {
 hipError_t enqueue_step(lbcg_sim *s, bool pulled) {
     const void *in = s->buf[s->cur];
     void *out = s->buf[s->cur ^ 1];
+    const uint32_t *ctr_in = s->ctr + s->cur;
+    uint32_t *ctr_out = s->ctr + (s->cur ^ 1);
     if (s->kernel == LBCG_KERNEL_FUSED && pulled)
-        return launch_step_fused(s->prec, s->g, s->md, in, out, s->shape, s->stream);
+        return launch_step_fused(s->prec, s->g, s->md, in, out, ctr_in, ctr_out, s->shape, s->stream);
     hipError_t e = launch_psi(s->lattice, s->prec, s->g, s->md, in, pulled, s->psi, s->stream);
     if (e != hipSuccess) return e;
-    return launch_step_generic(s->lattice, s->prec, s->g, s->md, in, pulled, s->psi, out, s->stream);
+    return launch_step_generic(s->lattice, s->prec, s->g, s->md, in, pulled, s->psi, out, ctr_in, ctr_out,
+                               s->stream);
 }
 
 // Capture kGraphSteps pulled steps starting from buffer `start` (even count,
@@ -269,6 +274,8 @@ int lbcg_create(const lbcg_params *p, void *dev_buf, size_t bytes, void *hip_str
     base += pl.partials;
     s->diag = reinterpret_cast<double *>(base);
     base += pl.diag;
+    s->ctr = reinterpret_cast<uint32_t *>(base);
+    base += pl.ctr;
     s->staging = reinterpret_cast<double *>(base);
     s->staging_nodes = pl.staging_nodes;
     s->state_bytes = pl.state;
@@ -349,6 +356,8 @@ int lbcg_init_fields(lbcg_sim *s, const double *rhoR, const double *rhoB, const 
         HIP_TRY(launch_init(s->lattice, s->prec, s->g, s->md, n0, cnt, sR, sB, sU, s->buf[0], s->stream));
         HIP_TRY(hipStreamSynchronize(s->stream));
     }
+    HIP_TRY(hipMemsetAsync(s->ctr, 0, 2 * sizeof(uint32_t), s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
     s->cur = 0;
     s->pulled = false;
     s->initialised = true;
@@ -530,6 +539,8 @@ int lbcg_set_state(lbcg_sim *s, const void *host, size_t bytes) {
     for (int c = 0; c < s->Q; ++c)
         HIP_TRY(hipMemcpyAsync(dst + 2 * size_t(c) * size_t(s->g.pitch) * s->elem, src + c * comp, comp,
                                hipMemcpyHostToDevice, s->stream));
+    const uint32_t ctr = uint32_t(h[7]);  // the step counter continues from the saved step
+    HIP_TRY(hipMemcpyAsync(s->ctr + s->cur, &ctr, sizeof(ctr), hipMemcpyHostToDevice, s->stream));
     HIP_TRY(hipStreamSynchronize(s->stream));
     s->pulled = h[6] == 1;
     s->step = h[7];
@@ -576,13 +587,16 @@ int lbcg_tune(lbcg_sim *s, int32_t *rows, int32_t *zchunks) {
         }
         const void *in = s->buf[s->cur];
         void *out = s->buf[s->cur ^ 1];
+        // the counter slot written is the one the next step writes too
+        const uint32_t *ctr_in = s->ctr + s->cur;
+        uint32_t *ctr_out = s->ctr + (s->cur ^ 1);
         float best = 0;
         FusedShape pick = s->shape;
         hipError_t e = hipSuccess;
         for (const FusedShape &c : cand) {
-            for (int k = 0; k < 2 && e == hipSuccess; ++k) e = launch_step_fused(s->prec, s->g, s->md, in, out, c, s->stream);
+            for (int k = 0; k < 2 && e == hipSuccess; ++k) e = launch_step_fused(s->prec, s->g, s->md, in, out, ctr_in, ctr_out, c, s->stream);
             if (e == hipSuccess) e = hipEventRecord(e0, s->stream);
-            for (int k = 0; k < 4 && e == hipSuccess; ++k) e = launch_step_fused(s->prec, s->g, s->md, in, out, c, s->stream);
+            for (int k = 0; k < 4 && e == hipSuccess; ++k) e = launch_step_fused(s->prec, s->g, s->md, in, out, ctr_in, ctr_out, c, s->stream);
             if (e == hipSuccess) e = hipEventRecord(e1, s->stream);
             if (e == hipSuccess) e = hipEventSynchronize(e1);
             float ms = 0;

@@ -20,6 +20,7 @@ struct lbcg_sim {
     int64_t step;
     void *psi;              // generic phase-field scratch (N values of the compute type)
     double *partials, *diag;
+    uint32_t *ctr;          // time-step counter pair: ctr[cur] = steps taken since initialisation
     double *staging;        // field / population staging
     int64_t staging_nodes;
     uint8_t *mask_dev;
