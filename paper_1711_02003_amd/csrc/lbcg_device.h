@@ -108,7 +108,22 @@ struct Geo {
     const uint8_t *mask;       // nullptr = all fluid
     const DevInlet *inlets;
     const DevOutlet *outlets;
+    const uint32_t *links;     // link words (below), D3Q19 with a mask only
 };
+
+// Link word of a node of a lattice with geometry, built on the host from the
+// mask so that a pull needs no per-direction mask reads.  Fluid node: bit i
+// (i < Q) set when the upstream node x - c_i is not fluid; kLinkFluid;
+// kLinkBoundary when some upstream node is an inlet or outlet (plus
+// kLinkOutlet if one is an outlet); and the mask code shared by all its
+// non-fluid upstream nodes in bits 20..27, or kLinkMixed when they differ
+// (walls included).  Non-fluid node: its own mask code in bits 20..27,
+// nothing else.
+constexpr uint32_t kLinkFluid = 1u << 19;
+constexpr uint32_t kLinkMixed = 1u << 28;
+constexpr uint32_t kLinkOutlet = 1u << 29;
+constexpr uint32_t kLinkBoundary = 1u << 30;
+__host__ __device__ constexpr uint8_t link_code(uint32_t lk) { return uint8_t((lk >> 20) & 0xffu); }
 
 __device__ __forceinline__ int wrap_m1(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
 
@@ -527,6 +542,83 @@ __device__ __forceinline__ T phat(T alpha) {
 }
 
 // ---------------------------------------------------------------- pull
+// Density, red density and velocity of a node's own post-collision
+// populations (the outlet rule's inputs).
+template <typename T>
+struct OwnMom {
+    T rho, rR, u[3];
+};
+// One population at a time, in a rolled loop (the rule is needed only next
+// to outlets, and this keeps its registers few), with exactly the
+// arithmetic and summation order of densities() and of the momentum sum.
+template <class L, typename S, typename T>
+__device__ __forceinline__ OwnMom<T> own_moments(const Geo &g, const S *__restrict__ st, int64_t n) {
+    const typename PairOf<S>::type *a = reinterpret_cast<const typename PairOf<S>::type *>(st);
+    T drho = 0, Ra = 0, Ba = 0, jx = 0, jy = 0, jz = 0;
+    int K = 0;
+#pragma unroll 1
+    for (int k = 0; k < L::Q; ++k) {
+        const typename PairOf<S>::type v = a[int64_t(k) * g.pitch + n];
+        bool fl;
+        const T d = Codec<S>::template df<L, T>(v.x, k);
+        const T m = Codec<S>::template col<T>(v.y, fl);
+        const T mu = m * (T(w36<L>(k)) + T(36) * d);
+        const T t = T(36) * d - mu;
+        drho += d;
+        Ra += fl ? t : mu;
+        Ba += fl ? mu : t;
+        K += fl ? w36<L>(k) : 0;
+        jx += T(L::cx[k]) * d;
+        jy += T(L::cy[k]) * d;
+        jz += T(L::cz[k]) * d;
+    }
+    OwnMom<T> om;
+    om.rho = T(1) + drho;
+    om.rR = (T(K) + Ra) / T(36);
+    om.u[0] = jx / om.rho;
+    om.u[1] = jy / om.rho;
+    om.u[2] = jz / om.rho;
+    (void)Ba;
+    return om;
+}
+
+// Link i of a fluid node whose upstream node is an inlet or outlet (code):
+// p holds at index i the node's own post-collision pair of the opposite
+// direction (what half-way bounce-back returns); replace it by the boundary
+// value.  Inlet: moving-wall bounce-back injecting the inlet's colour
+// densities.  Outlet: anti-bounce-back at the outlet density with the
+// node's own red fraction and velocity (om).
+template <class L, typename T>
+__device__ __forceinline__ void boundary_link(const Geo &g, const Model<T> &mo, int i, uint8_t code,
+                                              const OwnMom<T> &om, Pops<L, T> &p) {
+    const int io = L::opp[i];
+    const T fo = T(wgt<L>(io)) + p.df[i];
+    const T mu = p.mm[i] * fo;
+    const T fRo = p.flag(i) ? fo - mu : mu, fBo = fo - fRo;
+    T fR, fB;
+    if (code < kOutlet0) {
+        const DevInlet in = g.inlets[code - kInlet0];
+        const T cu = T(L::cx[io]) * T(in.u[0]) + T(L::cy[io]) * T(in.u[1]) + T(L::cz[io]) * T(in.u[2]);
+        const T mom = T(6.0 * wgt<L>(io)) * cu;  // 2 w c.u / c_s^2
+        fR = fRo - mom * T(in.rhoR);
+        fB = fBo - mom * T(in.rhoB);
+    } else {
+        const T rout = T(g.outlets[code - kOutlet0].rho);
+        const T rwR = rout * om.rR / om.rho, rwB = rout - rwR;
+        const T cu = T(L::cx[io]) * om.u[0] + T(L::cy[io]) * om.u[1] + T(L::cz[io]) * om.u[2];
+        const T uu = om.u[0] * om.u[0] + om.u[1] * om.u[1] + om.u[2] * om.u[2];
+        const T wv = T(wgt<L>(io)) * (T(4.5) * cu * cu - T(1.5) * uu);
+        const T phR = phi<L, T>(io, mo.aR), phB = phi<L, T>(io, mo.aB);
+        fR = T(2) * rwR * (phR + wv) - fRo;
+        fB = T(2) * rwB * (phB + wv) - fBo;
+    }
+    const T f = fR + fB;
+    T mm;
+    bool fl;
+    split_shares<T>(f != T(0) ? fR / f : T(0), f != T(0) ? fB / f : T(0), mm, fl);
+    p.set(i, f - T(wgt<L>(i)), mm, fl);
+}
+
 // Pre-collision populations of fluid node (x, y, z) = n at the new time level
 // from the stored post-collision state (Eq. (1), pull form), with the
 // boundary rules for non-fluid upstream nodes: wall -> half-way bounce-back;
@@ -543,7 +635,7 @@ __device__ __forceinline__ void pull_node(const Geo &g, const Model<T> &mo, cons
         return;
     }
     bool own = false;
-    T oRho = 0, oR = 0, oU[3] = {0, 0, 0};
+    OwnMom<T> om{};
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) {
         const int xs = wrap_m1(x - L::cx[i], g.nx);
@@ -555,60 +647,18 @@ __device__ __forceinline__ void pull_node(const Geo &g, const Model<T> &mo, cons
             load_raw<L, S, T>(st, g.pitch, m, i, p);
             continue;
         }
+        // the node's own pair of the opposite direction, at index i (w_io == w_i)
         const int io = L::opp[i];
         Pops<L, T> q;
         q.red = 0;
         load_raw<L, S, T>(st, g.pitch, n, io, q);
-        if (code == kWall) {
-            p.set(i, q.df[io], q.mm[io], q.flag(io));  // w_io == w_i
-            continue;
+        p.set(i, q.df[io], q.mm[io], q.flag(io));
+        if (code == kWall) continue;
+        if (code >= kOutlet0 && !own) {
+            om = own_moments<L, S, T>(g, st, n);
+            own = true;
         }
-        const T fo = T(wgt<L>(io)) + q.df[io];
-        const T fRo = q.fred(io), fBo = fo - fRo;
-        T fR, fB;
-        if (code < kOutlet0) {
-            const DevInlet in = g.inlets[code - kInlet0];
-            const T cu = T(L::cx[io]) * T(in.u[0]) + T(L::cy[io]) * T(in.u[1]) + T(L::cz[io]) * T(in.u[2]);
-            const T mom = T(6.0 * wgt<L>(io)) * cu;  // 2 w c.u / c_s^2
-            fR = fRo - mom * T(in.rhoR);
-            fB = fBo - mom * T(in.rhoB);
-        } else {
-            if (!own) {
-                // moments of this node's own post-collision populations
-                Pops<L, T> c;
-                c.red = 0;
-#pragma unroll
-                for (int k = 0; k < L::Q; ++k) load_raw<L, S, T>(st, g.pitch, n, k, c);
-                T odr, oR36, oB36;
-                densities<L, T>(c, odr, oR36, oB36);
-                oRho = T(1) + odr;
-                oR = oR36 / T(36);
-                T jx = 0, jy = 0, jz = 0;
-#pragma unroll
-                for (int k = 0; k < L::Q; ++k) {
-                    jx += T(L::cx[k]) * c.df[k];
-                    jy += T(L::cy[k]) * c.df[k];
-                    jz += T(L::cz[k]) * c.df[k];
-                }
-                oU[0] = jx / oRho;
-                oU[1] = jy / oRho;
-                oU[2] = jz / oRho;
-                own = true;
-            }
-            const T rout = T(g.outlets[code - kOutlet0].rho);
-            const T rwR = rout * oR / oRho, rwB = rout - rwR;
-            const T cu = T(L::cx[io]) * oU[0] + T(L::cy[io]) * oU[1] + T(L::cz[io]) * oU[2];
-            const T uu = oU[0] * oU[0] + oU[1] * oU[1] + oU[2] * oU[2];
-            const T wv = T(wgt<L>(io)) * (T(4.5) * cu * cu - T(1.5) * uu);
-            const T phR = phi<L, T>(io, mo.aR), phB = phi<L, T>(io, mo.aB);
-            fR = T(2) * rwR * (phR + wv) - fRo;
-            fB = T(2) * rwB * (phB + wv) - fBo;
-        }
-        const T f = fR + fB;
-        T mm;
-        bool fl;
-        split_shares<T>(f != T(0) ? fR / f : T(0), f != T(0) ? fB / f : T(0), mm, fl);
-        p.set(i, f - T(wgt<L>(i)), mm, fl);
+        boundary_link<L, T>(g, mo, i, code, om, p);
     }
 }
 

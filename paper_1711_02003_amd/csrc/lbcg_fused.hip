@@ -102,30 +102,30 @@ __device__ __forceinline__ void column_offsets(const FusedArgs<S> &a, int x, int
         for (int c = 0; c < 3; ++c) t[c + 3 * b] = (xs[c] + uint32_t(a.nx) * ys[b]) * E;
 }
 
-// Populations requested but not yet used.  Without geometry they stay as the
-// loaded pairs and are decoded only where they are consumed, so nothing
-// waits on a load before then; the boundary rules of the geometry path need
-// the values at once and keep them decoded.
-template <typename S, typename T, bool MASKED>
+// Populations requested but not yet used: the loaded pairs, decoded only
+// where they are consumed so that nothing waits on a load before then, and
+// (with geometry) the node's link word.
+template <typename S, typename T>
 struct Pending {
     typename PairOf<S>::type v[D3Q19::Q];
+    uint32_t lk;
     __device__ __forceinline__ void take(Pops<D3Q19, T> &p) const {
         p.red = 0;
 #pragma unroll
         for (int i = 0; i < D3Q19::Q; ++i) decode_pair<D3Q19, S, T>(v[i], i, p);
     }
 };
-template <typename S, typename T>
-struct Pending<S, T, true> {
-    Pops<D3Q19, T> p;
-    __device__ __forceinline__ void take(Pops<D3Q19, T> &q) const { q = p; }
-};
 
-// Request the 19 population pairs of a node without geometry at plane z,
-// from its column offsets t.
-template <typename S, typename T>
-__device__ __forceinline__ void pull_periodic(const FusedArgs<S> &a, __amdgpu_buffer_rsrc_t r, const uint32_t t[9],
-                                              int z, Pending<S, T, false> &pend) {
+// Request the 19 population pairs of a node at plane z from its column
+// offsets t.  With geometry (link word lk), a link whose upstream node is not
+// fluid reads the node's own pair of the opposite direction instead: that is
+// the half-way bounce-back value of a wall, and the start of the inlet and
+// outlet rules.  The buffer offsets stay non-negative: the scalar part is the
+// smaller of the two candidates' uniform parts and the vector part adds the
+// rest.
+template <typename S, typename T, bool MASKED>
+__device__ __forceinline__ void pull_plane(const FusedArgs<S> &a, __amdgpu_buffer_rsrc_t r, const uint32_t t[9],
+                                           int z, uint32_t lk, Pending<S, T> &pend) {
     using L = D3Q19;
     typedef typename PairOf<S>::type P2;
     constexpr uint32_t E = sizeof(P2);
@@ -134,8 +134,18 @@ __device__ __forceinline__ void pull_periodic(const FusedArgs<S> &a, __amdgpu_bu
     const uint32_t zo[3] = {uint32_t(uniform(z == 0 ? a.nz - 1 : z - 1)) * plane, uint32_t(uniform(z)) * plane,
                             uint32_t(uniform(z == a.nz - 1 ? 0 : z + 1)) * plane};
 #pragma unroll
-    for (int i = 0; i < L::Q; ++i)
-        pend.v[i] = load_pair<P2>(r, t[(1 - L::cx[i]) + 3 * (1 - L::cy[i])], uint32_t(i) * cstride + zo[1 - L::cz[i]]);
+    for (int i = 0; i < L::Q; ++i) {
+        const uint32_t up = uint32_t(i) * cstride + zo[1 - L::cz[i]];
+        const uint32_t tv = t[(1 - L::cx[i]) + 3 * (1 - L::cy[i])];
+        if (!MASKED || i == 0) {
+            pend.v[i] = load_pair<P2>(r, tv, up);
+        } else {
+            const uint32_t own = uint32_t(L::opp[i]) * cstride + zo[1];
+            const uint32_t base = own < up ? own : up;
+            const uint32_t vo = ((lk >> i) & 1u) ? t[4] + (own - base) : tv + (up - base);
+            pend.v[i] = load_pair<P2>(r, vo, base);
+        }
+    }
 }
 
 __device__ __forceinline__ int wrapz(int z, int nz) { return z < 0 ? z + nz : (z >= nz ? z - nz : z); }
@@ -151,6 +161,7 @@ __device__ __forceinline__ Geo geo_of(const FusedArgs<S> &a) {
     g.mask = a.mask;
     g.inlets = a.inlets;
     g.outlets = a.outlets;
+    g.links = a.links;
     return g;
 }
 
@@ -208,10 +219,6 @@ __device__ __forceinline__ void sweep(const FusedArgs<S> &a, const Model<T> &mo,
     auto node = [&](int xx, int yy, int zz) {
         return int64_t(xx) + int64_t(a.nx) * (int64_t(yy) + int64_t(a.ny) * zz);
     };
-    auto code = [&](int xx, int yy, int zz) -> uint8_t {
-        if (!MASKED) return kFluid;
-        return a.mask ? a.mask[node(xx, yy, zz)] : kFluid;
-    };
     // LDS psi of a non-fluid node: the inlet's phase value, or the sentinel
     // that the gradient replaces by the centre node's own psi
     auto solid_psi = [&](uint8_t c) -> float {
@@ -221,12 +228,24 @@ __device__ __forceinline__ void sweep(const FusedArgs<S> &a, const Model<T> &mo,
         }
         return kSentinel;
     };
-    auto pull = [&](int xx, int yy, int zz, const uint32_t t[9], Pending<S, T, MASKED> &pend) {
-        if constexpr (MASKED) {
-            const Geo g = geo_of(a);
-            pull_node<L, S, T>(g, mo, a.in, xx, yy, zz, node(xx, yy, zz), true, pend.p);
-        } else {
-            pull_periodic<S, T>(a, rin, t, zz, pend);
+    auto fluid = [&](uint32_t lk) { return !MASKED || (lk & kLinkFluid) != 0u; };
+    // Inlet and outlet links of a node (link word lk) whose requested pairs
+    // are in q: the redirected pair of such a link is the node's own pair of
+    // the opposite direction, which the rule turns into the boundary value.
+    auto settle = [&](int xx, int yy, int zz, uint32_t lk, Pops<L, T> &q) {
+        if (!MASKED || !(lk & kLinkBoundary)) return;
+        const Geo g = geo_of(a);
+        const int64_t n = node(xx, yy, zz);
+        OwnMom<T> om{};
+        if (lk & kLinkOutlet) om = own_moments<L, S, T>(g, a.in, n);
+#pragma unroll
+        for (int i = 1; i < L::Q; ++i) {
+            if (!((lk >> i) & 1u)) continue;
+            uint8_t c = link_code(lk);
+            if (lk & kLinkMixed)
+                c = a.mask[node(wrap_m1(xx - L::cx[i], a.nx), wrap_m1(yy - L::cy[i], a.ny),
+                                wrap_m1(zz - L::cz[i], a.nz))];
+            if (c != kWall) boundary_link<L, T>(g, mo, i, c, om, q);
         }
     };
 
@@ -240,27 +259,32 @@ __device__ __forceinline__ void sweep(const FusedArgs<S> &a, const Model<T> &mo,
     // interior populations of a plane are requested one iteration before
     // they are used, ring first: the neighbour tiles' rows are then requested
     // while those tiles load them too, and waiting for the ring (loads retire
-    // in order) leaves the interior loads in flight.
-    Pending<S, T, MASKED> rp;
-    uint8_t rcode = kFluid;
+    // in order) leaves the interior loads in flight.  With geometry, a node's
+    // link word for a plane is read one request earlier.
+    Pending<S, T> rp;
+    rp.lk = kLinkFluid;
+    uint32_t rlk = 0;  // link word of the next ring request
+    if (MASKED && has_ring) rlk = a.links[node(gx, gy, wrapz(z0 - 1, a.nz))];
     auto ring_issue = [&](int zp) {
         if (has_ring) {
             const int zz = wrapz(zp, a.nz);
-            rcode = code(gx, gy, zz);
-            if (rcode == kFluid) pull(gx, gy, zz, rxy, rp);
+            rp.lk = MASKED ? rlk : kLinkFluid;
+            if (fluid(rp.lk)) pull_plane<S, T, MASKED>(a, rin, rxy, zz, rp.lk, rp);
+            if (MASKED) rlk = a.links[node(gx, gy, wrapz(zp + 1, a.nz))];
         }
     };
     auto ring_finish = [&](int zp) {
         if (has_ring) {
             float v;
-            if (rcode == kFluid) {
+            if (fluid(rp.lk)) {
                 Pops<L, T> q;
                 rp.take(q);
+                settle(gx, gy, wrapz(zp, a.nz), rp.lk, q);
                 T dr, rR, rB;
                 densities<L, T>(q, dr, rR, rB);
                 v = float(psi_of<T>(dr, rR, rB));
             } else {
-                v = solid_psi(rcode);
+                v = solid_psi(link_code(rp.lk));
             }
             slot_of(zp)[(ry + 1) * W + rx + 1] = v;
         }
@@ -270,21 +294,30 @@ __device__ __forceinline__ void sweep(const FusedArgs<S> &a, const Model<T> &mo,
     // of plane z+1 are in flight.
     T cd = 0, cR = 0, cB = 0, cj[3] = {0, 0, 0}, cG[6] = {0, 0, 0, 0, 0, 0};
     bool cfl = false;
-    Pending<S, T, MASKED> pp;
-    uint8_t pcode = kFluid;
+    Pending<S, T> pp;
+    pp.lk = kLinkFluid;
+    uint32_t ilk = 0;  // link word of the next interior request
+    if (MASKED && intile) ilk = a.links[node(x, y, wrapz(z0 - 1, a.nz))];
+    int pz = 0;  // plane of the pending interior request
     auto interior_issue = [&](int zp) {
         if (intile) {
-            const int zz = wrapz(zp, a.nz);
-            pcode = code(x, y, zz);
-            if (pcode == kFluid) pull(x, y, zz, ixy, pp);
+            pz = wrapz(zp, a.nz);
+            pp.lk = MASKED ? ilk : kLinkFluid;
+            if (fluid(pp.lk)) pull_plane<S, T, MASKED>(a, rin, ixy, pz, pp.lk, pp);
+            if (MASKED) ilk = a.links[node(x, y, wrapz(zp + 1, a.nz))];
         }
+    };
+    // the pending interior populations, boundary rules applied
+    auto interior_take = [&](Pops<L, T> &q) {
+        pp.take(q);
+        settle(x, y, pz, pp.lk, q);
     };
     // moments of the pulled interior plane into (d, r36R, r36B, j, G); returns psi
     auto interior_moments = [&](T &d, T &r36R, T &r36B, T j[3], T G[6], bool &fl) -> float {
-        fl = pcode == kFluid;
-        if (!fl) return solid_psi(pcode);
+        fl = fluid(pp.lk);
+        if (!fl) return solid_psi(link_code(pp.lk));
         Pops<L, T> q;
-        pp.take(q);
+        interior_take(q);
         Mom<T> m;
         moments<L, T>(q, m);
         d = m.drho;
@@ -303,14 +336,14 @@ __device__ __forceinline__ void sweep(const FusedArgs<S> &a, const Model<T> &mo,
     interior_issue(z0 - 1);
     if (intile) {
         float v;
-        if (pcode == kFluid) {
+        if (fluid(pp.lk)) {
             Pops<L, T> q;
-            pp.take(q);
+            interior_take(q);
             T dr, rR, rB;
             densities<L, T>(q, dr, rR, rB);
             v = float(psi_of<T>(dr, rR, rB));
         } else {
-            v = solid_psi(pcode);
+            v = solid_psi(link_code(pp.lk));
         }
         slot_of(z0 - 1)[(row + 1) * W + lane + 1] = v;
     }
@@ -468,6 +501,7 @@ FusedArgs<S> fused_args(const Geo &g, const void *in, void *out, const uint32_t 
     a.mask = g.mask;
     a.inlets = g.inlets;
     a.outlets = g.outlets;
+    a.links = g.links;
     a.ntx = (g.nx + kTX - 1) / kTX;
     a.nty = (g.ny + sh.rows - 1) / sh.rows;
     a.zchunks = sh.zchunks < 1 ? 1 : (sh.zchunks > g.nz ? g.nz : sh.zchunks);

@@ -79,6 +79,7 @@ struct FusedArgs {
     const uint8_t *mask;  // nullptr = every node fluid
     const DevInlet *inlets;
     const DevOutlet *outlets;
+    const uint32_t *links;   // link words (with a mask)
     const uint32_t *ctr_in;  // time-step counter of this step
     uint32_t *ctr_out;       // receives ctr_in + 1
     int ntx, nty, zchunks;

@@ -28,7 +28,7 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 struct Plan {
     int Q;
     int64_t N, pitch, staging_nodes;
-    size_t elem, tsize, state, psi, mask, inl, outl, partials, diag, ctr, staging, total;
+    size_t elem, tsize, state, psi, mask, links, inl, outl, partials, diag, ctr, staging, total;
 };
 
 int validate(const lbcg_params *p) {
@@ -84,14 +84,15 @@ Plan make_plan(const lbcg_params *p) {
     pl.state = align_up(size_t(2 * pl.Q) * size_t(pl.pitch) * pl.elem, kAlign);
     pl.psi = align_up(size_t(pl.pitch) * pl.tsize, kAlign);
     pl.mask = p->mask ? align_up(size_t(pl.pitch), kAlign) : 0;
+    pl.links = (p->mask && p->lattice == LBCG_D3Q19) ? align_up(sizeof(uint32_t) * size_t(pl.pitch), kAlign) : 0;
     pl.inl = align_up(sizeof(DevInlet) * size_t(p->n_inlets > 0 ? p->n_inlets : 1), kAlign);
     pl.outl = align_up(sizeof(DevOutlet) * size_t(p->n_outlets > 0 ? p->n_outlets : 1), kAlign);
     pl.partials = align_up(sizeof(double) * kDiagBlocks * kDiagVals, kAlign);
     pl.diag = align_up(sizeof(double) * 16, kAlign);
     pl.ctr = kAlign;
     pl.staging = align_up(sizeof(double) * size_t(per) * size_t(pl.staging_nodes), kAlign);
-    pl.total = 2 * pl.state + pl.psi + pl.mask + pl.inl + pl.outl + pl.partials + pl.diag + pl.ctr + pl.staging +
-               kAlign;
+    pl.total = 2 * pl.state + pl.psi + pl.mask + pl.links + pl.inl + pl.outl + pl.partials + pl.diag + pl.ctr +
+               pl.staging + kAlign;
     return pl;
 }
 
@@ -180,6 +181,43 @@ bool build_graph(lbcg_sim *s, int start) {
     return true;
 }
 
+// Link words of a D3Q19 lattice with geometry (encoding in lbcg_device.h).
+std::vector<uint32_t> link_words(int nx, int ny, int nz, const uint8_t *mask) {
+    using L = D3Q19;
+    std::vector<uint32_t> out(size_t(nx) * ny * nz, 0u);
+    auto wrap = [](int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); };
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                const size_t n = size_t(x) + size_t(nx) * (size_t(y) + size_t(ny) * z);
+                if (mask[n] != kFluid) {
+                    out[n] = uint32_t(mask[n]) << 20;
+                    continue;
+                }
+                // the code of the non-fluid upstream nodes, walls included:
+                // one code for all of them, or "mixed"
+                uint32_t lk = kLinkFluid;
+                int code = -1;
+                for (int i = 1; i < L::Q; ++i) {
+                    const size_t m = size_t(wrap(x - L::cx[i], nx)) +
+                                     size_t(nx) * (size_t(wrap(y - L::cy[i], ny)) + size_t(ny) * wrap(z - L::cz[i], nz));
+                    const uint8_t c = mask[m];
+                    if (c == kFluid) continue;
+                    lk |= 1u << i;
+                    if (code < 0)
+                        code = c;
+                    else if (code != c)
+                        lk |= kLinkMixed;
+                    if (c == kWall) continue;
+                    lk |= kLinkBoundary;
+                    if (c >= kOutlet0) lk |= kLinkOutlet;
+                }
+                if (code >= 0 && !(lk & kLinkMixed)) lk |= uint32_t(code) << 20;
+                out[n] = lk;
+            }
+    return out;
+}
+
 void release(lbcg_sim *s) {
     for (int k = 0; k < 2; ++k)
         if (s->graph[k]) (void)hipGraphExecDestroy(s->graph[k]);
@@ -266,6 +304,8 @@ int lbcg_create(const lbcg_params *p, void *dev_buf, size_t bytes, void *hip_str
     base += pl.psi;
     s->mask_dev = p->mask ? reinterpret_cast<uint8_t *>(base) : nullptr;
     base += pl.mask;
+    uint32_t *links_dev = pl.links ? reinterpret_cast<uint32_t *>(base) : nullptr;
+    base += pl.links;
     s->in_dev = reinterpret_cast<DevInlet *>(base);
     base += pl.inl;
     s->out_dev = reinterpret_cast<DevOutlet *>(base);
@@ -296,6 +336,7 @@ int lbcg_create(const lbcg_params *p, void *dev_buf, size_t bytes, void *hip_str
     s->g.mask = s->mask_dev;
     s->g.inlets = s->in_dev;
     s->g.outlets = s->out_dev;
+    s->g.links = links_dev;
     std::vector<DevInlet> ins(size_t(p->n_inlets > 0 ? p->n_inlets : 1));
     for (int j = 0; j < p->n_inlets; ++j) {
         for (int a = 0; a < 3; ++a) ins[j].u[a] = p->inlets[j].u[a];
@@ -311,6 +352,12 @@ int lbcg_create(const lbcg_params *p, void *dev_buf, size_t bytes, void *hip_str
                            s->stream);
     if (e == hipSuccess && p->mask)
         e = hipMemcpyAsync(s->mask_dev, p->mask, size_t(pl.N), hipMemcpyHostToDevice, s->stream);
+    std::vector<uint32_t> links;
+    if (e == hipSuccess && links_dev) {
+        links = link_words(s->g.nx, s->g.ny, s->g.nz, p->mask);
+        e = hipMemcpyAsync(links_dev, links.data(), sizeof(uint32_t) * links.size(), hipMemcpyHostToDevice,
+                           s->stream);
+    }
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
     if (e != hipSuccess) {
         (void)hipGetLastError();
