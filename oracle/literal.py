@@ -112,7 +112,12 @@ def step(f, lattice, tau, A, beta, alpha=(0.0, 0.0), eps_F=1e-8, mask=None, inle
     Fn = np.sqrt((F * F).sum(0))
     hasF = Fn > eps_F
 
-    # per-colour relaxation, then the perturbation added to each colour
+    # each colour relaxed at the node's rate (the mixture viscosity is the
+    # colour-fraction-weighted harmonic mean of the component viscosities),
+    # then the perturbation added to each colour
+    with np.errstate(invalid="ignore", divide="ignore"):
+        nu = 1.0 / sum((rho_k[k] / rho) / (CS2 * (tau[k] - 0.5)) for k in range(2))
+        om = np.where(fluid, 1.0 / (nu / CS2 + 0.5), 0.0)
     f2k = np.zeros_like(f)
     Qt = np.einsum("ia,ib->iab", cf, cf) - CS2 * np.eye(3)[None]
     Fc = np.einsum("ia,a...->i...", cf, F)
@@ -121,7 +126,6 @@ def step(f, lattice, tau, A, beta, alpha=(0.0, 0.0), eps_F=1e-8, mask=None, inle
                                                 - B.reshape(-1, 1, 1, 1)), 0.0)
     for k in range(2):
         fe = equilibrium(lattice, rho_k[k], alpha[k], u)
-        om = 1.0 / tau[k]
         if bgk:
             f1 = f[k] - om * (f[k] - fe)
         else:

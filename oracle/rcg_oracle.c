@@ -11,15 +11,21 @@
  *      phase field psi = (rho^R - rho^B) / rho;
  *   2. colour gradient F = grad psi with the isotropic stencil
  *      (1/c_s^2) sum_i w_i c_i psi(x + c_i);
- *   3. per-colour regularized relaxation (Eqs. 5, 6, 7, 11): the
- *      post-collision population is the colour equilibrium plus
- *      (1 - 1/tau_k) times the second-order Hermite projection of the colour's
- *      non-equilibrium momentum flux; or plain BGK (Eq. 5) when requested;
+ *   3. regularized relaxation (Eqs. 5, 6, 7, 11) at the node's relaxation
+ *      time tau (below): the post-collision population is the sum of the
+ *      colour equilibria plus (1 - 1/tau) times the second-order Hermite
+ *      projection of the non-equilibrium momentum flux of both colours; or
+ *      plain BGK (Eq. 5) at the same rate when requested;
  *   4. perturbation (Eq. 9): add sum_k (A_k/2)|F| [w_i (F.c_i)^2/|F|^2 - B_i];
  *   5. recolouring (Eq. 10) of the total f_i into the two colours;
  *   6. streaming (Eq. 1) in push form with the boundary rules below.
  *
  * Readings where the paper is silent (all listed in the design notes):
+ *   - one relaxation time per node: Eq. (5) gives each component its own
+ *     rate and Eq. (11) a single tau; a node holding both colours relaxes
+ *     at tau = nu / c_s^2 + 1/2 with 1/nu = sum_k (rho^k / rho) / nu_k and
+ *     nu_k = c_s^2 (tau_k - 1/2) (the harmonic mean of the component
+ *     viscosities; the pure components keep their own tau_k);
  *   - B_i = w_i (|c_i|^2 - (D-1) c_s^2), which makes the perturbation
  *     mass-conserving with a traceless-in-the-normal stress;
  *   - D3Q19 phi_i^k: rest alpha_k, moving (1 - alpha_k) w_i / (1 - w_0),
@@ -348,39 +354,41 @@ static void collide(const orc_params *p, const lat_t *L, const double *fin, cons
     double u[3];
     for (int a = 0; a < 3; ++a) u[a] = j[a] / rho;
 
-    /* Step 3: per-colour relaxation. */
+    /* Step 3: relaxation at the node's rate; the colour equilibria are
+     * summed, so only the total momentum flux enters. */
+    double inv_nu = 0.0;
+    for (int k = 0; k < 2; ++k) inv_nu += (rho_k[k] / rho) / (CS2 * (p->tau[k] - 0.5));
+    const double omega = 1.0 / (1.0 / (CS2 * inv_nu) + 0.5);
+    double feq_sum[QMAX];
+    for (int i = 0; i < Q; ++i)
+        feq_sum[i] = feq(L, i, rho_k[0], alpha[0], u) + feq(L, i, rho_k[1], alpha[1], u);
     double f1[QMAX];
-    for (int i = 0; i < Q; ++i) f1[i] = 0.0;
-    for (int k = 0; k < 2; ++k) {
-        const double *fk = fin + k * Q;
-        const double omega = 1.0 / p->tau[k];
-        if (p->collision == ORC_BGK) {
-            /* Eq. (5). */
-            for (int i = 0; i < Q; ++i) {
-                double e = feq(L, i, rho_k[k], alpha[k], u);
-                f1[i] += fk[i] - omega * (fk[i] - e);
+    if (p->collision == ORC_BGK) {
+        /* Eq. (5) on the total population. */
+        for (int i = 0; i < Q; ++i) {
+            const double f = fin[i] + fin[Q + i];
+            f1[i] = f - omega * (f - feq_sum[i]);
+        }
+    } else {
+        /* Eq. (11): keep only rho^k, u and the momentum flux.  Pi^{neq} =
+         * sum_i f_i c_i c_i - sum_k rho^k (phat_k I + u u), the equilibrium
+         * flux of Eq. (6) summed over the colours. */
+        const double phat[2] = {phat_of(L, alpha[0]), phat_of(L, alpha[1])};
+        double Pi[3][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
+        for (int a = 0; a < L->D; ++a)
+            for (int b = 0; b < L->D; ++b) {
+                double s = 0.0;
+                for (int i = 0; i < Q; ++i) s += (fin[i] + fin[Q + i]) * L->c[i][a] * L->c[i][b];
+                for (int k = 0; k < 2; ++k) s -= rho_k[k] * ((a == b ? phat[k] : 0.0) + u[a] * u[b]);
+                Pi[a][b] = s;
             }
-        } else {
-            /* Eq. (11): keep only rho^k, u and the momentum flux.  Pi^{k,neq} =
-             * sum_i f_i^k c_i c_i - rho^k (phat_k I + u u), the equilibrium
-             * flux of Eq. (6). */
-            const double phat = phat_of(L, alpha[k]);
-            double Pi[3][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
+        for (int i = 0; i < Q; ++i) {
+            /* (c_i c_i - c_s^2 I) : Pi^{neq} */
+            double qpi = 0.0;
             for (int a = 0; a < L->D; ++a)
-                for (int b = 0; b < L->D; ++b) {
-                    double s = 0.0;
-                    for (int i = 0; i < Q; ++i) s += fk[i] * L->c[i][a] * L->c[i][b];
-                    Pi[a][b] = s - rho_k[k] * ((a == b ? phat : 0.0) + u[a] * u[b]);
-                }
-            for (int i = 0; i < Q; ++i) {
-                /* (c_i c_i - c_s^2 I) : Pi^{neq} */
-                double qpi = 0.0;
-                for (int a = 0; a < L->D; ++a)
-                    for (int b = 0; b < L->D; ++b)
-                        qpi += (L->c[i][a] * L->c[i][b] - (a == b ? CS2 : 0.0)) * Pi[a][b];
-                double e = feq(L, i, rho_k[k], alpha[k], u);
-                f1[i] += e + (1.0 - omega) * L->w[i] / (2.0 * CS2 * CS2) * qpi;
-            }
+                for (int b = 0; b < L->D; ++b)
+                    qpi += (L->c[i][a] * L->c[i][b] - (a == b ? CS2 : 0.0)) * Pi[a][b];
+            f1[i] = feq_sum[i] + (1.0 - omega) * L->w[i] / (2.0 * CS2 * CS2) * qpi;
         }
     }
 

@@ -42,7 +42,7 @@ typedef struct {
     int lattice;            /* ORC_D2Q9 or ORC_D3Q19 */
     int collision;          /* ORC_REGULARIZED or ORC_BGK */
     int nx, ny, nz;         /* nz = 1 for D2Q9 */
-    double tau[2];          /* relaxation times, Eq. (5): omega_k = 1/tau_k */
+    double tau[2];          /* relaxation times of the pure components, Eq. (5) */
     double A[2];            /* surface-tension parameters A_k, Eq. (9) */
     double alpha[2];        /* density-ratio parameters alpha_k, Eq. (7) */
     double beta;            /* recolouring parameter, Eq. (10) */

@@ -51,31 +51,24 @@ def test_moments_of_collision_and_perturbation(orc, lat, collision):
         u = j / rho
         # per-colour mass after recolouring (Eq. (10) with Eq. (2))
         assert np.allclose(post.sum(1), rk, rtol=0, atol=1e-15)
-        # total momentum (Eq. (3)): kept by the regularized relaxation, the
-        # perturbation and the recolouring.  Per-colour BGK (Eq. (5)) relaxes
-        # each colour's own momentum j^k towards rho^k u, which changes the
-        # total when tau_R != tau_B.
-        j_post = j.copy()
-        if collision == "bgk":
-            for k in range(2):
-                j_post -= (1 / tau[k]) * (fin[k] @ c - rk[k] * u)
-            assert np.abs(j_post - j).max() > 1e-6
-        assert np.allclose(np.einsum("ki,ia->a", post, c), j_post, atol=1e-15)
+        # total momentum (Eq. (3)): kept by the relaxation (one rate per
+        # node, both forms), the perturbation and the recolouring.
+        assert np.allclose(np.einsum("ki,ia->a", post, c), j, atol=1e-15)
         assert np.isclose(f2.sum(), rho, atol=1e-15)
-        assert np.allclose(f2 @ c, j_post, atol=1e-15)
+        assert np.allclose(f2 @ c, j, atol=1e-15)
         # second moment: relaxed momentum flux plus the perturbation stress
         # -2 Abar c_s^4 |F| (I - n n), Abar = sum_k A_k / 2
         Fn = np.linalg.norm(F)
         n = F / Fn
         I = np.eye(3)
         I[D:, D:] = 0
-        expect = np.zeros((3, 3))
-        for k in range(2):
-            ph = _phat(lat, w0)
-            Pi_eq = rk[k] * (ph * I + np.outer(u, u))
-            Pi = np.einsum("i,ia,ib->ab", fin[k], c, c)
-            om = 1 / tau[k]
-            expect += Pi_eq + (1 - om) * (Pi - Pi_eq)
+        # the node relaxes at the mixture viscosity, the harmonic mean of
+        # nu_k = (tau_k - 1/2)/3 weighted by the colour fractions
+        nu = 1 / sum(rk[k] / rho / ((tau[k] - 0.5) / 3) for k in range(2))
+        om = 1 / (3 * nu + 0.5)
+        Pi_eq = rho * (_phat(lat, w0) * I + np.outer(u, u))
+        Pi = np.einsum("ki,ia,ib->ab", fin, c, c)
+        expect = Pi_eq + (1 - om) * (Pi - Pi_eq)
         Abar = 0.5 * (A[0] + A[1])
         expect += -2 * Abar * CS2 ** 2 * Fn * (I - np.outer(n, n))
         assert np.allclose(np.einsum("i,ia,ib->ab", f2, c, c), expect, atol=2e-15)
@@ -165,3 +158,27 @@ def test_single_phase_and_zero_gradient(orc, lat):
         post, f2 = o.collide_node(fin, np.zeros(3))
         rk = fin.sum(1)
         assert np.allclose(post[0], rk[0] / rk.sum() * f2, atol=1e-17)
+
+
+@pytest.mark.parametrize("lat", ["D2Q9", "D3Q19"])
+@pytest.mark.parametrize("collision", ["reg", "bgk"])
+def test_pure_components_relax_at_their_own_rate(orc, lat, collision):
+    # A node holding one colour only relaxes its momentum flux by exactly
+    # 1 - 1/tau_k of that component (the mixture rule reduces to tau_k).
+    rng = np.random.default_rng(13)
+    tau = (1.3, 0.7)
+    o, t, D = _setup(orc, lat, tau, collision=orc.BGK if collision == "bgk" else orc.REGULARIZED)
+    c = t["c"].astype(float)
+    w0 = t["w"][0]
+    I = np.eye(3)
+    I[D:, D:] = 0
+    for k in range(2):
+        fin, _ = _random_node(rng, t, D)
+        fin[1 - k] = 0.0
+        post, _ = o.collide_node(fin, np.zeros(3))
+        rho = fin.sum()
+        u = fin[k] @ c / rho
+        Pi_eq = rho * (_phat(lat, w0) * I + np.outer(u, u))
+        Pi = np.einsum("i,ia,ib->ab", fin[k], c, c)
+        got = np.einsum("i,ia,ib->ab", post[k], c, c)
+        assert np.allclose(got, Pi_eq + (1 - 1 / tau[k]) * (Pi - Pi_eq), atol=2e-15)

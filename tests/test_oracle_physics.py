@@ -214,3 +214,61 @@ def test_interface_width(orc):
     x10 = np.interp(0.1, frac[::-1], x[::-1])
     width = x10 - x90
     assert 0.4 * g["value"] < width < 1.6 * g["value"]
+
+
+def _interface_radii(psi, centre, angles, rmax):
+    # distance from the centre to psi = 0 along each ray (bilinear samples)
+    r = np.linspace(1.0, rmax, int(rmax * 100))
+    out = []
+    for th in angles:
+        x, y = centre[0] + r * np.cos(th), centre[1] + r * np.sin(th)
+        x0, y0 = np.floor(x).astype(int), np.floor(y).astype(int)
+        fx, fy = x - x0, y - y0
+        v = (psi[y0, x0] * (1 - fx) * (1 - fy) + psi[y0, x0 + 1] * fx * (1 - fy)
+             + psi[y0 + 1, x0] * (1 - fx) * fy + psi[y0 + 1, x0 + 1] * fx * fy)
+        out.append(np.interp(0.0, -v, r))
+    return np.array(out)
+
+
+def test_regularized_droplet_stays_round(orc):
+    # Fig. 1: a resting droplet with relaxation time 5 inside and 1 outside.
+    # The regularized collision (Eq. (11)) keeps it round and its spurious
+    # currents well below those of plain BGK (Eq. (5)), whose droplet turns
+    # anisotropic.  The paper reports roughly an order of magnitude between
+    # the currents; this reading of the scheme gives 3-5x across A and beta
+    # (steady after ~1000 steps), so the pin asks for 2.5x.
+    w = W.static_droplet_2d(n=64, R=16.0, noise=0.0)
+    w.tau_R, w.tau_B = 5.0, 1.0
+    umax, spread = {}, {}
+    angles = np.linspace(0.0, np.pi / 4, 10)
+    for coll in (orc.REGULARIZED, orc.BGK):
+        f = oracle_for(orc, w, threads=8, collision=coll).step(1000).fields()
+        umax[coll] = float(np.sqrt((f["u"] ** 2).sum(0)).max())
+        r = _interface_radii(f["psi"][0], (31.5, 31.5), angles, 28.0)
+        spread[coll] = r.max() - r.min()
+        assert abs(r.mean() - 16.0) < 0.2
+    assert umax[orc.BGK] > 2.5 * umax[orc.REGULARIZED] > 0
+    assert spread[orc.REGULARIZED] < 0.03 and spread[orc.BGK] > 0.05
+
+
+def test_mixture_viscosity_is_harmonic_mean(orc):
+    # A uniform mixture (rho^R/rho = 1/4, tau_R = 2, tau_B = 0.6) carries no
+    # colour gradient, so a shear wave in it decays at the node's viscosity:
+    # 1/nu = (1/4)/nu_R + (3/4)/nu_B with nu_k = c_s^2 (tau_k - 1/2).  A rate
+    # per colour, or a mean of tau or of 1/tau, gives 0.075 or more.
+    L, U = 64, 1e-4
+    y = np.arange(L)
+    u = np.zeros((3, 1, L, 2))
+    u[0] = U * np.sin(2 * np.pi * y / L)[None, :, None]
+    w = W.Workload("shear_mix", "D2Q9", (2, L, 1), np.full((1, L, 2), 0.25), np.full((1, L, 2), 0.75), u,
+                   2.0, 0.6, 0.01, 0.7)
+    o = oracle_for(orc, w)
+    k = 2 * np.pi / L
+    nu_th = 1 / (0.25 / (1.5 / 3) + 0.75 / (0.1 / 3))
+    T = int(round(np.log(2) / (nu_th * k * k)))
+    amp = lambda: (o.fields()["u"][0, 0, :, 0] * np.sin(k * y)).sum() * 2 / L
+    o.step(20)
+    a0 = amp()
+    o.step(T)
+    nu = -np.log(amp() / a0) / (k * k * T)
+    assert abs(nu / nu_th - 1) < 0.01
