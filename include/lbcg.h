@@ -100,8 +100,10 @@ typedef struct {
     int32_t kernel;      /* LBCG_KERNEL_* */
     int64_t dims[3];     /* nx, ny, nz (nz = 1 for D2Q9); each >= 1 */
     const uint8_t *mask; /* host, nx*ny*nz codes; NULL = every node fluid */
-    double tau_R;        /* relaxation time of colour R (Eq. (5)), > 1/2 */
-    double tau_B;        /* relaxation time of colour B, > 1/2 */
+    double tau_R;        /* relaxation time of pure colour R (Eq. (5)), > 1/2 */
+    double tau_B;        /* relaxation time of pure colour B, > 1/2; a node
+                            holding both relaxes at tau = 3 nu + 1/2 with
+                            1/nu = sum_k (rho^k/rho) / nu_k, nu_k = (tau_k - 1/2)/3 */
     double A_R;          /* surface-tension parameter A_R (Eq. (9)) */
     double A_B;          /* surface-tension parameter A_B (Eq. (9)) */
     double beta;         /* recolouring parameter (Eq. (10)), in [0, 1] */

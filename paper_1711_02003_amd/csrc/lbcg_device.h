@@ -91,7 +91,7 @@ struct DevOutlet {
 // Scalars of the model in the compute type T, built once per launch.
 template <typename T>
 struct Model {
-    T omR, omB;      // 1/tau_k
+    T ivR, ivB;      // 1/nu_k = 1/(c_s^2 (tau_k - 1/2)), component viscosities
     T Abar;          // (A_R + A_B)/2: the perturbations of both colours summed
     T beta;
     T aR, aB;        // alpha_k (Eq. (7)); w_0 for equal densities
@@ -449,8 +449,8 @@ __device__ __forceinline__ T psi_of(T drho, T r36R, T r36B) {
 }
 
 // Moments of one node: densities, total momentum (Eq. (3)) and the
-// trace-adjusted momentum fluxes sum_i f_i Q_i and sum_i f_i^R Q_i with
-// Q_i = c_i c_i - I/3 (components xx, yy, zz, xy, xz, yz).  The flux sums use
+// trace-adjusted momentum flux sum_i f_i Q_i with Q_i = c_i c_i - I/3
+// (components xx, yy, zz, xy, xz, yz).  The flux sum uses
 // sum_i g_i (c_ia^2 - 1/3) = sum_{c_ia != 0} g_i - (1/3) sum_i g_i.
 template <typename T>
 struct Mom {
@@ -458,13 +458,12 @@ struct Mom {
     T r36R, r36B;  // 36 x rho^R, 36 x rho^B
     T j[3];
     T S[6];
-    T PR[6];
 };
 
 template <class L, typename T>
 __device__ __forceinline__ void moments(const Pops<L, T> &p, Mom<T> &m) {
     T drho = 0, Ra = 0, Ba = 0;
-    T jd[3] = {0, 0, 0}, Sd[3] = {0, 0, 0}, So[3] = {0, 0, 0}, Rd[3] = {0, 0, 0}, Ro[3] = {0, 0, 0};
+    T jd[3] = {0, 0, 0}, Sd[3] = {0, 0, 0}, So[3] = {0, 0, 0};
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) {
         T r36, b36;
@@ -479,16 +478,12 @@ __device__ __forceinline__ void moments(const Pops<L, T> &p, Mom<T> &m) {
             if (c[a]) {
                 jd[a] += c[a] > 0 ? d : -d;
                 Sd[a] += d;
-                Rd[a] += r36;
             }
         }
         const int off[3] = {c[0] * c[1], c[0] * c[2], c[1] * c[2]};
 #pragma unroll
         for (int b = 0; b < (L::D == 3 ? 3 : 1); ++b) {
-            if (off[b]) {
-                So[b] += off[b] > 0 ? d : -d;
-                Ro[b] += off[b] > 0 ? r36 : -r36;
-            }
+            if (off[b]) So[b] += off[b] > 0 ? d : -d;
         }
     }
     const uint32_t all = (1u << L::Q) - 2u;
@@ -500,26 +495,11 @@ __device__ __forceinline__ void moments(const Pops<L, T> &p, Mom<T> &m) {
     for (int a = 0; a < 3; ++a) m.j[a] = jd[a];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        if (a < L::D) {
-            // sum_{red} 36 w (3 c_a^2 - 1) = 3 sum_{red, c_a != 0} 36 w - K
-            const int Ka = 3 * w36_sum<L>(p.red, dir_mask<L>(a, 0), dir_mask<L>(a, 1), false) - K;
-            m.S[a] = Sd[a] - drho * T(1.0 / 3.0);
-            m.PR[a] = (T(Ka) + (T(3) * Rd[a] - Ra)) * T(1.0 / 108.0);
-        } else {
-            m.S[a] = T(0);
-            m.PR[a] = T(0);
-        }
+        m.S[a] = a < L::D ? Sd[a] - drho * T(1.0 / 3.0) : T(0);
     }
 #pragma unroll
     for (int b = 0; b < 3; ++b) {
-        if (b == 0 || L::D == 3) {
-            const int Kb = popc(p.red & dir_mask<L>(b, 2)) - popc(p.red & dir_mask<L>(b, 3));
-            m.S[3 + b] = So[b];
-            m.PR[3 + b] = (T(Kb) + Ro[b]) * T(1.0 / 36.0);
-        } else {
-            m.S[3 + b] = T(0);
-            m.PR[3 + b] = T(0);
-        }
+        m.S[3 + b] = (b == 0 || L::D == 3) ? So[b] : T(0);
     }
 }
 
@@ -672,25 +652,17 @@ struct PostOut {
     uint32_t red;
 };
 
-// The part of N = sum_k (1 - omega_k) Pi^{k,neq} that comes straight from
-// the populations: G = (1 - omega_B) sum_i f_i Q_i + (omega_B - omega_R)
-// sum_i f_i^R Q_i.  A node carries only (drho, rho^R, rho^B, j, G) into
-// collide.
-template <typename T>
-__device__ __forceinline__ void fold_flux(const Model<T> &mo, const Mom<T> &m, T G[6]) {
-    const T gR = T(1) - mo.omR, gB = T(1) - mo.omB;
-#pragma unroll
-    for (int q = 0; q < 6; ++q) G[q] = gB * m.S[q] + (gR - gB) * m.PR[q];
-}
-
 // Collision (Eq. (11), or Eq. (5) with bgk), perturbation (Eq. (9)) and
 // recolouring (Eq. (10)) from the node's density deviation, colour
-// densities, momentum, folded flux G, colour gradient F and - for plain BGK
-// only - its populations.  Opposite directions i and -i share every even term
-// (weights, Q_i, (c.u)^2, (F.c)^2, B_i, phi_i) and flip the odd ones (c.u,
-// cos), so the update is computed once per pair.
+// densities, momentum, trace-adjusted flux S, colour gradient F and - for
+// plain BGK only - its populations.  The node relaxes at one rate
+// omega = 1/tau, tau = nu/c_s^2 + 1/2, from the mixture viscosity
+// 1/nu = sum_k (rho^k/rho)/nu_k; with s = 1/nu that is omega = 2s/(s + 6).
+// Opposite directions i and -i share every even term (weights, Q_i, (c.u)^2,
+// (F.c)^2, B_i, phi_i) and flip the odd ones (c.u, cos), so the update is
+// computed once per pair.
 template <class L, typename T>
-__device__ __forceinline__ void collide(const Model<T> &mo, T drho, T r36R, T r36B, const T j[3], const T G[6],
+__device__ __forceinline__ void collide(const Model<T> &mo, T drho, T r36R, T r36B, const T j[3], const T S[6],
                                         const T F[3], const Pops<L, T> *pin, PostOut<L, T> &o) {
     const T rho = T(1) + drho;
     const T rR = r36R * T(1.0 / 36.0), rB = r36B * T(1.0 / 36.0);
@@ -698,15 +670,26 @@ __device__ __forceinline__ void collide(const Model<T> &mo, T drho, T r36R, T r3
     const T ux = j[0] * inv_rho, uy = j[1] * inv_rho, uz = j[2] * inv_rho;
     const T usq = ux * ux + uy * uy + uz * uz;
     const T pR = phat<L, T>(mo.aR), pB = phat<L, T>(mo.aB);
-    // N in Q form: Pi^{k,neq} = sum_i f_i^k c c - rho^k (phat_k I + u u)
-    //     = sum_i f_i^k Q_i + rho^k (1/3 - phat_k) I - rho^k u u.
-    const T gR = T(1) - mo.omR, gB = T(1) - mo.omB;
-    const T cw = gR * rR + gB * rB;
-    const T iso = gR * rR * (T(1.0 / 3.0) - pR) + gB * rB * (T(1.0 / 3.0) - pB);
+    // colour shares rho^k / rho, the minority one formed directly (exactly 0 in
+    // the other colour's bulk) with one correctly rounded division: a rounded
+    // constant or an approximate reciprocal would err to one side and bias
+    // colour mass through the recolouring.  rec_i / f_i may use the refined
+    // reciprocal: rec is odd in i, so a common error cancels between i and -i.
+    const T r36 = rho36<T>(drho);
+    const bool redmaj = r36R >= r36B;
+    const T sB = redmaj ? r36B / r36 : T(1) - r36R / r36;
+    const T sR = redmaj ? T(1) - sB : r36R / r36;
+    const T sv = sR * mo.ivR + sB * mo.ivB;
+    const T om = T(2) * sv * rcp<T>(sv + T(6));
+    const T gm = T(1) - om;
+    // N = (1 - omega) Pi^neq in Q form: Pi^neq = sum_i f_i c c -
+    // sum_k rho^k (phat_k I + u u) = S + sum_k rho^k (1/3 - phat_k) I - rho u u.
+    const T cw = gm * rho;
+    const T iso = gm * (rR * (T(1.0 / 3.0) - pR) + rB * (T(1.0 / 3.0) - pB));
     T N[6];
     const T uu[6] = {ux * ux, uy * uy, uz * uz, ux * uy, ux * uz, uy * uz};
 #pragma unroll
-    for (int q = 0; q < 6; ++q) N[q] = G[q] - cw * uu[q];
+    for (int q = 0; q < 6; ++q) N[q] = gm * S[q] - cw * uu[q];
     N[0] += iso;
     N[1] += iso;
     if (L::D == 3) N[2] += iso;
@@ -717,15 +700,6 @@ __device__ __forceinline__ void collide(const Model<T> &mo, T drho, T r36R, T r3
     const bool hasF = Fn > mo.eps_F;
     const T invFn = hasF ? rcp<T>(Fn) : T(0);
     const T seg = mo.beta * rR * rB * inv_rho * inv_rho;
-    // colour shares rho^k / rho, the minority one formed directly (exactly 0 in
-    // the other colour's bulk) with one correctly rounded division: a rounded
-    // constant or an approximate reciprocal would err to one side and bias
-    // colour mass through the recolouring.  rec_i / f_i may use the refined
-    // reciprocal: rec is odd in i, so a common error cancels between i and -i.
-    const T r36 = rho36<T>(drho);
-    const bool redmaj = r36R >= r36B;
-    const T sB = redmaj ? r36B / r36 : T(1) - r36R / r36;
-    const T sR = redmaj ? T(1) - sB : r36R / r36;
     const T wrho = rho * T(1.5) * usq;  // rho u^2 / (2 c_s^2)
     o.red = 0;
 
@@ -735,6 +709,11 @@ __device__ __forceinline__ void collide(const Model<T> &mo, T drho, T r36R, T r3
         const int ib = L::opp[i];
         const T w = T(wgt<L>(i));
         const T cx = T(L::cx[i]), cy = T(L::cy[i]), cz = T(L::cz[i]);
+        // the odd parts are formed from the momentum itself (rho c.u = c.j):
+        // a rounded velocity would change the node's momentum by a relative
+        // ulp per step, in the same direction every step, and so drift the
+        // total momentum of a box
+        const T cj = cx * j[0] + cy * j[1] + cz * j[2];
         const T cu = cx * ux + cy * uy + cz * uz;
         const T dpR = dphi<L, T>(i, mo.dR0, mo.kR), dpB = dphi<L, T>(i, mo.dB0, mo.kB);
         T ev, od;  // even and odd parts of the new total deviation of direction i
@@ -744,17 +723,17 @@ __device__ __forceinline__ void collide(const Model<T> &mo, T drho, T r36R, T r3
             qn += T(2) * cx * cy * N[3];
             if (L::D == 3) qn += T(2) * (cx * cz * N[4] + cy * cz * N[5]);
             // sum_k rho^k phi_i^k - w_i  +  w_i rho U  +  w_i/(2 c_s^4) Q_i : N
-            ev = w * drho + rR * dpR + rB * dpB + w * (T(4.5) * rho * cu * cu - wrho) + T(4.5) * w * qn;
-            od = T(3) * w * rho * cu;
+            ev = w * drho + rR * dpR + rB * dpB + w * (T(4.5) * cj * cu - wrho) + T(4.5) * w * qn;
+            od = T(3) * w * cj;
         } else {
-            // sum_k [(1 - omega_k) f_i^k + omega_k f_i^{k,eq}] - w_i, split into
-            // the parts even and odd under i <-> -i (the populations themselves
+            // (1 - omega) f_i + omega sum_k f_i^{k,eq} - w_i, split into the
+            // parts even and odd under i <-> -i (the populations themselves
             // have no symmetry, so both directions are formed here).
             const T U2 = T(4.5) * cu * cu - T(1.5) * usq;
-            const T base = -mo.omB * w + mo.omR * rR * (w + dpR + w * U2) + mo.omB * rB * (w + dpB + w * U2);
-            const T lin = (mo.omR * rR + mo.omB * rB) * w * T(3) * cu;
-            const T di = gB * pin->df[i] + (gR - gB) * pin->fred(i);
-            const T db = gB * pin->df[ib] + (gR - gB) * pin->fred(ib);
+            const T base = -om * w + om * (rR * (w + dpR + w * U2) + rB * (w + dpB + w * U2));
+            const T lin = om * w * T(3) * cj;
+            const T di = gm * pin->df[i];
+            const T db = gm * pin->df[ib];
             ev = base + T(0.5) * (di + db);
             od = lin + T(0.5) * (di - db);
         }

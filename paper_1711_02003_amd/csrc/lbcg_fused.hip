@@ -6,8 +6,8 @@
 // a column tile of 64 x R nodes (one wave per row) and sweeps a chunk of z
 // planes.  For plane z+1 it pulls the 19 populations of its nodes (Eq. (1);
 // each one a (total deviation, colour share) pair), keeps only the 12
-// scalars the collision needs (drho, 36 rho^R, 36 rho^B, j, folded momentum
-// flux G), and writes psi of the tile plus a one-node ring (the ring
+// scalars the collision needs (drho, 36 rho^R, 36 rho^B, j, trace-adjusted
+// momentum flux S), and writes psi of the tile plus a one-node ring (the ring
 // recomputes the neighbours' densities from cache) into a 5-slot LDS ring
 // buffer.  After one barrier it collides plane z with the gradient taken from
 // the LDS planes z-1, z, z+1 and stores the 19 new pairs coalesced, with
@@ -292,7 +292,7 @@ __device__ __forceinline__ void sweep(const FusedArgs<S> &a, const Model<T> &mo,
 
     // Interior: moments of plane z are carried in registers, the populations
     // of plane z+1 are in flight.
-    T cd = 0, cR = 0, cB = 0, cj[3] = {0, 0, 0}, cG[6] = {0, 0, 0, 0, 0, 0};
+    T cd = 0, cR = 0, cB = 0, cj[3] = {0, 0, 0}, cS[6] = {0, 0, 0, 0, 0, 0};
     bool cfl = false;
     Pending<S, T> pp;
     pp.lk = kLinkFluid;
@@ -312,8 +312,8 @@ __device__ __forceinline__ void sweep(const FusedArgs<S> &a, const Model<T> &mo,
         pp.take(q);
         settle(x, y, pz, pp.lk, q);
     };
-    // moments of the pulled interior plane into (d, r36R, r36B, j, G); returns psi
-    auto interior_moments = [&](T &d, T &r36R, T &r36B, T j[3], T G[6], bool &fl) -> float {
+    // moments of the pulled interior plane into (d, r36R, r36B, j, flux); returns psi
+    auto interior_moments = [&](T &d, T &r36R, T &r36B, T j[3], T flux[6], bool &fl) -> float {
         fl = fluid(pp.lk);
         if (!fl) return solid_psi(link_code(pp.lk));
         Pops<L, T> q;
@@ -326,7 +326,8 @@ __device__ __forceinline__ void sweep(const FusedArgs<S> &a, const Model<T> &mo,
         j[0] = m.j[0];
         j[1] = m.j[1];
         j[2] = m.j[2];
-        fold_flux<T>(mo, m, G);
+#pragma unroll
+        for (int q = 0; q < 6; ++q) flux[q] = m.S[q];
         return float(psi_of<T>(m.drho, m.r36R, m.r36B));
     };
 
@@ -350,7 +351,7 @@ __device__ __forceinline__ void sweep(const FusedArgs<S> &a, const Model<T> &mo,
     ring_finish(z0 - 1);
     ring_issue(z0);
     interior_issue(z0);
-    if (intile) slot_of(z0)[(row + 1) * W + lane + 1] = interior_moments(cd, cR, cB, cj, cG, cfl);
+    if (intile) slot_of(z0)[(row + 1) * W + lane + 1] = interior_moments(cd, cR, cB, cj, cS, cfl);
     ring_finish(z0);
     ring_issue(z0 + 1);
     interior_issue(z0 + 1);
@@ -379,14 +380,14 @@ __device__ __forceinline__ void sweep(const FusedArgs<S> &a, const Model<T> &mo,
 
     for (int z = z0; z < z1; ++z) {
         const bool more = z + 2 <= z1;  // uniform over the block
-        T nd = 0, nR = 0, nB = 0, nj[3] = {0, 0, 0}, nG[6] = {0, 0, 0, 0, 0, 0};
+        T nd = 0, nR = 0, nB = 0, nj[3] = {0, 0, 0}, nS[6] = {0, 0, 0, 0, 0, 0};
         bool nfl = false;
         // plane z+1: its ring and interior populations were requested one
         // iteration ago.  Wait for everything outstanding here, on every
         // path, so that no later use waits for the loads issued below.
         wait_memory();
         ring_finish(z + 1);
-        if (intile) slot_of(z + 1)[(row + 1) * W + lane + 1] = interior_moments(nd, nR, nB, nj, nG, nfl);
+        if (intile) slot_of(z + 1)[(row + 1) * W + lane + 1] = interior_moments(nd, nR, nB, nj, nS, nfl);
         if (more) {
             ring_issue(z + 2);
             interior_issue(z + 2);
@@ -411,7 +412,7 @@ __device__ __forceinline__ void sweep(const FusedArgs<S> &a, const Model<T> &mo,
             }
             const T F[3] = {fx, fy, fz};
             PostOut<L, T> o;
-            collide<L, T>(mo, cd, cR, cB, cj, cG, F, nullptr, o);
+            collide<L, T>(mo, cd, cR, cB, cj, cS, F, nullptr, o);
             Dither dz(step, uint32_t(x) + uint32_t(a.nx) * (uint32_t(y) + uint32_t(a.ny) * uint32_t(z)));
 #pragma unroll
             for (int i = 0; i < L::Q; ++i) ov[i] = encode_step<L, S, T>(o.df[i], o.mm[i], (o.red >> i) & 1u, i, dz);
@@ -425,7 +426,7 @@ __device__ __forceinline__ void sweep(const FusedArgs<S> &a, const Model<T> &mo,
 #pragma unroll
         for (int q = 0; q < 3; ++q) cj[q] = nj[q];
 #pragma unroll
-        for (int q = 0; q < 6; ++q) cG[q] = nG[q];
+        for (int q = 0; q < 6; ++q) cS[q] = nS[q];
     }
     if (kDelayStores) flush();
 }

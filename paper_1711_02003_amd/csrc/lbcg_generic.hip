@@ -122,12 +122,10 @@ __global__ void __launch_bounds__(kBlock) k_step_generic(Geo g, Model<T> mo, con
     pull_node<L, S, T>(g, mo, in, x, y, z, n, pulled, p);
     Mom<T> m;
     moments<L, T>(p, m);
-    T G[6];
-    fold_flux<T>(mo, m, G);
     T F[3];
     gradient<L, T>(g, psi, x, y, z, n, F);
     PostOut<L, T> o;
-    collide<L, T>(mo, m.drho, m.r36R, m.r36B, m.j, G, F, &p, o);
+    collide<L, T>(mo, m.drho, m.r36R, m.r36B, m.j, m.S, F, &p, o);
     store_out<L, S, T>(out, g.pitch, n, o, step);
 }
 

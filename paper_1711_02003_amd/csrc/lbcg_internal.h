@@ -10,7 +10,7 @@ namespace lbcg {
 
 // Model parameters in double; launchers convert to the compute type.
 struct ModelD {
-    double omR, omB, Abar, beta, aR, aB, eps_F;
+    double ivR, ivB, Abar, beta, aR, aB, eps_F;  // ivR, ivB: 1/nu_k
     double w0;  // rest weight of the lattice
     int bgk;
 };
@@ -18,8 +18,8 @@ struct ModelD {
 template <typename T>
 inline Model<T> to_model(const ModelD &m) {
     Model<T> r;
-    r.omR = T(m.omR);
-    r.omB = T(m.omB);
+    r.ivR = T(m.ivR);
+    r.ivB = T(m.ivB);
     r.Abar = T(m.Abar);
     r.beta = T(m.beta);
     r.aR = T(m.aR);

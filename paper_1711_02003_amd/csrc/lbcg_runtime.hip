@@ -272,8 +272,8 @@ int lbcg_create(const lbcg_params *p, void *dev_buf, size_t bytes, void *hip_str
     s->g.N = pl.N;
     s->g.pitch = pl.pitch;
     const double w0 = p->lattice == LBCG_D2Q9 ? 4.0 / 9.0 : 1.0 / 3.0;
-    s->md.omR = 1.0 / p->tau_R;
-    s->md.omB = 1.0 / p->tau_B;
+    s->md.ivR = 3.0 / (p->tau_R - 0.5);  // 1/nu_k, nu_k = c_s^2 (tau_k - 1/2)
+    s->md.ivB = 3.0 / (p->tau_B - 0.5);
     s->md.Abar = 0.5 * (p->A_R + p->A_B);
     s->md.beta = p->beta;
     s->md.aR = p->alpha_R > 0.0 ? p->alpha_R : w0;

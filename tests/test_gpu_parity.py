@@ -115,6 +115,29 @@ def test_config1_f64(L, orc):
     assert d1["p_in"] > d1["p_out"]
 
 
+@pytest.mark.parametrize("coll", ["reg", "bgk"])
+def test_fig1_droplet_viscosity_contrast_f64(L, orc, coll):
+    # Resting D2Q9 droplet with relaxation time 5 inside and 1 outside (the
+    # Fig. 1 set-up), both collision forms: every node relaxes at the rate of
+    # its mixture viscosity.  1e-12 after 100 steps, then the velocity field
+    # of step 1000 against the oracle's.
+    w = W.static_droplet_2d(n=64, R=16.0, noise=0.0)
+    w.tau_R, w.tau_B = 5.0, 1.0
+    _say(f"fig1 droplet f64 {coll}")
+    s = L.Sim.from_workload(w, precision="f64", kernel=L.KERNEL_GENERIC,
+                            collision=L.BGK if coll == "bgk" else L.REGULARIZED)
+    o = oracle_for(orc, w, threads=8, collision=orc.BGK if coll == "bgk" else orc.REGULARIZED)
+    s.step(100)
+    o.step(100)
+    assert _maxrel(s.populations(), o.populations()) < 1e-12
+    s.step(900)
+    o.step(900)
+    g, f = s.fields(), o.fields()
+    d = float(np.abs(g["u"] - f["u"]).max() / np.abs(f["u"]).max())
+    _say(f"  step 1000 max|u| {np.abs(g['u']).max():.3e}, max rel diff {d:.2e}")
+    assert d < 1e-9
+
+
 def test_fused_f32_config2_recipe_1000_steps(L, orc):
     # The 27-droplet recipe at 48^3 (tau_R = 1, tau_B = 0.6, A = 0.005):
     # FP32 fused kernel vs FP64 oracle after 1000 steps.
