@@ -74,6 +74,24 @@ template <class L>
 __host__ __device__ constexpr double bcoef(int i) {
     return wgt<L>(i) * (double(csq<L>(i)) - double(L::D - 1) / 3.0);
 }
+// 3 w_i in the compute type, for the odd part 3 w_i c_i.j of the new
+// populations.  The rounded constants are chosen so that sum_i 3 w_i c_i c_i
+// is exactly I in type T: D3Q19 needs 2 a + 8 b = 1 (a axis, b diagonal),
+// D2Q9 2 a + 4 b = 1, and one constant is the correctly rounded 1/12 or 1/3
+// while the other is derived from it exactly (Sterbenz).  With plain rounded
+// constants both round up for FP32, and every node's momentum would grow by
+// 3e-8 per step.
+template <class L, typename T>
+__host__ __device__ constexpr T odd_coef(int i) {
+    if (L::D == 3) {
+        constexpr T b = T(1) / T(12);
+        constexpr T a = (T(1) - T(8) * b) * T(0.5);
+        return csq<L>(i) == 1 ? a : b;
+    }
+    constexpr T a = T(1) / T(3);
+    constexpr T b = (T(1) - T(2) * a) * T(0.25);
+    return csq<L>(i) == 1 ? a : b;
+}
 template <class L>
 __host__ __device__ constexpr double inv_len(int i) {
     return csq<L>(i) == 0 ? 0.0 : (csq<L>(i) == 1 ? 1.0 : 0.70710678118654752440);
@@ -724,14 +742,14 @@ __device__ __forceinline__ void collide(const Model<T> &mo, T drho, T r36R, T r3
             if (L::D == 3) qn += T(2) * (cx * cz * N[4] + cy * cz * N[5]);
             // sum_k rho^k phi_i^k - w_i  +  w_i rho U  +  w_i/(2 c_s^4) Q_i : N
             ev = w * drho + rR * dpR + rB * dpB + w * (T(4.5) * cj * cu - wrho) + T(4.5) * w * qn;
-            od = T(3) * w * cj;
+            od = odd_coef<L, T>(i) * cj;
         } else {
             // (1 - omega) f_i + omega sum_k f_i^{k,eq} - w_i, split into the
             // parts even and odd under i <-> -i (the populations themselves
             // have no symmetry, so both directions are formed here).
             const T U2 = T(4.5) * cu * cu - T(1.5) * usq;
             const T base = -om * w + om * (rR * (w + dpR + w * U2) + rB * (w + dpB + w * U2));
-            const T lin = om * w * T(3) * cj;
+            const T lin = om * (odd_coef<L, T>(i) * cj);
             const T di = gm * pin->df[i];
             const T db = gm * pin->df[ib];
             ev = base + T(0.5) * (di + db);
