@@ -720,10 +720,11 @@ __device__ __forceinline__ void collide(const Model<T> &mo, T drho, T r36R, T r3
     const T seg = mo.beta * rR * rB * inv_rho * inv_rho;
     const T wrho = rho * T(1.5) * usq;  // rho u^2 / (2 c_s^2)
     o.red = 0;
+    T dsum = T(0);  // sum of the new moving deviations
 
 #pragma unroll
-    for (int i = 0; i < L::Q; ++i) {
-        if (i != 0 && L::opp[i] < i) continue;  // handled with its partner
+    for (int i = 1; i < L::Q; ++i) {
+        if (L::opp[i] < i) continue;  // handled with its partner
         const int ib = L::opp[i];
         const T w = T(wgt<L>(i));
         const T cx = T(L::cx[i]), cy = T(L::cy[i]), cz = T(L::cz[i]);
@@ -773,15 +774,28 @@ __device__ __forceinline__ void collide(const Model<T> &mo, T drho, T r36R, T r3
         o.df[i] = d_i;
         o.mm[i] = m;
         o.red |= fl ? (1u << i) : 0u;
-        if (i != 0) {
-            const T d_b = ev - od;
-            const T f_b = w + d_b;
-            const T q_b = f_b != T(0) ? rec * rcp<T>(f_b) : T(0);
-            split_shares<T>(sR - q_b, sB + q_b, m, fl);
-            o.df[ib] = d_b;
-            o.mm[ib] = m;
-            o.red |= fl ? (1u << ib) : 0u;
-        }
+        const T d_b = ev - od;
+        const T f_b = w + d_b;
+        const T q_b = f_b != T(0) ? rec * rcp<T>(f_b) : T(0);
+        split_shares<T>(sR - q_b, sB + q_b, m, fl);
+        o.df[ib] = d_b;
+        o.mm[ib] = m;
+        o.red |= fl ? (1u << ib) : 0u;
+        dsum += d_i + d_b;
+    }
+    // The rest population is the remainder that keeps the node's mass: the
+    // relaxation, the perturbation and the recolouring all conserve it, so
+    // this is the same value in exact arithmetic, while rounded constants
+    // that should cancel (sum_i (phi_i - w_i), sum_i w_i Q_i : N with
+    // phat != 1/3) would otherwise add a small mass of one sign every step.
+    // Its recolouring term is zero (cos phi_0 = 0), so its share is rho^R/rho.
+    {
+        T m;
+        bool fl;
+        split_shares<T>(sR, sB, m, fl);
+        o.df[0] = drho - dsum;
+        o.mm[0] = m;
+        o.red |= fl ? 1u : 0u;
     }
 }
 

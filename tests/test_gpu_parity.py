@@ -92,6 +92,53 @@ def test_f64_bgk_density_ratio(L, orc):
     assert _maxrel(s.populations(), o.populations()) < 1e-12
 
 
+@pytest.mark.parametrize("lat,dims", [("D2Q9", (13, 9, 1)), ("D3Q19", (9, 7, 5))])
+def test_f64_regularized_density_ratio(L, orc, lat, dims):
+    # regularized collision with alpha_R != alpha_B (Eqs. (7), (8), (11)):
+    # the colour equilibria and pressures differ per colour
+    w = _random_workload(lat, dims, False, seed=sum(dims) + 7)
+    s = L.Sim(w.lattice, w.dims, w.tau_R, w.tau_B, w.A, w.beta, "f64", kernel=L.KERNEL_GENERIC,
+              alpha_R=0.55, alpha_B=0.25).init_fields(w.rhoR, w.rhoB, w.u)
+    p = oracle_params(orc, w)
+    p.alpha = (0.55, 0.25)
+    o = orc.Oracle(p).init(w.rhoR, w.rhoB, w.u)
+    s.step(100)
+    o.step(100)
+    assert _maxrel(s.populations(), o.populations()) < 1e-12
+
+
+def test_fused_f32_density_ratio_slab(L, orc):
+    # FP32 fused kernel, alpha_R = 0.55 (D3Q19: rho^R / rho^B settles at
+    # (1 - 1/3) / (1 - 0.55) across a flat interface): the bulk ratio after
+    # 10000 steps within 1e-5 of that and of the oracle's.
+    nx = 64
+    dims = (nx, 8, 4)
+    sh = (4, 8, nx)
+    psi = np.tanh((16 - np.abs(np.arange(nx) + 0.5 - 32)) / 2.0)
+    psi = np.broadcast_to(psi, sh).copy()
+    w = W.Workload("slab", "D3Q19", dims, (1 + psi) / 2, (1 - psi) / 2, None, 0.8, 1.2, 0.01, 0.7)
+    _say("fused f32 density-ratio slab 64x8x4 x10000")
+    s = L.Sim(w.lattice, w.dims, w.tau_R, w.tau_B, w.A, w.beta, "f32", kernel=L.KERNEL_FUSED,
+              alpha_R=0.55).init_fields(w.rhoR, w.rhoB, w.u)
+    assert s.launch_info()["kernel"] == L.KERNEL_FUSED
+    p = oracle_params(orc, w)
+    p.alpha = (0.55, 0.0)
+    o = orc.Oracle(p).init(w.rhoR, w.rhoB, w.u)
+    s.step(10000)
+    o.step(10000)
+    g, f = s.fields(), o.fields()
+    target = (1 - 1 / 3) / (1 - 0.55)
+    rg = g["rhoR"][2, 4, 32] / g["rhoB"][2, 4, 0]
+    ro = f["rhoR"][2, 4, 32] / f["rhoB"][2, 4, 0]
+    _say(f"  ratio gpu {rg:.7f} oracle {ro:.7f} target {target:.7f}")
+    assert abs(rg / target - 1) < 1e-5
+    assert abs(rg / ro - 1) < 1e-5
+    # bulk densities on both sides (the interfaces themselves may sit ~1e-3
+    # apart: FP32 momentum round-off leaves a ~1e-7 drift velocity)
+    assert _maxrel(g["rhoR"][..., 26:38], f["rhoR"][..., 26:38]) < 1e-5
+    assert _maxrel(g["rhoB"][..., :6], f["rhoB"][..., :6]) < 1e-5
+
+
 def test_config1_f64(L, orc):
     # D2Q9 static droplet 64x64 (2000 steps): 1e-12 after 100 steps, then
     # per-colour mass conserved to round-off over the whole run (GPU FP64

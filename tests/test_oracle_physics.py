@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 
 from paper_1711_02003_amd import workloads as W
-from tests.helpers import oracle_for
+from tests.helpers import oracle_for, oracle_params
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")
 
@@ -272,3 +272,27 @@ def test_mixture_viscosity_is_harmonic_mean(orc):
     o.step(T)
     nu = -np.log(amp() / a0) / (k * k * T)
     assert abs(nu / nu_th - 1) < 0.01
+
+
+@pytest.mark.parametrize("lat,aR,aB", [("D2Q9", 0.6, 0.0), ("D2Q9", 0.3, 0.6), ("D3Q19", 0.55, 0.0)])
+def test_density_ratio_of_flat_interface(orc, lat, aR, aB):
+    # Eqs. (7)-(8): alpha_k sets the colour pressure p^k = rho^k phat_k, with
+    # phat_k = 3(1 - alpha_k)/5 (D2Q9) or (1 - alpha_k)/2 (D3Q19).  Across a
+    # flat interface the bulk pressures balance, so the bulk densities settle
+    # at rho^R / rho^B = (1 - alpha_B) / (1 - alpha_R) (alpha = 0 means w_0).
+    # Red slab of width 32 in a periodic box of 64, equal densities at start,
+    # tau_R = 0.8, tau_B = 1.2.
+    nx = 64
+    dims = (nx, 4, 1) if lat == "D2Q9" else (nx, 2, 2)
+    sh = (dims[2], dims[1], dims[0])
+    psi = np.tanh((16 - np.abs(np.arange(nx) + 0.5 - 32)) / 2.0)
+    psi = np.broadcast_to(psi, sh).copy()
+    w = W.Workload("slab", lat, dims, (1 + psi) / 2, (1 - psi) / 2, None, 0.8, 1.2, 0.01, 0.7)
+    p = oracle_params(orc, w)
+    p.alpha = (aR, aB)
+    f = orc.Oracle(p).init(w.rhoR, w.rhoB, w.u).step(10000).fields()
+    w0 = 4 / 9 if lat == "D2Q9" else 1 / 3
+    target = (1 - (aB or w0)) / (1 - (aR or w0))
+    ratio = f["rhoR"][0, 0, 32] / f["rhoB"][0, 0, 0]
+    assert abs(ratio / target - 1) < 1e-6
+    assert np.abs(f["u"]).max() < 1e-7
