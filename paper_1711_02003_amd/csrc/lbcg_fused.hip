@@ -26,10 +26,15 @@
 // neighbour contributes the centre node's psi to the gradient.
 //
 // Block -> work mapping (single lattice): work items (tile, z chunk) are
-// numbered tile-major and dealt to the 8 XCDs in contiguous bands matching the
-// round-robin dispatch of blocks to XCDs, so each XCD sweeps a compact band
-// of tiles and the ring re-reads mostly hit that XCD's L2.  The batched form
-// steps many lattices in one launch from a block -> (lattice, item) table.
+// numbered tile-major.  Periodic lattices deal them to the 8 XCDs in
+// contiguous bands matching the round-robin dispatch of blocks to XCDs, so
+// each XCD sweeps a compact band of tiles and the ring re-reads mostly hit
+// that XCD's L2.  With geometry the fluid is usually concentrated in a few
+// bands (a channel), so consecutive items go to consecutive XCDs instead:
+// XCD k gets the z chunks k, k + 8, ... of every tile, which spreads the
+// fluid evenly and still keeps each chunk's x-y neighbours on one XCD.  The
+// batched form steps many lattices in one launch from a block -> (lattice,
+// item) table, dealt the same two ways.
 #include "lbcg_internal.h"
 
 namespace lbcg {
@@ -182,6 +187,18 @@ __device__ __forceinline__ void sweep(const FusedArgs<S> &a, const Model<T> &mo,
     const bool intile = lane < tw && row < th;
     const int x = x0 + lane, y = y0 + row;
     const uint32_t step = *a.ctr_in;  // seeds the stochastic rounding of 16-bit shares
+
+    // With geometry, a chunk whose own nodes are all non-fluid has nothing to
+    // do: no fluid node reads a non-fluid node's state (its links are
+    // redirected to its own pairs), and the ring only feeds the gradients of
+    // the chunk's own fluid nodes.
+    if (MASKED) {
+        bool any = false;
+        if (intile)
+            for (int zz = z0; zz < z1 && !any; ++zz)
+                any = (a.links[int64_t(x) + int64_t(a.nx) * (int64_t(y) + int64_t(a.ny) * zz)] & kLinkFluid) != 0u;
+        if (!__syncthreads_or(any)) return;  // uniform over the block
+    }
 
     // ring node of this thread (at most one): rows -1 and th over x in [-1, tw],
     // then columns -1 and tw over y in [0, th)
@@ -431,28 +448,33 @@ __device__ __forceinline__ void sweep(const FusedArgs<S> &a, const Model<T> &mo,
     if (kDelayStores) flush();
 }
 
-// Single lattice, XCD-banded work mapping (see the file comment).
+// Block -> table or item index: XCD bands for periodic lattices, plain
+// order (consecutive indices on consecutive XCDs) with geometry.
+template <bool MASKED>
+__device__ __forceinline__ int work_index(int total) {
+    if (MASKED) return int(blockIdx.x);
+    const int xcd = blockIdx.x % kXCD, l = blockIdx.x / kXCD;
+    return xcd * (total / kXCD) + min(xcd, total % kXCD) + l;
+}
+
+// Single lattice (see the file comment for the work mapping).
 template <typename S, typename T, int R, bool MASKED>
 __global__ void __launch_bounds__(kTX * R) k_step_fused(FusedArgs<S> a, Model<T> mo) {
     extern __shared__ float lds[];
-    const int total = a.ntx * a.nty * a.zchunks;
-    const int xcd = blockIdx.x % kXCD, l = blockIdx.x / kXCD;
-    const int item = xcd * (total / kXCD) + min(xcd, total % kXCD) + l;
+    const int item = work_index<MASKED>(a.ntx * a.nty * a.zchunks);
     if (item == 0 && threadIdx.x == 0) *a.ctr_out = *a.ctr_in + 1u;
     sweep<S, T, R, MASKED>(a, mo, item / a.zchunks, item % a.zchunks, lds);
 }
 
 // Many lattices in one launch: the grid covers table entries [0, gridDim.x),
-// dealt to the XCDs in contiguous bands as above; entry k is work item
-// bitem[k] of lattice blat[k].
+// dealt to the XCDs as above; entry k is work item bitem[k] of lattice
+// blat[k].
 template <typename S, typename T, int R, bool MASKED>
 __global__ void __launch_bounds__(kTX * R)
     k_step_fused_batch(const BatchDesc<S> *__restrict__ desc, const int *__restrict__ blat,
                        const int *__restrict__ bitem) {
     extern __shared__ float lds[];
-    const int total = gridDim.x;
-    const int xcd = blockIdx.x % kXCD, l = blockIdx.x / kXCD;
-    const int k = xcd * (total / kXCD) + min(xcd, total % kXCD) + l;
+    const int k = work_index<MASKED>(int(gridDim.x));
     const int item = bitem[k];
     const BatchDesc<S> d = desc[blat[k]];
     if (item == 0 && threadIdx.x == 0) *d.a.ctr_out = *d.a.ctr_in + 1u;
