@@ -130,8 +130,8 @@ struct Geo {
 };
 
 // Link word of a node of a lattice with geometry, built on the host from the
-// mask so that a pull needs no per-direction mask reads.  Fluid node: bit i
-// (i < Q) set when the upstream node x - c_i is not fluid; kLinkFluid;
+// mask so that the boundary writes need no per-direction mask reads.  Fluid
+// node: bit i (i < Q) set when the upstream node x - c_i is not fluid; kLinkFluid;
 // kLinkBoundary when some upstream node is an inlet or outlet (plus
 // kLinkOutlet if one is an outlet); and the mask code shared by all its
 // non-fluid upstream nodes in bits 20..27, or kLinkMixed when they differ
@@ -141,6 +141,7 @@ constexpr uint32_t kLinkFluid = 1u << 19;
 constexpr uint32_t kLinkMixed = 1u << 28;
 constexpr uint32_t kLinkOutlet = 1u << 29;
 constexpr uint32_t kLinkBoundary = 1u << 30;
+constexpr uint32_t kLinkBits = (1u << 19) - 2u;  // the per-direction bits 1..18
 __host__ __device__ constexpr uint8_t link_code(uint32_t lk) { return uint8_t((lk >> 20) & 0xffu); }
 
 __device__ __forceinline__ int wrap_m1(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
@@ -540,26 +541,32 @@ __device__ __forceinline__ T phat(T alpha) {
 }
 
 // ---------------------------------------------------------------- pull
-// Density, red density and velocity of a node's own post-collision
-// populations (the outlet rule's inputs).
+// Boundary rules are applied when a fluid node stores its new state: for
+// every link i whose upstream node x - c_i is not fluid, the node writes the
+// value it will pull through that link at the next step into the upstream
+// node's slot of direction i.  Only this node ever reads that slot, so a pull
+// is a plain load on every link.  Wall: half-way bounce-back (the node's own
+// new pair of the opposite direction, copied as stored).  Inlet: moving-wall
+// bounce-back injecting the inlet's colour densities.  Outlet:
+// anti-bounce-back at the outlet density with the node's own red fraction
+// and velocity, taken from its stored new pairs.
+
+// Density, red density and velocity of a node's stored new pairs (the outlet
+// rule's inputs), with the arithmetic and summation order of densities() and
+// of the momentum sum.
 template <typename T>
 struct OwnMom {
     T rho, rR, u[3];
 };
-// One population at a time, in a rolled loop (the rule is needed only next
-// to outlets, and this keeps its registers few), with exactly the
-// arithmetic and summation order of densities() and of the momentum sum.
 template <class L, typename S, typename T>
-__device__ __forceinline__ OwnMom<T> own_moments(const Geo &g, const S *__restrict__ st, int64_t n) {
-    const typename PairOf<S>::type *a = reinterpret_cast<const typename PairOf<S>::type *>(st);
+__device__ __forceinline__ OwnMom<T> own_moments(const typename PairOf<S>::type *enc) {
     T drho = 0, Ra = 0, Ba = 0, jx = 0, jy = 0, jz = 0;
     int K = 0;
-#pragma unroll 1
+#pragma unroll
     for (int k = 0; k < L::Q; ++k) {
-        const typename PairOf<S>::type v = a[int64_t(k) * g.pitch + n];
         bool fl;
-        const T d = Codec<S>::template df<L, T>(v.x, k);
-        const T m = Codec<S>::template col<T>(v.y, fl);
+        const T d = Codec<S>::template df<L, T>(enc[k].x, k);
+        const T m = Codec<S>::template col<T>(enc[k].y, fl);
         const T mu = m * (T(w36<L>(k)) + T(36) * d);
         const T t = T(36) * d - mu;
         drho += d;
@@ -580,19 +587,23 @@ __device__ __forceinline__ OwnMom<T> own_moments(const Geo &g, const S *__restri
     return om;
 }
 
-// Link i of a fluid node whose upstream node is an inlet or outlet (code):
-// p holds at index i the node's own post-collision pair of the opposite
-// direction (what half-way bounce-back returns); replace it by the boundary
-// value.  Inlet: moving-wall bounce-back injecting the inlet's colour
-// densities.  Outlet: anti-bounce-back at the outlet density with the
-// node's own red fraction and velocity (om).
-template <class L, typename T>
-__device__ __forceinline__ void boundary_link(const Geo &g, const Model<T> &mo, int i, uint8_t code,
-                                              const OwnMom<T> &om, Pops<L, T> &p) {
+// Value a fluid node pulls through link i from a non-fluid upstream node of
+// mask code `code`, from the node's own stored new pair of the opposite
+// direction (own_io) and, for outlets, its own moments.  Walls return own_io
+// unchanged; inlet and outlet values are encoded rounded to nearest.
+template <class L, typename S, typename T>
+__device__ __forceinline__ typename PairOf<S>::type boundary_pair(const Geo &g, const Model<T> &mo, int i,
+                                                                  uint8_t code,
+                                                                  typename PairOf<S>::type own_io,
+                                                                  const OwnMom<T> &om) {
+    if (code == kWall) return own_io;
     const int io = L::opp[i];
-    const T fo = T(wgt<L>(io)) + p.df[i];
-    const T mu = p.mm[i] * fo;
-    const T fRo = p.flag(i) ? fo - mu : mu, fBo = fo - fRo;
+    bool flo;
+    const T dfo = Codec<S>::template df<L, T>(own_io.x, io);
+    const T mo_ = Codec<S>::template col<T>(own_io.y, flo);
+    const T fo = T(wgt<L>(io)) + dfo;
+    const T mu = mo_ * fo;
+    const T fRo = flo ? fo - mu : mu, fBo = fo - fRo;
     T fR, fB;
     if (code < kOutlet0) {
         const DevInlet in = g.inlets[code - kInlet0];
@@ -614,49 +625,28 @@ __device__ __forceinline__ void boundary_link(const Geo &g, const Model<T> &mo, 
     T mm;
     bool fl;
     split_shares<T>(f != T(0) ? fR / f : T(0), f != T(0) ? fB / f : T(0), mm, fl);
-    p.set(i, f - T(wgt<L>(i)), mm, fl);
+    return encode_pair<L, S, T>(f - T(wgt<L>(i)), mm, fl, i);
 }
 
 // Pre-collision populations of fluid node (x, y, z) = n at the new time level
-// from the stored post-collision state (Eq. (1), pull form), with the
-// boundary rules for non-fluid upstream nodes: wall -> half-way bounce-back;
-// inlet -> moving-wall bounce-back injecting the inlet's colour densities;
-// outlet -> anti-bounce-back at the outlet density.  With pulled == false the
-// stored state already is pre-collision and is read in place.
+// from the stored post-collision state (Eq. (1), pull form).  A link from a
+// non-fluid node reads the boundary value its fluid neighbour stored there.
+// With pulled == false the stored state already is pre-collision and is read
+// in place.
 template <class L, typename S, typename T>
-__device__ __forceinline__ void pull_node(const Geo &g, const Model<T> &mo, const S *__restrict__ st,
+__device__ __forceinline__ void pull_node(const Geo &g, const Model<T> &, const S *__restrict__ st,
                                           int x, int y, int z, int64_t n, bool pulled, Pops<L, T> &p) {
     p.red = 0;
-    if (!pulled) {
-#pragma unroll
-        for (int i = 0; i < L::Q; ++i) load_raw<L, S, T>(st, g.pitch, n, i, p);
-        return;
-    }
-    bool own = false;
-    OwnMom<T> om{};
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) {
-        const int xs = wrap_m1(x - L::cx[i], g.nx);
-        const int ys = wrap_m1(y - L::cy[i], g.ny);
-        const int zs = wrap_m1(z - L::cz[i], g.nz);
-        const int64_t m = xs + int64_t(g.nx) * (ys + int64_t(g.ny) * zs);
-        const uint8_t code = g.mask ? g.mask[m] : kFluid;
-        if (code == kFluid) {
-            load_raw<L, S, T>(st, g.pitch, m, i, p);
-            continue;
+        int64_t m = n;
+        if (pulled) {
+            const int xs = wrap_m1(x - L::cx[i], g.nx);
+            const int ys = wrap_m1(y - L::cy[i], g.ny);
+            const int zs = wrap_m1(z - L::cz[i], g.nz);
+            m = xs + int64_t(g.nx) * (ys + int64_t(g.ny) * zs);
         }
-        // the node's own pair of the opposite direction, at index i (w_io == w_i)
-        const int io = L::opp[i];
-        Pops<L, T> q;
-        q.red = 0;
-        load_raw<L, S, T>(st, g.pitch, n, io, q);
-        p.set(i, q.df[io], q.mm[io], q.flag(io));
-        if (code == kWall) continue;
-        if (code >= kOutlet0 && !own) {
-            om = own_moments<L, S, T>(g, st, n);
-            own = true;
-        }
-        boundary_link<L, T>(g, mo, i, code, om, p);
+        load_raw<L, S, T>(st, g.pitch, m, i, p);
     }
 }
 
@@ -799,14 +789,41 @@ __device__ __forceinline__ void collide(const Model<T> &mo, T drho, T r36R, T r3
     }
 }
 
+// Encoded new pairs of one node (16-bit storage rounds stochastically with
+// the node's generator).
 template <class L, typename S, typename T>
-__device__ __forceinline__ void store_out(S *__restrict__ st, int64_t pitch, int64_t node,
-                                          const PostOut<L, T> &o, uint32_t step) {
-    typename PairOf<S>::type *a = reinterpret_cast<typename PairOf<S>::type *>(st);
-    Dither dz(step, uint32_t(node));
+__device__ __forceinline__ void encode_out(const PostOut<L, T> &o, uint32_t step, uint32_t node,
+                                           typename PairOf<S>::type enc[L::Q]) {
+    Dither dz(step, node);
 #pragma unroll
-    for (int i = 0; i < L::Q; ++i)
-        a[int64_t(i) * pitch + node] = encode_step<L, S, T>(o.df[i], o.mm[i], (o.red >> i) & 1u, i, dz);
+    for (int i = 0; i < L::Q; ++i) enc[i] = encode_step<L, S, T>(o.df[i], o.mm[i], (o.red >> i) & 1u, i, dz);
+}
+
+// Store a fluid node's encoded new pairs and, with geometry, the boundary
+// values of its non-fluid links into the upstream nodes' slots.
+template <class L, typename S, typename T>
+__device__ __forceinline__ void store_node(const Geo &g, const Model<T> &mo, S *__restrict__ st, int x, int y,
+                                           int z, int64_t node, const typename PairOf<S>::type enc[L::Q]) {
+    typename PairOf<S>::type *a = reinterpret_cast<typename PairOf<S>::type *>(st);
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) a[int64_t(i) * g.pitch + node] = enc[i];
+    if (!g.mask) return;
+    bool own = false;
+    OwnMom<T> om{};
+#pragma unroll
+    for (int i = 1; i < L::Q; ++i) {
+        const int xs = wrap_m1(x - L::cx[i], g.nx);
+        const int ys = wrap_m1(y - L::cy[i], g.ny);
+        const int zs = wrap_m1(z - L::cz[i], g.nz);
+        const int64_t m = xs + int64_t(g.nx) * (ys + int64_t(g.ny) * zs);
+        const uint8_t code = g.mask[m];
+        if (code == kFluid) continue;
+        if (code >= kOutlet0 && !own) {
+            om = own_moments<L, S, T>(enc);
+            own = true;
+        }
+        a[int64_t(i) * g.pitch + m] = boundary_pair<L, S, T>(g, mo, i, code, enc[L::opp[i]], om);
+    }
 }
 
 }  // namespace lbcg

@@ -122,15 +122,12 @@ struct Pending {
 };
 
 // Request the 19 population pairs of a node at plane z from its column
-// offsets t.  With geometry (link word lk), a link whose upstream node is not
-// fluid reads the node's own pair of the opposite direction instead: that is
-// the half-way bounce-back value of a wall, and the start of the inlet and
-// outlet rules.  The buffer offsets stay non-negative: the scalar part is the
-// smaller of the two candidates' uniform parts and the vector part adds the
-// rest.
-template <typename S, typename T, bool MASKED>
+// offsets t.  With geometry, a link whose upstream node is not fluid reads
+// the boundary value that the node itself stored in that node's slot at the
+// previous step, so every link is a plain load.
+template <typename S, typename T>
 __device__ __forceinline__ void pull_plane(const FusedArgs<S> &a, __amdgpu_buffer_rsrc_t r, const uint32_t t[9],
-                                           int z, uint32_t lk, Pending<S, T> &pend) {
+                                           int z, Pending<S, T> &pend) {
     using L = D3Q19;
     typedef typename PairOf<S>::type P2;
     constexpr uint32_t E = sizeof(P2);
@@ -139,18 +136,8 @@ __device__ __forceinline__ void pull_plane(const FusedArgs<S> &a, __amdgpu_buffe
     const uint32_t zo[3] = {uint32_t(uniform(z == 0 ? a.nz - 1 : z - 1)) * plane, uint32_t(uniform(z)) * plane,
                             uint32_t(uniform(z == a.nz - 1 ? 0 : z + 1)) * plane};
 #pragma unroll
-    for (int i = 0; i < L::Q; ++i) {
-        const uint32_t up = uint32_t(i) * cstride + zo[1 - L::cz[i]];
-        const uint32_t tv = t[(1 - L::cx[i]) + 3 * (1 - L::cy[i])];
-        if (!MASKED || i == 0) {
-            pend.v[i] = load_pair<P2>(r, tv, up);
-        } else {
-            const uint32_t own = uint32_t(L::opp[i]) * cstride + zo[1];
-            const uint32_t base = own < up ? own : up;
-            const uint32_t vo = ((lk >> i) & 1u) ? t[4] + (own - base) : tv + (up - base);
-            pend.v[i] = load_pair<P2>(r, vo, base);
-        }
-    }
+    for (int i = 0; i < L::Q; ++i)
+        pend.v[i] = load_pair<P2>(r, t[(1 - L::cx[i]) + 3 * (1 - L::cy[i])], uint32_t(i) * cstride + zo[1 - L::cz[i]]);
 }
 
 __device__ __forceinline__ int wrapz(int z, int nz) { return z < 0 ? z + nz : (z >= nz ? z - nz : z); }
@@ -246,26 +233,6 @@ __device__ __forceinline__ void sweep(const FusedArgs<S> &a, const Model<T> &mo,
         return kSentinel;
     };
     auto fluid = [&](uint32_t lk) { return !MASKED || (lk & kLinkFluid) != 0u; };
-    // Inlet and outlet links of a node (link word lk) whose requested pairs
-    // are in q: the redirected pair of such a link is the node's own pair of
-    // the opposite direction, which the rule turns into the boundary value.
-    auto settle = [&](int xx, int yy, int zz, uint32_t lk, Pops<L, T> &q) {
-        if (!MASKED || !(lk & kLinkBoundary)) return;
-        const Geo g = geo_of(a);
-        const int64_t n = node(xx, yy, zz);
-        OwnMom<T> om{};
-        if (lk & kLinkOutlet) om = own_moments<L, S, T>(g, a.in, n);
-#pragma unroll
-        for (int i = 1; i < L::Q; ++i) {
-            if (!((lk >> i) & 1u)) continue;
-            uint8_t c = link_code(lk);
-            if (lk & kLinkMixed)
-                c = a.mask[node(wrap_m1(xx - L::cx[i], a.nx), wrap_m1(yy - L::cy[i], a.ny),
-                                wrap_m1(zz - L::cz[i], a.nz))];
-            if (c != kWall) boundary_link<L, T>(g, mo, i, c, om, q);
-        }
-    };
-
     // psi planes live in a 5-slot LDS ring: iteration z writes plane z+1
     // (interior and ring) and then collides plane z from planes z-1..z+1; the
     // barrier keeps the waves within one iteration of each other, so a slot
@@ -286,7 +253,7 @@ __device__ __forceinline__ void sweep(const FusedArgs<S> &a, const Model<T> &mo,
         if (has_ring) {
             const int zz = wrapz(zp, a.nz);
             rp.lk = MASKED ? rlk : kLinkFluid;
-            if (fluid(rp.lk)) pull_plane<S, T, MASKED>(a, rin, rxy, zz, rp.lk, rp);
+            if (fluid(rp.lk)) pull_plane<S, T>(a, rin, rxy, zz, rp);
             if (MASKED) rlk = a.links[node(gx, gy, wrapz(zp + 1, a.nz))];
         }
     };
@@ -296,7 +263,6 @@ __device__ __forceinline__ void sweep(const FusedArgs<S> &a, const Model<T> &mo,
             if (fluid(rp.lk)) {
                 Pops<L, T> q;
                 rp.take(q);
-                settle(gx, gy, wrapz(zp, a.nz), rp.lk, q);
                 T dr, rR, rB;
                 densities<L, T>(q, dr, rR, rB);
                 v = float(psi_of<T>(dr, rR, rB));
@@ -311,6 +277,7 @@ __device__ __forceinline__ void sweep(const FusedArgs<S> &a, const Model<T> &mo,
     // of plane z+1 are in flight.
     T cd = 0, cR = 0, cB = 0, cj[3] = {0, 0, 0}, cS[6] = {0, 0, 0, 0, 0, 0};
     bool cfl = false;
+    uint32_t clk = 0;  // link word of the plane being collided
     Pending<S, T> pp;
     pp.lk = kLinkFluid;
     uint32_t ilk = 0;  // link word of the next interior request
@@ -320,15 +287,11 @@ __device__ __forceinline__ void sweep(const FusedArgs<S> &a, const Model<T> &mo,
         if (intile) {
             pz = wrapz(zp, a.nz);
             pp.lk = MASKED ? ilk : kLinkFluid;
-            if (fluid(pp.lk)) pull_plane<S, T, MASKED>(a, rin, ixy, pz, pp.lk, pp);
+            if (fluid(pp.lk)) pull_plane<S, T>(a, rin, ixy, pz, pp);
             if (MASKED) ilk = a.links[node(x, y, wrapz(zp + 1, a.nz))];
         }
     };
-    // the pending interior populations, boundary rules applied
-    auto interior_take = [&](Pops<L, T> &q) {
-        pp.take(q);
-        settle(x, y, pz, pp.lk, q);
-    };
+    auto interior_take = [&](Pops<L, T> &q) { pp.take(q); };
     // moments of the pulled interior plane into (d, r36R, r36B, j, flux); returns psi
     auto interior_moments = [&](T &d, T &r36R, T &r36B, T j[3], T flux[6], bool &fl) -> float {
         fl = fluid(pp.lk);
@@ -369,6 +332,7 @@ __device__ __forceinline__ void sweep(const FusedArgs<S> &a, const Model<T> &mo,
     ring_issue(z0);
     interior_issue(z0);
     if (intile) slot_of(z0)[(row + 1) * W + lane + 1] = interior_moments(cd, cR, cB, cj, cS, cfl);
+    clk = pp.lk;
     ring_finish(z0);
     ring_issue(z0 + 1);
     interior_issue(z0 + 1);
@@ -405,6 +369,7 @@ __device__ __forceinline__ void sweep(const FusedArgs<S> &a, const Model<T> &mo,
         wait_memory();
         ring_finish(z + 1);
         if (intile) slot_of(z + 1)[(row + 1) * W + lane + 1] = interior_moments(nd, nR, nB, nj, nS, nfl);
+        const uint32_t nlk = pp.lk;
         if (more) {
             ring_issue(z + 2);
             interior_issue(z + 2);
@@ -433,10 +398,32 @@ __device__ __forceinline__ void sweep(const FusedArgs<S> &a, const Model<T> &mo,
             Dither dz(step, uint32_t(x) + uint32_t(a.nx) * (uint32_t(y) + uint32_t(a.ny) * uint32_t(z)));
 #pragma unroll
             for (int i = 0; i < L::Q; ++i) ov[i] = encode_step<L, S, T>(o.df[i], o.mm[i], (o.red >> i) & 1u, i, dz);
+            // boundary values of the node's non-fluid links, stored in the
+            // upstream nodes' slots (the addresses it pulls them from)
+            if (MASKED && (clk & kLinkBits)) {
+                const Geo g = geo_of(a);
+                const uint32_t zg[3] = {uint32_t(uniform(z == 0 ? a.nz - 1 : z - 1)) * plane,
+                                        uint32_t(uniform(z)) * plane,
+                                        uint32_t(uniform(z == a.nz - 1 ? 0 : z + 1)) * plane};
+                OwnMom<T> om{};
+                if (clk & kLinkOutlet) om = own_moments<L, S, T>(ov);
+#pragma unroll
+                for (int i = 1; i < L::Q; ++i) {
+                    if (!((clk >> i) & 1u)) continue;
+                    uint8_t c = link_code(clk);
+                    if (clk & kLinkMixed)
+                        c = a.mask[node(wrap_m1(x - L::cx[i], a.nx), wrap_m1(y - L::cy[i], a.ny),
+                                        wrap_m1(z - L::cz[i], a.nz))];
+                    store_pair<P2>(rout, ixy[(1 - L::cx[i]) + 3 * (1 - L::cy[i])],
+                                   uint32_t(i) * cstride + zg[1 - L::cz[i]],
+                                   boundary_pair<L, S, T>(g, mo, i, c, ov[L::opp[i]], om));
+                }
+            }
         }
         ozoff = uint32_t(uniform(z)) * plane;
         if (!kDelayStores) flush();
         cfl = nfl;
+        clk = nlk;
         cd = nd;
         cR = nR;
         cB = nB;

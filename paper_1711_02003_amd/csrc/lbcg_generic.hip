@@ -126,7 +126,9 @@ __global__ void __launch_bounds__(kBlock) k_step_generic(Geo g, Model<T> mo, con
     gradient<L, T>(g, psi, x, y, z, n, F);
     PostOut<L, T> o;
     collide<L, T>(mo, m.drho, m.r36R, m.r36B, m.j, m.S, F, &p, o);
-    store_out<L, S, T>(out, g.pitch, n, o, step);
+    typename PairOf<S>::type enc[L::Q];
+    encode_out<L, S, T>(o, step, uint32_t(n), enc);
+    store_node<L, S, T>(g, mo, out, x, y, z, n, enc);
 }
 
 template <class L, typename S, typename T>
