@@ -608,7 +608,8 @@ int lbcg_tune(lbcg_sim *s, int32_t *rows, int32_t *zchunks) {
     if (!s->initialised) return LBCG_E_STATE;
     if (s->kernel == LBCG_KERNEL_FUSED) {
         // Candidate shapes: both tile heights, z splits that fill the device
-        // once, twice or four times, and fixed chunk lengths.  Each is timed
+        // once, twice or four times, and fixed chunk lengths (short chunks
+        // balance lattices whose fluid sits in a few tiles).  Each is timed
         // stepping buf[cur] into the other buffer, which leaves the current
         // state untouched.
         const bool masked = s->g.mask != nullptr;
@@ -618,7 +619,7 @@ int lbcg_tune(lbcg_sim *s, int32_t *rows, int32_t *zchunks) {
             const int64_t resident = fused_resident_blocks(s->prec, r, masked);
             std::vector<int64_t> zs = {1};
             for (int m : {1, 2, 4}) zs.push_back((m * resident + tiles - 1) / tiles);
-            for (int planes : {8, 16, 32, 64}) zs.push_back((s->g.nz + planes - 1) / planes);
+            for (int planes : {2, 4, 8, 16, 32, 64}) zs.push_back((s->g.nz + planes - 1) / planes);
             for (int64_t z : zs) {
                 const int zc = int(z < 1 ? 1 : (z > s->g.nz ? s->g.nz : (z > 4096 ? 4096 : z)));
                 bool seen = false;
