@@ -6,11 +6,11 @@
  * "Regularized lattice Boltzmann multicomponent models for low Capillary and
  * Reynolds microfluidics flows" (arXiv:1711.02003), Sec. II: two colour
  * distributions f_i^R, f_i^B (Eq. (1)), colour densities (Eq. (2)), a common
- * velocity (Eq. (3)), a composite collision (Eq. (4)) made of a per-colour
- * relaxation towards the colour equilibrium (Eqs. (5)-(7)) in its
- * regularized form (Eq. (11)), a surface-tension perturbation driven by the
- * colour gradient (Eq. (9)) and a recolouring step (Eq. (10)), followed by
- * streaming (Eq. (1)).
+ * velocity (Eq. (3)), a composite collision (Eq. (4)) made of a relaxation
+ * towards the sum of the colour equilibria (Eqs. (5)-(7)) in its regularized
+ * form (Eq. (11)), at one rate per node taken from the mixture viscosity, a
+ * surface-tension perturbation driven by the colour gradient (Eq. (9)) and a
+ * recolouring step (Eq. (10)), followed by streaming (Eq. (1)).
  *
  * Conventions used by every call:
  *   - a lattice has dims[0] x dims[1] x dims[2] = nx x ny x nz nodes
@@ -54,8 +54,8 @@ extern "C" {
 #define LBCG_F32 1
 #define LBCG_F16 2
 
-/* Per-colour relaxation: the regularized form of Eq. (11) (default) or the
- * plain BGK form of Eq. (5). */
+/* Relaxation: the regularized form of Eq. (11) (default) or the plain BGK
+ * form of Eq. (5), both at the node's rate (see tau_B below). */
 #define LBCG_REGULARIZED 0
 #define LBCG_BGK 1
 
