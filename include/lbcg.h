@@ -69,7 +69,9 @@ extern "C" {
 
 /* Mask codes (one byte per node): 0 fluid; 1 wall (half-way bounce-back);
  * 2 + j inlet j (moving-wall velocity inlet); 128 + j outlet j (pressure
- * outlet).  Non-fluid nodes hold no fluid and are never updated. */
+ * outlet).  Non-fluid nodes hold no fluid and are never collided; their
+ * storage holds the boundary values that neighbouring fluid nodes pull, and
+ * every export reports zeros for them. */
 #define LBCG_FLUID 0
 #define LBCG_WALL 1
 #define LBCG_INLET0 2
