@@ -95,6 +95,15 @@ def load_library() -> C.CDLL:
     """Load liblbcg.so (built in-tree by ``paper_1711_02003_amd.build``)."""
     global _lib
     if _lib is None:
+        # PyTorch ships its own HIP runtime and hands this library its device
+        # memory and streams: load torch first so that liblbcg.so binds to
+        # that same runtime (loading it first would bring in a second runtime,
+        # and every call with torch's pointers would then fail).
+        try:
+            import torch
+            torch.cuda.is_available()
+        except ImportError:  # pragma: no cover
+            pass
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with "
                                "`python -m paper_1711_02003_amd.build` (hipcc, gfx950)")
