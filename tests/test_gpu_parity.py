@@ -310,3 +310,23 @@ def test_full_size_config2_sampled(L, orc):
     assert abs(d1["mass_R"] - d0["mass_R"]) / d0["mass_R"] < 1e-6
     assert abs(d1["mass_B"] - d0["mass_B"]) / d0["mass_B"] < 1e-6
     s.close()
+
+
+def test_library_loaded_before_torch_in_fresh_process(L):
+    # A caller that imports the binding and creates a lattice without ever
+    # importing torch itself: the binding must still run on torch's HIP
+    # runtime (the one that owns the device memory it hands over).
+    import subprocess
+    import sys
+    code = ("import sys; sys.path.insert(0, '.');"
+            "from paper_1711_02003_amd import lbcg, workloads as W;"
+            "w = W.config2(L=16, seed=2);"
+            "s = lbcg.Sim.from_workload(w, precision='f32');"
+            "s.step(3); f = s.fields();"
+            "assert abs(f['rhoR'].sum() + f['rhoB'].sum() - 16 ** 3) < 1e-2;"
+            "print('fresh process ok', flush=True)")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, timeout=240)
+    _say(r.stdout.strip()[-200:])
+    assert r.returncode == 0, r.stderr[-2000:]
+    assert "fresh process ok" in r.stdout
