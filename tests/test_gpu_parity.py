@@ -273,25 +273,18 @@ def test_determinism_and_checkpoint(L):
     assert c.diagnostics()["step"] == 40
 
 
-def test_full_size_config2_sampled(L, orc):
-    # Full 256^3 lattice in the benchmark's launch configuration: each sampled
-    # node's next state depends only on the current state within two nodes,
-    # so the oracle steps a periodic 5^3 box cut around it.
-    w = W.config2(L=256, seed=2)
-    _say("full size 256^3 fused f32")
-    s = L.Sim.from_workload(w, precision="f32")
-    info = s.launch_info()
-    _say(f"  launch {info}")
-    d0 = s.diagnostics(check=True)
-    s.step(20)
-    rng = np.random.default_rng(0)
-    Lx = 256
-    centres = rng.integers(0, Lx, (48, 3))
+def _sampled_one_step(L, orc, w, s, n_samples=48, seed=0):
+    # Each sampled node's next state depends only on the current state within
+    # two nodes, so the oracle steps a periodic 5^3 box cut around it.
+    nx, ny, nz = w.dims
+    rng = np.random.default_rng(seed)
+    centres = np.stack([rng.integers(0, nx, n_samples), rng.integers(0, ny, n_samples),
+                        rng.integers(0, nz, n_samples)], 1)
     off = np.arange(-2, 3)
     boxes = []
     for cx, cy, cz in centres:
-        zz, yy, xx = np.meshgrid((cz + off) % Lx, (cy + off) % Lx, (cx + off) % Lx, indexing="ij")
-        boxes.append((xx + Lx * (yy + Lx * zz)).reshape(-1))
+        zz, yy, xx = np.meshgrid((cz + off) % nz, (cy + off) % ny, (cx + off) % nx, indexing="ij")
+        boxes.append((xx + nx * (yy + ny * zz)).reshape(-1))
     nodes = np.concatenate(boxes)
     before = s.populations_at(nodes).reshape(len(centres), 5, 5, 5, 2, 19)
     s.step(1)
@@ -304,11 +297,43 @@ def test_full_size_config2_sampled(L, orc):
         o.step(1)
         ref = o.populations()[:, :, 2, 2, 2]
         worst = max(worst, float(np.abs(after[j] - ref).max() / np.abs(ref).max()))
+    return worst
+
+
+def test_full_size_config2_sampled(L, orc):
+    # Full 256^3 lattice in the benchmark's launch configuration.
+    w = W.config2(L=256, seed=2)
+    _say("full size 256^3 fused f32")
+    s = L.Sim.from_workload(w, precision="f32")
+    info = s.launch_info()
+    _say(f"  launch {info}")
+    d0 = s.diagnostics(check=True)
+    s.step(20)
+    worst = _sampled_one_step(L, orc, w, s)
     _say(f"  sampled one-step max rel diff {worst:.2e}")
     assert worst < 2e-6
     d1 = s.diagnostics(check=True)
     assert abs(d1["mass_R"] - d0["mass_R"]) / d0["mass_R"] < 1e-6
     assert abs(d1["mass_B"] - d0["mass_B"]) / d0["mass_B"] < 1e-6
+    s.close()
+
+
+@pytest.mark.parametrize("edge,kernel", [(304, "fused"), (306, "generic")])
+def test_largest_fused_lattice_and_beyond(L, orc, edge, kernel):
+    # The fused kernel addresses a state buffer with 32-bit byte offsets:
+    # 304^3 FP32 (4.27 GB per buffer) is the largest cube it takes, with
+    # offsets up to 2^32 - 25 MB; at 306^3 (4.36 GB) the automatic choice
+    # falls back to the generic kernel.  Both stay within the one-step bar.
+    w = W.config2(L=edge, seed=2)
+    _say(f"{edge}^3 f32, expect {kernel}")
+    s = L.Sim.from_workload(w, precision="f32")
+    info = s.launch_info()
+    _say(f"  launch {info}")
+    assert info["kernel"] == (L.KERNEL_FUSED if kernel == "fused" else L.KERNEL_GENERIC)
+    s.step(3)
+    worst = _sampled_one_step(L, orc, w, s, n_samples=32, seed=edge)
+    _say(f"  sampled one-step max rel diff {worst:.2e}")
+    assert worst < 2e-6
     s.close()
 
 
