@@ -131,16 +131,14 @@ struct Geo {
 
 // Link word of a node of a lattice with geometry, built on the host from the
 // mask so that the boundary writes need no per-direction mask reads.  Fluid
-// node: bit i (i < Q) set when the upstream node x - c_i is not fluid; kLinkFluid;
-// kLinkBoundary when some upstream node is an inlet or outlet (plus
-// kLinkOutlet if one is an outlet); and the mask code shared by all its
-// non-fluid upstream nodes in bits 20..27, or kLinkMixed when they differ
-// (walls included).  Non-fluid node: its own mask code in bits 20..27,
-// nothing else.
+// node: bit i (i < Q) set when the upstream node x - c_i is not fluid;
+// kLinkFluid; kLinkOutlet when some upstream node is an outlet; and the mask
+// code shared by all its non-fluid upstream nodes in bits 20..27, or
+// kLinkMixed when they differ (walls included).  Non-fluid node: its own
+// mask code in bits 20..27, nothing else.
 constexpr uint32_t kLinkFluid = 1u << 19;
 constexpr uint32_t kLinkMixed = 1u << 28;
 constexpr uint32_t kLinkOutlet = 1u << 29;
-constexpr uint32_t kLinkBoundary = 1u << 30;
 constexpr uint32_t kLinkBits = (1u << 19) - 2u;  // the per-direction bits 1..18
 __host__ __device__ constexpr uint8_t link_code(uint32_t lk) { return uint8_t((lk >> 20) & 0xffu); }
 

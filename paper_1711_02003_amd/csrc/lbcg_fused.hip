@@ -65,7 +65,6 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t state_rsrc(const S *p, uint32_
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<S *>(p), (short)0, int(bytes), kRsrcWord3);
 }
 
-
 template <typename P2>
 __device__ __forceinline__ P2 load_pair(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
     if constexpr (sizeof(P2) == 8)
@@ -176,9 +175,9 @@ __device__ __forceinline__ void sweep(const FusedArgs<S> &a, const Model<T> &mo,
     const uint32_t step = *a.ctr_in;  // seeds the stochastic rounding of 16-bit shares
 
     // With geometry, a chunk whose own nodes are all non-fluid has nothing to
-    // do: no fluid node reads a non-fluid node's state (its links are
-    // redirected to its own pairs), and the ring only feeds the gradients of
-    // the chunk's own fluid nodes.
+    // do: a non-fluid node's slots hold only the boundary values that its
+    // fluid neighbours store there themselves, and the ring only feeds the
+    // gradients of the chunk's own fluid nodes.
     if (MASKED) {
         bool any = false;
         if (intile)

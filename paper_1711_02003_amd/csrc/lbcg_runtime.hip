@@ -208,8 +208,6 @@ std::vector<uint32_t> link_words(int nx, int ny, int nz, const uint8_t *mask) {
                         code = c;
                     else if (code != c)
                         lk |= kLinkMixed;
-                    if (c == kWall) continue;
-                    lk |= kLinkBoundary;
                     if (c >= kOutlet0) lk |= kLinkOutlet;
                 }
                 if (code >= 0 && !(lk & kLinkMixed)) lk |= uint32_t(code) << 20;
