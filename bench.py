@@ -120,6 +120,31 @@ def f16_form(torch, lbcg, W, size, steps=200, warmup=10):
             "zchunks": shape["zchunks"], "steps": steps}
 
 
+def d2q9_form(torch, lbcg, W, steps=200, warmup=10):
+    """D2Q9 4096^2 with 256 droplets, FP32 storage: the fused strip sweep
+    (tuned) and, for comparison, the two-pass generic kernel (a psi pass,
+    then the step), both against the 144 B per node that one read and one
+    write of every population pair move."""
+    w = W.droplets_2d(n=4096, seed=6)
+    out = {"workload": w.name, "storage": "f32", "bytes_per_node": 144, "steps": steps}
+    for name, kernel in (("fused", lbcg.KERNEL_FUSED), ("generic", lbcg.KERNEL_GENERIC)):
+        stream = torch.cuda.Stream()
+        sim = lbcg.Sim.from_workload(w, precision="f32", kernel=kernel, stream=stream.cuda_stream)
+        sim.step(1)
+        if kernel == lbcg.KERNEL_FUSED:
+            sim.tune()
+        ms = time_sim(torch, sim, stream, steps, warmup)
+        info = sim.launch_info()
+        sim.close()
+        gbs = 144 * w.fluid_nodes * steps / (ms / 1e3) / 1e9
+        out[name] = {"mlups": round(w.fluid_nodes * steps / (ms / 1e3) / 1e6, 1),
+                     "ms_per_step": round(ms / steps, 4), "achieved_gbs": round(gbs, 1),
+                     "frac": round(gbs / HBM_PEAK_GBS, 4)}
+        if kernel == lbcg.KERNEL_FUSED:
+            out[name]["ychunks"] = info["zchunks"]
+    return out
+
+
 def focusing_form(torch, lbcg, W, steps=200, warmup=10):
     """Flow-focusing cross junction 512 x 128 x 64 (walls, inlets, outlet):
     FP32 and FP16 storage, fluid-node MLUPS and all-node MLUPS."""
@@ -302,6 +327,8 @@ def main():
     if not args.no_forms:
         forms = {"f16": f16_form(torch, lbcg, W, args.size)}
         log(f"f16 {forms['f16']}")
+        forms["d2q9"] = d2q9_form(torch, lbcg, W)
+        log(f"d2q9 {forms['d2q9']}")
         forms["focusing"] = focusing_form(torch, lbcg, W)
         log(f"focusing {forms['focusing']}")
         forms["batched"] = batched_form(torch, lbcg, W)

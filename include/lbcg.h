@@ -60,9 +60,10 @@ extern "C" {
 #define LBCG_BGK 1
 
 /* Kernel choice: automatic, the two-pass generic kernel (every lattice,
- * precision, collision and boundary) or the fused single-pass kernel (D3Q19,
- * F32 or F16 storage, regularized collision, any geometry; state buffers
- * below 4 GiB).  Automatic picks the fused kernel where it applies. */
+ * precision, collision and boundary) or the fused single-pass kernel (F32 or
+ * F16 storage, regularized collision, state buffers below 4 GiB; D3Q19 with
+ * any geometry, D2Q9 periodic).  Automatic picks the fused kernel where it
+ * applies. */
 #define LBCG_KERNEL_AUTO 0
 #define LBCG_KERNEL_GENERIC 1
 #define LBCG_KERNEL_FUSED 2
@@ -116,8 +117,9 @@ typedef struct {
     int32_t n_outlets;   /* entries in outlets (<= 128) */
     const lbcg_inlet *inlets;   /* host, copied */
     const lbcg_outlet *outlets; /* host, copied */
-    int32_t tile[3];     /* fused-kernel launch shape: rows per block (4 or 8),
-                            z chunks (<= 4096), reserved; 0 = automatic */
+    int32_t tile[3];     /* fused-kernel launch shape: rows per block (4 or 8;
+                            D3Q19 only), z chunks (D2Q9: row chunks; <= 4096),
+                            reserved; 0 = automatic */
 } lbcg_params;
 
 /* FP64 diagnostics of the current state S_t (pre-collision), summed over fluid

@@ -218,7 +218,7 @@ int lbcg_batch_create(lbcg_sim *const *sims, int32_t n, const int32_t *tile, lbc
     if (!tuned && ((tile[0] != 4 && tile[0] != 8) || tile[1] < 1)) return LBCG_E_INVAL;
     for (int j = 0; j < n; ++j) {
         const lbcg_sim *s = sims[j];
-        if (!s || !s->initialised || s->kernel != LBCG_KERNEL_FUSED) return LBCG_E_INVAL;
+        if (!s || !s->initialised || s->kernel != LBCG_KERNEL_FUSED || s->lattice != LBCG_D3Q19) return LBCG_E_INVAL;
         if (s->prec != sims[0]->prec || s->stream != sims[0]->stream) return LBCG_E_INVAL;
         for (int k = 0; k < j; ++k)
             if (sims[k] == s) return LBCG_E_INVAL;

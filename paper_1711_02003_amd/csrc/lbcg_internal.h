@@ -94,6 +94,12 @@ bool fused_supported(int lattice, int prec, const Geo &g);
 // Blocks of the fused kernel that fit on the device at once.
 int fused_resident_blocks(int prec, int rows, bool masked);
 
+// Fused single-pass D2Q9 step on periodic lattices, F32 or F16 storage:
+// strips of 64 columns, each row range split into ychunks.
+hipError_t launch_step_fused2d(int prec, const Geo &g, const ModelD &md, const void *in, void *out,
+                               const uint32_t *ctr_in, uint32_t *ctr_out, int ychunks, hipStream_t s);
+bool fused2d_supported(int prec, const Geo &g);
+
 // Batched fused step: one launch steps many lattices by one time level.
 // Block b sweeps work item bitem[b] (tile-major (tile, z chunk) index) of
 // lattice blat[b], described by desc[blat[b]].

@@ -113,8 +113,36 @@ int check_device() {
     return LBCG_OK;
 }
 
+// The fused kernel of a lattice: the D3Q19 column sweep or the D2Q9 strip
+// sweep (periodic lattices only).
+bool any_fused_supported(int lattice, int prec, const Geo &g) {
+    return lattice == LBCG_D3Q19 ? fused_supported(lattice, prec, g) : fused2d_supported(prec, g);
+}
+
+hipError_t launch_fused(const lbcg_sim *s, const void *in, void *out, const uint32_t *ctr_in, uint32_t *ctr_out,
+                        FusedShape shape) {
+    if (s->lattice == LBCG_D2Q9)
+        return launch_step_fused2d(s->prec, s->g, s->md, in, out, ctr_in, ctr_out, shape.zchunks, s->stream);
+    return launch_step_fused(s->prec, s->g, s->md, in, out, ctr_in, ctr_out, shape, s->stream);
+}
+
 FusedShape pick_shape(const lbcg_sim *s, const lbcg_params *p) {
     FusedShape sh;
+    if (s->lattice == LBCG_D2Q9) {
+        // strips of 64 columns, rows split into chunks (zchunks counts them):
+        // about 4096 strip chunks fill the device with 4 waves per SIMD, and
+        // chunks keep >= 8 rows
+        sh.rows = 1;
+        int yc = p->tile[1];
+        if (!yc && s->kernel == LBCG_KERNEL_FUSED) {
+            const int64_t strips = (s->g.nx + 63) / 64;
+            const int64_t want = (4096 + strips - 1) / strips;
+            const int64_t cap = s->g.ny / 8 > 1 ? s->g.ny / 8 : 1;
+            yc = int(want < 1 ? 1 : (want > cap ? cap : want));
+        }
+        sh.zchunks = yc < 1 ? 1 : yc;
+        return sh;
+    }
     sh.rows = p->tile[0] ? p->tile[0] : 8;
     int zc = p->tile[1];
     if (!zc && s->kernel == LBCG_KERNEL_FUSED) {
@@ -136,8 +164,7 @@ hipError_t enqueue_step(lbcg_sim *s, bool pulled) {
     void *out = s->buf[s->cur ^ 1];
     const uint32_t *ctr_in = s->ctr + s->cur;
     uint32_t *ctr_out = s->ctr + (s->cur ^ 1);
-    if (s->kernel == LBCG_KERNEL_FUSED && pulled)
-        return launch_step_fused(s->prec, s->g, s->md, in, out, ctr_in, ctr_out, s->shape, s->stream);
+    if (s->kernel == LBCG_KERNEL_FUSED && pulled) return launch_fused(s, in, out, ctr_in, ctr_out, s->shape);
     hipError_t e = launch_psi(s->lattice, s->prec, s->g, s->md, in, pulled, s->psi, s->stream);
     if (e != hipSuccess) return e;
     return launch_step_generic(s->lattice, s->prec, s->g, s->md, in, pulled, s->psi, out, ctr_in, ctr_out,
@@ -366,11 +393,11 @@ int lbcg_create(const lbcg_params *p, void *dev_buf, size_t bytes, void *hip_str
 
     int kind = p->kernel;
     if (kind == LBCG_KERNEL_AUTO)
-        kind = (fused_supported(s->lattice, s->prec, s->g) && s->collision == LBCG_REGULARIZED)
+        kind = (any_fused_supported(s->lattice, s->prec, s->g) && s->collision == LBCG_REGULARIZED)
                    ? LBCG_KERNEL_FUSED
                    : LBCG_KERNEL_GENERIC;
     if (kind == LBCG_KERNEL_FUSED &&
-        (!fused_supported(s->lattice, s->prec, s->g) || s->collision != LBCG_REGULARIZED)) {
+        (!any_fused_supported(s->lattice, s->prec, s->g) || s->collision != LBCG_REGULARIZED)) {
         release(s);
         delete s;
         return LBCG_E_INVAL;
@@ -612,7 +639,17 @@ int lbcg_tune(lbcg_sim *s, int32_t *rows, int32_t *zchunks) {
         // state untouched.
         const bool masked = s->g.mask != nullptr;
         std::vector<FusedShape> cand;
+        if (s->lattice == LBCG_D2Q9) {
+            // strip sweep: row chunks of 8 to 512 rows
+            for (int len : {8, 16, 32, 64, 128, 256, 512}) {
+                const int yc = (s->g.ny + len - 1) / len;
+                bool seen = false;
+                for (const FusedShape &c : cand) seen = seen || c.zchunks == yc;
+                if (!seen) cand.push_back(FusedShape{1, yc});
+            }
+        }
         for (int r : {4, 8}) {
+            if (s->lattice == LBCG_D2Q9) break;
             const int64_t tiles = int64_t((s->g.nx + 63) / 64) * ((s->g.ny + r - 1) / r);
             const int64_t resident = fused_resident_blocks(s->prec, r, masked);
             std::vector<int64_t> zs = {1};
@@ -640,9 +677,9 @@ int lbcg_tune(lbcg_sim *s, int32_t *rows, int32_t *zchunks) {
         FusedShape pick = s->shape;
         hipError_t e = hipSuccess;
         for (const FusedShape &c : cand) {
-            for (int k = 0; k < 2 && e == hipSuccess; ++k) e = launch_step_fused(s->prec, s->g, s->md, in, out, ctr_in, ctr_out, c, s->stream);
+            for (int k = 0; k < 2 && e == hipSuccess; ++k) e = launch_fused(s, in, out, ctr_in, ctr_out, c);
             if (e == hipSuccess) e = hipEventRecord(e0, s->stream);
-            for (int k = 0; k < 4 && e == hipSuccess; ++k) e = launch_step_fused(s->prec, s->g, s->md, in, out, ctr_in, ctr_out, c, s->stream);
+            for (int k = 0; k < 4 && e == hipSuccess; ++k) e = launch_fused(s, in, out, ctr_in, ctr_out, c);
             if (e == hipSuccess) e = hipEventRecord(e1, s->stream);
             if (e == hipSuccess) e = hipEventSynchronize(e1);
             float ms = 0;

@@ -166,6 +166,34 @@ def config2(L: int = 256, seed: int = 2, steps: int = 1000) -> Workload:
                     steps=steps)
 
 
+def droplets_2d(n: int = 4096, seed: int = 6, steps: int = 1000) -> Workload:
+    """D2Q9 periodic square with 256 droplets on a jittered 16 x 16 lattice
+    (the 2-D counterpart of config2).
+
+    At n = 4096: centres (i + 1/2) n/16 + U(-32, 32) per axis, radii
+    U[24, 56]; other n scale the jitter and radii by n/4096.  Velocity
+    N(0, 1e-3) per in-plane component per node.  tau_R = 1.0, tau_B = 0.6,
+    A = 0.005, beta = 0.7.  Draws: 512 jitters (droplet-major, x y), 256
+    radii, then u (2, 1, n, n).
+    """
+    rng = np.random.default_rng(seed)
+    s = n / 4096.0
+    jit = rng.uniform(-32.0 * s, 32.0 * s, (256, 2))
+    radii = rng.uniform(24.0 * s, 56.0 * s, 256)
+    centres = []
+    d = 0
+    for j in range(16):
+        for i in range(16):
+            centres.append(((i + 0.5) * n / 16.0 + jit[d, 0], (j + 0.5) * n / 16.0 + jit[d, 1], 0.0))
+            d += 1
+    psi = droplet_phase((n, n, 1), centres, radii, 2.0)
+    rR, rB = colour_densities(psi)
+    u = np.zeros((3, 1, n, n))
+    u[:2] = rng.normal(0.0, 1e-3, (2, 1, n, n))
+    return Workload(f"d2q9_256_droplets_{n}", "D2Q9", (n, n, 1), rR, rB, u, 1.0, 0.6, 0.005, 0.7,
+                    steps=steps)
+
+
 def flow_focusing(nx: int = 512, ny: int = 128, nz: int = 64, lam: float = 1.0,
                   u_disp: float = 0.005, u_side: float = 0.01, A: float = 0.01,
                   steps: int = 20000) -> Workload:
