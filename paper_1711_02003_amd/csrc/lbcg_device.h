@@ -126,7 +126,7 @@ struct Geo {
     const uint8_t *mask;       // nullptr = all fluid
     const DevInlet *inlets;
     const DevOutlet *outlets;
-    const uint32_t *links;     // link words (below), D3Q19 with a mask only
+    const uint32_t *links;     // link words (below), with a mask only
 };
 
 // Link word of a node of a lattice with geometry, built on the host from the

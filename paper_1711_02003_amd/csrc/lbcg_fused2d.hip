@@ -1,5 +1,5 @@
-// Fused single-pass D2Q9 step on periodic lattices (arXiv:1711.02003, Sec. II,
-// Eqs. (1)-(11)), FP32 or FP16 storage.
+// Fused single-pass D2Q9 step (arXiv:1711.02003, Sec. II, Eqs. (1)-(11)), FP32
+// or FP16 storage, with or without geometry.
 //
 // The 2-D counterpart of the D3Q19 sweep: each wave owns a strip of 64
 // columns and sweeps a chunk of rows.  For row y+1 it pulls the 9 population
@@ -10,6 +10,12 @@
 // populations of a row are requested one row ahead of their use.  A wave's
 // LDS rows are its own, so no barrier is needed: a wave's LDS accesses
 // complete in program order.
+//
+// With geometry (compile-time switch) a node's link word tells whether it is
+// fluid; non-fluid nodes pull nothing and put the inlet's phase value (or a
+// sentinel that the gradient replaces by the centre node's psi) into the
+// LDS ring; a fluid node with non-fluid links stores its boundary values in
+// the upstream nodes' slots after its collision, as in the D3Q19 sweep.
 //
 // Every stored population is read from HBM once and written once: 2 x 18 x
 // sizeof(storage) bytes per node (144 B FP32), against ~224 B for the
@@ -29,6 +35,10 @@ struct Fused2dArgs {
     S *out;
     int nx, ny;
     int64_t pitch;
+    const uint8_t *mask;       // nullptr = every node fluid
+    const DevInlet *inlets;
+    const DevOutlet *outlets;
+    const uint32_t *links;     // link words (with a mask)
     const uint32_t *ctr_in;
     uint32_t *ctr_out;
     int nstrips, ychunks;
@@ -62,7 +72,9 @@ __device__ __forceinline__ void take2d(const Pending2d<S> &p, Pops<D2Q9, float> 
     for (int i = 0; i < D2Q9::Q; ++i) decode_pair<D2Q9, S, float>(p.v[i], i, q);
 }
 
-template <typename S>
+constexpr float kSentinel2d = 1e30f;  // LDS psi of a wall or outlet node
+
+template <typename S, bool MASKED>
 __device__ __forceinline__ void sweep2d(const Fused2dArgs<S> &a, const Model<float> &mo, int strip, int chunk,
                                         float *lds) {
     using L = D2Q9;
@@ -97,25 +109,56 @@ __device__ __forceinline__ void sweep2d(const Fused2dArgs<S> &a, const Model<flo
     // the 3-row psi ring of this wave: row yy lives in slot (yy - y0 + 1) % 3
     auto slot = [&](int yy) { return lds + ((yy - y0 + 1) % 3) * kRing; };
     auto wrapy = [&](int yy) { return yy < 0 ? yy + a.ny : (yy >= a.ny ? yy - a.ny : yy); };
+    auto link = [&](int xx, int yy) { return MASKED ? a.links[int64_t(xx) + int64_t(a.nx) * wrapy(yy)] : kLinkFluid; };
+    auto fluid = [&](uint32_t lk) { return !MASKED || (lk & kLinkFluid) != 0u; };
+    // LDS psi of a non-fluid node: the inlet's phase value, or the sentinel
+    // that the gradient replaces by the centre node's own psi
+    auto solid_psi = [&](uint8_t c) -> float {
+        if (c >= kInlet0 && c < kOutlet0) {
+            const DevInlet in = a.inlets[c - kInlet0];
+            return float((in.rhoR - in.rhoB) / (in.rhoR + in.rhoB));
+        }
+        return kSentinel2d;
+    };
 
     Pending2d<S> pp, rp;
+    // link words of the pending rows, and of the next request (read one
+    // request ahead, so that a pull never waits for its own link word)
+    uint32_t plk = kLinkFluid, rlk = kLinkFluid, ilk = kLinkFluid, glk = kLinkFluid;
+    if (MASKED && intile) ilk = link(x, y0 - 1);
+    if (MASKED && has_ring) glk = link(gx, y0 - 1);
     auto issue = [&](int yy) {
         const int yw = wrapy(yy);
-        if (has_ring) pull_row<S>(a, rin, rt, yw, rp);
-        if (intile) pull_row<S>(a, rin, it, yw, pp);
+        if (has_ring) {
+            rlk = glk;
+            if (fluid(rlk)) pull_row<S>(a, rin, rt, yw, rp);
+            if (MASKED) glk = link(gx, yy + 1);
+        }
+        if (intile) {
+            plk = ilk;
+            if (fluid(plk)) pull_row<S>(a, rin, it, yw, pp);
+            if (MASKED) ilk = link(x, yy + 1);
+        }
     };
     auto ring_psi = [&](int yy) {
         if (has_ring) {
-            Pops<L, T> q;
-            take2d<S>(rp, q);
-            T dr, rR, rB;
-            densities<L, T>(q, dr, rR, rB);
-            slot(yy)[rslot] = float(psi_of<T>(dr, rR, rB));
+            float v;
+            if (fluid(rlk)) {
+                Pops<L, T> q;
+                take2d<S>(rp, q);
+                T dr, rR, rB;
+                densities<L, T>(q, dr, rR, rB);
+                v = float(psi_of<T>(dr, rR, rB));
+            } else {
+                v = solid_psi(link_code(rlk));
+            }
+            slot(yy)[rslot] = v;
         }
     };
     T cd = 0, cR = 0, cB = 0, cj[3] = {0, 0, 0}, cS[6] = {0, 0, 0, 0, 0, 0};
     auto interior = [&](int yy, T &d, T &r36R, T &r36B, T j[3], T flux[6]) {
-        if (intile) {
+        if (intile && !fluid(plk)) slot(yy)[lane + 1] = solid_psi(link_code(plk));
+        if (intile && fluid(plk)) {
             Pops<L, T> q;
             take2d<S>(pp, q);
             Mom<T> m;
@@ -131,6 +174,26 @@ __device__ __forceinline__ void sweep2d(const Fused2dArgs<S> &a, const Model<flo
         }
     };
 
+    // With geometry, a chunk with no fluid node of its own has nothing to do
+    // (a non-fluid node's slots hold only what its fluid neighbours store).
+    // The link words are read 8 at a time, so that the loads of a batch are in
+    // flight together (a chunk of non-fluid nodes is then dismissed in a few
+    // load latencies, not one per row).
+    if (MASKED) {
+        bool any = false;
+        if (intile)
+            for (int yb = y0; yb < y1 && !any; yb += 8) {
+                uint32_t w[8];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) w[k] = link(x, min(yb + k, y1 - 1));
+                uint32_t acc = 0;
+#pragma unroll
+                for (int k = 0; k < 8; ++k) acc |= w[k];
+                any = (acc & kLinkFluid) != 0u;
+            }
+        if (!__builtin_amdgcn_ballot_w64(any)) return;  // uniform over the wave
+    }
+
     // prologue: psi of rows y0-1 and y0, moments of y0, requests of y0+1
     {
         T d, r, b, j[3], f[6];
@@ -143,6 +206,7 @@ __device__ __forceinline__ void sweep2d(const Fused2dArgs<S> &a, const Model<flo
     wait_memory();
     ring_psi(y0);
     interior(y0, cd, cR, cB, cj, cS);
+    uint32_t clk = plk;  // link word of the row being collided
     issue(y0 + 1);
 
     for (int y = y0; y < y1; ++y) {
@@ -152,16 +216,20 @@ __device__ __forceinline__ void sweep2d(const Fused2dArgs<S> &a, const Model<flo
         wait_memory();
         ring_psi(y + 1);
         interior(y + 1, nd, nR, nB, nj, nS);
+        const uint32_t nlk = plk;
         if (y + 2 <= y1) issue(y + 2);
         __builtin_amdgcn_wave_barrier();
-        if (intile) {
+        if (intile && fluid(clk)) {
             const float *sm = slot(y - 1), *s0 = slot(y), *sp = slot(y + 1);
             const int c = lane + 1;
+            const float pc = s0[c];
             T fx = 0, fy = 0;
 #pragma unroll
             for (int i = 1; i < L::Q; ++i) {
                 const float *sl = L::cy[i] > 0 ? sp : (L::cy[i] < 0 ? sm : s0);
-                const T wp = T(3.0 * wgt<L>(i)) * T(sl[c + L::cx[i]]);
+                float pv = sl[c + L::cx[i]];
+                if (MASKED) pv = pv == kSentinel2d ? pc : pv;
+                const T wp = T(3.0 * wgt<L>(i)) * T(pv);
                 if (L::cx[i]) fx += L::cx[i] > 0 ? wp : -wp;
                 if (L::cy[i]) fy += L::cy[i] > 0 ? wp : -wp;
             }
@@ -173,8 +241,37 @@ __device__ __forceinline__ void sweep2d(const Fused2dArgs<S> &a, const Model<flo
             const uint32_t yo = uint32_t(uniform(y)) * row;
 #pragma unroll
             for (int i = 0; i < L::Q; ++i) store_pair<P2>(rout, it[1], uint32_t(i) * cstride + yo, enc[i]);
+            // boundary values of the node's non-fluid links, stored in the
+            // upstream nodes' slots (the addresses it pulls them from)
+            if (MASKED && (clk & kLinkBits)) {
+                Geo g;
+                g.nx = a.nx;
+                g.ny = a.ny;
+                g.nz = 1;
+                g.N = int64_t(a.nx) * a.ny;
+                g.pitch = a.pitch;
+                g.mask = a.mask;
+                g.inlets = a.inlets;
+                g.outlets = a.outlets;
+                g.links = a.links;
+                const uint32_t yg[3] = {uint32_t(uniform(y == 0 ? a.ny - 1 : y - 1)) * row, yo,
+                                        uint32_t(uniform(y == a.ny - 1 ? 0 : y + 1)) * row};
+                OwnMom<T> om{};
+                if (clk & kLinkOutlet) om = own_moments<L, S, T>(enc);
+#pragma unroll
+                for (int i = 1; i < L::Q; ++i) {
+                    if (!((clk >> i) & 1u)) continue;
+                    uint8_t cd8 = link_code(clk);
+                    if (clk & kLinkMixed)
+                        cd8 = a.mask[int64_t(wrap_m1(x - L::cx[i], a.nx)) +
+                                     int64_t(a.nx) * wrap_m1(y - L::cy[i], a.ny)];
+                    store_pair<P2>(rout, it[1 - L::cx[i]], uint32_t(i) * cstride + yg[1 - L::cy[i]],
+                                   boundary_pair<L, S, T>(g, mo, i, cd8, enc[L::opp[i]], om));
+                }
+            }
         }
         __builtin_amdgcn_wave_barrier();
+        clk = nlk;
         cd = nd;
         cR = nR;
         cB = nB;
@@ -185,21 +282,27 @@ __device__ __forceinline__ void sweep2d(const Fused2dArgs<S> &a, const Model<flo
     }
 }
 
-// Work item k = chunk * nstrips + strip, kStripWaves items per block
-// (neighbouring strips of one chunk share a block and an L2).
-template <typename S>
+// kStripWaves work items per block.  Periodic lattices number the items
+// chunk-major (neighbouring strips of one chunk share a block and an L2).
+// With geometry they are numbered strip-major, so that the busy items of a
+// channel form runs of consecutive blocks (busy blocks interleaved with
+// blocks that return at once were measured to crowd onto fewer CUs), and the
+// tuner picks short chunks that spread a channel over the device.
+template <typename S, bool MASKED>
 __global__ void __launch_bounds__(kStrip * kStripWaves) k_step_fused2d(Fused2dArgs<S> a, Model<float> mo) {
     __shared__ float lds[kStripWaves * 3 * kRing];
     const int wave = threadIdx.x / kStrip;
     const int item = blockIdx.x * kStripWaves + wave;
     if (item == 0 && threadIdx.x == 0) *a.ctr_out = *a.ctr_in + 1u;
     if (item >= a.nstrips * a.ychunks) return;  // uniform over the wave
-    sweep2d<S>(a, mo, item % a.nstrips, item / a.nstrips, lds + wave * 3 * kRing);
+    const int strip = MASKED ? item / a.ychunks : item % a.nstrips;
+    const int chunk = MASKED ? item % a.ychunks : item / a.nstrips;
+    sweep2d<S, MASKED>(a, mo, strip, chunk, lds + wave * 3 * kRing);
 }
 
 bool fused2d_supported(int prec, const Geo &g) {
     const uint64_t elem = prec == 1 ? 4 : 2;
-    return (prec == 1 || prec == 2) && g.mask == nullptr && g.nz == 1 &&
+    return (prec == 1 || prec == 2) && g.nz == 1 && (g.mask == nullptr || g.links != nullptr) &&
            uint64_t(2 * D2Q9::Q) * uint64_t(g.pitch) * elem < (uint64_t(1) << 32);
 }
 
@@ -212,13 +315,22 @@ static hipError_t launch2d(const Geo &g, const ModelD &md, const void *in, void 
     a.nx = g.nx;
     a.ny = g.ny;
     a.pitch = g.pitch;
+    a.mask = g.mask;
+    a.inlets = g.inlets;
+    a.outlets = g.outlets;
+    a.links = g.links;
     a.ctr_in = ctr_in;
     a.ctr_out = ctr_out;
     a.nstrips = (g.nx + kStrip - 1) / kStrip;
     a.ychunks = ychunks < 1 ? 1 : (ychunks > g.ny ? g.ny : ychunks);
     const int items = a.nstrips * a.ychunks;
     const int blocks = (items + kStripWaves - 1) / kStripWaves;
-    hipLaunchKernelGGL(k_step_fused2d<S>, dim3(blocks), dim3(kStrip * kStripWaves), 0, s, a, to_model<float>(md));
+    if (g.mask)
+        hipLaunchKernelGGL((k_step_fused2d<S, true>), dim3(blocks), dim3(kStrip * kStripWaves), 0, s, a,
+                           to_model<float>(md));
+    else
+        hipLaunchKernelGGL((k_step_fused2d<S, false>), dim3(blocks), dim3(kStrip * kStripWaves), 0, s, a,
+                           to_model<float>(md));
     return hipGetLastError();
 }
 

@@ -84,7 +84,7 @@ Plan make_plan(const lbcg_params *p) {
     pl.state = align_up(size_t(2 * pl.Q) * size_t(pl.pitch) * pl.elem, kAlign);
     pl.psi = align_up(size_t(pl.pitch) * pl.tsize, kAlign);
     pl.mask = p->mask ? align_up(size_t(pl.pitch), kAlign) : 0;
-    pl.links = (p->mask && p->lattice == LBCG_D3Q19) ? align_up(sizeof(uint32_t) * size_t(pl.pitch), kAlign) : 0;
+    pl.links = p->mask ? align_up(sizeof(uint32_t) * size_t(pl.pitch), kAlign) : 0;
     pl.inl = align_up(sizeof(DevInlet) * size_t(p->n_inlets > 0 ? p->n_inlets : 1), kAlign);
     pl.outl = align_up(sizeof(DevOutlet) * size_t(p->n_outlets > 0 ? p->n_outlets : 1), kAlign);
     pl.partials = align_up(sizeof(double) * kDiagBlocks * kDiagVals, kAlign);
@@ -131,12 +131,13 @@ FusedShape pick_shape(const lbcg_sim *s, const lbcg_params *p) {
     if (s->lattice == LBCG_D2Q9) {
         // strips of 64 columns, rows split into chunks (zchunks counts them):
         // about 4096 strip chunks fill the device with 4 waves per SIMD, and
-        // chunks keep >= 8 rows
+        // chunks keep >= 8 rows; with geometry, chunks of 16 rows (the fluid
+        // of a channel then still spreads over the device)
         sh.rows = 1;
         int yc = p->tile[1];
         if (!yc && s->kernel == LBCG_KERNEL_FUSED) {
             const int64_t strips = (s->g.nx + 63) / 64;
-            const int64_t want = (4096 + strips - 1) / strips;
+            const int64_t want = s->g.mask ? (s->g.ny + 15) / 16 : (4096 + strips - 1) / strips;
             const int64_t cap = s->g.ny / 8 > 1 ? s->g.ny / 8 : 1;
             yc = int(want < 1 ? 1 : (want > cap ? cap : want));
         }
@@ -208,9 +209,9 @@ bool build_graph(lbcg_sim *s, int start) {
     return true;
 }
 
-// Link words of a D3Q19 lattice with geometry (encoding in lbcg_device.h).
+// Link words of a lattice with geometry (encoding in lbcg_device.h).
+template <class L>
 std::vector<uint32_t> link_words(int nx, int ny, int nz, const uint8_t *mask) {
-    using L = D3Q19;
     std::vector<uint32_t> out(size_t(nx) * ny * nz, 0u);
     auto wrap = [](int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); };
     for (int z = 0; z < nz; ++z)
@@ -379,7 +380,8 @@ int lbcg_create(const lbcg_params *p, void *dev_buf, size_t bytes, void *hip_str
         e = hipMemcpyAsync(s->mask_dev, p->mask, size_t(pl.N), hipMemcpyHostToDevice, s->stream);
     std::vector<uint32_t> links;
     if (e == hipSuccess && links_dev) {
-        links = link_words(s->g.nx, s->g.ny, s->g.nz, p->mask);
+        links = s->lattice == LBCG_D3Q19 ? link_words<D3Q19>(s->g.nx, s->g.ny, s->g.nz, p->mask)
+                                         : link_words<D2Q9>(s->g.nx, s->g.ny, s->g.nz, p->mask);
         e = hipMemcpyAsync(links_dev, links.data(), sizeof(uint32_t) * links.size(), hipMemcpyHostToDevice,
                            s->stream);
     }

@@ -230,6 +230,40 @@ def flow_focusing(nx: int = 512, ny: int = 128, nz: int = 64, lam: float = 1.0,
                     0.5 + lam / 2.0, 1.0, A, 0.7, mask, inlets, outlets, steps)
 
 
+def flow_focusing_2d(nx: int = 2048, ny: int = 512, lam: float = 3.0, u_disp: float = 0.005,
+                     u_side: float = 0.01, A: float = 0.01, steps: int = 20000) -> Workload:
+    """D2Q9 flow-focusing cross junction (the paper's 2-D device geometry,
+    after its Fig. 2): the D3Q19 junction's cross-section.
+
+    Dispersed (red) channel y in [3ny/8, 5ny/8) from x = 1, fed at x = 0 by
+    inlet 0 (u = (u_disp, 0), red).  Two side channels x in [nx/4, nx/4 +
+    ny/4) fed at y = 0 and y = ny-1 by inlets 1 and 2 (u = (0, +-u_side),
+    blue).  Main channel from x = nx/4 to the outlet column x = nx-1 (outlet
+    0, density 1).  Everything else wall.  tau_B = 1, tau_R = 1/2 + lam/2.
+    """
+    mask = np.full((1, ny, nx), WALL, np.uint8)
+    y0, y1 = 3 * ny // 8, 5 * ny // 8
+    xj0, xj1 = nx // 4, nx // 4 + ny // 4
+    mask[0, y0:y1, 1:nx - 1] = FLUID
+    mask[0, 1:ny - 1, xj0:xj1] = FLUID
+    mask[0, y0:y1, 0] = INLET0 + 0
+    mask[0, 0, xj0:xj1] = INLET0 + 1
+    mask[0, ny - 1, xj0:xj1] = INLET0 + 2
+    mask[0, y0:y1, nx - 1] = OUTLET0 + 0
+    x = np.arange(nx)[None, None, :]
+    psi = np.broadcast_to(tanh_profile(xj0 - 0.5 - x, 2.0), (1, ny, nx)).copy()
+    psi[:, :y0, :] = -1.0
+    psi[:, y1:, :] = -1.0
+    psi[mask != FLUID] = -1.0
+    rR, rB = colour_densities(psi)
+    inlets = [{"u": (u_disp, 0.0, 0.0), "rho_R": 1.0, "rho_B": 0.0},
+              {"u": (0.0, u_side, 0.0), "rho_R": 0.0, "rho_B": 1.0},
+              {"u": (0.0, -u_side, 0.0), "rho_R": 0.0, "rho_B": 1.0}]
+    outlets = [{"rho": 1.0}]
+    return Workload(f"d2q9_flow_focusing_{nx}x{ny}", "D2Q9", (nx, ny, 1), rR, rB, None,
+                    0.5 + lam / 2.0, 1.0, A, 0.7, mask, inlets, outlets, steps)
+
+
 def batch_boxes(n_boxes: int = 64, seed: int = 4, edge_lo: int = 32, edge_hi: int = 96,
                 steps: int = 1000) -> List[Workload]:
     """Independent periodic D3Q19 droplet boxes of uneven size.

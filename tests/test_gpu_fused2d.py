@@ -1,5 +1,5 @@
-"""GPU: the fused D2Q9 strip sweep (periodic lattices, FP32 and FP16
-storage) against the generic two-pass kernel (bitwise: both run the same
+"""GPU: the fused D2Q9 strip sweep (FP32 and FP16 storage, with and without
+geometry) against the generic two-pass kernel (bitwise: both run the same
 device arithmetic in the same order) and against the FP64 oracle."""
 import numpy as np
 import pytest
@@ -82,13 +82,64 @@ def test_fused2d_f32_matches_oracle_1000_steps(L, orc):
     assert abs(d1["mass_R"] - d0["mass_R"]) / d0["mass_R"] < 1e-6
 
 
-def test_geometry_and_bgk_stay_on_the_generic_kernel(L):
-    w = _random_2d((32, 16, 1), seed=1)
+def _masked_2d(dims, seed):
+    # walls along y = 0 and y = ny-1, an inlet column at x = 0, an outlet
+    # column at x = nx-1 and one interior wall node
+    w = _random_2d(dims, seed)
+    nx, ny, _ = dims
     m = np.zeros(w.shape, np.uint8)
-    m[:, 0, :] = 1
+    m[0, 0, :] = 1
+    m[0, -1, :] = 1
+    m[0, 1:-1, 0] = 2
+    m[0, 1:-1, -1] = 128
+    m[0, ny // 2, nx // 2] = 1
     w.mask = m
+    w.inlets = [{"u": (0.01, 0.002, 0.0), "rho_R": 0.8, "rho_B": 0.2}]
+    w.outlets = [{"rho": 1.02}]
+    return w
+
+
+@pytest.mark.parametrize("dims", [(70, 23, 1), (130, 9, 1), (7, 5, 1)])
+@pytest.mark.parametrize("prec", ["f32", "f16"])
+def test_fused2d_masked_matches_generic_bitwise(L, dims, prec):
+    w = _masked_2d(dims, seed=sum(dims) + 1)
+    _say(f"fused2d masked vs generic {dims} {prec}")
+    a = L.Sim.from_workload(w, precision=prec, kernel=L.KERNEL_FUSED)
+    b = L.Sim.from_workload(w, precision=prec, kernel=L.KERNEL_GENERIC)
+    a.step(50)
+    b.step(50)
+    assert np.array_equal(a.populations(), b.populations())
+
+
+@pytest.mark.parametrize("ychunks", [1, 4, 32])
+def test_fused2d_junction_chunk_invariance(L, ychunks):
+    w = W.flow_focusing_2d(256, 64)
+    ref = L.Sim.from_workload(w, precision="f32", kernel=L.KERNEL_GENERIC)
+    s = L.Sim.from_workload(w, precision="f32", kernel=L.KERNEL_FUSED, tile=(0, ychunks, 0))
+    ref.step(30)
+    s.step(30)
+    assert np.array_equal(s.populations(), ref.populations())
+
+
+def test_fused2d_junction_matches_oracle(L, orc):
+    # 2-D flow-focusing junction 256 x 64 (walls, three inlets, an outlet):
+    # FP32 strip sweep vs FP64 oracle after 500 steps.
+    w = W.flow_focusing_2d(256, 64)
+    _say("fused2d f32 junction 256x64 x500")
     s = L.Sim.from_workload(w, precision="f32")
-    assert s.launch_info()["kernel"] == L.KERNEL_GENERIC
-    w.mask = None
+    assert s.launch_info()["kernel"] == L.KERNEL_FUSED
+    o = oracle_for(orc, w, threads=8)
+    s.step(500)
+    o.step(500)
+    g, f = s.fields(), o.fields()
+    fl = w.mask == 0
+    eu = rel_l2(g["u"][:, fl], f["u"][:, fl])
+    ep = rel_l2(g["psi"][fl], f["psi"][fl])
+    _say(f"  relL2 u {eu:.3e} psi {ep:.3e} max|u| {np.abs(f['u']).max():.3e}")
+    assert eu < 1e-5 and ep < 1e-5
+
+
+def test_bgk_stays_on_the_generic_kernel(L):
+    w = _random_2d((32, 16, 1), seed=1)
     s = L.Sim.from_workload(w, precision="f32", collision=L.BGK)
     assert s.launch_info()["kernel"] == L.KERNEL_GENERIC
