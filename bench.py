@@ -145,6 +145,29 @@ def d2q9_form(torch, lbcg, W, steps=200, warmup=10):
     return out
 
 
+def focusing2d_form(torch, lbcg, W, steps=200, warmup=10):
+    """D2Q9 flow-focusing junction 8192 x 2048 (the paper's 2-D device
+    geometry: walls, three inlets, an outlet), FP32: the fused strip sweep
+    (tuned) and the two-pass generic kernel, fluid-node MLUPS."""
+    w = W.flow_focusing_2d(8192, 2048)
+    out = {"workload": w.name, "fluid_nodes": w.fluid_nodes, "nodes": w.nodes, "steps": steps}
+    for name, kernel in (("fused", lbcg.KERNEL_FUSED), ("generic", lbcg.KERNEL_GENERIC)):
+        stream = torch.cuda.Stream()
+        sim = lbcg.Sim.from_workload(w, precision="f32", kernel=kernel, stream=stream.cuda_stream)
+        sim.step(1)
+        if kernel == lbcg.KERNEL_FUSED:
+            sim.tune()
+        ms = time_sim(torch, sim, stream, steps, warmup)
+        info = sim.launch_info()
+        sim.close()
+        out[name] = {"mlups": round(w.fluid_nodes * steps / (ms / 1e3) / 1e6, 1),
+                     "ms_per_step": round(ms / steps, 4),
+                     "frac": round((144 + 1) * w.fluid_nodes * steps / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
+        if kernel == lbcg.KERNEL_FUSED:
+            out[name]["ychunks"] = info["zchunks"]
+    return out
+
+
 def focusing_form(torch, lbcg, W, steps=200, warmup=10):
     """Flow-focusing cross junction 512 x 128 x 64 (walls, inlets, outlet):
     FP32 and FP16 storage, fluid-node MLUPS and all-node MLUPS."""
@@ -329,6 +352,8 @@ def main():
         log(f"f16 {forms['f16']}")
         forms["d2q9"] = d2q9_form(torch, lbcg, W)
         log(f"d2q9 {forms['d2q9']}")
+        forms["focusing2d"] = focusing2d_form(torch, lbcg, W)
+        log(f"focusing2d {forms['focusing2d']}")
         forms["focusing"] = focusing_form(torch, lbcg, W)
         log(f"focusing {forms['focusing']}")
         forms["batched"] = batched_form(torch, lbcg, W)
