@@ -162,7 +162,7 @@ def focusing2d_form(torch, lbcg, W, steps=200, warmup=10):
         sim.close()
         out[name] = {"mlups": round(w.fluid_nodes * steps / (ms / 1e3) / 1e6, 1),
                      "ms_per_step": round(ms / steps, 4),
-                     "frac": round((144 + 1) * w.fluid_nodes * steps / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
+                     "frac": round((144 + 4) * w.fluid_nodes * steps / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
         if kernel == lbcg.KERNEL_FUSED:
             out[name]["ychunks"] = info["zchunks"]
     return out
@@ -184,7 +184,7 @@ def focusing_form(torch, lbcg, W, steps=200, warmup=10):
         out[prec] = {"mlups": round(w.fluid_nodes * steps / (ms / 1e3) / 1e6, 1),
                      "lattice_mlups": round(w.nodes * steps / (ms / 1e3) / 1e6, 1),
                      "ms_per_step": round(ms / steps, 4),
-                     "frac": round((2 * 38 * elem + 1) * w.fluid_nodes * steps / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "frac": round((2 * 38 * elem + 4) * w.fluid_nodes * steps / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
                      "rows": shape["rows"], "zchunks": shape["zchunks"]}
     return out
 
