@@ -5,6 +5,8 @@
     python -m paper_1711_02003_amd.profiling traffic <fetch counter_collection.csv>
         <write counter_collection.csv> <kernel substring> <timed dispatches> <nodes> <out.txt>
         "<commands>"
+    python -m paper_1711_02003_amd.profiling forms <kernel_trace.csv> <out.md> <timed dispatches>
+        "<command>"
 
 The benchmark first times candidate launch shapes of the kernel (same kernel
 name), then runs the timed region; both summaries therefore report the last
@@ -114,6 +116,39 @@ def traffic_summary(fetch_csv, write_csv, kernel_sub, timed, nodes, out_txt, com
     return txt
 
 
+FORM_KERNELS = [("D2Q9 4096² droplets, FP32", "void lbcg::k_step_fused2d<float, false>"),
+                ("D2Q9 junction 8192×2048, FP32", "void lbcg::k_step_fused2d<float, true>"),
+                ("D3Q19 junction 512×128×64, FP32", "void lbcg::k_step_fused<float, float, 8, true>"),
+                ("D3Q19 junction 512×128×64, FP16", "_ZN4lbcg12k_step_fusedIDF16_fLi8ELb1EE")]
+
+
+def forms_summary(trace_csv, out_md, timed, command):
+    """Per benchmark form, the last `timed` dispatches of its fused kernel
+    (each form's timed region comes after its warm-up and tuning)."""
+    rows = list(csv.DictReader(open(trace_csv)))
+    lines = ["# rocprofv3 kernel trace: benchmark forms (fused sweeps)", "",
+             f"Command: `{command}`", "",
+             f"Each form times {timed} steps after its warm-up (and, for the fused sweeps, after the tuner's "
+             f"trial launches); the rows below take the last {timed} dispatches of each kernel, i.e. that "
+             "form's timed region.", "",
+             "| form | kernel | dispatches in run | avg us (timed) | min us | max us | "
+             "first start to last end, per dispatch us |",
+             "|---|---|---|---|---|---|---|"]
+    for form, prefix in FORM_KERNELS:
+        ks = sorted([r for r in rows if r["Kernel_Name"].startswith(prefix)], key=lambda r: int(r["Start_Timestamp"]))
+        if not ks:
+            continue
+        tail = ks[-timed:]
+        d = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in tail]
+        span = (int(tail[-1]["End_Timestamp"]) - int(tail[0]["Start_Timestamp"])) / 1e3
+        lines.append(f"| {form} | `{prefix.replace('void lbcg::', '')}` | {len(ks)} | {sum(d) / len(d):.1f} | "
+                     f"{min(d):.1f} | {max(d):.1f} | {span / len(d):.1f} |")
+    txt = "\n".join(lines) + "\n"
+    with open(out_md, "w") as f:
+        f.write(txt)
+    return txt
+
+
 if __name__ == "__main__":
     mode = sys.argv[1]
     if mode == "trace":
@@ -121,5 +156,7 @@ if __name__ == "__main__":
     elif mode == "traffic":
         print(traffic_summary(sys.argv[2], sys.argv[3], sys.argv[4], int(sys.argv[5]), int(sys.argv[6]),
                               sys.argv[7], sys.argv[8]))
+    elif mode == "forms":
+        print(forms_summary(sys.argv[2], sys.argv[3], int(sys.argv[4]), sys.argv[5]))
     else:
         raise SystemExit(__doc__)
