@@ -143,3 +143,42 @@ def test_bgk_stays_on_the_generic_kernel(L):
     w = _random_2d((32, 16, 1), seed=1)
     s = L.Sim.from_workload(w, precision="f32", collision=L.BGK)
     assert s.launch_info()["kernel"] == L.KERNEL_GENERIC
+
+
+def _laplace_fit(runs, n):
+    # pressure jump of each disc (Eq. (8), alpha = 4/9: p = rho / 3) and the
+    # fit dp = sigma / R + c over the effective radii
+    yy, xx = np.mgrid[0:n, 0:n]
+    c = (n - 1) / 2
+    r = np.sqrt((xx - c) ** 2 + (yy - c) ** 2)
+    Rs, dps = [], []
+    for f in runs:
+        p = (f["rhoR"] + f["rhoB"])[0] / 3
+        Reff = np.sqrt(((1 + f["psi"][0]) / 2).sum() / np.pi)
+        Rs.append(Reff)
+        dps.append(p[r < Reff - 5].mean() - p[r > Reff + 8].mean())
+    M = np.vstack([1 / np.array(Rs), np.ones(len(Rs))]).T
+    (sigma, c0), *_ = np.linalg.lstsq(M, np.array(dps), rcond=None)
+    return sigma, c0, Rs, dps
+
+
+def test_laplace_law_fused_f32_matches_oracle(L, orc):
+    # Static discs R in {10, 16, 24} on 96^2 (tau = 1, A = 0.01, 3000 steps):
+    # the FP32 strip sweep gives the same effective radii, pressure jumps and
+    # fitted surface tension as the FP64 oracle.
+    n, A = 96, 0.01
+    gpu, ref = [], []
+    for R in (10, 16, 24):
+        w = W.static_droplet_2d(n=n, R=R, noise=0.0, A=A)
+        s = L.Sim.from_workload(w, precision="f32")
+        assert s.launch_info()["kernel"] == L.KERNEL_FUSED
+        s.step(3000)
+        gpu.append(s.fields())
+        s.close()
+        ref.append(oracle_for(orc, w, threads=8).step(3000).fields())
+    sg, cg, Rg, dg = _laplace_fit(gpu, n)
+    so, co, Ro, do = _laplace_fit(ref, n)
+    _say(f"  sigma gpu {sg:.6e} oracle {so:.6e}; dp gpu {np.round(dg, 8)} oracle {np.round(do, 8)}")
+    assert np.allclose(Rg, Ro, rtol=0, atol=1e-4)
+    assert np.allclose(dg, do, rtol=1e-3, atol=0)
+    assert abs(sg / so - 1) < 1e-3
