@@ -355,3 +355,41 @@ def test_library_loaded_before_torch_in_fresh_process(L):
     _say(r.stdout.strip()[-200:])
     assert r.returncode == 0, r.stderr[-2000:]
     assert "fresh process ok" in r.stdout
+
+
+def test_laplace_law_3d_fused_f32_matches_oracle(L, orc):
+    # Static spheres R in {6, 8, 10} in 32^3 (tau = 1, A = 0.005, 1500 steps):
+    # the FP32 fused D3Q19 sweep gives the oracle's effective radii, pressure
+    # jumps (p = rho / 3, Eq. (8) for D3Q19 with alpha = w_0) and fitted
+    # surface tension of dp = 2 sigma / R.
+    n = 32
+    zz, yy, xx = np.mgrid[0:n, 0:n, 0:n]
+    c = (n - 1) / 2
+    r = np.sqrt((xx - c) ** 2 + (yy - c) ** 2 + (zz - c) ** 2)
+
+    def jump(f):
+        p = (f["rhoR"] + f["rhoB"]) / 3
+        Reff = (3 * ((1 + f["psi"]) / 2).sum() / (4 * np.pi)) ** (1 / 3)
+        return Reff, p[r < Reff - 4].mean() - p[r > Reff + 5].mean()
+
+    res = {"gpu": [], "orc": []}
+    for R in (6.0, 8.0, 10.0):
+        w = W.static_droplet_3d(n, R=R, A=0.005)
+        s = L.Sim.from_workload(w, precision="f32")
+        assert s.launch_info()["kernel"] == L.KERNEL_FUSED
+        s.step(1500)
+        res["gpu"].append(jump(s.fields()))
+        s.close()
+        res["orc"].append(jump(oracle_for(orc, w, threads=16).step(1500).fields()))
+    fits = {}
+    for k, v in res.items():
+        Rs, dps = np.array(v).T
+        M = np.vstack([2 / Rs, np.ones(len(Rs))]).T
+        (sigma, c0), *_ = np.linalg.lstsq(M, dps, rcond=None)
+        fits[k] = sigma
+    _say(f"  radii gpu {[round(x[0], 5) for x in res['gpu']]} oracle {[round(x[0], 5) for x in res['orc']]}; "
+         f"sigma gpu {fits['gpu']:.6e} oracle {fits['orc']:.6e}")
+    for (Rg, dg), (Ro, do) in zip(res["gpu"], res["orc"]):
+        assert abs(Rg - Ro) < 1e-4
+        assert abs(dg / do - 1) < 1e-3
+    assert abs(fits["gpu"] / fits["orc"] - 1) < 1e-3
