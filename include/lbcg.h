@@ -61,12 +61,29 @@ extern "C" {
 
 /* Kernel choice: automatic, the two-pass generic kernel (every lattice,
  * precision, collision and boundary) or the fused single-pass kernel (F32 or
- * F16 storage, regularized collision, state buffers below 4 GiB; D3Q19 with
- * any geometry, D2Q9 periodic).  Automatic picks the fused kernel where it
- * applies. */
+ * F16 storage, regularized collision, state buffers below 4 GiB; D3Q19 or
+ * D2Q9, any geometry).  Automatic picks the fused kernel where it applies.
+ *
+ * LBCG_KERNEL_COMPACT (never picked automatically): the fused D3Q19 sweep on
+ * a compact state, for periodic lattices (no mask), F32, regularized
+ * collision, tiles of 8 rows (tile[0] 0 or 8), 38 x 4 x pitch bytes below
+ * 4 GiB (pitch = node count rounded up to 64).  Eq. (10) splits every
+ * population of a node with coefficients that depend only on that node and
+ * on the speed class of the direction, so each node stores its 19 total
+ * populations and a 32-byte record of colour scalars (its minority share and
+ * one 3-vector per speed class) and the receiver of a population splits it:
+ * 216 bytes of memory traffic per node and step instead of 304.  Results
+ * agree with the pair-state kernels up to rounding.  The first step
+ * after lbcg_init_fields or lbcg_set_state reads the pair state; the calls
+ * that read the state (fields, populations, diagnostics, lbcg_get_state)
+ * first convert the compact state to a pair state in the handle's pair
+ * buffer, which the compact steps leave unused (one extra kernel, no change
+ * to the trajectory).  lbcg_footprint
+ * adds the two compact buffers (2 x 108 x pitch bytes). */
 #define LBCG_KERNEL_AUTO 0
 #define LBCG_KERNEL_GENERIC 1
 #define LBCG_KERNEL_FUSED 2
+#define LBCG_KERNEL_COMPACT 3
 
 /* Mask codes (one byte per node): 0 fluid; 1 wall (half-way bounce-back);
  * 2 + j inlet j (moving-wall velocity inlet); 128 + j outlet j (pressure
@@ -197,11 +214,11 @@ void lbcg_destroy(lbcg_sim *s);
 /* Static description of an LBCG_* status code. */
 const char *lbcg_strerror(int status);
 
-/* Launch shape chosen for the handle: kernel kind (LBCG_KERNEL_GENERIC or
- * LBCG_KERNEL_FUSED), rows per block, z chunks. */
+/* Launch shape chosen for the handle: kernel kind (LBCG_KERNEL_GENERIC,
+ * LBCG_KERNEL_FUSED or LBCG_KERNEL_COMPACT), rows per block, z chunks. */
 int lbcg_launch_info(lbcg_sim *s, int32_t *kernel, int32_t *rows, int32_t *zchunks);
 
-/* Choose the fused kernel's launch shape for this handle by timing candidate
+/* Choose the fused (or compact) kernel's launch shape for this handle by timing candidate
  * shapes (rows 4 or 8; z splits that fill the device once, twice or four
  * times; chunks of 8 to 64 planes) on the handle's own lattice, stepping the
  * current state into the spare buffer so the state does not change.  Keeps

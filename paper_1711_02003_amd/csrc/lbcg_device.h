@@ -301,6 +301,20 @@ struct Pops {
     }
 };
 
+// Populations pulled from the compact state: population i came from node
+// x - c_i with that node's minority share mm[i] and majority flag, and vd[i]
+// is 36 x its recolouring term c_i . V (V of the sender's speed class, signed
+// for the sender's minority colour), so that 36 x the minority colour part is
+// mm[i] (36 w_i + 36 df[i]) + vd[i].
+template <class L, typename T>
+struct CPops {
+    T df[L::Q];
+    T mm[L::Q];
+    T vd[L::Q];
+    uint32_t red;
+    __device__ __forceinline__ bool flag(int i) const { return (red >> i) & 1u; }
+};
+
 // The two stored values of a population travel together: the state is Q
 // arrays (one per direction) of value pairs (df_i, m_i), element n of array i
 // at pair index i * pitch + n.  A pull then moves one 2-wide element per
@@ -427,13 +441,22 @@ __device__ __forceinline__ void colour_parts(const Pops<L, T> &p, int i, T &r36,
     r36 = fl ? t : mu;
     b36 = fl ? mu : t;
 }
+template <class L, typename T>
+__device__ __forceinline__ void colour_parts(const CPops<L, T> &p, int i, T &r36, T &b36) {
+    const T d = p.df[i];
+    const T mu = p.mm[i] * (T(w36<L>(i)) + T(36) * d) + p.vd[i];
+    const T t = T(36) * d - mu;
+    const bool fl = p.flag(i);
+    r36 = fl ? t : mu;
+    b36 = fl ? mu : t;
+}
 
 // Densities (Eq. (2)): the deviation of the total density and 36 x the red
 // and blue densities (each exact in the other colour's bulk).  Every path
 // computes psi through this one expression sequence, so psi is bitwise the
 // same whichever kernel or tile shape produced it.
-template <class L, typename T>
-__device__ __forceinline__ void densities(const Pops<L, T> &p, T &drho_out, T &r36R, T &r36B) {
+template <class L, typename T, class P>
+__device__ __forceinline__ void densities(const P &p, T &drho_out, T &r36R, T &r36B) {
     T drho = 0, Ra = 0, Ba = 0;
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) {
@@ -477,8 +500,8 @@ struct Mom {
     T S[6];
 };
 
-template <class L, typename T>
-__device__ __forceinline__ void moments(const Pops<L, T> &p, Mom<T> &m) {
+template <class L, typename T, class P>
+__device__ __forceinline__ void moments(const P &p, Mom<T> &m) {
     T drho = 0, Ra = 0, Ba = 0;
     T jd[3] = {0, 0, 0}, Sd[3] = {0, 0, 0}, So[3] = {0, 0, 0};
 #pragma unroll
@@ -653,10 +676,38 @@ __device__ __forceinline__ void pull_node(const Geo &g, const Model<T> &, const 
 // of every direction.
 template <class L, typename T>
 struct PostOut {
+    static constexpr bool kCompact = false;
     T df[L::Q];
     T mm[L::Q];
     uint32_t red;
 };
+
+// Output of one node in compact form: the new total deviations and the
+// node's colour scalars, from which a receiver recolours each population
+// (Eq. (10) is linear in f_i with coefficients that depend only on the
+// sending node and on the speed class of c_i).  For a population f_i that
+// the node sends, its minority colour part is
+//   M f_i + (c_i . V_c) / 36,
+// with M the node's minority share, c the speed class of c_i (axis or
+// diagonal) and V_c = +-36 beta rho^R rho^B / rho^2 k_c F / |F|, signed for
+// the minority colour, k_c = (w_c rho + rho^R (phi_c^R - w_c) +
+// rho^B (phi_c^B - w_c)) / |c_c|.
+template <class L, typename T>
+struct CompactOut {
+    static constexpr bool kCompact = true;
+    T df[L::Q];
+    T M;
+    bool redmaj;
+    T Va[3], Vd[3];
+};
+
+// First axis and first diagonal direction of a lattice.
+template <class L>
+__host__ __device__ constexpr int first_dir(int n2) {
+    for (int i = 1; i < L::Q; ++i)
+        if (csq<L>(i) == n2) return i;
+    return 0;
+}
 
 // Collision (Eq. (11), or Eq. (5) with bgk), perturbation (Eq. (9)) and
 // recolouring (Eq. (10)) from the node's density deviation, colour
@@ -667,9 +718,13 @@ struct PostOut {
 // Opposite directions i and -i share every even term (weights, Q_i, (c.u)^2,
 // (F.c)^2, B_i, phi_i) and flip the odd ones (c.u, cos), so the update is
 // computed once per pair.
-template <class L, typename T>
+//
+// With a CompactOut the recolouring is left to the receiver: the node emits
+// its total deviations and the scalars that define every population's
+// colour split.
+template <class L, typename T, class O>
 __device__ __forceinline__ void collide(const Model<T> &mo, T drho, T r36R, T r36B, const T j[3], const T S[6],
-                                        const T F[3], const Pops<L, T> *pin, PostOut<L, T> &o) {
+                                        const T F[3], const Pops<L, T> *pin, O &o) {
     const T rho = T(1) + drho;
     const T rR = r36R * T(1.0 / 36.0), rB = r36B * T(1.0 / 36.0);
     const T inv_rho = rcp<T>(rho);
@@ -707,7 +762,7 @@ __device__ __forceinline__ void collide(const Model<T> &mo, T drho, T r36R, T r3
     const T invFn = hasF ? rcp<T>(Fn) : T(0);
     const T seg = mo.beta * rR * rB * inv_rho * inv_rho;
     const T wrho = rho * T(1.5) * usq;  // rho u^2 / (2 c_s^2)
-    o.red = 0;
+    if constexpr (!O::kCompact) o.red = 0;
     T dsum = T(0);  // sum of the new moving deviations
 
 #pragma unroll
@@ -744,6 +799,15 @@ __device__ __forceinline__ void collide(const Model<T> &mo, T drho, T r36R, T r3
             ev = base + T(0.5) * (di + db);
             od = lin + T(0.5) * (di - db);
         }
+        if constexpr (O::kCompact) {
+            if (hasF) {
+                const T Fh = (Fx * cx + Fy * cy + Fz * cz) * invFn;
+                ev += mo.Abar * Fn * (w * Fh * Fh - T(bcoef<L>(i)));
+            }
+            o.df[i] = ev + od;
+            o.df[ib] = ev - od;
+            dsum += o.df[i] + o.df[ib];
+        } else {
         T cosp = T(0);
         if (hasF) {
             const T Fh = (Fx * cx + Fy * cy + Fz * cz) * invFn;
@@ -770,6 +834,7 @@ __device__ __forceinline__ void collide(const Model<T> &mo, T drho, T r36R, T r3
         o.mm[ib] = m;
         o.red |= fl ? (1u << ib) : 0u;
         dsum += d_i + d_b;
+        }
     }
     // The rest population is the remainder that keeps the node's mass: the
     // relaxation, the perturbation and the recolouring all conserve it, so
@@ -777,7 +842,29 @@ __device__ __forceinline__ void collide(const Model<T> &mo, T drho, T r36R, T r3
     // that should cancel (sum_i (phi_i - w_i), sum_i w_i Q_i : N with
     // phat != 1/3) would otherwise add a small mass of one sign every step.
     // Its recolouring term is zero (cos phi_0 = 0), so its share is rho^R/rho.
-    {
+    if constexpr (O::kCompact) {
+        T m;
+        bool fl;
+        split_shares<T>(sR, sB, m, fl);
+        o.df[0] = drho - dsum;
+        o.M = m;
+        o.redmaj = fl;
+        // 36 x the recolouring term of Eq. (10) as c_i . V_c, signed for the
+        // minority colour (f^B_i = (rho^B/rho) f_i - rec_i, f^R_i = ... + rec_i)
+        constexpr int ia = first_dir<L>(1), id = first_dir<L>(2);
+        const T g = hasF ? (fl ? T(-36) : T(36)) * seg * invFn : T(0);
+        const T ka = T(inv_len<L>(ia)) * (T(wgt<L>(ia)) * rho + rR * dphi<L, T>(ia, mo.dR0, mo.kR) +
+                                          rB * dphi<L, T>(ia, mo.dB0, mo.kB));
+        const T kd = T(inv_len<L>(id)) * (T(wgt<L>(id)) * rho + rR * dphi<L, T>(id, mo.dR0, mo.kR) +
+                                          rB * dphi<L, T>(id, mo.dB0, mo.kB));
+        const T ga = g * ka, gd = g * kd;
+        o.Va[0] = ga * Fx;
+        o.Va[1] = ga * Fy;
+        o.Va[2] = ga * Fz;
+        o.Vd[0] = gd * Fx;
+        o.Vd[1] = gd * Fy;
+        o.Vd[2] = gd * Fz;
+    } else {
         T m;
         bool fl;
         split_shares<T>(sR, sB, m, fl);

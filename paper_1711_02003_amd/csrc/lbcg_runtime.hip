@@ -28,7 +28,7 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 struct Plan {
     int Q;
     int64_t N, pitch, staging_nodes;
-    size_t elem, tsize, state, psi, mask, links, inl, outl, partials, diag, ctr, staging, total;
+    size_t elem, tsize, state, cstate, psi, mask, links, inl, outl, partials, diag, ctr, staging, total;
 };
 
 int validate(const lbcg_params *p) {
@@ -36,7 +36,7 @@ int validate(const lbcg_params *p) {
     if (p->lattice != LBCG_D2Q9 && p->lattice != LBCG_D3Q19) return LBCG_E_INVAL;
     if (p->precision < LBCG_F64 || p->precision > LBCG_F16) return LBCG_E_INVAL;
     if (p->collision != LBCG_REGULARIZED && p->collision != LBCG_BGK) return LBCG_E_INVAL;
-    if (p->kernel < LBCG_KERNEL_AUTO || p->kernel > LBCG_KERNEL_FUSED) return LBCG_E_INVAL;
+    if (p->kernel < LBCG_KERNEL_AUTO || p->kernel > LBCG_KERNEL_COMPACT) return LBCG_E_INVAL;
     for (int a = 0; a < 3; ++a)
         if (p->dims[a] < 1 || p->dims[a] > (int64_t(1) << 20)) return LBCG_E_INVAL;
     if (p->lattice == LBCG_D2Q9 && p->dims[2] != 1) return LBCG_E_INVAL;
@@ -68,6 +68,7 @@ int validate(const lbcg_params *p) {
     }
     if (p->tile[0] < 0 || p->tile[1] < 0) return LBCG_E_INVAL;
     if (p->tile[0] != 0 && p->tile[0] != 4 && p->tile[0] != 8) return LBCG_E_INVAL;
+    if (p->kernel == LBCG_KERNEL_COMPACT && p->tile[0] == 4) return LBCG_E_INVAL;  // 8-row tiles only
     if (p->tile[1] > 4096) return LBCG_E_INVAL;
     return LBCG_OK;
 }
@@ -82,6 +83,9 @@ Plan make_plan(const lbcg_params *p) {
     pl.staging_nodes = pl.N < kStagingMax ? pl.N : kStagingMax;
     const int per = 2 * pl.Q > 6 ? 2 * pl.Q : 6;
     pl.state = align_up(size_t(2 * pl.Q) * size_t(pl.pitch) * pl.elem, kAlign);
+    pl.cstate = p->kernel == LBCG_KERNEL_COMPACT
+                    ? align_up(size_t(kCompactBytes) * size_t(pl.pitch), kAlign)
+                    : 0;
     pl.psi = align_up(size_t(pl.pitch) * pl.tsize, kAlign);
     pl.mask = p->mask ? align_up(size_t(pl.pitch), kAlign) : 0;
     pl.links = p->mask ? align_up(sizeof(uint32_t) * size_t(pl.pitch), kAlign) : 0;
@@ -91,7 +95,7 @@ Plan make_plan(const lbcg_params *p) {
     pl.diag = align_up(sizeof(double) * 16, kAlign);
     pl.ctr = kAlign;
     pl.staging = align_up(sizeof(double) * size_t(per) * size_t(pl.staging_nodes), kAlign);
-    pl.total = 2 * pl.state + pl.psi + pl.mask + pl.links + pl.inl + pl.outl + pl.partials + pl.diag + pl.ctr +
+    pl.total = 2 * pl.state + 2 * pl.cstate + pl.psi + pl.mask + pl.links + pl.inl + pl.outl + pl.partials + pl.diag + pl.ctr +
                pl.staging + kAlign;
     return pl;
 }
@@ -146,11 +150,13 @@ FusedShape pick_shape(const lbcg_sim *s, const lbcg_params *p) {
     }
     sh.rows = p->tile[0] ? p->tile[0] : 8;
     int zc = p->tile[1];
-    if (!zc && s->kernel == LBCG_KERNEL_FUSED) {
+    if (!zc && (s->kernel == LBCG_KERNEL_FUSED || s->kernel == LBCG_KERNEL_COMPACT)) {
         // One wave of resident blocks: each z chunk re-reads two planes, so use
         // as few (long) chunks as fill the device, but keep chunks >= 8 planes.
         const int64_t tiles = int64_t((s->g.nx + 63) / 64) * ((s->g.ny + sh.rows - 1) / sh.rows);
-        const int64_t resident = fused_resident_blocks(s->prec, sh.rows, s->g.mask != nullptr);
+        const int64_t resident = s->kernel == LBCG_KERNEL_COMPACT
+                                     ? compact_resident_blocks(sh.rows)
+                                     : fused_resident_blocks(s->prec, sh.rows, s->g.mask != nullptr);
         int64_t want = (resident + tiles - 1) / tiles;
         const int64_t cap = s->g.nz / 8 > 1 ? s->g.nz / 8 : 1;
         zc = int(want < 1 ? 1 : (want > cap ? cap : want));
@@ -160,11 +166,24 @@ FusedShape pick_shape(const lbcg_sim *s, const lbcg_params *p) {
 }
 
 // One time step from buf[cur] into buf[cur ^ 1].
+// With the compact kernel, a pulled step reads cbuf[cur] (or, right after an
+// initialisation or a restore, the pair state in buf[cur]) and writes
+// cbuf[cur ^ 1].
 hipError_t enqueue_step(lbcg_sim *s, bool pulled) {
     const void *in = s->buf[s->cur];
     void *out = s->buf[s->cur ^ 1];
     const uint32_t *ctr_in = s->ctr + s->cur;
     uint32_t *ctr_out = s->ctr + (s->cur ^ 1);
+    if (s->kernel == LBCG_KERNEL_COMPACT && pulled) {
+        const bool pair_in = !s->compact;
+        hipError_t e = launch_step_compact(s->g, s->md, pair_in ? s->buf[s->cur] : s->cbuf[s->cur], pair_in,
+                                           s->cbuf[s->cur ^ 1], ctr_in, ctr_out, s->shape, s->stream);
+        if (e == hipSuccess) {
+            s->compact = true;
+            s->expanded = false;
+        }
+        return e;
+    }
     if (s->kernel == LBCG_KERNEL_FUSED && pulled) return launch_fused(s, in, out, ctr_in, ctr_out, s->shape);
     hipError_t e = launch_psi(s->lattice, s->prec, s->g, s->md, in, pulled, s->psi, s->stream);
     if (e != hipSuccess) return e;
@@ -326,6 +345,10 @@ int lbcg_create(const lbcg_params *p, void *dev_buf, size_t bytes, void *hip_str
     base += pl.state;
     s->buf[1] = base;
     base += pl.state;
+    s->cbuf[0] = pl.cstate ? base : nullptr;
+    base += pl.cstate;
+    s->cbuf[1] = pl.cstate ? base : nullptr;
+    base += pl.cstate;
     s->psi = base;
     base += pl.psi;
     s->mask_dev = p->mask ? reinterpret_cast<uint8_t *>(base) : nullptr;
@@ -398,8 +421,10 @@ int lbcg_create(const lbcg_params *p, void *dev_buf, size_t bytes, void *hip_str
         kind = (any_fused_supported(s->lattice, s->prec, s->g) && s->collision == LBCG_REGULARIZED)
                    ? LBCG_KERNEL_FUSED
                    : LBCG_KERNEL_GENERIC;
-    if (kind == LBCG_KERNEL_FUSED &&
-        (!any_fused_supported(s->lattice, s->prec, s->g) || s->collision != LBCG_REGULARIZED)) {
+    if ((kind == LBCG_KERNEL_FUSED &&
+         (!any_fused_supported(s->lattice, s->prec, s->g) || s->collision != LBCG_REGULARIZED)) ||
+        (kind == LBCG_KERNEL_COMPACT &&
+         (!compact_supported(s->lattice, s->prec, s->g) || s->collision != LBCG_REGULARIZED))) {
         release(s);
         delete s;
         return LBCG_E_INVAL;
@@ -407,6 +432,8 @@ int lbcg_create(const lbcg_params *p, void *dev_buf, size_t bytes, void *hip_str
     s->kernel = kind;
     s->shape = pick_shape(s, p);
     s->cur = 0;
+    s->compact = false;
+    s->expanded = false;
     s->pulled = false;
     s->initialised = false;
     s->step = 0;
@@ -433,6 +460,7 @@ int lbcg_init_fields(lbcg_sim *s, const double *rhoR, const double *rhoB, const 
     HIP_TRY(hipMemsetAsync(s->ctr, 0, 2 * sizeof(uint32_t), s->stream));
     HIP_TRY(hipStreamSynchronize(s->stream));
     s->cur = 0;
+    s->compact = false;
     s->pulled = false;
     s->initialised = true;
     s->step = 0;
@@ -451,9 +479,10 @@ int lbcg_step(lbcg_sim *s, int64_t n) {
             ++s->step;
             continue;
         }
-        if (n >= kGraphSteps && !s->graph_failed) {
+        if (n >= kGraphSteps && !s->graph_failed && (s->kernel != LBCG_KERNEL_COMPACT || s->compact)) {
             if (!s->graph[s->cur] && !build_graph(s, s->cur)) continue;
             HIP_TRY(hipGraphLaunch(s->graph[s->cur], s->stream));
+            s->expanded = false;
             n -= kGraphSteps;
             s->step += kGraphSteps;
             continue;
@@ -466,6 +495,15 @@ int lbcg_step(lbcg_sim *s, int64_t n) {
     return LBCG_OK;
 }
 
+// Pair state of a compact state in buf[cur], for the calls that read the
+// state (the compact state itself stays the one the next step reads).
+static hipError_t ensure_pairs(lbcg_sim *s) {
+    if (!s->compact || s->expanded) return hipSuccess;
+    hipError_t e = launch_expand(s->g, s->cbuf[s->cur], s->buf[s->cur], s->stream);
+    if (e == hipSuccess) s->expanded = true;
+    return e;
+}
+
 int lbcg_synchronize(lbcg_sim *s) {
     if (!s) return LBCG_E_INVAL;
     HIP_TRY(hipStreamSynchronize(s->stream));
@@ -475,6 +513,7 @@ int lbcg_synchronize(lbcg_sim *s) {
 int lbcg_fields(lbcg_sim *s, double *rhoR, double *rhoB, double *u, double *psi) {
     if (!s) return LBCG_E_INVAL;
     if (!s->initialised) return LBCG_E_STATE;
+    HIP_TRY(ensure_pairs(s));
     const int64_t N = s->g.N, C = s->staging_nodes;
     for (int64_t n0 = 0; n0 < N; n0 += C) {
         const int64_t cnt = (N - n0) < C ? (N - n0) : C;
@@ -496,6 +535,7 @@ int lbcg_fields(lbcg_sim *s, double *rhoR, double *rhoB, double *u, double *psi)
 int lbcg_populations(lbcg_sim *s, double *f) {
     if (!s || !f) return LBCG_E_INVAL;
     if (!s->initialised) return LBCG_E_STATE;
+    HIP_TRY(ensure_pairs(s));
     const int64_t N = s->g.N, C = s->staging_nodes;
     for (int64_t n0 = 0; n0 < N; n0 += C) {
         const int64_t cnt = (N - n0) < C ? (N - n0) : C;
@@ -514,6 +554,7 @@ int lbcg_populations_at(lbcg_sim *s, const int64_t *nodes, int64_t count, double
     if (!s->initialised) return LBCG_E_STATE;
     for (int64_t j = 0; j < count; ++j)
         if (nodes[j] < 0 || nodes[j] >= s->g.N) return LBCG_E_INVAL;
+    HIP_TRY(ensure_pairs(s));
     // staging holds per-chunk outputs (2Q doubles per node) followed by the
     // chunk's node indices
     const int64_t per = 2 * s->Q;
@@ -535,6 +576,7 @@ int lbcg_populations_at(lbcg_sim *s, const int64_t *nodes, int64_t count, double
 int lbcg_diagnostics(lbcg_sim *s, lbcg_diag *out) {
     if (!s || !out) return LBCG_E_INVAL;
     if (!s->initialised) return LBCG_E_STATE;
+    HIP_TRY(ensure_pairs(s));
     HIP_TRY(launch_diag(s->lattice, s->prec, s->g, s->md, s->buf[s->cur], s->pulled, s->partials, s->diag,
                         s->stream));
     double r[kDiagVals];
@@ -577,6 +619,7 @@ int lbcg_get_state(lbcg_sim *s, void *host, size_t bytes) {
     if (rc) return rc;
     if (bytes < need) return LBCG_E_NOMEM;
     if (!s->initialised) return LBCG_E_STATE;
+    HIP_TRY(ensure_pairs(s));
     int64_t *h = static_cast<int64_t *>(host);
     h[0] = kMagic;
     h[1] = s->lattice;
@@ -618,6 +661,7 @@ int lbcg_set_state(lbcg_sim *s, const void *host, size_t bytes) {
     HIP_TRY(hipStreamSynchronize(s->stream));
     s->pulled = h[6] == 1;
     s->step = h[7];
+    s->compact = false;
     s->initialised = true;
     return LBCG_OK;
 }
@@ -633,7 +677,8 @@ int lbcg_launch_info(lbcg_sim *s, int32_t *kernel, int32_t *rows, int32_t *zchun
 int lbcg_tune(lbcg_sim *s, int32_t *rows, int32_t *zchunks) {
     if (!s) return LBCG_E_INVAL;
     if (!s->initialised) return LBCG_E_STATE;
-    if (s->kernel == LBCG_KERNEL_FUSED) {
+    if (s->kernel == LBCG_KERNEL_FUSED || s->kernel == LBCG_KERNEL_COMPACT) {
+        const bool cmp = s->kernel == LBCG_KERNEL_COMPACT;
         // Candidate shapes: both tile heights, z splits that fill the device
         // once, twice or four times, and fixed chunk lengths (short chunks
         // balance lattices whose fluid sits in a few tiles).  Each is timed
@@ -652,8 +697,9 @@ int lbcg_tune(lbcg_sim *s, int32_t *rows, int32_t *zchunks) {
         }
         for (int r : {4, 8}) {
             if (s->lattice == LBCG_D2Q9) break;
+            if (cmp && r != 8) continue;
             const int64_t tiles = int64_t((s->g.nx + 63) / 64) * ((s->g.ny + r - 1) / r);
-            const int64_t resident = fused_resident_blocks(s->prec, r, masked);
+            const int64_t resident = cmp ? compact_resident_blocks(r) : fused_resident_blocks(s->prec, r, masked);
             std::vector<int64_t> zs = {1};
             for (int m : {1, 2, 4}) zs.push_back((m * resident + tiles - 1) / tiles);
             for (int planes : {2, 4, 8, 16, 32, 64}) zs.push_back((s->g.nz + planes - 1) / planes);
@@ -670,18 +716,25 @@ int lbcg_tune(lbcg_sim *s, int32_t *rows, int32_t *zchunks) {
             (void)hipEventDestroy(e0);
             return LBCG_E_DEVICE;
         }
-        const void *in = s->buf[s->cur];
-        void *out = s->buf[s->cur ^ 1];
+        // the compact kernel reads the compact state (or the pair state before
+        // its first step) and writes the other compact buffer
+        const bool pair_in = cmp && !s->compact;
+        const void *in = cmp && s->compact ? s->cbuf[s->cur] : s->buf[s->cur];
+        void *out = cmp ? s->cbuf[s->cur ^ 1] : s->buf[s->cur ^ 1];
         // the counter slot written is the one the next step writes too
         const uint32_t *ctr_in = s->ctr + s->cur;
         uint32_t *ctr_out = s->ctr + (s->cur ^ 1);
+        auto run = [&](const FusedShape &c) {
+            return cmp ? launch_step_compact(s->g, s->md, in, pair_in, out, ctr_in, ctr_out, c, s->stream)
+                       : launch_fused(s, in, out, ctr_in, ctr_out, c);
+        };
         float best = 0;
         FusedShape pick = s->shape;
         hipError_t e = hipSuccess;
         for (const FusedShape &c : cand) {
-            for (int k = 0; k < 2 && e == hipSuccess; ++k) e = launch_fused(s, in, out, ctr_in, ctr_out, c);
+            for (int k = 0; k < 2 && e == hipSuccess; ++k) e = run(c);
             if (e == hipSuccess) e = hipEventRecord(e0, s->stream);
-            for (int k = 0; k < 4 && e == hipSuccess; ++k) e = launch_fused(s, in, out, ctr_in, ctr_out, c);
+            for (int k = 0; k < 4 && e == hipSuccess; ++k) e = run(c);
             if (e == hipSuccess) e = hipEventRecord(e1, s->stream);
             if (e == hipSuccess) e = hipEventSynchronize(e1);
             float ms = 0;

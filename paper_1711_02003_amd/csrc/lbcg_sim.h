@@ -31,6 +31,11 @@ struct lbcg_sim {
     void *arena;
     bool own_arena;
     size_t arena_bytes;
+    // Compact state (LBCG_KERNEL_COMPACT): cbuf[cur] holds the state while
+    // compact is true; before a read of the state it is expanded into buf[cur]
+    // (expanded marks that buf[cur] is current).
+    void *cbuf[2];
+    bool compact, expanded;
     hipGraphExec_t graph[2];  // graph_steps steps starting from buffer 0 / 1
     int graph_steps;
     bool graph_failed;

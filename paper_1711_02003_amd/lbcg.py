@@ -22,7 +22,7 @@ OK, E_INVAL, E_NOMEM, E_DEVICE, E_UNSTABLE, E_STATE = 0, -1, -2, -3, -4, -5
 D2Q9, D3Q19 = 0, 1
 F64, F32, F16 = 0, 1, 2
 REGULARIZED, BGK = 0, 1
-KERNEL_AUTO, KERNEL_GENERIC, KERNEL_FUSED = 0, 1, 2
+KERNEL_AUTO, KERNEL_GENERIC, KERNEL_FUSED, KERNEL_COMPACT = 0, 1, 2, 3
 PRECISIONS = {"f64": F64, "f32": F32, "f16": F16}
 LATTICES = {"D2Q9": D2Q9, "D3Q19": D3Q19}
 

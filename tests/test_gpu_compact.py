@@ -1,0 +1,201 @@
+"""GPU parity of the compact-state D3Q19 sweep (LBCG_KERNEL_COMPACT).
+
+The compact state keeps, per node, the 19 total populations and 7 colour
+scalars from which the receiver of a population splits it into colours
+(Eq. (10) is linear in f_i, with coefficients of the sending node and of the
+speed class of c_i).  In exact arithmetic the step is the pair-state step, so
+the bars are those of the FP32 pair-state fused kernel: velocity and phase
+within relative L2 1e-5 of the FP64 oracle after 1000 steps, colour mass
+drift below 1e-6, sampled one-step agreement within 2e-6 at the full
+256^3 size, and bitwise invariance under the tile shape and under reads of
+the state.
+"""
+import numpy as np
+import pytest
+
+from paper_1711_02003_amd import workloads as W
+from tests.helpers import oracle_for, oracle_params, rel_l2
+from tests.test_gpu_parity import _maxrel, _sampled_one_step
+
+pytestmark = pytest.mark.gpu
+
+EPS32 = float(np.finfo(np.float32).eps)
+
+
+@pytest.fixture(scope="module")
+def L():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1711_02003_amd import lbcg
+    lbcg.load_library()
+    return lbcg
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _droplets(dims, seed, tau=(1.2, 0.7), A=0.01):
+    nx, ny, nz = dims
+    rng = np.random.default_rng(seed)
+    psi = W.droplet_phase(dims, [(nx / 3, ny / 2, nz / 2), (0.8 * nx, 0.2 * ny, 0.7 * nz)],
+                          [min(dims) / 3 + 1, min(dims) / 5 + 1])
+    rR, rB = W.colour_densities(psi)
+    return W.Workload("compact", "D3Q19", dims, rR, rB, rng.normal(0, 1e-3, (3, nz, ny, nx)), tau[0], tau[1],
+                      A, 0.7)
+
+
+def test_compact_config2_recipe_1000_steps(L, orc):
+    # The 27-droplet recipe at 48^3 (tau_R = 1, tau_B = 0.6, A = 0.005).
+    w = W.config2(L=48, seed=2)
+    _say("compact f32 48^3 x1000")
+    s = L.Sim.from_workload(w, precision="f32", kernel=L.KERNEL_COMPACT)
+    assert s.launch_info()["kernel"] == L.KERNEL_COMPACT
+    d0 = s.diagnostics()
+    s.step(1000)
+    g = s.fields()
+    d1 = s.diagnostics(check=True)
+    drifts = {k: abs(d1[k] - d0[k]) / d0[k] for k in ("mass_R", "mass_B")}
+    _say(f"  mass drift R {drifts['mass_R']:.2e} B {drifts['mass_B']:.2e}")
+    o = oracle_for(orc, w, threads=16).step(1000)
+    f = o.fields()
+    eu, ep = rel_l2(g["u"], f["u"]), rel_l2(g["psi"], f["psi"])
+    _say(f"  relL2 u {eu:.3e} psi {ep:.3e}")
+    assert eu < 1e-5
+    assert ep < 1e-5
+    for k, v in drifts.items():
+        assert v < 1e-6, (k, v)
+
+
+def test_compact_density_ratio_slab(L, orc):
+    # alpha_R = 0.55 != alpha_B: the colour equilibria differ per colour, so
+    # the scalars' class amplitudes carry the phi_i^k terms.  The bulk ratio
+    # after 10000 steps within 1e-5 of the flat-interface value and of the
+    # oracle's.
+    nx = 64
+    dims = (nx, 8, 4)
+    sh = (4, 8, nx)
+    psi = np.tanh((16 - np.abs(np.arange(nx) + 0.5 - 32)) / 2.0)
+    psi = np.broadcast_to(psi, sh).copy()
+    w = W.Workload("slab", "D3Q19", dims, (1 + psi) / 2, (1 - psi) / 2, None, 0.8, 1.2, 0.01, 0.7)
+    _say("compact f32 density-ratio slab 64x8x4 x10000")
+    s = L.Sim(w.lattice, w.dims, w.tau_R, w.tau_B, w.A, w.beta, "f32", kernel=L.KERNEL_COMPACT,
+              alpha_R=0.55).init_fields(w.rhoR, w.rhoB, w.u)
+    p = oracle_params(orc, w)
+    p.alpha = (0.55, 0.0)
+    o = orc.Oracle(p).init(w.rhoR, w.rhoB, w.u)
+    s.step(10000)
+    o.step(10000)
+    g, f = s.fields(), o.fields()
+    target = (1 - 1 / 3) / (1 - 0.55)
+    rg = g["rhoR"][2, 4, 32] / g["rhoB"][2, 4, 0]
+    ro = f["rhoR"][2, 4, 32] / f["rhoB"][2, 4, 0]
+    _say(f"  ratio gpu {rg:.7f} oracle {ro:.7f} target {target:.7f}")
+    assert abs(rg / target - 1) < 1e-5
+    assert abs(rg / ro - 1) < 1e-5
+    assert _maxrel(g["rhoR"][..., 26:38], f["rhoR"][..., 26:38]) < 1e-5
+    assert _maxrel(g["rhoB"][..., :6], f["rhoB"][..., :6]) < 1e-5
+
+
+def test_compact_agrees_with_pair_fused_ragged(L):
+    # nx not a multiple of 64, ny not a multiple of the tile rows: the compact
+    # and the pair-state sweeps differ only in rounding
+    w = _droplets((70, 37, 20), seed=3)
+    a = L.Sim.from_workload(w, precision="f32", kernel=L.KERNEL_COMPACT)
+    b = L.Sim.from_workload(w, precision="f32", kernel=L.KERNEL_FUSED)
+    a.step(50)
+    b.step(50)
+    d = _maxrel(a.populations(), b.populations())
+    _say(f"compact vs fused ragged 70x37x20 x50: {d:.2e}")
+    assert d < 50 * 4 * EPS32
+
+
+@pytest.mark.parametrize("dims", [(96, 40, 24), (64, 16, 9), (5, 3, 2)])
+def test_compact_tile_shape_invariance(L, dims):
+    # every tile height and z split gives bitwise the same state: ring and
+    # interior nodes split the pulled populations by one expression sequence
+    w = _droplets(dims, seed=5)
+    ref = None
+    for tile in ((8, 1, 0), (8, 3, 0), (8, 8, 0), (8, 0, 0)):
+        s = L.Sim.from_workload(w, precision="f32", kernel=L.KERNEL_COMPACT, tile=tile)
+        s.step(17)
+        p = s.populations()
+        if ref is None:
+            ref = p
+        else:
+            assert np.array_equal(p, ref), tile
+        s.close()
+
+
+def test_compact_reads_leave_trajectory_unchanged(L):
+    # reading the state converts it into the pair buffer but steps go on from
+    # the compact state: a run with reads is bitwise the run without
+    w = _droplets((64, 24, 16), seed=8)
+    a = L.Sim.from_workload(w, precision="f32", kernel=L.KERNEL_COMPACT)
+    b = L.Sim.from_workload(w, precision="f32", kernel=L.KERNEL_COMPACT)
+    for _ in range(3):
+        a.step(10)
+        a.populations()
+        a.diagnostics()
+        a.fields()
+    b.step(30)
+    assert np.array_equal(a.populations(), b.populations())
+    assert a.diagnostics()["step"] == 30
+
+
+def test_compact_checkpoint_resume(L):
+    # a checkpoint of a compact handle is a pair state: it resumes on a
+    # compact or a pair-state handle, within rounding of the uninterrupted run
+    w = W.config2(L=40, seed=9)
+    a = L.Sim.from_workload(w, precision="f32", kernel=L.KERNEL_COMPACT)
+    a.step(40)
+    pa = a.populations()
+    b = L.Sim.from_workload(w, precision="f32", kernel=L.KERNEL_COMPACT)
+    b.step(15)
+    blob = b.get_state()
+    for kernel in (L.KERNEL_COMPACT, L.KERNEL_FUSED):
+        c = L.Sim.from_workload(w, precision="f32", kernel=kernel)
+        c.set_state(blob)
+        c.step(25)
+        d = _maxrel(c.populations(), pa)
+        _say(f"resume on kernel {kernel}: {d:.2e}")
+        assert d < 25 * 4 * EPS32
+        assert c.diagnostics()["step"] == 40
+        c.close()
+
+
+def test_compact_full_size_config2_sampled(L, orc):
+    # Full 256^3 lattice: sampled nodes' next state against the oracle's step
+    # from the same (converted) state, and colour masses over 20 steps.
+    w = W.config2(L=256, seed=2)
+    _say("full size 256^3 compact f32")
+    s = L.Sim.from_workload(w, precision="f32", kernel=L.KERNEL_COMPACT)
+    _say(f"  launch {s.launch_info()}")
+    d0 = s.diagnostics(check=True)
+    s.step(20)
+    worst = _sampled_one_step(L, orc, w, s)
+    _say(f"  sampled one-step max rel diff {worst:.2e}")
+    assert worst < 2e-6
+    d1 = s.diagnostics(check=True)
+    assert abs(d1["mass_R"] - d0["mass_R"]) / d0["mass_R"] < 1e-6
+    assert abs(d1["mass_B"] - d0["mass_B"]) / d0["mass_B"] < 1e-6
+    s.close()
+
+
+def test_compact_rejects_what_it_does_not_cover(L):
+    w = _droplets((16, 8, 8), seed=1)
+    for kw in ({"precision": "f16"}, {"precision": "f64"}, {"collision": L.BGK}):
+        with pytest.raises(L.LbcgError):
+            L.Sim.from_workload(w, kernel=L.KERNEL_COMPACT, **kw)
+    m = np.zeros(w.shape, np.uint8)
+    m[:, 0, :] = 1
+    w.mask = m
+    with pytest.raises(L.LbcgError):
+        L.Sim.from_workload(w, precision="f32", kernel=L.KERNEL_COMPACT)
+    w2 = W.droplets_2d(n=64, seed=1)
+    with pytest.raises(L.LbcgError):
+        L.Sim.from_workload(w2, precision="f32", kernel=L.KERNEL_COMPACT)
+    w.mask = None
+    with pytest.raises(L.LbcgError):  # 8-row tiles only
+        L.Sim.from_workload(w, precision="f32", kernel=L.KERNEL_COMPACT, tile=(4, 0, 0))
