@@ -2,21 +2,25 @@
 
 Workload: the 27-droplet periodic D3Q19 box, 256^3, FP32 storage and
 arithmetic (tau_R = 1, tau_B = 0.6, A = 0.005, beta = 0.7), fused
-single-pass kernel.  A step is one full time step of every node (both
-colours).  Prints one JSON line:
+single-pass kernel on the compact state (receiver-side recolouring; the
+pair-state sweep is reported among the forms).  A step is one full time step
+of every node (both colours).  Prints one JSON line:
 
   value      whole-job two-component MLUPS (fluid nodes x steps / time), inputs
              resident in HBM, timed with HIP events on the simulation's stream;
-  roofline   HBM roofline of the fused kernel: algorithmic bytes per node
-             (read + write every population of both colours once, 2 x 38 x 4 =
-             304 B) x nodes / average kernel time, against 8 TB/s; traffic =
-             HBM bytes per launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE
-             counters scaled by a copy-kernel calibration (null when the
-             kernel source changed since the counters were taken);
+  roofline   HBM roofline of the step's kernel: algorithmic bytes per node
+             (read + write the state once: compact 2 x (19 x 4 + 32) = 216 B,
+             pair state 2 x 38 x 4 = 304 B) x nodes / average kernel time,
+             against 8 TB/s; traffic = HBM bytes per launch from the rocprofv3
+             FETCH_SIZE / WRITE_SIZE counters scaled by a copy-kernel
+             calibration (null when the kernel source changed since the
+             counters were taken);
   cpu_baseline  the FP64 CPU oracle timed on this host on a bounded sample;
   copy_probe achieved bandwidth of a plain device-to-device copy (context);
   forms      the other forms of the step, each measured on its own workload:
-             f16 (the same lattice with FP16 deviation storage), focusing (the
+             pair_f32 (the same lattice on the pair-state sweep: per
+             population its total and minority share), f16 (the same lattice
+             with FP16 pair storage), focusing (the
              512 x 128 x 64 flow-focusing junction, FP32 and FP16), batched (64
              uneven periodic boxes in one launch per time level vs the same
              boxes stepped one after another) and served (a Poisson stream of
@@ -36,7 +40,8 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fused_d3q19_f32_256_traffic.txt")
+TRAFFIC_FILES = {"k_step_compact": os.path.join(ROOT, "profiles", "compact_d3q19_f32_256_traffic.txt"),
+                 "k_step_fused": os.path.join(ROOT, "profiles", "fused_d3q19_f32_256_traffic.txt")}
 
 
 def log(msg):
@@ -44,17 +49,19 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def read_traffic():
-    """HBM bytes per launch from the committed counter summary, if current."""
-    if not os.path.exists(TRAFFIC_FILE):
+def read_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary, if
+    current."""
+    path = TRAFFIC_FILES[kernel]
+    if not os.path.exists(path):
         return None
     vals = {}
-    for line in open(TRAFFIC_FILE):
+    for line in open(path):
         if ":" in line:
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
     from paper_1711_02003_amd.profiling import kernel_hash
-    if vals.get("kernel_hash") != kernel_hash():
+    if vals.get("kernel_hash") != kernel_hash(kernel):
         return None
     try:
         return float(vals["hbm_bytes_per_launch"])
@@ -102,6 +109,22 @@ def time_sim(torch, sim, stream, steps, warmup):
     e1.record(stream)
     e1.synchronize()
     return e0.elapsed_time(e1)
+
+
+def pair_f32_form(torch, lbcg, W, size, steps=200, warmup=10):
+    w = W.config2(L=size, seed=2)
+    stream = torch.cuda.Stream()
+    sim = lbcg.Sim.from_workload(w, precision="f32", kernel=lbcg.KERNEL_FUSED, stream=stream.cuda_stream)
+    sim.step(1)
+    shape = sim.tune()
+    ms = time_sim(torch, sim, stream, steps, warmup)
+    sim.close()
+    mlups = w.fluid_nodes * steps / (ms / 1e3) / 1e6
+    gbs = 304 * w.fluid_nodes * steps / (ms / 1e3) / 1e9
+    return {"workload": w.name, "storage": "f32 pairs", "mlups": round(mlups, 1),
+            "ms_per_step": round(ms / steps, 4), "achieved_gbs": round(gbs, 1),
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "bytes_per_node": 304, "rows": shape["rows"],
+            "zchunks": shape["zchunks"], "steps": steps}
 
 
 def f16_form(torch, lbcg, W, size, steps=200, warmup=10):
@@ -269,6 +292,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--size", type=int, default=256)
     ap.add_argument("--precision", default="f32", choices=["f32", "f16"])
+    ap.add_argument("--kernel", default="compact", choices=["compact", "fused"],
+                    help="compact state (FP32 only) or the pair-state sweep")
     ap.add_argument("--rows", type=int, default=0)
     ap.add_argument("--zchunks", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -288,9 +313,12 @@ def main():
     from paper_1711_02003_amd import workloads as W
 
     w = W.config2(L=args.size, seed=2)
+    compact = args.kernel == "compact" and args.precision == "f32"
+    kname = "k_step_compact" if compact else "k_step_fused"
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
-        sim = lbcg.Sim.from_workload(w, precision=args.precision, kernel=lbcg.KERNEL_FUSED,
+        sim = lbcg.Sim.from_workload(w, precision=args.precision,
+                                     kernel=lbcg.KERNEL_COMPACT if compact else lbcg.KERNEL_FUSED,
                                      tile=(args.rows, args.zchunks, 0))
     if not (args.rows or args.zchunks):
         sim.step(1)
@@ -318,10 +346,10 @@ def main():
 
     N = w.fluid_nodes
     elem = 4 if args.precision == "f32" else 2
-    bytes_node = 2 * 2 * 19 * elem
+    bytes_node = 2 * (19 * 4 + 32) if compact else 2 * 2 * 19 * elem
     mlups = N * args.steps / (ms / 1e3) / 1e6
     achieved = bytes_node * N / (ms_step / 1e3) / 1e9
-    traffic = read_traffic() if args.precision == "f32" and args.size == 256 else None
+    traffic = read_traffic(kname) if args.precision == "f32" and args.size == 256 else None
     out = {
         "metric": "two-component MLUPS, D3Q19 regularized colour-gradient step",
         "value": round(mlups, 1),
@@ -337,7 +365,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "lattice": "D3Q19", "dims": list(w.dims),
                    "droplets": 27, "tau_R": w.tau_R, "tau_B": w.tau_B, "A": w.A, "beta": w.beta,
-                   "storage": args.precision, "kernel": "fused",
+                   "storage": args.precision, "kernel": "fused compact" if compact else "fused",
                    "rows": info["rows"], "zchunks": info["zchunks"]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -348,7 +376,9 @@ def main():
     if not args.no_copy_probe:
         out["copy_probe"] = copy_probe(torch)
     if not args.no_forms:
-        forms = {"f16": f16_form(torch, lbcg, W, args.size)}
+        forms = {"pair_f32": pair_f32_form(torch, lbcg, W, args.size)}
+        log(f"pair_f32 {forms['pair_f32']}")
+        forms["f16"] = f16_form(torch, lbcg, W, args.size)
         log(f"f16 {forms['f16']}")
         forms["d2q9"] = d2q9_form(torch, lbcg, W)
         log(f"d2q9 {forms['d2q9']}")

@@ -4,7 +4,7 @@
         <timed dispatches> "<command>"
     python -m paper_1711_02003_amd.profiling traffic <fetch counter_collection.csv>
         <write counter_collection.csv> <kernel substring> <timed dispatches> <nodes> <out.txt>
-        "<commands>"
+        "<commands>"   (kernel substring k_step_compact or k_step_fused)
     python -m paper_1711_02003_amd.profiling forms <kernel_trace.csv> <out.md> <timed dispatches>
         "<command>"
 
@@ -29,14 +29,22 @@ import os
 import sys
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-KERNEL_SOURCES = ["paper_1711_02003_amd/csrc/lbcg_fused.hip", "paper_1711_02003_amd/csrc/lbcg_device.h"]
 COPY_BYTES = 2 << 30  # the copy probe moves 2 GiB in and 2 GiB out per dispatch
-BYTES_PER_NODE = 2 * 38 * 4  # FP32: every population pair read once and written once
+# Per headline kernel: the sources its code comes from and its algorithmic
+# bytes per node and step (FP32).  Pair state: every population pair read
+# once and written once, 2 x 38 x 4.  Compact state: 19 totals and one
+# 32-byte scalar record read once and written once, 2 x (19 x 4 + 32).
+KERNELS = {
+    "k_step_compact": (["paper_1711_02003_amd/csrc/lbcg_compact.hip", "paper_1711_02003_amd/csrc/lbcg_device.h"],
+                       2 * (19 * 4 + 32)),
+    "k_step_fused": (["paper_1711_02003_amd/csrc/lbcg_fused.hip", "paper_1711_02003_amd/csrc/lbcg_device.h"],
+                     2 * 38 * 4),
+}
 
 
-def kernel_hash() -> str:
+def kernel_hash(kernel: str) -> str:
     h = hashlib.sha256()
-    for p in KERNEL_SOURCES:
+    for p in KERNELS[kernel][0]:
         with open(os.path.join(ROOT, p), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -91,10 +99,10 @@ def traffic_summary(fetch_csv, write_csv, kernel_sub, timed, nodes, out_txt, com
     w_fac = COPY_BYTES / (wc * 1024)
     fkib, wkib = sum(kf) / len(kf), sum(kw) / len(kw)
     fb, wb = fkib * 1024 * f_fac, wkib * 1024 * w_fac
-    alg = BYTES_PER_NODE * nodes / 2  # read (or write) bytes of the algorithm
+    alg = KERNELS[kernel_sub][1] * nodes / 2  # read (or write) bytes of the algorithm
     lines = [
         f"kernel: {kernel_sub}",
-        f"kernel_hash: {kernel_hash()}",
+        f"kernel_hash: {kernel_hash(kernel_sub)}",
         f"commands: {commands}",
         f"timed_dispatches: {len(kf)} fetch, {len(kw)} write",
         f"fetch_kib_per_dispatch: {fkib:.1f}",
