@@ -9,7 +9,7 @@ of every node (both colours).  Prints one JSON line:
   value      whole-job two-component MLUPS (fluid nodes x steps / time), inputs
              resident in HBM, timed with HIP events on the simulation's stream;
   roofline   HBM roofline of the step's kernel: algorithmic bytes per node
-             (read + write the state once: compact 2 x (19 x 4 + 32) = 216 B,
+             (read + write the state once: compact 2 x (19 x 4 + 28) = 208 B,
              pair state 2 x 38 x 4 = 304 B) x nodes / average kernel time,
              against 8 TB/s; traffic = HBM bytes per launch from the rocprofv3
              FETCH_SIZE / WRITE_SIZE counters scaled by a copy-kernel
@@ -346,7 +346,7 @@ def main():
 
     N = w.fluid_nodes
     elem = 4 if args.precision == "f32" else 2
-    bytes_node = 2 * (19 * 4 + 32) if compact else 2 * 2 * 19 * elem
+    bytes_node = 2 * (19 * 4 + 28) if compact else 2 * 2 * 19 * elem
     mlups = N * args.steps / (ms / 1e3) / 1e6
     achieved = bytes_node * N / (ms_step / 1e3) / 1e9
     traffic = read_traffic(kname) if args.precision == "f32" and args.size == 256 else None

@@ -70,16 +70,16 @@ extern "C" {
  * 4 GiB (pitch = node count rounded up to 64).  Eq. (10) splits every
  * population of a node with coefficients that depend only on that node and
  * on the speed class of the direction, so each node stores its 19 total
- * populations and a 32-byte record of colour scalars (its minority share and
- * one 3-vector per speed class) and the receiver of a population splits it:
- * 216 bytes of memory traffic per node and step instead of 304.  Results
+ * populations and 7 colour scalars (its minority share and one 3-vector per
+ * speed class) and the receiver of a population splits it: 208 bytes of
+ * memory traffic per node and step instead of 304.  Results
  * agree with the pair-state kernels up to rounding.  The first step
  * after lbcg_init_fields or lbcg_set_state reads the pair state; the calls
  * that read the state (fields, populations, diagnostics, lbcg_get_state)
  * first convert the compact state to a pair state in the handle's pair
  * buffer, which the compact steps leave unused (one extra kernel, no change
  * to the trajectory).  lbcg_footprint
- * adds the two compact buffers (2 x 108 x pitch bytes). */
+ * adds the two compact buffers (2 x 104 x pitch bytes). */
 #define LBCG_KERNEL_AUTO 0
 #define LBCG_KERNEL_GENERIC 1
 #define LBCG_KERNEL_FUSED 2

@@ -7,16 +7,18 @@
 //   minority colour part of f_i = M f_i + (c_i . V_c) / 36,
 // with M the node's minority share and V_c one 3-vector per speed class
 // (axis, diagonal).  So a node need not store the two colours of every
-// population: it stores its 19 new total deviations and one 32-byte record
-// of colour scalars (M with the majority flag in its lowest bit, V_axis,
-// V_diag, one pad word), and the receiver splits each pulled population with
-// the scalars of the node it came from.  In exact arithmetic the step is the
-// same as the pair-state step; it moves 2 x (19 x 4 + 32) = 216 bytes per
-// node instead of 2 x 38 x 4 = 304.
+// population: it stores its 19 new total deviations and 7 colour scalars (M
+// with the majority flag in its lowest bit, V_axis, V_diag), and the
+// receiver splits each pulled population with the scalars of the node it
+// came from.  In exact arithmetic the step is the same as the pair-state
+// step; it moves 2 x (19 x 4 + 28) = 208 bytes per node instead of
+// 2 x 38 x 4 = 304.
 //
 // Layout: 19 arrays of `pitch` floats (array i at i * pitch + node: total
-// deviation f_i - w_i), then `pitch` records of 8 floats
-// {M, V_axis x, y, z, V_diag x, y, z, 0} (record n at 19 * pitch + 8 n).
+// deviation f_i - w_i), then `pitch` 16-byte records {M, V_axis x, y, z}
+// (record n at float 19 * pitch + 4 n) and `pitch` 12-byte records
+// {V_diag x, y, z} (at float 23 * pitch + 3 n), so that each wide load or
+// store of a wave covers one contiguous span.
 //
 // The sweep is the pair-state sweep's: a block owns a 64 x 8 column tile and
 // sweeps a chunk of z planes; plane z+1 is pulled (interior and a one-node
@@ -26,8 +28,8 @@
 // memory per direction that would be ~68 loads per node, more than a wave
 // can keep in flight (its memory counter holds 63), so the records are
 // staged instead: each plane's records over the tile plus a two-node halo
-// (the ring's own senders) are loaded once, with two 16-byte loads per
-// node, into a 4-slot LDS ring, three planes ahead of their first use, and
+// (the ring's own senders) are loaded once, with a 16-byte and a 12-byte
+// load per node, into a 4-slot LDS ring, three planes ahead of their first use, and
 // the receivers read them from there.  The threads of the three waves that
 // hold the ring nodes load no records, so every wave keeps fewer than 63
 // memory operations in flight.  The first step after an initialisation or a
@@ -43,7 +45,11 @@ namespace {
 constexpr int kCTX = 64;
 constexpr int kCR = 8;                      // tile rows
 constexpr int kCXCD = 8;
-constexpr int kRec = 8;                     // floats per scalar record
+// Scalar records: {M, V_axis} (16 B) in one array after the 19 total
+// arrays, V_diag (12 B) in a second one; byte offsets from the first total
+// array: 19 x 4 x pitch + 16 n and 23 x 4 x pitch + 12 n.
+constexpr uint32_t kRecA = 16, kRecB = 12;
+constexpr int kRecBytes = int(kRecA + kRecB);
 constexpr int kNS = 7;                      // scalars kept in LDS: M, V_axis, V_diag
 constexpr int kSW = kCTX + 4, kSH = kCR + 4, kSN = kSW * kSH;  // record tile with a 2-node halo
 constexpr int kSSlots = 4;
@@ -95,8 +101,16 @@ __device__ __forceinline__ float load_f(__amdgpu_buffer_rsrc_t r, uint32_t voff,
 __device__ __forceinline__ f4 load_f4(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
     return __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(r, int(voff), int(soff), 0));
 }
+typedef float f3 __attribute__((ext_vector_type(3)));
+typedef unsigned int u3 __attribute__((ext_vector_type(3)));
+__device__ __forceinline__ f3 load_f3(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    return __builtin_bit_cast(f3, __builtin_amdgcn_raw_buffer_load_b96(r, int(voff), int(soff), 0));
+}
 __device__ __forceinline__ void store_f4(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, f4 v) {
     __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, v), r, int(voff), int(soff), kNonTemporal);
+}
+__device__ __forceinline__ void store_f3(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, f3 v) {
+    __builtin_amdgcn_raw_buffer_store_b96(__builtin_bit_cast(u3, v), r, int(voff), int(soff), kNonTemporal);
 }
 
 // Byte offsets of planes z-1, z, z+1 (periodic) for plane size `plane`.
@@ -115,12 +129,11 @@ __device__ __forceinline__ void store_compact(const CompactArgs &a, __amdgpu_buf
     const uint32_t zoff = uint32_t(uniform(z)) * (uint32_t(a.nx) * uint32_t(a.ny) * 4u);
 #pragma unroll
     for (int i = 0; i < D3Q19::Q; ++i) store_pair<float>(rout, own, uint32_t(i) * cs + zoff, o.df[i]);
-    // record: byte 19 * 4 * pitch + 32 n
-    const uint32_t rb = uint32_t(D3Q19::Q) * cs + zoff * uint32_t(kRec);
+    // records: own and zoff count 4 bytes per node
     const f4 q0 = {Codec<float>::enc_col<float>(o.M, o.redmaj), o.Va[0], o.Va[1], o.Va[2]};
-    const f4 q1 = {o.Vd[0], o.Vd[1], o.Vd[2], 0.0f};
-    store_f4(rout, own * uint32_t(kRec), rb, q0);
-    store_f4(rout, own * uint32_t(kRec), rb + 16u, q1);
+    const f3 q1 = {o.Vd[0], o.Vd[1], o.Vd[2]};
+    store_f4(rout, own * 4u, uint32_t(D3Q19::Q) * cs + zoff * 4u, q0);
+    store_f3(rout, own * 3u, uint32_t(D3Q19::Q + 4) * cs + zoff * 3u, q1);
 }
 
 // Split of the 19 pulled totals d of a node with its senders' scalars, read
@@ -192,7 +205,7 @@ __device__ __forceinline__ void sweep_compact(const CompactArgs &a, const Model<
     }
     const int gx = wrap_m1(x0 + rx, a.nx), gy = wrap_m1(y0 + ry, a.ny);
 
-    const uint32_t bytes = uint32_t(L::Q) * uint32_t(a.pitch) * 4u + uint32_t(a.pitch) * uint32_t(kRec * 4);
+    const uint32_t bytes = uint32_t(L::Q) * uint32_t(a.pitch) * 4u + uint32_t(a.pitch) * uint32_t(kRecBytes);
     const __amdgpu_buffer_rsrc_t rin = state_rsrc(a.in, bytes);
     const __amdgpu_buffer_rsrc_t rout = state_rsrc(a.out, bytes);
     const uint32_t cs = uint32_t(uniform(int(uint32_t(a.pitch) * 4u)));
@@ -213,10 +226,10 @@ __device__ __forceinline__ void sweep_compact(const CompactArgs &a, const Model<
         lon[k] = threadIdx.x >= kLoad0 && j < sn;
         const int sx = lon[k] ? j % sw - 2 : 0, sy = lon[k] ? j / sw - 2 : 0;
         lidx[k] = (sy + 2) * kSW + (sx + 2);
-        lcol[k] = (uint32_t(wrap_any(x0 + sx, a.nx)) + uint32_t(a.nx) * uint32_t(wrap_any(y0 + sy, a.ny))) *
-                  uint32_t(kRec * 4);
+        lcol[k] = uint32_t(wrap_any(x0 + sx, a.nx)) + uint32_t(a.nx) * uint32_t(wrap_any(y0 + sy, a.ny));
     }
-    f4 lq0[kPerLoader], lq1[kPerLoader];
+    f4 lq0[kPerLoader];
+    f3 lq1[kPerLoader];
 
     float *psi_lds = lds;
     float *rec_lds = lds + kPSlots * kPN;
@@ -224,12 +237,13 @@ __device__ __forceinline__ void sweep_compact(const CompactArgs &a, const Model<
     auto rslot = [&](int q) { return rec_lds + ((q - z0 + 2 * kSSlots) % kSSlots) * (kNS * kSN); };
 
     auto rec_issue = [&](int q) {
-        const uint32_t rb = uint32_t(L::Q) * cs + uint32_t(uniform(wrap_any(q, a.nz))) * plane4 * uint32_t(kRec);
+        const uint32_t zq = uint32_t(uniform(wrap_any(q, a.nz))) * (uint32_t(a.nx) * uint32_t(a.ny));
+        const uint32_t ra = uint32_t(L::Q) * cs + zq * kRecA, rb = uint32_t(L::Q + 4) * cs + zq * kRecB;
 #pragma unroll
         for (int k = 0; k < kPerLoader; ++k)
             if (lon[k]) {
-                lq0[k] = load_f4(rin, lcol[k], rb);
-                lq1[k] = load_f4(rin, lcol[k], rb + 16u);
+                lq0[k] = load_f4(rin, lcol[k] * kRecA, ra);
+                lq1[k] = load_f3(rin, lcol[k] * kRecB, rb);
             }
     };
     auto rec_write = [&](int q) {
@@ -440,7 +454,7 @@ __device__ __forceinline__ void sweep_pairs(const CompactArgs &a, const Model<fl
 
     const __amdgpu_buffer_rsrc_t rin = state_rsrc(a.in, uint32_t(2 * L::Q) * uint32_t(a.pitch) * 4u);
     const __amdgpu_buffer_rsrc_t rout =
-        state_rsrc(a.out, uint32_t(L::Q) * uint32_t(a.pitch) * 4u + uint32_t(a.pitch) * uint32_t(kRec * 4));
+        state_rsrc(a.out, uint32_t(L::Q) * uint32_t(a.pitch) * 4u + uint32_t(a.pitch) * uint32_t(kRecBytes));
     uint32_t ixy[9], rxy[9], oxy[9];
     col_offsets<8>(a, intile ? x : 0, intile ? y : 0, ixy);
     col_offsets<8>(a, gx, gy, rxy);
@@ -560,10 +574,10 @@ __global__ void k_expand(const float *__restrict__ cin, typename PairOf<float>::
     using L = D3Q19;
     const int64_t n = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (n >= N) return;
-    const float *rec = cin + int64_t(L::Q) * pitch + int64_t(kRec) * n;
+    const float *ra = cin + int64_t(L::Q) * pitch + 4 * n, *rb = cin + int64_t(L::Q + 4) * pitch + 3 * n;
     bool fl;
-    const float M = Codec<float>::col<float>(rec[0], fl);
-    const float Va[3] = {rec[1], rec[2], rec[3]}, Vd[3] = {rec[4], rec[5], rec[6]};
+    const float M = Codec<float>::col<float>(ra[0], fl);
+    const float Va[3] = {ra[1], ra[2], ra[3]}, Vd[3] = {rb[0], rb[1], rb[2]};
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) {
         const float d = cin[int64_t(i) * pitch + n];
