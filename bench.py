@@ -20,7 +20,8 @@ of every node (both colours).  Prints one JSON line:
   forms      the other forms of the step, each measured on its own workload:
              pair_f32 (the same lattice on the pair-state sweep: per
              population its total and minority share), f16 (the same lattice
-             with FP16 pair storage), focusing (the
+             with FP16 pair storage), batched_compact (the batched boxes on
+             the compact state), focusing (the
              512 x 128 x 64 flow-focusing junction, FP32 and FP16), batched (64
              uneven periodic boxes in one launch per time level vs the same
              boxes stepped one after another) and served (a Poisson stream of
@@ -212,13 +213,14 @@ def focusing_form(torch, lbcg, W, steps=200, warmup=10):
     return out
 
 
-def batched_form(torch, lbcg, W, steps=200, warmup=10):
+def batched_form(torch, lbcg, W, steps=200, warmup=10, compact=False):
     ws = W.batch_boxes(n_boxes=64, seed=4)
     nodes = sum(w.fluid_nodes for w in ws)
     stream = torch.cuda.Stream()
-    sims = [lbcg.Sim.from_workload(w, precision="f32", stream=stream.cuda_stream) for w in ws]
+    kernel = lbcg.KERNEL_COMPACT if compact else lbcg.KERNEL_FUSED
+    sims = [lbcg.Sim.from_workload(w, precision="f32", kernel=kernel, stream=stream.cuda_stream) for w in ws]
     for s in sims:
-        s.step(1)
+        s.step(2)
     b = lbcg.Batch(sims)
     info = b.launch_info()
     b.step(warmup)
@@ -245,9 +247,11 @@ def batched_form(torch, lbcg, W, steps=200, warmup=10):
         s.close()
     mb = nodes * steps / (ms_b / 1e3) / 1e6
     mp = nodes * steps / (ms_p / 1e3) / 1e6
+    bpn = 2 * (19 * 4 + 28) if compact else 304
     return {"workload": "64 periodic D3Q19 boxes, edges U{32..96}, seed 4", "nodes": nodes,
+            "state": "compact" if compact else "pairs", "bytes_per_node": bpn,
             "steps": steps, "batched_mlups": round(mb, 1), "plain_mlups": round(mp, 1),
-            "speedup": round(mb / mp, 3), "frac": round(mb * 304 / 1e3 / HBM_PEAK_GBS, 4),
+            "speedup": round(mb / mp, 3), "frac": round(mb * bpn / 1e3 / HBM_PEAK_GBS, 4),
             "rows": info["rows"], "zplanes": info["zplanes"], "blocks": info["blocks"]}
 
 
@@ -388,6 +392,8 @@ def main():
         log(f"focusing {forms['focusing']}")
         forms["batched"] = batched_form(torch, lbcg, W)
         log(f"batched {forms['batched']}")
+        forms["batched_compact"] = batched_form(torch, lbcg, W, compact=True)
+        log(f"batched_compact {forms['batched_compact']}")
         forms["served"] = served_form(torch, lbcg, W, n=args.served_requests,
                                       steps_scale=args.served_steps_scale)
         log(f"served {forms['served']}")

@@ -230,10 +230,12 @@ int lbcg_tune(lbcg_sim *s, int32_t *rows, int32_t *zchunks);
  * once): one fused launch per time level covers every lattice that still has
  * steps left, with runs of 32 levels replayed from HIP graphs.  A batch
  * refers to existing handles; it does not own them, and they must outlive
- * it.  Requirements: every handle initialised, on the fused kernel (D3Q19,
- * F32 or F16 storage, regularized collision), one storage precision, one
- * stream, no handle listed twice; geometry and periodic lattices may mix.
- * tile: {rows per block (4 or 8), z planes per chunk (>= 1)}; NULL or {0, 0}
+ * it.  Requirements: every handle initialised, all on the fused kernel
+ * (D3Q19, F32 or F16 storage, regularized collision; geometry and periodic
+ * lattices may mix) or all on the compact kernel, one storage precision, one
+ * stream, no handle listed twice.
+ * tile: {rows per block (4 or 8; 8 on the compact kernel), z planes per
+ * chunk (>= 1)}; NULL or {0, 0}
  * = choose by timing candidate shapes on the batch (the states do not
  * change).  Errors: LBCG_E_INVAL for a violated requirement, LBCG_E_NOMEM /
  * LBCG_E_DEVICE for allocation or HIP failures.  The batch allocates its

@@ -1,5 +1,5 @@
-// Batched form of the fused D3Q19 step: many independent lattices advance
-// together, one kernel launch per time level over every lattice that still
+// Batched form of the fused D3Q19 step (pair-state or compact-state sweep):
+// many independent lattices advance together, one kernel launch per time level over every lattice that still
 // has steps left (two launches when geometry and periodic lattices are
 // mixed).  Per lattice the arithmetic is the fused sweep of the single
 // lattice form, so each lattice's result is bitwise that of stepping it
@@ -52,6 +52,7 @@ int dev_err(hipError_t e) {
 struct lbcg_batch {
     std::vector<lbcg_sim *> sims;
     int prec = 0;
+    bool compact = false;  // every lattice on the compact-state kernel
     int rows = 8, zplanes = 32;
     hipStream_t stream = nullptr;
     std::vector<int> zchunks, items;  // per lattice, for the current shape
@@ -116,8 +117,9 @@ int stage(lbcg_batch *b, const std::vector<int> &order) {
         for (size_t j = 0; j < n; ++j) {
             const lbcg_sim *s = b->sims[j];
             const FusedShape sh{b->rows, b->zchunks[j]};
-            const void *in = s->buf[s->cur ^ par];
-            void *out = s->buf[s->cur ^ par ^ 1];
+            void *const *bufs = b->compact ? s->cbuf : s->buf;
+            const void *in = bufs[s->cur ^ par];
+            void *out = bufs[s->cur ^ par ^ 1];
             std::memset(&d[j], 0, sizeof(Desc));
             d[j].a = fused_args<float>(s->g, in, out, s->ctr + (s->cur ^ par), s->ctr + (s->cur ^ par ^ 1), sh);
             d[j].mo = to_model<float>(s->md);
@@ -140,6 +142,9 @@ int stage(lbcg_batch *b, const std::vector<int> &order) {
 }
 
 hipError_t launch_level(lbcg_batch *b, int parity, int nbU, int nbM) {
+    if (b->compact)
+        return launch_step_compact_batch(b->desc(b->dmem, parity), b->tab(b->dmem, false, false),
+                                         b->tab(b->dmem, false, true), nbU, b->stream);
     hipError_t e = hipSuccess;
     if (nbU > 0)
         e = launch_step_fused_batch(b->prec, b->desc(b->dmem, parity), b->tab(b->dmem, false, false),
@@ -218,8 +223,10 @@ int lbcg_batch_create(lbcg_sim *const *sims, int32_t n, const int32_t *tile, lbc
     if (!tuned && ((tile[0] != 4 && tile[0] != 8) || tile[1] < 1)) return LBCG_E_INVAL;
     for (int j = 0; j < n; ++j) {
         const lbcg_sim *s = sims[j];
-        if (!s || !s->initialised || s->kernel != LBCG_KERNEL_FUSED || s->lattice != LBCG_D3Q19) return LBCG_E_INVAL;
-        if (s->prec != sims[0]->prec || s->stream != sims[0]->stream) return LBCG_E_INVAL;
+        if (!s || !s->initialised || s->lattice != LBCG_D3Q19) return LBCG_E_INVAL;
+        if (s->kernel != LBCG_KERNEL_FUSED && s->kernel != LBCG_KERNEL_COMPACT) return LBCG_E_INVAL;
+        if (s->kernel != sims[0]->kernel || s->prec != sims[0]->prec || s->stream != sims[0]->stream)
+            return LBCG_E_INVAL;
         for (int k = 0; k < j; ++k)
             if (sims[k] == s) return LBCG_E_INVAL;
     }
@@ -228,12 +235,18 @@ int lbcg_batch_create(lbcg_sim *const *sims, int32_t n, const int32_t *tile, lbc
     b->sims.assign(sims, sims + n);
     b->prec = sims[0]->prec;
     b->stream = sims[0]->stream;
+    b->compact = sims[0]->kernel == LBCG_KERNEL_COMPACT;
+    if (b->compact && !tuned && tile[0] != 8) {  // the compact sweep has 8-row tiles
+        delete b;
+        return LBCG_E_INVAL;
+    }
 
     // candidate shapes; the tables are sized for the largest
     std::vector<std::pair<int, int>> cand;
     if (tuned) {
         for (int r : {4, 8})
-            for (int p : {8, 16, 32, 64, kMaxPlanes}) cand.push_back({r, p});
+            for (int p : {8, 16, 32, 64, kMaxPlanes})
+                if (!b->compact || r == 8) cand.push_back({r, p});
     } else {
         cand.push_back({tile[0], tile[1]});
     }
@@ -287,14 +300,17 @@ int lbcg_batch_step(lbcg_batch *b, const int64_t *nsteps) {
     std::vector<int64_t> left(nsteps, nsteps + n);
     for (int j = 0; j < n; ++j)
         if (left[j] < 0) return LBCG_E_INVAL;
-    // The fused sweep reads post-collision state; a lattice fresh from
-    // initialisation takes its first step alone.
-    for (int j = 0; j < n; ++j)
-        if (left[j] > 0 && !b->sims[j]->pulled) {
-            const int rc = lbcg_step(b->sims[j], 1);
+    // The fused sweep reads post-collision state, and the batched compact
+    // sweep a compact one: a lattice fresh from initialisation (or, on the
+    // compact kernel, from a restore) takes its first steps alone.
+    for (int j = 0; j < n; ++j) {
+        lbcg_sim *s = b->sims[j];
+        while (left[j] > 0 && (!s->pulled || (b->compact && !s->compact))) {
+            const int rc = lbcg_step(s, 1);
             if (rc) return rc;
             --left[j];
         }
+    }
     std::vector<int> order;
     for (int j = 0; j < n; ++j)
         if (left[j] > 0) order.push_back(j);
@@ -329,6 +345,7 @@ int lbcg_batch_step(lbcg_batch *b, const int64_t *nsteps) {
         lbcg_sim *s = b->sims[j];
         s->cur ^= int(left[j] & 1);
         s->step += left[j];
+        s->expanded = false;
     }
     return LBCG_OK;
 }

@@ -566,6 +566,34 @@ __global__ void __launch_bounds__(kCTX * kCR) k_step_compact(CompactArgs a, Mode
         sweep_compact(a, mo, item / a.zchunks, item % a.zchunks, lds);
 }
 
+// Many lattices in one launch (batched form): entry k of the block table is
+// work item bitem[k] of lattice blat[k]; entries are dealt to the XCDs in
+// bands as above.  Every lattice is compact and periodic with 8-row tiles.
+__global__ void __launch_bounds__(kCTX * kCR)
+    k_step_compact_batch(const BatchDesc<float> *__restrict__ desc, const int *__restrict__ blat,
+                         const int *__restrict__ bitem) {
+    extern __shared__ float lds[];
+    const int total = int(gridDim.x);
+    const int xcd = blockIdx.x % kCXCD, l = blockIdx.x / kCXCD;
+    const int k = xcd * (total / kCXCD) + min(xcd, total % kCXCD) + l;
+    const int item = bitem[k];
+    const BatchDesc<float> d = desc[blat[k]];
+    CompactArgs a;
+    a.in = d.a.in;
+    a.out = d.a.out;
+    a.nx = d.a.nx;
+    a.ny = d.a.ny;
+    a.nz = d.a.nz;
+    a.pitch = d.a.pitch;
+    a.ctr_in = d.a.ctr_in;
+    a.ctr_out = d.a.ctr_out;
+    a.ntx = d.a.ntx;
+    a.nty = d.a.nty;
+    a.zchunks = d.a.zchunks;
+    if (item == 0 && threadIdx.x == 0) *a.ctr_out = *a.ctr_in + 1u;
+    sweep_compact(a, d.mo, item / a.zchunks, item % a.zchunks, lds);
+}
+
 // Pair state of nodes [0, N) from a compact state: each population's
 // minority colour part M f_i + (c_i . V_c) / 36 (the split the receiver
 // makes), as a share of f_i, with the flag of the colour it belongs to.
@@ -649,6 +677,21 @@ hipError_t launch_step_compact(const Geo &g, const ModelD &md, const void *in, b
         hipLaunchKernelGGL((k_step_compact<true>), grid, block, kPairInLds, s, a, mo);
     else
         hipLaunchKernelGGL((k_step_compact<false>), grid, block, kCompactLds, s, a, mo);
+    return hipGetLastError();
+}
+
+hipError_t launch_step_compact_batch(const void *desc, const int *blat, const int *bitem, int nblocks,
+                                     hipStream_t s) {
+    if (nblocks <= 0) return hipSuccess;
+    static bool lds_set = false;  // allow the record ring's LDS beyond 64 KiB
+    if (!lds_set) {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_step_compact_batch),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, int(kCompactLds));
+        (void)hipGetLastError();
+        lds_set = true;
+    }
+    hipLaunchKernelGGL(k_step_compact_batch, dim3(unsigned(nblocks)), dim3(unsigned(kCTX * kCR)), kCompactLds, s,
+                       static_cast<const BatchDesc<float> *>(desc), blat, bitem);
     return hipGetLastError();
 }
 

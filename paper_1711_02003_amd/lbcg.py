@@ -332,7 +332,8 @@ class Sim:
 
 
 class Batch:
-    """Many Sim handles (fused kernel, one precision, one stream) stepped together.
+    """Many Sim handles (all on the fused or all on the compact kernel, one
+    precision, one stream) stepped together.
 
     ``tile`` = (rows per block, z planes per chunk); None = chosen by timing on
     the batch.  The batch keeps references to its handles.

@@ -191,6 +191,39 @@ def test_batch_fresh_handles_and_f16(L, stream):
         assert np.array_equal(s.populations(), ref.populations()), w.name
 
 
+def test_batch_compact_matches_plain_bitwise(L, stream):
+    # compact-state lattices batched: each lattice bitwise as stepped alone;
+    # fresh handles and restored ones take their pair-state steps alone first
+    ws = _boxes(4, seed=14)
+    nsteps = [70, 33, 0, 5]  # a run of >= 32 levels replays graphs
+    sims = [L.Sim.from_workload(w, precision="f32", kernel=L.KERNEL_COMPACT, stream=stream.cuda_stream)
+            for w in ws]
+    sims[0].step(3)
+    b = L.Batch(sims)
+    info = b.launch_info()
+    _say(f"compact batch autotuned shape {info}")
+    assert info["rows"] == 8
+    b.step(nsteps)
+    for w, s, n, pre in zip(ws, sims, nsteps, [3, 0, 0, 0]):
+        ref = L.Sim.from_workload(w, precision="f32", kernel=L.KERNEL_COMPACT)
+        ref.step(pre + n)
+        assert np.array_equal(s.populations(), ref.populations()), w.name
+        assert s.diagnostics()["step"] == pre + n
+    sims[1].set_state(sims[1].get_state())
+    b.step([0, 40, 0, 0])
+    ref = L.Sim.from_workload(ws[1], precision="f32", kernel=L.KERNEL_COMPACT)
+    ref.step(33)
+    ref.set_state(ref.get_state())
+    ref.step(40)
+    assert np.array_equal(sims[1].populations(), ref.populations())
+    b.close()
+    with pytest.raises(L.LbcgError):
+        L.Batch(sims, tile=(4, 16))  # 8-row tiles only
+    pair = L.Sim.from_workload(ws[0], precision="f32", stream=stream.cuda_stream)
+    with pytest.raises(L.LbcgError):
+        L.Batch([sims[0], pair])  # one kernel kind per batch
+
+
 def test_batch_rejects_mixed_streams(L, stream):
     ws = _boxes(2, seed=13)
     a = L.Sim.from_workload(ws[0], precision="f32", stream=stream.cuda_stream)
