@@ -128,6 +128,26 @@ def test_compact_tile_shape_invariance(L, dims):
         s.close()
 
 
+def test_compact_concurrent_streams_match_sequential(L):
+    # handles on their own streams stepping at the same time, with chunks
+    # down to one plane (every record plane read by other blocks than the
+    # one that wrote it): bitwise the result of one handle stepped alone
+    w = W.config2(L=64, seed=3)
+    ref = L.Sim.from_workload(w, precision="f32", kernel=L.KERNEL_COMPACT, tile=(8, 1, 0))
+    ref.step(20)
+    ref.synchronize()
+    pr = ref.populations()
+    for zc in (64, 8, 2):
+        a = L.Sim.from_workload(w, precision="f32", kernel=L.KERNEL_COMPACT, tile=(8, zc, 0))
+        b = L.Sim.from_workload(w, precision="f32", kernel=L.KERNEL_COMPACT, tile=(8, 1, 0))
+        a.step(20)
+        b.step(20)
+        assert np.array_equal(a.populations(), pr), zc
+        assert np.array_equal(b.populations(), pr), zc
+        a.close()
+        b.close()
+
+
 def test_compact_reads_leave_trajectory_unchanged(L):
     # reading the state converts it into the pair buffer but steps go on from
     # the compact state: a run with reads is bitwise the run without
