@@ -29,12 +29,18 @@
 // can keep in flight (its memory counter holds 63), so the records are
 // staged instead: each plane's records over the tile plus a two-node halo
 // (the ring's own senders) are loaded once, with a 16-byte and a 12-byte
-// load per node, into a 4-slot LDS ring, three planes ahead of their first use, and
-// the receivers read them from there.  The threads of the three waves that
-// hold the ring nodes load no records, so every wave keeps fewer than 63
-// memory operations in flight.  The first step after an initialisation or a
-// restore reads a pair state instead (the same sweep with pair pulls), so
-// the compact state always holds what a recolouring produced.
+// load per node, into a 4-slot LDS ring, three planes ahead of their first
+// use, and the receivers read them from there.  The threads of the three
+// waves that hold the ring nodes load no records, so every wave keeps fewer
+// than 63 memory operations in flight.  The batched form runs the same sweep
+// over many lattices from a block table.  The first step after an
+// initialisation or a restore reads a pair state instead (the same sweep
+// with pair pulls), so the compact state always holds what a recolouring
+// produced.
+#include <mutex>
+#include <set>
+#include <utility>
+
 #include "lbcg_buffer.h"
 #include "lbcg_internal.h"
 
@@ -623,6 +629,22 @@ __global__ void k_expand(const float *__restrict__ cin, typename PairOf<float>::
 constexpr size_t kCompactLds = (size_t(kPSlots) * kPN + size_t(kSSlots) * kNS * kSN) * sizeof(float);
 constexpr size_t kPairInLds = size_t(kPSlots) * kPN * sizeof(float);
 
+// Allows a compact kernel (k = 0 single, 1 batched) the record ring's LDS
+// beyond 64 KiB, once per device and kernel.
+void allow_lds(const void *fn, int k) {
+    static std::mutex mu;
+    static std::set<std::pair<int, int>> done;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return;
+    }
+    std::lock_guard<std::mutex> lock(mu);
+    if (!done.insert({dev, k}).second) return;
+    (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(kCompactLds));
+    (void)hipGetLastError();
+}
+
 }  // namespace
 
 // The first step reads the pair state, so both layouts must stay within
@@ -665,13 +687,7 @@ hipError_t launch_step_compact(const Geo &g, const ModelD &md, const void *in, b
     const int64_t nblocks = int64_t(a.ntx) * a.nty * a.zchunks;
     if (nblocks > 0x7fffffff) return hipErrorInvalidValue;
     const Model<float> mo = to_model<float>(md);
-    static bool lds_set = false;  // allow the record ring's LDS beyond 64 KiB
-    if (!lds_set) {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_step_compact<false>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, int(kCompactLds));
-        (void)hipGetLastError();
-        lds_set = true;
-    }
+    allow_lds(reinterpret_cast<const void *>(&k_step_compact<false>), 0);
     const dim3 grid = dim3(unsigned(nblocks)), block = dim3(unsigned(kCTX * kCR));
     if (pair_in)
         hipLaunchKernelGGL((k_step_compact<true>), grid, block, kPairInLds, s, a, mo);
@@ -683,13 +699,7 @@ hipError_t launch_step_compact(const Geo &g, const ModelD &md, const void *in, b
 hipError_t launch_step_compact_batch(const void *desc, const int *blat, const int *bitem, int nblocks,
                                      hipStream_t s) {
     if (nblocks <= 0) return hipSuccess;
-    static bool lds_set = false;  // allow the record ring's LDS beyond 64 KiB
-    if (!lds_set) {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_step_compact_batch),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, int(kCompactLds));
-        (void)hipGetLastError();
-        lds_set = true;
-    }
+    allow_lds(reinterpret_cast<const void *>(&k_step_compact_batch), 1);
     hipLaunchKernelGGL(k_step_compact_batch, dim3(unsigned(nblocks)), dim3(unsigned(kCTX * kCR)), kCompactLds, s,
                        static_cast<const BatchDesc<float> *>(desc), blat, bitem);
     return hipGetLastError();
