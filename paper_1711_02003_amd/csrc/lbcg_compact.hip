@@ -101,22 +101,28 @@ __device__ __forceinline__ void col_offsets(const CompactArgs &a, int x, int y, 
         for (int c = 0; c < 3; ++c) t[c + 3 * b] = (xs[c] + uint32_t(a.nx) * ys[b]) * E;
 }
 
+// Every buffer access takes its wave-uniform byte offset through
+// readfirstlane at the point of use: the compiler otherwise may merge equal
+// offsets of different accesses into vector registers and then wrap each
+// access in a loop over the distinct values of its scalar offset.
+__device__ __forceinline__ int su(uint32_t v) { return __builtin_amdgcn_readfirstlane(int(v)); }
+
 __device__ __forceinline__ float load_f(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, int(voff), int(soff), 0));
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, int(voff), su(soff), 0));
 }
 __device__ __forceinline__ f4 load_f4(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
-    return __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(r, int(voff), int(soff), 0));
+    return __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(r, int(voff), su(soff), 0));
 }
 typedef float f3 __attribute__((ext_vector_type(3)));
 typedef unsigned int u3 __attribute__((ext_vector_type(3)));
 __device__ __forceinline__ f3 load_f3(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
-    return __builtin_bit_cast(f3, __builtin_amdgcn_raw_buffer_load_b96(r, int(voff), int(soff), 0));
+    return __builtin_bit_cast(f3, __builtin_amdgcn_raw_buffer_load_b96(r, int(voff), su(soff), 0));
 }
 __device__ __forceinline__ void store_f4(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, f4 v) {
-    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, v), r, int(voff), int(soff), kNonTemporal);
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, v), r, int(voff), su(soff), kNonTemporal);
 }
 __device__ __forceinline__ void store_f3(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, f3 v) {
-    __builtin_amdgcn_raw_buffer_store_b96(__builtin_bit_cast(u3, v), r, int(voff), int(soff), kNonTemporal);
+    __builtin_amdgcn_raw_buffer_store_b96(__builtin_bit_cast(u3, v), r, int(voff), su(soff), kNonTemporal);
 }
 
 // Byte offsets of planes z-1, z, z+1 (periodic) for plane size `plane`.
@@ -134,7 +140,7 @@ __device__ __forceinline__ void store_compact(const CompactArgs &a, __amdgpu_buf
     const uint32_t cs = uint32_t(uniform(int(uint32_t(a.pitch) * 4u)));
     const uint32_t zoff = uint32_t(uniform(z)) * (uint32_t(a.nx) * uint32_t(a.ny) * 4u);
 #pragma unroll
-    for (int i = 0; i < D3Q19::Q; ++i) store_pair<float>(rout, own, uint32_t(i) * cs + zoff, o.df[i]);
+    for (int i = 0; i < D3Q19::Q; ++i) store_pair<float>(rout, own, uint32_t(su(uint32_t(i) * cs + zoff)), o.df[i]);
     // records: own and zoff count 4 bytes per node
     const f4 q0 = {Codec<float>::enc_col<float>(o.M, o.redmaj), o.Va[0], o.Va[1], o.Va[2]};
     const f3 q1 = {o.Vd[0], o.Vd[1], o.Vd[2]};
@@ -421,7 +427,7 @@ __device__ __forceinline__ void pull_pairs(const CompactArgs &a, __amdgpu_buffer
 #pragma unroll
     for (int i = 0; i < L::Q; ++i)
         pd.v[i] = load_pair<typename PairOf<float>::type>(r, t[(1 - L::cx[i]) + 3 * (1 - L::cy[i])],
-                                                          uint32_t(i) * cs + zo[1 - L::cz[i]]);
+                                                          uint32_t(su(uint32_t(i) * cs + zo[1 - L::cz[i]])));
 }
 
 __device__ __forceinline__ void sweep_pairs(const CompactArgs &a, const Model<float> &mo, int tile, int chunk,
