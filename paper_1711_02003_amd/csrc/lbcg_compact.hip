@@ -66,7 +66,6 @@ constexpr int kLoaders = kCTX * kCR - kLoad0;
 constexpr int kPerLoader = (kSN + kLoaders - 1) / kLoaders;
 
 typedef float f4 __attribute__((ext_vector_type(4)));
-typedef unsigned int u4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ void c_lds_barrier() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
@@ -114,15 +113,22 @@ __device__ __forceinline__ f4 load_f4(__amdgpu_buffer_rsrc_t r, uint32_t voff, u
     return __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(r, int(voff), su(soff), 0));
 }
 typedef float f3 __attribute__((ext_vector_type(3)));
-typedef unsigned int u3 __attribute__((ext_vector_type(3)));
 __device__ __forceinline__ f3 load_f3(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
     return __builtin_bit_cast(f3, __builtin_amdgcn_raw_buffer_load_b96(r, int(voff), su(soff), 0));
 }
-__device__ __forceinline__ void store_f4(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, f4 v) {
-    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, v), r, int(voff), su(soff), kNonTemporal);
+// Records are written with stores of at most 8 bytes per lane.  A wider
+// store (12 or 16 bytes) may read its data registers after later
+// instructions have been issued, and the compiler reuses those registers at
+// once (seen: the next store's address written into the first data register
+// of a 12-byte store, with its later lanes' data lost under memory
+// back-pressure).
+typedef float f2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void store_f2(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, f2 v) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, int(voff), su(soff), kNonTemporal);
 }
-__device__ __forceinline__ void store_f3(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, f3 v) {
-    __builtin_amdgcn_raw_buffer_store_b96(__builtin_bit_cast(u3, v), r, int(voff), su(soff), kNonTemporal);
+__device__ __forceinline__ void store_f1(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, float v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, int(voff), su(soff), kNonTemporal);
 }
 
 // Byte offsets of planes z-1, z, z+1 (periodic) for plane size `plane`.
@@ -142,10 +148,13 @@ __device__ __forceinline__ void store_compact(const CompactArgs &a, __amdgpu_buf
 #pragma unroll
     for (int i = 0; i < D3Q19::Q; ++i) store_pair<float>(rout, own, uint32_t(su(uint32_t(i) * cs + zoff)), o.df[i]);
     // records: own and zoff count 4 bytes per node
-    const f4 q0 = {Codec<float>::enc_col<float>(o.M, o.redmaj), o.Va[0], o.Va[1], o.Va[2]};
-    const f3 q1 = {o.Vd[0], o.Vd[1], o.Vd[2]};
-    store_f4(rout, own * 4u, uint32_t(D3Q19::Q) * cs + zoff * 4u, q0);
-    store_f3(rout, own * 3u, uint32_t(D3Q19::Q + 4) * cs + zoff * 3u, q1);
+    const uint32_t ra = uint32_t(D3Q19::Q) * cs + zoff * 4u, rb = uint32_t(D3Q19::Q + 4) * cs + zoff * 3u;
+    const f2 a01 = {Codec<float>::enc_col<float>(o.M, o.redmaj), o.Va[0]}, a23 = {o.Va[1], o.Va[2]};
+    const f2 b01 = {o.Vd[0], o.Vd[1]};
+    store_f2(rout, own * 4u, ra, a01);
+    store_f2(rout, own * 4u, ra + 8u, a23);
+    store_f2(rout, own * 3u, rb, b01);
+    store_f1(rout, own * 3u, rb + 8u, o.Vd[2]);
 }
 
 // Split of the 19 pulled totals d of a node with its senders' scalars, read
