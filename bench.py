@@ -145,26 +145,29 @@ def f16_form(torch, lbcg, W, size, steps=200, warmup=10):
 
 
 def d2q9_form(torch, lbcg, W, steps=200, warmup=10):
-    """D2Q9 4096^2 with 256 droplets, FP32 storage: the fused strip sweep
-    (tuned) and, for comparison, the two-pass generic kernel (a psi pass,
-    then the step), both against the 144 B per node that one read and one
-    write of every population pair move."""
+    """D2Q9 4096^2 with 256 droplets, FP32 storage: the fused strip sweep on
+    the compact state (tuned; 112 B per node: every total and the senders'
+    5 colour scalars read and written once), on the pair state (tuned; 144 B
+    per node: one read and one write of every population pair) and, for
+    comparison, the two-pass generic kernel (a psi pass, then the step)
+    against the same 144 B."""
     w = W.droplets_2d(n=4096, seed=6)
     out = {"workload": w.name, "storage": "f32", "bytes_per_node": 144, "steps": steps}
-    for name, kernel in (("fused", lbcg.KERNEL_FUSED), ("generic", lbcg.KERNEL_GENERIC)):
+    for name, kernel, bpn in (("compact", lbcg.KERNEL_COMPACT, 112), ("fused", lbcg.KERNEL_FUSED, 144),
+                              ("generic", lbcg.KERNEL_GENERIC, 144)):
         stream = torch.cuda.Stream()
         sim = lbcg.Sim.from_workload(w, precision="f32", kernel=kernel, stream=stream.cuda_stream)
-        sim.step(1)
-        if kernel == lbcg.KERNEL_FUSED:
+        sim.step(2)
+        if kernel != lbcg.KERNEL_GENERIC:
             sim.tune()
         ms = time_sim(torch, sim, stream, steps, warmup)
         info = sim.launch_info()
         sim.close()
-        gbs = 144 * w.fluid_nodes * steps / (ms / 1e3) / 1e9
+        gbs = bpn * w.fluid_nodes * steps / (ms / 1e3) / 1e9
         out[name] = {"mlups": round(w.fluid_nodes * steps / (ms / 1e3) / 1e6, 1),
                      "ms_per_step": round(ms / steps, 4), "achieved_gbs": round(gbs, 1),
-                     "frac": round(gbs / HBM_PEAK_GBS, 4)}
-        if kernel == lbcg.KERNEL_FUSED:
+                     "frac": round(gbs / HBM_PEAK_GBS, 4), "bytes_per_node": bpn}
+        if kernel != lbcg.KERNEL_GENERIC:
             out[name]["ychunks"] = info["zchunks"]
     return out
 

@@ -64,22 +64,24 @@ extern "C" {
  * F16 storage, regularized collision, state buffers below 4 GiB; D3Q19 or
  * D2Q9, any geometry).  Automatic picks the fused kernel where it applies.
  *
- * LBCG_KERNEL_COMPACT (never picked automatically): the fused D3Q19 sweep on
- * a compact state, for periodic lattices (no mask), F32, regularized
- * collision, tiles of 8 rows (tile[0] 0 or 8), 38 x 4 x pitch bytes below
- * 4 GiB (pitch = node count rounded up to 64).  Eq. (10) splits every
- * population of a node with coefficients that depend only on that node and
- * on the speed class of the direction, so each node stores its 19 total
- * populations and 7 colour scalars (its minority share and one 3-vector per
- * speed class) and the receiver of a population splits it: 208 bytes of
- * memory traffic per node and step instead of 304.  Results
+ * LBCG_KERNEL_COMPACT (never picked automatically): the fused sweeps on a
+ * compact state, for periodic lattices (no mask), F32, regularized
+ * collision; D3Q19 with tiles of 8 rows (tile[0] 0 or 8) or D2Q9; 2Q x 4 x
+ * pitch bytes below 4 GiB (pitch = node count rounded up to 64).  Eq. (10)
+ * splits every population of a node with coefficients that depend only on
+ * that node and on the speed class of the direction, so each node stores its
+ * Q total populations and its colour scalars (its minority share and one
+ * vector per speed class) and the receiver of a population splits it: 208
+ * bytes of memory traffic per node and step instead of 304 (D3Q19), 112
+ * instead of 144 (D2Q9).  Results
  * agree with the pair-state kernels up to rounding.  The first step
  * after lbcg_init_fields or lbcg_set_state reads the pair state; the calls
  * that read the state (fields, populations, diagnostics, lbcg_get_state)
  * first convert the compact state to a pair state in the handle's pair
  * buffer, which the compact steps leave unused (one extra kernel, no change
  * to the trajectory).  lbcg_footprint
- * adds the two compact buffers (2 x 104 x pitch bytes). */
+ * adds the two compact buffers (2 x 104 x pitch bytes for D3Q19, 2 x 56 x
+ * pitch for D2Q9). */
 #define LBCG_KERNEL_AUTO 0
 #define LBCG_KERNEL_GENERIC 1
 #define LBCG_KERNEL_FUSED 2

@@ -665,8 +665,9 @@ void allow_lds(const void *fn, int k) {
 // The first step reads the pair state, so both layouts must stay within
 // 32-bit byte offsets.
 bool compact_supported(int lattice, int prec, const Geo &g) {
-    return lattice == 1 && prec == 1 && g.mask == nullptr &&
-           uint64_t(2 * D3Q19::Q) * uint64_t(g.pitch) * 4u < (uint64_t(1) << 32);
+    if (prec != 1 || g.mask != nullptr) return false;
+    if (lattice == 0) return g.nz == 1 && uint64_t(2 * D2Q9::Q) * uint64_t(g.pitch) * 4u < (uint64_t(1) << 32);
+    return lattice == 1 && uint64_t(2 * D3Q19::Q) * uint64_t(g.pitch) * 4u < (uint64_t(1) << 32);
 }
 
 int compact_resident_blocks(int) {

@@ -84,7 +84,9 @@ Plan make_plan(const lbcg_params *p) {
     const int per = 2 * pl.Q > 6 ? 2 * pl.Q : 6;
     pl.state = align_up(size_t(2 * pl.Q) * size_t(pl.pitch) * pl.elem, kAlign);
     pl.cstate = p->kernel == LBCG_KERNEL_COMPACT
-                    ? align_up(size_t(kCompactBytes) * size_t(pl.pitch), kAlign)
+                    ? align_up(size_t(p->lattice == LBCG_D2Q9 ? kCompactBytes2d : kCompactBytes) *
+                                   size_t(pl.pitch),
+                               kAlign)
                     : 0;
     pl.psi = align_up(size_t(pl.pitch) * pl.tsize, kAlign);
     pl.mask = p->mask ? align_up(size_t(pl.pitch), kAlign) : 0;
@@ -130,6 +132,15 @@ hipError_t launch_fused(const lbcg_sim *s, const void *in, void *out, const uint
     return launch_step_fused(s->prec, s->g, s->md, in, out, ctr_in, ctr_out, shape, s->stream);
 }
 
+// The compact-state sweep of the lattice: D3Q19 column sweep or D2Q9 strip
+// sweep (shape.zchunks counts row chunks there).
+hipError_t launch_compact(const lbcg_sim *s, const void *in, bool pair_in, void *out, const uint32_t *ctr_in,
+                          uint32_t *ctr_out, FusedShape shape) {
+    if (s->lattice == LBCG_D2Q9)
+        return launch_step_compact2d(s->g, s->md, in, pair_in, out, ctr_in, ctr_out, shape.zchunks, s->stream);
+    return launch_step_compact(s->g, s->md, in, pair_in, out, ctr_in, ctr_out, shape, s->stream);
+}
+
 FusedShape pick_shape(const lbcg_sim *s, const lbcg_params *p) {
     FusedShape sh;
     if (s->lattice == LBCG_D2Q9) {
@@ -139,7 +150,7 @@ FusedShape pick_shape(const lbcg_sim *s, const lbcg_params *p) {
         // of a channel then still spreads over the device)
         sh.rows = 1;
         int yc = p->tile[1];
-        if (!yc && s->kernel == LBCG_KERNEL_FUSED) {
+        if (!yc && (s->kernel == LBCG_KERNEL_FUSED || s->kernel == LBCG_KERNEL_COMPACT)) {
             const int64_t strips = (s->g.nx + 63) / 64;
             const int64_t want = s->g.mask ? (s->g.ny + 15) / 16 : (4096 + strips - 1) / strips;
             const int64_t cap = s->g.ny / 8 > 1 ? s->g.ny / 8 : 1;
@@ -176,8 +187,8 @@ hipError_t enqueue_step(lbcg_sim *s, bool pulled) {
     uint32_t *ctr_out = s->ctr + (s->cur ^ 1);
     if (s->kernel == LBCG_KERNEL_COMPACT && pulled) {
         const bool pair_in = !s->compact;
-        hipError_t e = launch_step_compact(s->g, s->md, pair_in ? s->buf[s->cur] : s->cbuf[s->cur], pair_in,
-                                           s->cbuf[s->cur ^ 1], ctr_in, ctr_out, s->shape, s->stream);
+        hipError_t e = launch_compact(s, pair_in ? s->buf[s->cur] : s->cbuf[s->cur], pair_in, s->cbuf[s->cur ^ 1],
+                                      ctr_in, ctr_out, s->shape);
         if (e == hipSuccess) {
             s->compact = true;
             s->expanded = false;
@@ -499,7 +510,8 @@ int lbcg_step(lbcg_sim *s, int64_t n) {
 // state (the compact state itself stays the one the next step reads).
 static hipError_t ensure_pairs(lbcg_sim *s) {
     if (!s->compact || s->expanded) return hipSuccess;
-    hipError_t e = launch_expand(s->g, s->cbuf[s->cur], s->buf[s->cur], s->stream);
+    hipError_t e = s->lattice == LBCG_D2Q9 ? launch_expand2d(s->g, s->cbuf[s->cur], s->buf[s->cur], s->stream)
+                                           : launch_expand(s->g, s->cbuf[s->cur], s->buf[s->cur], s->stream);
     if (e == hipSuccess) s->expanded = true;
     return e;
 }
@@ -725,7 +737,7 @@ int lbcg_tune(lbcg_sim *s, int32_t *rows, int32_t *zchunks) {
         const uint32_t *ctr_in = s->ctr + s->cur;
         uint32_t *ctr_out = s->ctr + (s->cur ^ 1);
         auto run = [&](const FusedShape &c) {
-            return cmp ? launch_step_compact(s->g, s->md, in, pair_in, out, ctr_in, ctr_out, c, s->stream)
+            return cmp ? launch_compact(s, in, pair_in, out, ctr_in, ctr_out, c)
                        : launch_fused(s, in, out, ctr_in, ctr_out, c);
         };
         float best = 0;

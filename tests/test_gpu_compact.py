@@ -1,4 +1,4 @@
-"""GPU parity of the compact-state D3Q19 sweep (LBCG_KERNEL_COMPACT).
+"""GPU parity of the compact-state sweeps (LBCG_KERNEL_COMPACT), D3Q19 and D2Q9.
 
 The compact state keeps, per node, the 19 total populations and 7 colour
 scalars from which the receiver of a population splits it into colours
@@ -215,7 +215,137 @@ def test_compact_rejects_what_it_does_not_cover(L):
         L.Sim.from_workload(w, precision="f32", kernel=L.KERNEL_COMPACT)
     w2 = W.droplets_2d(n=64, seed=1)
     with pytest.raises(L.LbcgError):
-        L.Sim.from_workload(w2, precision="f32", kernel=L.KERNEL_COMPACT)
+        L.Sim.from_workload(w2, precision="f16", kernel=L.KERNEL_COMPACT)
     w.mask = None
     with pytest.raises(L.LbcgError):  # 8-row tiles only
         L.Sim.from_workload(w, precision="f32", kernel=L.KERNEL_COMPACT, tile=(4, 0, 0))
+
+
+# ---------------------------------------------------------------- D2Q9
+
+def _random_2d(dims, seed):
+    rng = np.random.default_rng(seed)
+    nx, ny, _ = dims
+    sh = (1, ny, nx)
+    u = np.zeros((3,) + sh)
+    u[:2] = rng.uniform(-0.04, 0.04, (2,) + sh)
+    return W.Workload("random2d", "D2Q9", dims, rng.uniform(0.05, 1, sh), rng.uniform(0.05, 1, sh), u,
+                      1.3, 0.7, 0.01, 0.7)
+
+
+@pytest.mark.parametrize("dims", [(64, 64, 1), (100, 37, 1), (130, 9, 1), (5, 3, 1)])
+def test_compact2d_agrees_with_pair_fused(L, dims):
+    # several strips, a ragged strip, a lattice narrower than the record halo
+    w = _random_2d(dims, seed=sum(dims) + 1)
+    a = L.Sim.from_workload(w, precision="f32", kernel=L.KERNEL_COMPACT)
+    b = L.Sim.from_workload(w, precision="f32", kernel=L.KERNEL_FUSED)
+    assert a.launch_info()["kernel"] == L.KERNEL_COMPACT
+    a.step(50)
+    b.step(50)
+    d = _maxrel(a.populations(), b.populations())
+    _say(f"compact2d vs fused2d {dims} x50: {d:.2e}")
+    assert d < 50 * 4 * EPS32
+
+
+@pytest.mark.parametrize("ychunks", [3, 16, 256])
+def test_compact2d_chunk_invariance(L, ychunks):
+    w = W.droplets_2d(n=256, seed=6)
+    ref = L.Sim.from_workload(w, precision="f32", kernel=L.KERNEL_COMPACT, tile=(0, 1, 0))
+    s = L.Sim.from_workload(w, precision="f32", kernel=L.KERNEL_COMPACT, tile=(0, ychunks, 0))
+    assert s.launch_info()["zchunks"] == ychunks
+    ref.step(20)
+    ref.synchronize()
+    s.step(20)
+    assert np.array_equal(s.populations(), ref.populations())
+
+
+def test_compact2d_concurrent_streams_match_sequential(L):
+    # one-row chunks stepping while other handles run on their own streams:
+    # every row's records are written in the last stores of a wave, under
+    # the memory traffic of the other kernels; bitwise the handle alone
+    w = W.droplets_2d(n=256, seed=6)
+    ref = L.Sim.from_workload(w, precision="f32", kernel=L.KERNEL_COMPACT, tile=(0, 1, 0))
+    ref.step(20)
+    ref.synchronize()
+    pr = ref.populations()
+    for trial in range(3):
+        for yc in (256, 64):
+            a = L.Sim.from_workload(w, precision="f32", kernel=L.KERNEL_COMPACT, tile=(0, yc, 0))
+            b = L.Sim.from_workload(w, precision="f32", kernel=L.KERNEL_FUSED, tile=(0, 1, 0))
+            c = L.Sim.from_workload(w, precision="f32", kernel=L.KERNEL_COMPACT, tile=(0, 1, 0))
+            b.step(60)
+            c.step(60)
+            a.step(20)
+            assert np.array_equal(a.populations(), pr), (trial, yc)
+            for h in (a, b, c):
+                h.close()
+
+
+def test_compact2d_f32_matches_oracle_1000_steps(L, orc):
+    # 256^2 with 256 droplets (tau_R = 1, tau_B = 0.6, A = 0.005), tuned shape
+    w = W.droplets_2d(n=256, seed=6)
+    _say("compact2d f32 256^2 x1000")
+    s = L.Sim.from_workload(w, precision="f32", kernel=L.KERNEL_COMPACT)
+    s.step(2)
+    s.tune()
+    o = oracle_for(orc, w, threads=8)
+    o.step(2)
+    d0 = s.diagnostics(check=True)
+    s.step(998)
+    o.step(998)
+    g, f = s.fields(), o.fields()
+    eu, ep = rel_l2(g["u"], f["u"]), rel_l2(g["psi"], f["psi"])
+    _say(f"  relL2 u {eu:.3e} psi {ep:.3e}")
+    assert eu < 1e-5 and ep < 1e-5
+    d1 = s.diagnostics(check=True)
+    assert abs(d1["mass_R"] - d0["mass_R"]) / d0["mass_R"] < 1e-6
+    assert abs(d1["mass_B"] - d0["mass_B"]) / d0["mass_B"] < 1e-6
+
+
+def test_compact2d_full_size_sampled(L, orc):
+    # the benchmark's 4096^2 D2Q9 lattice: sampled nodes' next state against
+    # the oracle's step of a periodic 5 x 5 box cut around each
+    w = W.droplets_2d(n=4096, seed=6)
+    _say("full size 4096^2 compact2d f32")
+    s = L.Sim.from_workload(w, precision="f32", kernel=L.KERNEL_COMPACT)
+    s.step(2)
+    s.tune()
+    s.step(18)
+    nx, ny, _ = w.dims
+    rng = np.random.default_rng(3)
+    centres = np.stack([rng.integers(0, nx, 48), rng.integers(0, ny, 48)], 1)
+    off = np.arange(-2, 3)
+    boxes = []
+    for cx, cy in centres:
+        yy, xx = np.meshgrid((cy + off) % ny, (cx + off) % nx, indexing="ij")
+        boxes.append((xx + nx * yy).reshape(-1))
+    before = s.populations_at(np.concatenate(boxes)).reshape(len(centres), 1, 5, 5, 2, 9)
+    s.step(1)
+    after = s.populations_at(np.array([b[12] for b in boxes]))  # 12 = centre of a 5 x 5 box
+    p = orc.Params(lattice=orc.D2Q9, dims=(5, 5, 1), tau=(w.tau_R, w.tau_B), A=(w.A, w.A), beta=w.beta)
+    worst = 0.0
+    for j in range(len(centres)):
+        o = orc.Oracle(p)
+        o.set_populations(np.moveaxis(before[j], (3, 4), (0, 1)))
+        o.step(1)
+        ref = o.populations()[:, :, 0, 2, 2]
+        worst = max(worst, float(np.abs(after[j] - ref).max() / np.abs(ref).max()))
+    _say(f"  sampled one-step max rel diff {worst:.2e}")
+    assert worst < 2e-6
+
+
+def test_compact2d_reads_and_resume(L):
+    w = W.droplets_2d(n=128, seed=2)
+    a = L.Sim.from_workload(w, precision="f32", kernel=L.KERNEL_COMPACT)
+    b = L.Sim.from_workload(w, precision="f32", kernel=L.KERNEL_COMPACT)
+    for _ in range(3):
+        a.step(10)
+        a.populations()
+        a.diagnostics()
+    b.step(30)
+    assert np.array_equal(a.populations(), b.populations())
+    c = L.Sim.from_workload(w, precision="f32", kernel=L.KERNEL_FUSED)
+    c.set_state(b.get_state())
+    b.step(20)
+    c.step(20)
+    assert _maxrel(c.populations(), b.populations()) < 20 * 4 * EPS32
