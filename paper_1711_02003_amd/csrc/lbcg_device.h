@@ -342,6 +342,24 @@ __device__ __forceinline__ void decode_pair(typename PairOf<S>::type v, int i, P
     p.set(i, d, m, fl);
 }
 
+// Stores of more than 8 bytes per lane may read their data registers after
+// the compiler has already reused them (seen on 12-byte stores: data of the
+// last lanes of each 16-lane group lost under memory back-pressure from a
+// concurrent kernel), so 16-byte (FP64) pairs are written as two 8-byte
+// halves, with a compiler barrier between them that keeps them from being
+// merged into one store again.
+template <typename P2>
+__device__ __forceinline__ void put_pair(P2 *p, P2 v) {
+    if constexpr (sizeof(P2) > 8) {
+        double *d = reinterpret_cast<double *>(p);
+        d[0] = double(v.x);
+        asm volatile("" ::: "memory");
+        d[1] = double(v.y);
+    } else {
+        *p = v;
+    }
+}
+
 template <class L, typename S, typename T>
 __device__ __forceinline__ typename PairOf<S>::type encode_pair(T df, T m, bool redmaj, int i) {
     typename PairOf<S>::type v;
@@ -891,7 +909,7 @@ __device__ __forceinline__ void store_node(const Geo &g, const Model<T> &mo, S *
                                            int z, int64_t node, const typename PairOf<S>::type enc[L::Q]) {
     typename PairOf<S>::type *a = reinterpret_cast<typename PairOf<S>::type *>(st);
 #pragma unroll
-    for (int i = 0; i < L::Q; ++i) a[int64_t(i) * g.pitch + node] = enc[i];
+    for (int i = 0; i < L::Q; ++i) put_pair(a + int64_t(i) * g.pitch + node, enc[i]);
     if (!g.mask) return;
     bool own = false;
     OwnMom<T> om{};
@@ -907,7 +925,7 @@ __device__ __forceinline__ void store_node(const Geo &g, const Model<T> &mo, S *
             om = own_moments<L, S, T>(enc);
             own = true;
         }
-        a[int64_t(i) * g.pitch + m] = boundary_pair<L, S, T>(g, mo, i, code, enc[L::opp[i]], om);
+        put_pair(a + int64_t(i) * g.pitch + m, boundary_pair<L, S, T>(g, mo, i, code, enc[L::opp[i]], om));
     }
 }
 

@@ -50,8 +50,8 @@ __global__ void __launch_bounds__(kBlock) k_init(Geo g, Model<T> mo, int64_t n0,
         double m;
         bool redmaj;
         split_shares<double>(f != 0.0 ? fR / f : 0.0, f != 0.0 ? fB / f : 0.0, m, redmaj);
-        reinterpret_cast<typename PairOf<S>::type *>(st)[int64_t(i) * g.pitch + n] =
-            encode_pair<L, S, double>(f - w, m, redmaj, i);
+        put_pair(reinterpret_cast<typename PairOf<S>::type *>(st) + int64_t(i) * g.pitch + n,
+                 encode_pair<L, S, double>(f - w, m, redmaj, i));
     }
 }
 
@@ -194,7 +194,10 @@ __global__ void __launch_bounds__(kBlock) k_pops_at(Geo g, Model<T> mo, const S 
     double *o = out + j * 2 * L::Q;
     if (n < 0 || n >= g.N || code_at(g, n) != kFluid) {
 #pragma unroll
-        for (int i = 0; i < 2 * L::Q; ++i) o[i] = 0.0;
+        for (int i = 0; i < 2 * L::Q; ++i) {
+            o[i] = 0.0;
+            asm volatile("" ::: "memory");  // 8-byte stores only (see put_pair)
+        }
         return;
     }
     int x, y, z;
@@ -207,6 +210,7 @@ __global__ void __launch_bounds__(kBlock) k_pops_at(Geo g, Model<T> mo, const S 
         const T r = p.fred(i);
         o[i] = double(r);
         o[L::Q + i] = double(f - r);
+        asm volatile("" ::: "memory");  // 8-byte stores only (see put_pair)
     }
 }
 
