@@ -124,10 +124,12 @@ def traffic_summary(fetch_csv, write_csv, kernel_sub, timed, nodes, out_txt, com
     return txt
 
 
-FORM_KERNELS = [("D2Q9 4096² droplets, FP32", "void lbcg::k_step_fused2d<float, false>"),
+FORM_KERNELS = [("D2Q9 4096² droplets, FP32 compact", "void lbcg::(anonymous namespace)::k_step_compact2d<false>"),
+                ("D2Q9 4096² droplets, FP32", "void lbcg::k_step_fused2d<float, false>"),
                 ("D2Q9 junction 8192×2048, FP32", "void lbcg::k_step_fused2d<float, true>"),
                 ("D3Q19 junction 512×128×64, FP32", "void lbcg::k_step_fused<float, float, 8, true>"),
-                ("D3Q19 junction 512×128×64, FP16", "_ZN4lbcg12k_step_fusedIDF16_fLi8ELb1EE")]
+                ("D3Q19 junction 512×128×64, FP16", "_ZN4lbcg12k_step_fusedIDF16_fLi8ELb1EE"),
+                ("D3Q19 64 boxes batched, FP32 compact", "lbcg::(anonymous namespace)::k_step_compact_batch")]
 
 
 def forms_summary(trace_csv, out_md, timed, command):
