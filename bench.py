@@ -9,7 +9,7 @@ of every node (both colours).  Prints one JSON line:
   value      whole-job two-component MLUPS (fluid nodes x steps / time), inputs
              resident in HBM, timed with HIP events on the simulation's stream;
   roofline   HBM roofline of the step's kernel: algorithmic bytes per node
-             (read + write the state once: compact 2 x (19 x 4 + 28) = 208 B,
+             (read + write the state once: compact 2 x (19 x 4 + 20) = 192 B,
              pair state 2 x 38 x 4 = 304 B) x nodes / average kernel time,
              against 8 TB/s; traffic = HBM bytes per launch from the rocprofv3
              FETCH_SIZE / WRITE_SIZE counters scaled by a copy-kernel
@@ -250,7 +250,7 @@ def batched_form(torch, lbcg, W, steps=200, warmup=10, compact=False):
         s.close()
     mb = nodes * steps / (ms_b / 1e3) / 1e6
     mp = nodes * steps / (ms_p / 1e3) / 1e6
-    bpn = 2 * (19 * 4 + 28) if compact else 304
+    bpn = 2 * (19 * 4 + 20) if compact else 304
     return {"workload": "64 periodic D3Q19 boxes, edges U{32..96}, seed 4", "nodes": nodes,
             "state": "compact" if compact else "pairs", "bytes_per_node": bpn,
             "steps": steps, "batched_mlups": round(mb, 1), "plain_mlups": round(mp, 1),
@@ -353,7 +353,7 @@ def main():
 
     N = w.fluid_nodes
     elem = 4 if args.precision == "f32" else 2
-    bytes_node = 2 * (19 * 4 + 28) if compact else 2 * 2 * 19 * elem
+    bytes_node = 2 * (19 * 4 + 20) if compact else 2 * 2 * 19 * elem
     mlups = N * args.steps / (ms / 1e3) / 1e6
     achieved = bytes_node * N / (ms_step / 1e3) / 1e9
     traffic = read_traffic(kname) if args.precision == "f32" and args.size == 256 else None

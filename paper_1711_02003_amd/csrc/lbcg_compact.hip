@@ -6,19 +6,19 @@
 // densities, density and colour gradient) and on the speed class of c_i:
 //   minority colour part of f_i = M f_i + (c_i . V_c) / 36,
 // with M the node's minority share and V_c one 3-vector per speed class
-// (axis, diagonal).  So a node need not store the two colours of every
-// population: it stores its 19 new total deviations and 7 colour scalars (M
-// with the majority flag in its lowest bit, V_axis, V_diag), and the
-// receiver splits each pulled population with the scalars of the node it
-// came from.  In exact arithmetic the step is the same as the pair-state
-// step; it moves 2 x (19 x 4 + 28) = 208 bytes per node instead of
-// 2 x 38 x 4 = 304.
+// (axis, diagonal).  Both vectors are the unit colour gradient scaled by a
+// class amplitude, so V_diag = R_d V_axis with the node scalar
+// R_d = k_diag / k_axis.  So a node need not store the two colours of every
+// population: it stores its 19 new total deviations and 5 colour scalars (M
+// with the majority flag in its lowest bit, V_axis, R_d), and the receiver
+// splits each pulled population with the scalars of the node it came from.
+// In exact arithmetic the step is the same as the pair-state step; it moves
+// 2 x (19 x 4 + 20) = 192 bytes per node instead of 2 x 38 x 4 = 304.
 //
 // Layout: 19 arrays of `pitch` floats (array i at i * pitch + node: total
 // deviation f_i - w_i), then `pitch` 16-byte records {M, V_axis x, y, z}
-// (record n at float 19 * pitch + 4 n) and `pitch` 12-byte records
-// {V_diag x, y, z} (at float 23 * pitch + 3 n), so that each wide load or
-// store of a wave covers one contiguous span.
+// (record n at float 19 * pitch + 4 n) and an array of `pitch` floats R_d
+// (at float 23 * pitch + n).
 //
 // The sweep is the pair-state sweep's: a block owns a 64 x 8 column tile and
 // sweeps a chunk of z planes; plane z+1 is pulled (interior and a one-node
@@ -28,7 +28,7 @@
 // memory per direction that would be ~68 loads per node, more than a wave
 // can keep in flight (its memory counter holds 63), so the records are
 // staged instead: each plane's records over the tile plus a two-node halo
-// (the ring's own senders) are loaded once, with a 16-byte and a 12-byte
+// (the ring's own senders) are loaded once, with a 16-byte and a 4-byte
 // load per node, into a 4-slot LDS ring, three planes ahead of their first
 // use, and the receivers read them from there.  The threads of the three
 // waves that hold the ring nodes load no records, so every wave keeps fewer
@@ -52,11 +52,11 @@ constexpr int kCTX = 64;
 constexpr int kCR = 8;                      // tile rows
 constexpr int kCXCD = 8;
 // Scalar records: {M, V_axis} (16 B) in one array after the 19 total
-// arrays, V_diag (12 B) in a second one; byte offsets from the first total
-// array: 19 x 4 x pitch + 16 n and 23 x 4 x pitch + 12 n.
-constexpr uint32_t kRecA = 16, kRecB = 12;
+// arrays, R_d (4 B) in a second one; byte offsets from the first total
+// array: 19 x 4 x pitch + 16 n and 23 x 4 x pitch + 4 n.
+constexpr uint32_t kRecA = 16, kRecB = 4;
 constexpr int kRecBytes = int(kRecA + kRecB);
-constexpr int kNS = 7;                      // scalars kept in LDS: M, V_axis, V_diag
+constexpr int kNS = 5;                      // scalars kept in LDS: M, V_axis, R_d
 constexpr int kSW = kCTX + 4, kSH = kCR + 4, kSN = kSW * kSH;  // record tile with a 2-node halo
 constexpr int kSSlots = 4;
 constexpr int kPW = kCTX + 2, kPH = kCR + 2, kPN = kPW * kPH;  // psi tile with a 1-node halo
@@ -112,10 +112,6 @@ __device__ __forceinline__ float load_f(__amdgpu_buffer_rsrc_t r, uint32_t voff,
 __device__ __forceinline__ f4 load_f4(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
     return __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(r, int(voff), su(soff), 0));
 }
-typedef float f3 __attribute__((ext_vector_type(3)));
-__device__ __forceinline__ f3 load_f3(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
-    return __builtin_bit_cast(f3, __builtin_amdgcn_raw_buffer_load_b96(r, int(voff), su(soff), 0));
-}
 // Records are written with stores of at most 8 bytes per lane.  A wider
 // store (12 or 16 bytes) may read its data registers after later
 // instructions have been issued, and the compiler reuses those registers at
@@ -148,13 +144,11 @@ __device__ __forceinline__ void store_compact(const CompactArgs &a, __amdgpu_buf
 #pragma unroll
     for (int i = 0; i < D3Q19::Q; ++i) store_pair<float>(rout, own, uint32_t(su(uint32_t(i) * cs + zoff)), o.df[i]);
     // records: own and zoff count 4 bytes per node
-    const uint32_t ra = uint32_t(D3Q19::Q) * cs + zoff * 4u, rb = uint32_t(D3Q19::Q + 4) * cs + zoff * 3u;
+    const uint32_t ra = uint32_t(D3Q19::Q) * cs + zoff * 4u, rb = uint32_t(D3Q19::Q + 4) * cs + zoff;
     const f2 a01 = {Codec<float>::enc_col<float>(o.M, o.redmaj), o.Va[0]}, a23 = {o.Va[1], o.Va[2]};
-    const f2 b01 = {o.Vd[0], o.Vd[1]};
     store_f2(rout, own * 4u, ra, a01);
     store_f2(rout, own * 4u, ra + 8u, a23);
-    store_f2(rout, own * 3u, rb, b01);
-    store_f1(rout, own * 3u, rb + 8u, o.Vd[2]);
+    store_f1(rout, own, rb, o.Rd);
 }
 
 // Split of the 19 pulled totals d of a node with its senders' scalars, read
@@ -182,9 +176,9 @@ __device__ __forceinline__ void split_pulled(const float d[D3Q19::Q], const floa
             p.vd[i] = cv[ax] > 0 ? v : -v;
         } else {
             const int a0 = cv[0] ? 0 : 1, a1 = cv[2] ? 2 : 1;
-            const float v0 = s[(4 + a0) * kSN + k], v1 = s[(4 + a1) * kSN + k];
+            const float v0 = s[(1 + a0) * kSN + k], v1 = s[(1 + a1) * kSN + k];
             const float s0 = cv[a0] > 0 ? v0 : -v0;
-            p.vd[i] = cv[a1] > 0 ? s0 + v1 : s0 - v1;
+            p.vd[i] = s[4 * kSN + k] * (cv[a1] > 0 ? s0 + v1 : s0 - v1);
         }
     }
 }
@@ -250,7 +244,7 @@ __device__ __forceinline__ void sweep_compact(const CompactArgs &a, const Model<
         lcol[k] = uint32_t(wrap_any(x0 + sx, a.nx)) + uint32_t(a.nx) * uint32_t(wrap_any(y0 + sy, a.ny));
     }
     f4 lq0[kPerLoader];
-    f3 lq1[kPerLoader];
+    float lq1[kPerLoader];
 
     float *psi_lds = lds;
     float *rec_lds = lds + kPSlots * kPN;
@@ -264,7 +258,7 @@ __device__ __forceinline__ void sweep_compact(const CompactArgs &a, const Model<
         for (int k = 0; k < kPerLoader; ++k)
             if (lon[k]) {
                 lq0[k] = load_f4(rin, lcol[k] * kRecA, ra);
-                lq1[k] = load_f3(rin, lcol[k] * kRecB, rb);
+                lq1[k] = load_f(rin, lcol[k] * kRecB, rb);
             }
     };
     auto rec_write = [&](int q) {
@@ -276,9 +270,7 @@ __device__ __forceinline__ void sweep_compact(const CompactArgs &a, const Model<
                 s[1 * kSN + lidx[k]] = lq0[k][1];
                 s[2 * kSN + lidx[k]] = lq0[k][2];
                 s[3 * kSN + lidx[k]] = lq0[k][3];
-                s[4 * kSN + lidx[k]] = lq1[k][0];
-                s[5 * kSN + lidx[k]] = lq1[k][1];
-                s[6 * kSN + lidx[k]] = lq1[k][2];
+                s[4 * kSN + lidx[k]] = lq1[k];
             }
     };
 
@@ -623,16 +615,17 @@ __global__ void k_expand(const float *__restrict__ cin, typename PairOf<float>::
     using L = D3Q19;
     const int64_t n = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (n >= N) return;
-    const float *ra = cin + int64_t(L::Q) * pitch + 4 * n, *rb = cin + int64_t(L::Q + 4) * pitch + 3 * n;
+    const float *ra = cin + int64_t(L::Q) * pitch + 4 * n, *rb = cin + int64_t(L::Q + 4) * pitch + n;
     bool fl;
     const float M = Codec<float>::col<float>(ra[0], fl);
-    const float Va[3] = {ra[1], ra[2], ra[3]}, Vd[3] = {rb[0], rb[1], rb[2]};
+    const float Va[3] = {ra[1], ra[2], ra[3]}, Rd = rb[0];
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) {
         const float d = cin[int64_t(i) * pitch + n];
         const int n2 = csq<L>(i);
-        const float *V = n2 == 1 ? Va : Vd;
-        const float vd = n2 == 0 ? 0.0f : float(L::cx[i]) * V[0] + float(L::cy[i]) * V[1] + float(L::cz[i]) * V[2];
+        // the receiver's expression: c_i . V_axis, times R_d for a diagonal
+        const float cva = float(L::cx[i]) * Va[0] + float(L::cy[i]) * Va[1] + float(L::cz[i]) * Va[2];
+        const float vd = n2 == 0 ? 0.0f : (n2 == 1 ? cva : Rd * cva);
         const float f = float(wgt<L>(i)) + d;
         const float mu36 = M * (float(w36<L>(i)) + 36.0f * d) + vd;
         const float q = f != 0.0f ? mu36 / (36.0f * f) : 0.0f;

@@ -717,6 +717,7 @@ struct CompactOut {
     T M;
     bool redmaj;
     T Va[3], Vd[3];
+    T Rd;  // k_diag / k_axis: V_diag = Rd V_axis
 };
 
 // First axis and first diagonal direction of a lattice.
@@ -882,6 +883,7 @@ __device__ __forceinline__ void collide(const Model<T> &mo, T drho, T r36R, T r3
         o.Vd[0] = gd * Fx;
         o.Vd[1] = gd * Fy;
         o.Vd[2] = gd * Fz;
+        o.Rd = kd / ka;  // ka > 0: rho^k phi_c^k > 0 for alpha_k < 1
     } else {
         T m;
         bool fl;

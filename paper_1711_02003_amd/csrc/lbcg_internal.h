@@ -101,11 +101,11 @@ hipError_t launch_step_fused2d(int prec, const Geo &g, const ModelD &md, const v
 bool fused2d_supported(int prec, const Geo &g);
 
 // Fused D3Q19 step on the compact state (periodic, FP32, regularized, tiles
-// of 8 rows): 19 arrays of pitch floats (total deviations) and 7 colour
+// of 8 rows): 19 arrays of pitch floats (total deviations) and 5 colour
 // scalars per node in two record arrays, kCompactBytes per pitch node.  pair_in: `in` is
 // a pair state (the first step after an initialisation or a restore); `out`
 // is always compact.
-constexpr int kCompactBytes = 19 * 4 + 28;
+constexpr int kCompactBytes = 19 * 4 + 20;  // D3Q19: 19 totals, 5 scalars
 constexpr int kCompactBytes2d = 9 * 4 + 20;  // D2Q9: 9 totals, 5 scalars
 hipError_t launch_step_compact(const Geo &g, const ModelD &md, const void *in, bool pair_in, void *out,
                                const uint32_t *ctr_in, uint32_t *ctr_out, FusedShape shape, hipStream_t s);

@@ -32,11 +32,11 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 COPY_BYTES = 2 << 30  # the copy probe moves 2 GiB in and 2 GiB out per dispatch
 # Per headline kernel: the sources its code comes from and its algorithmic
 # bytes per node and step (FP32).  Pair state: every population pair read
-# once and written once, 2 x 38 x 4.  Compact state: 19 totals and 7
-# colour scalars read once and written once, 2 x (19 x 4 + 28).
+# once and written once, 2 x 38 x 4.  Compact state: 19 totals and 5
+# colour scalars read once and written once, 2 x (19 x 4 + 20).
 KERNELS = {
     "k_step_compact": (["paper_1711_02003_amd/csrc/lbcg_compact.hip", "paper_1711_02003_amd/csrc/lbcg_device.h"],
-                       2 * (19 * 4 + 28)),
+                       2 * (19 * 4 + 20)),
     "k_step_fused": (["paper_1711_02003_amd/csrc/lbcg_fused.hip", "paper_1711_02003_amd/csrc/lbcg_device.h"],
                      2 * 38 * 4),
 }

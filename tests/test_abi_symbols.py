@@ -72,7 +72,7 @@ def test_strerror_and_validation_without_device(lib):
 
 def test_compact_footprint_adds_two_compact_buffers(lib):
     # LBCG_KERNEL_COMPACT keeps two compact states (19 x 4 B of totals and
-    # 28 B of colour scalars per pitch node) beside the two pair buffers
+    # 20 B of colour scalars per pitch node) beside the two pair buffers
     from paper_1711_02003_amd import lbcg
     lbcg._lib = None
     dims = (70, 37, 20)
@@ -80,7 +80,7 @@ def test_compact_footprint_adds_two_compact_buffers(lib):
     f, keep = lbcg.make_params("D3Q19", dims, 1.0, 0.6, 0.005, 0.005, 0.7, kernel=lbcg.KERNEL_FUSED)
     c, keep2 = lbcg.make_params("D3Q19", dims, 1.0, 0.6, 0.005, 0.005, 0.7, kernel=lbcg.KERNEL_COMPACT)
     extra = lbcg.footprint(c) - lbcg.footprint(f)
-    one = -(-(19 * 4 + 28) * pitch // 256) * 256
+    one = -(-(19 * 4 + 20) * pitch // 256) * 256
     assert one * 2 - 512 <= extra <= one * 2 + 512, (extra, one)
     # 8-row tiles only
     t, keep3 = lbcg.make_params("D3Q19", dims, 1.0, 0.6, 0.005, 0.005, 0.7, kernel=lbcg.KERNEL_COMPACT,
