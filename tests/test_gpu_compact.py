@@ -203,6 +203,24 @@ def test_compact_full_size_config2_sampled(L, orc):
     s.close()
 
 
+def test_compact_largest_lattice_and_beyond(L, orc):
+    # The first compact step reads the pair state with 32-bit byte offsets:
+    # 304^3 (4.27 GB per pair buffer) is the largest cube the compact kernel
+    # takes; 306^3 is refused (the automatic choice would use the generic
+    # kernel there).
+    w = W.config2(L=304, seed=2)
+    _say("304^3 compact f32")
+    s = L.Sim.from_workload(w, precision="f32", kernel=L.KERNEL_COMPACT)
+    assert s.launch_info()["kernel"] == L.KERNEL_COMPACT
+    s.step(3)
+    worst = _sampled_one_step(L, orc, w, s, n_samples=32, seed=304)
+    _say(f"  sampled one-step max rel diff {worst:.2e}")
+    assert worst < 2e-6
+    s.close()
+    with pytest.raises(L.LbcgError):
+        L.Sim("D3Q19", (306, 306, 306), 1.0, 0.6, 0.005, 0.7, "f32", kernel=L.KERNEL_COMPACT)
+
+
 def test_compact_rejects_what_it_does_not_cover(L):
     w = _droplets((16, 8, 8), seed=1)
     for kw in ({"precision": "f16"}, {"precision": "f64"}, {"collision": L.BGK}):
