@@ -203,6 +203,24 @@ def test_compact_full_size_config2_sampled(L, orc):
     s.close()
 
 
+@pytest.mark.parametrize("dims", [(1, 1, 1), (2, 1, 3), (1, 4, 1), (3, 3, 2)])
+def test_compact_degenerate_lattices(L, dims):
+    # one node, one-wide dimensions: every neighbour wraps onto the node or
+    # its few neighbours; the compact sweep agrees with the pair-state sweep
+    rng = np.random.default_rng(sum(dims))
+    nx, ny, nz = dims
+    sh = (nz, ny, nx)
+    w = W.Workload("tiny", "D3Q19", dims, rng.uniform(0.2, 1, sh), rng.uniform(0.2, 1, sh),
+                   rng.uniform(-0.02, 0.02, (3,) + sh), 1.2, 0.7, 0.01, 0.7)
+    a = L.Sim.from_workload(w, precision="f32", kernel=L.KERNEL_COMPACT)
+    b = L.Sim.from_workload(w, precision="f32", kernel=L.KERNEL_FUSED)
+    a.step(30)
+    b.step(30)
+    d = _maxrel(a.populations(), b.populations())
+    _say(f"compact vs fused {dims} x30: {d:.2e}")
+    assert d < 30 * 4 * EPS32
+
+
 def test_compact_largest_lattice_and_beyond(L, orc):
     # The first compact step reads the pair state with 32-bit byte offsets:
     # 304^3 (4.27 GB per pair buffer) is the largest cube the compact kernel
@@ -251,7 +269,7 @@ def _random_2d(dims, seed):
                       1.3, 0.7, 0.01, 0.7)
 
 
-@pytest.mark.parametrize("dims", [(64, 64, 1), (100, 37, 1), (130, 9, 1), (5, 3, 1)])
+@pytest.mark.parametrize("dims", [(64, 64, 1), (100, 37, 1), (130, 9, 1), (5, 3, 1), (1, 1, 1), (1, 6, 1), (7, 1, 1)])
 def test_compact2d_agrees_with_pair_fused(L, dims):
     # several strips, a ragged strip, a lattice narrower than the record halo
     w = _random_2d(dims, seed=sum(dims) + 1)
