@@ -146,14 +146,14 @@ def f16_form(torch, lbcg, W, size, steps=200, warmup=10):
 
 def d2q9_form(torch, lbcg, W, steps=200, warmup=10):
     """D2Q9 4096^2 with 256 droplets, FP32 storage: the fused strip sweep on
-    the compact state (tuned; 112 B per node: every total and the senders'
-    5 colour scalars read and written once), on the pair state (tuned; 144 B
+    the compact state (tuned; 104 B per node: every total and the senders'
+    4 colour scalars read and written once), on the pair state (tuned; 144 B
     per node: one read and one write of every population pair) and, for
     comparison, the two-pass generic kernel (a psi pass, then the step)
     against the same 144 B."""
     w = W.droplets_2d(n=4096, seed=6)
     out = {"workload": w.name, "storage": "f32", "bytes_per_node": 144, "steps": steps}
-    for name, kernel, bpn in (("compact", lbcg.KERNEL_COMPACT, 112), ("fused", lbcg.KERNEL_FUSED, 144),
+    for name, kernel, bpn in (("compact", lbcg.KERNEL_COMPACT, 104), ("fused", lbcg.KERNEL_FUSED, 144),
                               ("generic", lbcg.KERNEL_GENERIC, 144)):
         stream = torch.cuda.Stream()
         sim = lbcg.Sim.from_workload(w, precision="f32", kernel=kernel, stream=stream.cuda_stream)

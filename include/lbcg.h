@@ -72,7 +72,7 @@ extern "C" {
  * that node and on the speed class of the direction, so each node stores its
  * Q total populations and its colour scalars (its minority share and one
  * vector per speed class) and the receiver of a population splits it: 192
- * bytes of memory traffic per node and step instead of 304 (D3Q19), 112
+ * bytes of memory traffic per node and step instead of 304 (D3Q19), 104
  * instead of 144 (D2Q9).  Results
  * agree with the pair-state kernels up to rounding.  The first step
  * after lbcg_init_fields or lbcg_set_state reads the pair state; the calls
@@ -80,7 +80,7 @@ extern "C" {
  * first convert the compact state to a pair state in the handle's pair
  * buffer, which the compact steps leave unused (one extra kernel, no change
  * to the trajectory).  lbcg_footprint
- * adds the two compact buffers (2 x 96 x pitch bytes for D3Q19, 2 x 56 x
+ * adds the two compact buffers (2 x 96 x pitch bytes for D3Q19, 2 x 52 x
  * pitch for D2Q9). */
 #define LBCG_KERNEL_AUTO 0
 #define LBCG_KERNEL_GENERIC 1

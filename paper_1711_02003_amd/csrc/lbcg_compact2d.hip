@@ -2,19 +2,18 @@
 // Sec. II, Eqs. (1)-(11)), periodic lattices, FP32.
 //
 // The 2-D counterpart of the compact D3Q19 sweep: a node stores its 9 new
-// total deviations and 5 colour scalars (minority share M with the majority
-// flag in its lowest bit, V_axis (x, y), V_diag (x, y)), from which the
-// receiver of a population splits it into colours (Eq. (10): the minority
-// colour part of f_i is M f_i + (c_i . V_c) / 36 with the sender's M and the
-// V of the speed class of c_i).  2 x (9 x 4 + 20) = 112 bytes per node and
-// step instead of 2 x 18 x 4 = 144.
+// total deviations and 4 colour scalars (minority share M with the majority
+// flag in its lowest bit, V_axis (x, y) and R_d, with V_diag = R_d V_axis),
+// from which the receiver of a population splits it into colours (Eq. (10):
+// the minority colour part of f_i is M f_i + (c_i . V_c) / 36 with the
+// sender's M and the V of the speed class of c_i).  2 x (9 x 4 + 16) = 104
+// bytes per node and step instead of 2 x 18 x 4 = 144.
 //
 // Layout: 9 arrays of `pitch` floats (total deviation f_i - w_i of direction
-// i at i * pitch + node), then `pitch` 12-byte records {M, V_axis x, y} (at
-// float 9 * pitch + 3 n) and `pitch` 8-byte records {V_diag x, y} (at float
-// 12 * pitch + 2 n).  The records are read with 12- and 8-byte loads and
-// written with stores of at most 8 bytes per lane (a wider store may read
-// its data registers after the compiler has already reused them).
+// i at i * pitch + node), then `pitch` 16-byte records {M, V_axis x, y, R_d}
+// (at float 9 * pitch + 4 n).  The records are read with 16-byte loads and
+// written with two 8-byte stores per lane (a wider store may read its data
+// registers after the compiler has already reused them).
 //
 // The sweep is the pair-state strip sweep's: each wave owns 64 columns and
 // sweeps a chunk of rows, pulling row y+1 (and, on two lanes, the nodes left
@@ -37,11 +36,10 @@ constexpr int kS2 = 64;             // columns of a strip (one wave)
 constexpr int kW2 = 4;              // strips (work items) per block
 constexpr int kP2 = kS2 + 2;        // psi row: the strip and one node each side
 constexpr int kR2 = kS2 + 4;        // record row: the strip and two nodes each side
-constexpr int kNS2 = 5;             // scalars per record
-constexpr int kRecA2 = 12, kRecB2 = 8;
+constexpr int kNS2 = 4;             // scalars per record: M, V_axis x, y, R_d
+constexpr int kRec2 = 16;           // bytes per record
 constexpr int kLds2 = 3 * kP2 + 3 * kNS2 * kR2;  // floats per wave
 
-typedef float f3 __attribute__((ext_vector_type(3)));
 typedef float f2 __attribute__((ext_vector_type(2)));
 typedef unsigned int u2 __attribute__((ext_vector_type(2)));
 
@@ -75,8 +73,9 @@ __device__ __forceinline__ int su2(uint32_t v) { return __builtin_amdgcn_readfir
 __device__ __forceinline__ float ld1(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, int(voff), su2(soff), 0));
 }
-__device__ __forceinline__ f3 ld3(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
-    return __builtin_bit_cast(f3, __builtin_amdgcn_raw_buffer_load_b96(r, int(voff), su2(soff), 0));
+typedef float f4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ f4 ld4(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    return __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(r, int(voff), su2(soff), 0));
 }
 __device__ __forceinline__ f2 ld2(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
     return __builtin_bit_cast(f2, __builtin_amdgcn_raw_buffer_load_b64(r, int(voff), su2(soff), 0));
@@ -105,9 +104,9 @@ __device__ __forceinline__ void split2(const float d[D2Q9::Q], const float *cons
             const float v = cx ? s[1 * kR2 + k] : s[2 * kR2 + k];
             p.vd[i] = (cx + cy) > 0 ? v : -v;
         } else {
-            const float vx = s[3 * kR2 + k], vy = s[4 * kR2 + k];
+            const float vx = s[1 * kR2 + k], vy = s[2 * kR2 + k];
             const float sx = cx > 0 ? vx : -vx;
-            p.vd[i] = cy > 0 ? sx + vy : sx - vy;
+            p.vd[i] = s[3 * kR2 + k] * (cy > 0 ? sx + vy : sx - vy);
         }
     }
 }
@@ -141,8 +140,8 @@ __device__ __forceinline__ void sweep_c2d(const Compact2dArgs &a, const Model<fl
     const uint32_t cs = uint32_t(uniform(int(uint32_t(a.pitch) * EI)));
     const uint32_t row = uint32_t(uniform(int(uint32_t(a.nx) * EI)));
     const uint32_t in_bytes = PAIR_IN ? uint32_t(2 * L::Q) * uint32_t(a.pitch) * 4u
-                                      : uint32_t(L::Q) * uint32_t(a.pitch) * 4u + uint32_t(a.pitch) * (kRecA2 + kRecB2);
-    const uint32_t out_bytes = uint32_t(L::Q) * uint32_t(a.pitch) * 4u + uint32_t(a.pitch) * (kRecA2 + kRecB2);
+                                      : uint32_t(L::Q) * uint32_t(a.pitch) * 4u + uint32_t(a.pitch) * kRec2;
+    const uint32_t out_bytes = uint32_t(L::Q) * uint32_t(a.pitch) * 4u + uint32_t(a.pitch) * kRec2;
     const __amdgpu_buffer_rsrc_t rin = state_rsrc(a.in, in_bytes);
     const __amdgpu_buffer_rsrc_t rout = state_rsrc(a.out, out_bytes);
     const uint32_t cso = uint32_t(uniform(int(uint32_t(a.pitch) * 4u)));
@@ -160,19 +159,16 @@ __device__ __forceinline__ void sweep_c2d(const Compact2dArgs &a, const Model<fl
     const int rn = tw + 4;
     const bool lon0 = lane < rn, lon1 = lane + kS2 < rn;
     const uint32_t lc0 = uint32_t(wrap2(x0 - 2 + lane, a.nx)), lc1 = uint32_t(wrap2(x0 - 2 + lane + kS2, a.nx));
-    f3 ra0, ra1;
-    f2 rb0, rb1;
+    f4 ra0, ra1;
     auto rec_issue = [&](int yy) {
         if (PAIR_IN) return;
         const uint32_t n0 = uint32_t(uniform(wrapy(yy))) * uint32_t(a.nx);
-        const uint32_t sa = uint32_t(L::Q) * cso + n0 * kRecA2, sb = uint32_t(L::Q) * cso + uint32_t(a.pitch) * kRecA2 + n0 * kRecB2;
+        const uint32_t sa = uint32_t(L::Q) * cso + n0 * kRec2;
         if (lon0) {
-            ra0 = ld3(rin, lc0 * kRecA2, sa);
-            rb0 = ld2(rin, lc0 * kRecB2, sb);
+            ra0 = ld4(rin, lc0 * kRec2, sa);
         }
         if (lon1) {
-            ra1 = ld3(rin, lc1 * kRecA2, sa);
-            rb1 = ld2(rin, lc1 * kRecB2, sb);
+            ra1 = ld4(rin, lc1 * kRec2, sa);
         }
     };
     auto rec_write = [&](int yy) {
@@ -182,15 +178,13 @@ __device__ __forceinline__ void sweep_c2d(const Compact2dArgs &a, const Model<fl
             s[0 * kR2 + lane] = ra0[0];
             s[1 * kR2 + lane] = ra0[1];
             s[2 * kR2 + lane] = ra0[2];
-            s[3 * kR2 + lane] = rb0[0];
-            s[4 * kR2 + lane] = rb0[1];
+            s[3 * kR2 + lane] = ra0[3];
         }
         if (lon1) {
             s[0 * kR2 + lane + kS2] = ra1[0];
             s[1 * kR2 + lane + kS2] = ra1[1];
             s[2 * kR2 + lane + kS2] = ra1[2];
-            s[3 * kR2 + lane + kS2] = rb1[0];
-            s[4 * kR2 + lane + kS2] = rb1[1];
+            s[3 * kR2 + lane + kS2] = ra1[3];
         }
     };
 
@@ -321,14 +315,11 @@ __device__ __forceinline__ void sweep_c2d(const Compact2dArgs &a, const Model<fl
             for (int i = 0; i < L::Q; ++i) store_pair<float>(rout, own * 4u, uint32_t(su2(uint32_t(i) * cso + yo)), o.df[i]);
             const uint32_t n = uint32_t(uniform(y)) * uint32_t(a.nx) + own;
             const f2 qa = {Codec<float>::enc_col<float>(o.M, o.redmaj), o.Va[0]};
-            const f2 qb = {o.Vd[0], o.Vd[1]};
-            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, qa), rout, int(n * kRecA2),
+            const f2 qb = {o.Va[1], o.Rd};
+            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, qa), rout, int(n * kRec2),
                                                   su2(uint32_t(L::Q) * cso), kNonTemporal);
-            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, o.Va[1]), rout,
-                                                  int(n * kRecA2), su2(uint32_t(L::Q) * cso + 8u), kNonTemporal);
-            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, qb), rout, int(n * kRecB2),
-                                                  su2(uint32_t(L::Q) * cso + uint32_t(a.pitch) * kRecA2),
-                                                  kNonTemporal);
+            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, qb), rout, int(n * kRec2),
+                                                  su2(uint32_t(L::Q) * cso + 8u), kNonTemporal);
         }
         wave_sync();
         cd = nd;
@@ -359,16 +350,17 @@ __global__ void k_expand2d(const float *__restrict__ cin, typename PairOf<float>
     using L = D2Q9;
     const int64_t n = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (n >= N) return;
-    const float *ra = cin + int64_t(L::Q) * pitch + 3 * n, *rb = cin + int64_t(L::Q + 3) * pitch + 2 * n;
+    const float *ra = cin + int64_t(L::Q) * pitch + 4 * n;
     bool fl;
     const float M = Codec<float>::col<float>(ra[0], fl);
-    const float Va[2] = {ra[1], ra[2]}, Vd[2] = {rb[0], rb[1]};
+    const float Va[2] = {ra[1], ra[2]}, Rd = ra[3];
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) {
         const float d = cin[int64_t(i) * pitch + n];
         const int n2 = csq<L>(i);
-        const float *V = n2 == 1 ? Va : Vd;
-        const float vd = n2 == 0 ? 0.0f : float(L::cx[i]) * V[0] + float(L::cy[i]) * V[1];
+        // the receiver's expression: c_i . V_axis, times R_d for a diagonal
+        const float cva = float(L::cx[i]) * Va[0] + float(L::cy[i]) * Va[1];
+        const float vd = n2 == 0 ? 0.0f : (n2 == 1 ? cva : Rd * cva);
         const float f = float(wgt<L>(i)) + d;
         const float mu36 = M * (float(w36<L>(i)) + 36.0f * d) + vd;
         const float q = f != 0.0f ? mu36 / (36.0f * f) : 0.0f;

@@ -106,7 +106,7 @@ bool fused2d_supported(int prec, const Geo &g);
 // a pair state (the first step after an initialisation or a restore); `out`
 // is always compact.
 constexpr int kCompactBytes = 19 * 4 + 20;  // D3Q19: 19 totals, 5 scalars
-constexpr int kCompactBytes2d = 9 * 4 + 20;  // D2Q9: 9 totals, 5 scalars
+constexpr int kCompactBytes2d = 9 * 4 + 16;  // D2Q9: 9 totals, 4 scalars
 hipError_t launch_step_compact(const Geo &g, const ModelD &md, const void *in, bool pair_in, void *out,
                                const uint32_t *ctr_in, uint32_t *ctr_out, FusedShape shape, hipStream_t s);
 bool compact_supported(int lattice, int prec, const Geo &g);
@@ -114,8 +114,8 @@ int compact_resident_blocks(int rows);
 // Pair state (post-collision, as the pair kernels store it) of a compact state.
 hipError_t launch_expand(const Geo &g, const void *cin, void *pout, hipStream_t s);
 // The D2Q9 strip sweep on the compact state (periodic, FP32, regularized):
-// 9 arrays of pitch floats and 5 colour scalars per node in two record
-// arrays, kCompactBytes2d per pitch node; rows split into ychunks.
+// 9 arrays of pitch floats and 4 colour scalars per node in one record
+// array, kCompactBytes2d per pitch node; rows split into ychunks.
 hipError_t launch_step_compact2d(const Geo &g, const ModelD &md, const void *in, bool pair_in, void *out,
                                  const uint32_t *ctr_in, uint32_t *ctr_out, int ychunks, hipStream_t s);
 hipError_t launch_expand2d(const Geo &g, const void *cin, void *pout, hipStream_t s);
