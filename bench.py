@@ -20,11 +20,13 @@ of every node (both colours).  Prints one JSON line:
   forms      the other forms of the step, each measured on its own workload:
              pair_f32 (the same lattice on the pair-state sweep: per
              population its total and minority share), f16 (the same lattice
-             with FP16 pair storage), batched_compact (the batched boxes on
-             the compact state), focusing (the
-             512 x 128 x 64 flow-focusing junction, FP32 and FP16), batched (64
-             uneven periodic boxes in one launch per time level vs the same
-             boxes stepped one after another) and served (a Poisson stream of
+             with FP16 pair storage), d2q9 (a 4096^2 D2Q9 box: compact and
+             pair-state strip sweeps and the two-pass generic kernel),
+             focusing2d (the 8192 x 2048 D2Q9 junction), focusing (the
+             512 x 128 x 64 D3Q19 flow-focusing junction, FP32 and FP16),
+             batched and batched_compact (64 uneven periodic boxes in one
+             launch per time level, pair and compact state, vs the same boxes
+             stepped one after another) and served (a Poisson stream of
              step-emulsifier requests through the continuous-batching server
              vs one request at a time; p50 / p99 time to result).
 """
