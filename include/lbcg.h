@@ -220,10 +220,12 @@ const char *lbcg_strerror(int status);
  * LBCG_KERNEL_FUSED or LBCG_KERNEL_COMPACT), rows per block, z chunks. */
 int lbcg_launch_info(lbcg_sim *s, int32_t *kernel, int32_t *rows, int32_t *zchunks);
 
-/* Choose the fused (or compact) kernel's launch shape for this handle by timing candidate
- * shapes (rows 4 or 8; z splits that fill the device once, twice or four
- * times; chunks of 8 to 64 planes) on the handle's own lattice, stepping the
- * current state into the spare buffer so the state does not change.  Keeps
+/* Choose the fused (or compact) kernel's launch shape for this handle by
+ * timing candidate shapes on the handle's own lattice (D3Q19: rows 4 or 8,
+ * 8 only for the compact kernel, z splits that fill the device once, twice
+ * or four times and chunks of 2 to 64 planes; D2Q9: row chunks of 8 to 512
+ * rows), stepping the current state into the spare buffer so the state does
+ * not change.  Keeps
  * the fastest shape for later steps and reports it.  No effect on the
  * generic kernel.  Synchronizes. */
 int lbcg_tune(lbcg_sim *s, int32_t *rows, int32_t *zchunks);
