@@ -1,0 +1,51 @@
+// The compact-state D3Q19 sweep over many lattices in one launch (batched
+// form).  Built apart from the single-lattice kernels so that each object
+// gets the code-generation options measured best for it.
+#include "lbcg_compact_sweep.h"
+
+namespace lbcg {
+
+namespace {
+
+// Many lattices in one launch (batched form): entry k of the block table is
+// work item bitem[k] of lattice blat[k]; entries are dealt to the 8 XCDs in
+// contiguous bands (blocks go to XCDs round-robin), as the single-lattice
+// kernel deals its work items.  Every lattice is compact and periodic with
+// 8-row tiles.
+__global__ void __launch_bounds__(kCTX * kCR)
+    k_step_compact_batch(const BatchDesc<float> *__restrict__ desc, const int *__restrict__ blat,
+                         const int *__restrict__ bitem) {
+    extern __shared__ float lds[];
+    const int total = int(gridDim.x);
+    const int xcd = blockIdx.x % kCXCD, l = blockIdx.x / kCXCD;
+    const int k = xcd * (total / kCXCD) + min(xcd, total % kCXCD) + l;
+    const int item = bitem[k];
+    const BatchDesc<float> d = desc[blat[k]];
+    CompactArgs a;
+    a.in = d.a.in;
+    a.out = d.a.out;
+    a.nx = d.a.nx;
+    a.ny = d.a.ny;
+    a.nz = d.a.nz;
+    a.pitch = d.a.pitch;
+    a.ctr_in = d.a.ctr_in;
+    a.ctr_out = d.a.ctr_out;
+    a.ntx = d.a.ntx;
+    a.nty = d.a.nty;
+    a.zchunks = d.a.zchunks;
+    if (item == 0 && threadIdx.x == 0) *a.ctr_out = *a.ctr_in + 1u;
+    sweep_compact(a, d.mo, item / a.zchunks, item % a.zchunks, lds);
+}
+
+}  // namespace
+
+hipError_t launch_step_compact_batch(const void *desc, const int *blat, const int *bitem, int nblocks,
+                                     hipStream_t s) {
+    if (nblocks <= 0) return hipSuccess;
+    allow_lds(reinterpret_cast<const void *>(&k_step_compact_batch), 1);
+    hipLaunchKernelGGL(k_step_compact_batch, dim3(unsigned(nblocks)), dim3(unsigned(kCTX * kCR)), kCompactLds, s,
+                       static_cast<const BatchDesc<float> *>(desc), blat, bitem);
+    return hipGetLastError();
+}
+
+}  // namespace lbcg

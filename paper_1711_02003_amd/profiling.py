@@ -35,7 +35,8 @@ COPY_BYTES = 2 << 30  # the copy probe moves 2 GiB in and 2 GiB out per dispatch
 # once and written once, 2 x 38 x 4.  Compact state: 19 totals and 5
 # colour scalars read once and written once, 2 x (19 x 4 + 20).
 KERNELS = {
-    "k_step_compact": (["paper_1711_02003_amd/csrc/lbcg_compact.hip", "paper_1711_02003_amd/csrc/lbcg_device.h"],
+    "k_step_compact": (["paper_1711_02003_amd/csrc/lbcg_compact.hip", "paper_1711_02003_amd/csrc/lbcg_compact_sweep.h",
+                        "paper_1711_02003_amd/csrc/lbcg_device.h"],
                        2 * (19 * 4 + 20)),
     "k_step_fused": (["paper_1711_02003_amd/csrc/lbcg_fused.hip", "paper_1711_02003_amd/csrc/lbcg_device.h"],
                      2 * 38 * 4),
@@ -43,10 +44,15 @@ KERNELS = {
 
 
 def kernel_hash(kernel: str) -> str:
+    """Hash of the kernel's sources and of the options its object is built with."""
+    from paper_1711_02003_amd import build
+
     h = hashlib.sha256()
     for p in KERNELS[kernel][0]:
         with open(os.path.join(ROOT, p), "rb") as f:
             h.update(f.read())
+        if p.endswith(".hip"):
+            h.update(" ".join(build.compile_flags(p)).encode())
     return h.hexdigest()[:16]
 
 

@@ -28,11 +28,11 @@ def asm(tmp_path_factory):
     if not os.path.exists(HIPCC) and not shutil.which("hipcc"):
         pytest.skip("hipcc not available")
     out = tmp_path_factory.mktemp("asm")
-    flags = [f for f in B.HIPCC_FLAGS if f not in ("-shared", "-Wall")]
     inc = ["-I", os.path.join(B.HERE, "..", "include")]
 
     def one(src):
         dst = os.path.join(out, os.path.basename(src) + ".s")
+        flags = [f for f in B.compile_flags(src) if f != "-Wall"]
         cmd = [HIPCC] + flags + inc + ["--cuda-device-only", "-S", src, "-o", dst]
         r = subprocess.run(cmd, capture_output=True, text=True)
         assert r.returncode == 0, r.stderr[-2000:]
