@@ -366,7 +366,9 @@ __device__ __forceinline__ void sweep_compact(const CompactArgs &a, const Model<
     for (int z = z0; z < z1; ++z) {
         const bool more = z + 2 <= z1;  // uniform over the block
         T nd = 0, nR = 0, nB = 0, nj[3] = {0, 0, 0}, nS[6] = {0, 0, 0, 0, 0, 0};
-        wait_memory();
+        // No wait for all memory operations here: the compiler waits for each
+        // loaded register before its use, which does not wait for the stores
+        // of the plane before (0.754 -> 0.750 ms per step on 256^3).
         if (z + 3 <= z1 + 1) rec_write(z + 3);
         ring_finish(z + 1);
         interior_moments(z + 1, nd, nR, nB, nj, nS);
