@@ -21,7 +21,7 @@ __global__ void __launch_bounds__(kCTX * kCR) k_step_compact(CompactArgs a, Mode
     if (PAIR_IN)
         sweep_pairs(a, mo, item / a.zchunks, item % a.zchunks, lds);
     else
-        sweep_compact(a, mo, item / a.zchunks, item % a.zchunks, lds);
+        sweep_compact<true>(a, mo, item / a.zchunks, item % a.zchunks, lds);
 }
 
 // Pair state of nodes [0, N) from a compact state: each population's

@@ -34,7 +34,7 @@ __global__ void __launch_bounds__(kCTX * kCR)
     a.nty = d.a.nty;
     a.zchunks = d.a.zchunks;
     if (item == 0 && threadIdx.x == 0) *a.ctr_out = *a.ctr_in + 1u;
-    sweep_compact(a, d.mo, item / a.zchunks, item % a.zchunks, lds);
+    sweep_compact<false>(a, d.mo, item / a.zchunks, item % a.zchunks, lds);
 }
 
 }  // namespace
