@@ -1,7 +1,8 @@
 """Properties of the gfx950 code the kernel sources compile to (no GPU needed:
 hipcc cross-compiles the device code to assembly).
 
-* No kernel writes more than 8 bytes per lane in one store.  A 12- or
+* No kernel writes more than 8 bytes per lane in one device-memory store
+  (LDS writes are not concerned).  A 12- or
   16-byte store may read its data registers after the compiler has reused
   them; on the compact D2Q9 sweep that lost the minority shares of lanes
   12-15 of each 16-lane group whenever another kernel ran beside it.
