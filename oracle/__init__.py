@@ -25,7 +25,8 @@ LIB_PATH = os.path.join(HERE, "librcg_oracle.so")
 SRC = os.path.join(HERE, "rcg_oracle.c")
 
 D2Q9, D3Q19 = 0, 1
-REGULARIZED, BGK = 0, 1
+REGULARIZED, BGK, BGK_COLOUR = 0, 1, 2
+INLET0, WALL0, OUTLET0 = 2, 64, 128  # mask codes: inlet j, wetting wall j, outlet j
 
 
 def build(force: bool = True) -> str:
@@ -48,6 +49,10 @@ class _Outlet(C.Structure):
     _fields_ = [("rho", C.c_double)]
 
 
+class _Wall(C.Structure):
+    _fields_ = [("psi", C.c_double)]
+
+
 class _Params(C.Structure):
     _fields_ = [
         ("lattice", C.c_int), ("collision", C.c_int),
@@ -57,7 +62,17 @@ class _Params(C.Structure):
         ("mask", C.POINTER(C.c_uint8)),
         ("n_inlets", C.c_int), ("inlets", C.POINTER(_Inlet)),
         ("n_outlets", C.c_int), ("outlets", C.POINTER(_Outlet)),
+        ("n_walls", C.c_int), ("walls", C.POINTER(_Wall)),
         ("n_threads", C.c_int),
+    ]
+
+
+class _Diag(C.Structure):
+    _fields_ = [
+        ("mass", C.c_double * 2), ("momentum", C.c_double * 3), ("max_u", C.c_double),
+        ("p_in", C.c_double), ("p_out", C.c_double), ("n_in", C.c_long), ("n_out", C.c_long),
+        ("vol_R", C.c_double), ("R_eff", C.c_double), ("nonfinite", C.c_long),
+        ("fluid_nodes", C.c_long),
     ]
 
 
@@ -78,6 +93,7 @@ def _load():
         lib.orc_step.argtypes = [P, dp, C.c_int]
         lib.orc_fields.argtypes = [P, dp, dp, dp, dp, dp]
         lib.orc_gradient.argtypes = [P, dp, dp]
+        lib.orc_diagnostics.argtypes = [P, dp, C.POINTER(_Diag)]
         lib.orc_collide_node.argtypes = [P, dp, dp, dp, dp]
         _lib = lib
     return _lib
@@ -115,6 +131,11 @@ class Outlet:
 
 
 @dataclass
+class Wall:
+    psi: float = 0.0  # phase value the colour gradient sees at this wetting wall
+
+
+@dataclass
 class Params:
     """Model parameters, named as in the paper (Eqs. (5), (7), (9), (10))."""
     lattice: int
@@ -127,6 +148,7 @@ class Params:
     mask: Optional[np.ndarray] = None     # uint8 (nz, ny, nx)
     inlets: Sequence[Inlet] = field(default_factory=list)
     outlets: Sequence[Outlet] = field(default_factory=list)
+    walls: Sequence[Wall] = field(default_factory=list)   # mask codes WALL0 + j
     collision: int = REGULARIZED
     threads: int = 0
 
@@ -168,9 +190,13 @@ class Oracle:
         outs = (_Outlet * max(1, len(p.outlets)))()
         for j, o in enumerate(p.outlets):
             outs[j].rho = float(o.rho)
-        self._keep += [ins, outs]
+        wls = (_Wall * max(1, len(p.walls)))()
+        for j, wl in enumerate(p.walls):
+            wls[j].psi = float(wl.psi)
+        self._keep += [ins, outs, wls]
         cp.n_inlets, cp.inlets = len(p.inlets), ins
         cp.n_outlets, cp.outlets = len(p.outlets), outs
+        cp.n_walls, cp.walls = len(p.walls), wls
         cp.n_threads = p.threads
         self._cp = cp
         self.f = np.zeros((nz, ny, nx, 2, p.Q), dtype=np.float64)
@@ -208,6 +234,18 @@ class Oracle:
         if rc:
             raise ValueError(f"orc_gradient failed ({rc})")
         return F
+
+    def diagnostics(self) -> dict:
+        """FP64 diagnostics of the current state (mass, momentum, max |u|,
+        Eq. (8) pressures inside and outside, R_eff, non-finite count)."""
+        d = _Diag()
+        rc = self._lib.orc_diagnostics(self._pp(), _dp(self.f), C.byref(d))
+        if rc:
+            raise ValueError(f"orc_diagnostics failed ({rc})")
+        out = {k: getattr(d, k) for k, _ in _Diag._fields_}
+        out["mass"] = list(d.mass)
+        out["momentum"] = list(d.momentum)
+        return out
 
     def collide_node(self, fin: np.ndarray, F: Sequence[float]):
         """Collision + perturbation + recolouring at one node: returns (post[2,Q], f2[Q])."""

@@ -78,8 +78,13 @@ def _opp(c):
 
 
 def step(f, lattice, tau, A, beta, alpha=(0.0, 0.0), eps_F=1e-8, mask=None, inlets=(),
-         outlets=(), bgk=False):
-    """One time step.  f: (2, Q, nz, ny, nx) pre-collision; returns the next one."""
+         outlets=(), bgk=False, walls=(), bgk_colour=False):
+    """One time step.  f: (2, Q, nz, ny, nx) pre-collision; returns the next one.
+
+    Mask codes: 1 neutral wall, 2 + j inlet j, 64 + j wetting wall j (its
+    phase value walls[j].psi enters the gradient), 128 + j outlet j.
+    bgk: Eq. (5) at the node's rate; bgk_colour: Eq. (5) with each colour at
+    its own rate 1/tau_k."""
     c, w, B, D = tables(lattice)
     Q = len(w)
     alpha = [a if a > 0 else w[0] for a in alpha]
@@ -107,6 +112,8 @@ def step(f, lattice, tau, A, beta, alpha=(0.0, 0.0), eps_F=1e-8, mask=None, inle
         for j, inl in enumerate(inlets):
             rw = inl.rho_w
             ps = np.where(mn == 2 + j, (rw[0] - rw[1]) / (rw[0] + rw[1]), ps)
+        for j, wl in enumerate(walls):
+            ps = np.where(mn == 64 + j, wl.psi, ps)
         F += (w[i] / CS2) * cf[i][:, None, None, None] * ps[None]
     F = np.where(fluid[None], F, 0.0)
     Fn = np.sqrt((F * F).sum(0))
@@ -126,7 +133,9 @@ def step(f, lattice, tau, A, beta, alpha=(0.0, 0.0), eps_F=1e-8, mask=None, inle
                                                 - B.reshape(-1, 1, 1, 1)), 0.0)
     for k in range(2):
         fe = equilibrium(lattice, rho_k[k], alpha[k], u)
-        if bgk:
+        if bgk_colour:
+            f1 = f[k] - (f[k] - fe) / tau[k]
+        elif bgk:
             f1 = f[k] - om * (f[k] - fe)
         else:
             Pneq = np.einsum("i...,ia,ib->ab...", f[k] - fe, cf, cf)
@@ -166,9 +175,9 @@ def step(f, lattice, tau, A, beta, alpha=(0.0, 0.0), eps_F=1e-8, mask=None, inle
                         if code == 0:
                             continue
                         io = opp[i]
-                        if code == 1:
+                        if code == 1 or 64 <= code < 128:
                             new[:, i, z, y, x] = post[:, io, z, y, x]
-                        elif code < 128:
+                        elif code < 64:
                             inl = inlets[code - 2]
                             cu = float(np.dot(c[io], inl.u))
                             for k in range(2):

@@ -15,7 +15,9 @@
  *      time tau (below): the post-collision population is the sum of the
  *      colour equilibria plus (1 - 1/tau) times the second-order Hermite
  *      projection of the non-equilibrium momentum flux of both colours; or
- *      plain BGK (Eq. 5) at the same rate when requested;
+ *      plain BGK (Eq. 5) on the total population at the same rate; or
+ *      Eq. (5) as it is written, each colour relaxed towards its own
+ *      equilibrium at its own rate 1/tau_k, when requested;
  *   4. perturbation (Eq. 9): add sum_k (A_k/2)|F| [w_i (F.c_i)^2/|F|^2 - B_i];
  *   5. recolouring (Eq. 10) of the total f_i into the two colours;
  *   6. streaming (Eq. 1) in push form with the boundary rules below.
@@ -32,8 +34,9 @@
  *     the same rule that gives Eq. (7) for D2Q9;
  *   - cos(phi_0) = 0 for the rest direction; for |F| <= eps_F the
  *     perturbation is skipped and all cosines are zero;
- *   - walls: half-way bounce-back of each colour, psi seen by the gradient =
- *     psi of the fluid node itself (neutral wetting);
+ *   - walls: half-way bounce-back of each colour; psi seen by the gradient =
+ *     psi of the fluid node itself (neutral wetting, mask code 1) or the
+ *     wall's own phase value psi_w (wetting walls, codes 64..127);
  *   - inlets: moving-wall bounce-back injecting colour k with density
  *     rho_w^k, psi seen by the gradient = psi of the inlet densities;
  *   - outlets: anti-bounce-back pressure boundary per colour: a population
@@ -176,13 +179,15 @@ static int check_params(const orc_params *p, lat_t *L)
     if (p->nx <= 0 || p->ny <= 0 || p->nz <= 0) return -1;
     if (p->lattice == ORC_D2Q9 && p->nz != 1) return -1;
     if (p->tau[0] <= 0.5 || p->tau[1] <= 0.5) return -1;
+    if (p->collision < ORC_REGULARIZED || p->collision > ORC_BGK_COLOUR) return -1;
     build_lattice(p->lattice, L);
     if (p->mask) {
         long N = (long)p->nx * p->ny * p->nz;
         for (long n = 0; n < N; ++n) {
             int m = p->mask[n];
-            if (m >= 2 && m < 128 && m - 2 >= p->n_inlets) return -1;
-            if (m >= 128 && m - 128 >= p->n_outlets) return -1;
+            if (m >= ORC_INLET0 && m < ORC_WALL0 && m - ORC_INLET0 >= p->n_inlets) return -1;
+            if (m >= ORC_WALL0 && m < ORC_OUTLET0 && m - ORC_WALL0 >= p->n_walls) return -1;
+            if (m >= ORC_OUTLET0 && m - ORC_OUTLET0 >= p->n_outlets) return -1;
         }
     }
     return 0;
@@ -300,8 +305,8 @@ static void phase_field(const orc_params *p, const lat_t *L, const double *f, do
 }
 
 /* Colour gradient at fluid node (x,y,z): F = (1/c_s^2) sum_i w_i c_i psi~(x+c_i),
- * psi~ = psi at fluid neighbours, psi(x) at walls and outlets, the inlet's own
- * phase value at inlets. */
+ * psi~ = psi at fluid neighbours, psi(x) at neutral walls and outlets, the
+ * inlet's own phase value at inlets, psi_w at wetting walls. */
 static void gradient_at(const orc_params *p, const lat_t *L, const double *psi, long x, long y,
                         long z, double F[3])
 {
@@ -313,10 +318,12 @@ static void gradient_at(const orc_params *p, const lat_t *L, const double *psi, 
         double ps;
         if (code == 0)
             ps = psi[m];
-        else if (code >= 2 && code < 128) {
-            const orc_inlet *in = &p->inlets[code - 2];
+        else if (code >= ORC_INLET0 && code < ORC_WALL0) {
+            const orc_inlet *in = &p->inlets[code - ORC_INLET0];
             ps = (in->rho_w[0] - in->rho_w[1]) / (in->rho_w[0] + in->rho_w[1]);
-        } else
+        } else if (code >= ORC_WALL0 && code < ORC_OUTLET0)
+            ps = p->walls[code - ORC_WALL0].psi;
+        else
             ps = psi[n];
         for (int a = 0; a < 3; ++a) F[a] += L->w[i] * L->c[i][a] * ps / CS2;
     }
@@ -339,6 +346,52 @@ int orc_gradient(const orc_params *p, const double *f, double *F)
         for (int a = 0; a < 3; ++a) F[a * N + n] = Fn[a];
     }
     free(psi);
+    return 0;
+}
+
+int orc_diagnostics(const orc_params *p, const double *f, orc_diag *d)
+{
+    lat_t L;
+    if (check_params(p, &L) || !d) return -1;
+    const long N = (long)p->nx * p->ny * p->nz;
+    const int Q = L.Q;
+    /* Eq. (8): the colour pressure is phat_k rho^k, phat_k the isotropic part
+     * of the equilibrium momentum flux per unit density (3(1 - alpha_k)/5 for
+     * D2Q9, 1/3 for alpha_k = w_0). */
+    const double phat[2] = {phat_of(&L, alpha_or_default(&L, p->alpha[0])),
+                            phat_of(&L, alpha_or_default(&L, p->alpha[1]))};
+    double sum_in = 0.0, sum_out = 0.0;
+    memset(d, 0, sizeof(*d));
+    for (long n = 0; n < N; ++n) {
+        if (mask_of(p, n) != 0) continue;
+        d->fluid_nodes += 1;
+        double rR, rB, j[3];
+        node_moments(&L, f + n * 2 * Q, &rR, &rB, j);
+        if (!(isfinite(rR) && isfinite(rB) && isfinite(j[0]) && isfinite(j[1]) && isfinite(j[2]))) {
+            d->nonfinite += 1;
+            continue;
+        }
+        const double rho = rR + rB;
+        const double psi = (rR - rB) / rho;
+        const double speed = sqrt(j[0] * j[0] + j[1] * j[1] + j[2] * j[2]) / rho;
+        const double pres = phat[0] * rR + phat[1] * rB;
+        d->mass[0] += rR;
+        d->mass[1] += rB;
+        for (int a = 0; a < 3; ++a) d->momentum[a] += j[a];
+        if (speed > d->max_u) d->max_u = speed;
+        if (psi > 0.99) {
+            sum_in += pres;
+            d->n_in += 1;
+        } else if (psi < -0.99) {
+            sum_out += pres;
+            d->n_out += 1;
+        }
+        d->vol_R += 0.5 * (1.0 + psi);
+    }
+    d->p_in = d->n_in > 0 ? sum_in / (double)d->n_in : 0.0;
+    d->p_out = d->n_out > 0 ? sum_out / (double)d->n_out : 0.0;
+    const double pi = 3.14159265358979323846;
+    d->R_eff = L.D == 2 ? sqrt(d->vol_R / pi) : cbrt(3.0 * d->vol_R / (4.0 * pi));
     return 0;
 }
 
@@ -368,6 +421,16 @@ static void collide(const orc_params *p, const lat_t *L, const double *fin, cons
         for (int i = 0; i < Q; ++i) {
             const double f = fin[i] + fin[Q + i];
             f1[i] = f - omega * (f - feq_sum[i]);
+        }
+    } else if (p->collision == ORC_BGK_COLOUR) {
+        /* Eq. (5) as written: colour k relaxes towards its own equilibrium
+         * at its own rate omega_k = 1/tau_k, and the colours are summed. */
+        for (int i = 0; i < Q; ++i) {
+            f1[i] = 0.0;
+            for (int k = 0; k < 2; ++k) {
+                const double fk = fin[k * Q + i];
+                f1[i] += fk - (1.0 / p->tau[k]) * (fk - feq(L, i, rho_k[k], alpha[k], u));
+            }
         }
     } else {
         /* Eq. (11): keep only rho^k, u and the momentum flux.  Pi^{neq} =
@@ -465,7 +528,8 @@ int orc_step(const orc_params *p, double *f, int nsteps)
 
         /* Step 6: streaming, Eq. (1), push form.  Each fluid node sends its
          * post-collision populations along c_i.  A population that would enter
-         * a wall comes back reversed to the sender (half-way bounce-back); one
+         * a wall of either kind comes back reversed to the sender (half-way
+         * bounce-back); one
          * entering an inlet comes back reversed with the moving-wall momentum
          * term; one entering an outlet comes back by anti-bounce-back.  Every
          * fluid slot has exactly one writer, so the loop is race-free. */
@@ -480,15 +544,15 @@ int orc_step(const orc_params *p, double *f, int nsteps)
                 const int io = L.opp[i];
                 if (code == 0) {
                     for (int k = 0; k < 2; ++k) f[(m * 2 + k) * Q + i] = pn[k * Q + i];
-                } else if (code == 1) {
+                } else if (code == 1 || (code >= ORC_WALL0 && code < ORC_OUTLET0)) {
                     for (int k = 0; k < 2; ++k) f[(n * 2 + k) * Q + io] = pn[k * Q + i];
-                } else if (code < 128) {
-                    const orc_inlet *in = &p->inlets[code - 2];
+                } else if (code < ORC_WALL0) {
+                    const orc_inlet *in = &p->inlets[code - ORC_INLET0];
                     double cu = L.c[i][0] * in->u[0] + L.c[i][1] * in->u[1] + L.c[i][2] * in->u[2];
                     for (int k = 0; k < 2; ++k)
                         f[(n * 2 + k) * Q + io] = pn[k * Q + i] - 2.0 * L.w[i] * in->rho_w[k] * cu / CS2;
                 } else {
-                    const orc_outlet *o = &p->outlets[code - 128];
+                    const orc_outlet *o = &p->outlets[code - ORC_OUTLET0];
                     double rP[2], jP[3], uP[3];
                     node_moments(&L, pn, &rP[0], &rP[1], jP);
                     for (int a = 0; a < 3; ++a) uP[a] = jP[a] / (rP[0] + rP[1]);

@@ -43,6 +43,7 @@ class Workload:
     inlets: List[dict] = field(default_factory=list)   # {"u": (3,), "rho_R":, "rho_B":}
     outlets: List[dict] = field(default_factory=list)  # {"rho": outlet density}
     steps: int = 1000
+    walls: List[dict] = field(default_factory=list)    # {"psi": phase value of wetting wall j}
 
     @property
     def shape(self):

@@ -11,6 +11,7 @@ def oracle_params(orc, w, threads=0, collision=None):
         eps_F=1e-8, mask=w.mask,
         inlets=[orc.Inlet(u=i["u"], rho_w=(i["rho_R"], i["rho_B"])) for i in w.inlets],
         outlets=[orc.Outlet(rho=o["rho"]) for o in w.outlets],
+        walls=[orc.Wall(psi=wl["psi"]) for wl in getattr(w, "walls", [])],
         collision=orc.REGULARIZED if collision is None else collision, threads=threads)
 
 

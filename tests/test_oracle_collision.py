@@ -182,3 +182,53 @@ def test_pure_components_relax_at_their_own_rate(orc, lat, collision):
         Pi = np.einsum("i,ia,ib->ab", fin[k], c, c)
         got = np.einsum("i,ia,ib->ab", post[k], c, c)
         assert np.allclose(got, Pi_eq + (1 - 1 / tau[k]) * (Pi - Pi_eq), atol=2e-15)
+
+
+@pytest.mark.parametrize("lat", ["D2Q9", "D3Q19"])
+@pytest.mark.parametrize("alpha", [(0.0, 0.0), (0.3, 0.55)])
+def test_moments_of_per_colour_bgk(orc, lat, alpha):
+    # Eq. (5) as written: colour k relaxes towards its own equilibrium
+    # f^{k,eq}(rho^k, u) (Eq. (6), common u of Eq. (3)) at omega_k = 1/tau_k.
+    # Zeroth and first moments of the relaxed total (F = 0: no perturbation):
+    #   sum_i f_i = rho,
+    #   sum_i f_i c_i = sum_k (1 - omega_k) j^k + omega_k rho^k u,
+    # so momentum is not kept when tau_R != tau_B (j^k != rho^k u); second
+    # moment sum_k (1 - omega_k) Pi^k + omega_k rho^k (phat_k I + u u).
+    rng = np.random.default_rng(17)
+    tau = (1.6, 0.6)
+    o, t, D = _setup(orc, lat, tau, alpha=alpha, collision=orc.BGK_COLOUR)
+    c = t["c"].astype(float)
+    w0 = t["w"][0]
+    al = [a if a > 0 else w0 for a in alpha]
+    I = np.eye(3)
+    I[D:, D:] = 0
+    for _ in range(10):
+        fin, _ = _random_node(rng, t, D)
+        post, f2 = o.collide_node(fin, np.zeros(3))
+        rk = fin.sum(1)
+        rho = rk.sum()
+        jk = fin @ c
+        u = jk.sum(0) / rho
+        om = [1 / tau[0], 1 / tau[1]]
+        assert np.isclose(f2.sum(), rho, atol=1e-15)
+        expect_j = sum((1 - om[k]) * jk[k] + om[k] * rk[k] * u for k in range(2))
+        assert np.allclose(f2 @ c, expect_j, atol=1e-15)
+        assert np.abs(f2 @ c - jk.sum(0)).max() > 1e-6  # momentum changes
+        Pk = np.einsum("ki,ia,ib->kab", fin, c, c)
+        expect_P = sum((1 - om[k]) * Pk[k] + om[k] * rk[k] * (_phat(lat, al[k]) * I + np.outer(u, u))
+                       for k in range(2))
+        assert np.allclose(np.einsum("i,ia,ib->ab", f2, c, c), expect_P, atol=2e-15)
+        assert np.allclose(post.sum(1), rk, atol=1e-15)
+
+
+@pytest.mark.parametrize("lat", ["D2Q9", "D3Q19"])
+def test_per_colour_bgk_at_equal_rates_is_node_rate_bgk(orc, lat):
+    # With tau_R = tau_B both readings of Eq. (5) relax at the same rate.
+    rng = np.random.default_rng(19)
+    a_o, t, D = _setup(orc, lat, tau=(0.9, 0.9), collision=orc.BGK_COLOUR)
+    b_o, _, _ = _setup(orc, lat, tau=(0.9, 0.9), collision=orc.BGK)
+    for _ in range(5):
+        fin, F = _random_node(rng, t, D)
+        a, _ = a_o.collide_node(fin, F)
+        b, _ = b_o.collide_node(fin, F)
+        assert np.abs(a - b).max() < 1e-15

@@ -1,6 +1,7 @@
 """Brute force on tiny lattices: the C oracle against the independent
-per-equation NumPy version (oracle/literal.py), with and without walls,
-inlets and outlets, regularized and plain BGK."""
+per-equation NumPy version (oracle/literal.py), with and without walls
+(neutral and wetting), inlets and outlets; regularized, plain BGK at the
+node's rate and Eq. (5) with a rate per colour."""
 import numpy as np
 import pytest
 
@@ -16,25 +17,30 @@ def _geometry(orc, lat, sh):
     if lat == "D3Q19":
         mask[0, :, :] = 1
         mask[-1, 2, 3] = 1  # an isolated obstacle node
+        mask[0, 1:3, 1:4] = orc.WALL0 + 1  # a wetting patch in the z = 0 wall
+    else:
+        mask[0, 0, 2:5] = orc.WALL0  # wetting patches in the y = 0 wall
+        mask[0, -1, 3] = orc.WALL0 + 1
     inlets = [orc.Inlet(u=(0.01, 0.002, 0.001 if lat == "D3Q19" else 0.0), rho_w=(0.8, 0.2))]
     outlets = [orc.Outlet(rho=1.02)]
-    return mask, inlets, outlets
+    walls = [orc.Wall(psi=0.6), orc.Wall(psi=-0.8)]
+    return mask, inlets, outlets, walls
 
 
 @pytest.mark.parametrize("lat,dims", [("D2Q9", (8, 8, 1)), ("D3Q19", (6, 5, 4))])
 @pytest.mark.parametrize("masked", [False, True])
-@pytest.mark.parametrize("bgk", [False, True])
-def test_c_oracle_matches_literal(orc, lat, dims, masked, bgk):
-    rng = np.random.default_rng(hash((lat, masked, bgk)) % 2 ** 32)
+@pytest.mark.parametrize("coll", ["reg", "bgk", "bgk_colour"])
+def test_c_oracle_matches_literal(orc, lat, dims, masked, coll):
+    rng = np.random.default_rng(sum(map(ord, lat + coll)) + 7 * masked)
     nx, ny, nz = dims
     sh = (nz, ny, nx)
-    mask, inlets, outlets = _geometry(orc, lat, sh) if masked else (None, [], [])
+    mask, inlets, outlets, walls = _geometry(orc, lat, sh) if masked else (None, [], [], [])
     tau, A, alpha, beta = (1.3, 0.7), (0.01, 0.02), (0.0, 0.0), 0.7
-    if bgk:
+    if coll != "reg":
         alpha = (0.3, 0.5) if lat == "D2Q9" else (0.25, 0.4)
     p = orc.Params(lattice=orc.D2Q9 if lat == "D2Q9" else orc.D3Q19, dims=dims, tau=tau, A=A,
-                   alpha=alpha, beta=beta, mask=mask, inlets=inlets, outlets=outlets,
-                   collision=orc.BGK if bgk else orc.REGULARIZED)
+                   alpha=alpha, beta=beta, mask=mask, inlets=inlets, outlets=outlets, walls=walls,
+                   collision={"reg": orc.REGULARIZED, "bgk": orc.BGK, "bgk_colour": orc.BGK_COLOUR}[coll])
     rR = rng.uniform(0, 1, sh)
     rB = rng.uniform(0, 1, sh)
     u = rng.uniform(-0.05, 0.05, (3,) + sh)
@@ -47,6 +53,6 @@ def test_c_oracle_matches_literal(orc, lat, dims, masked, bgk):
     for _ in range(6):
         o.step(1)
         fl = L.step(fl, lat, tau, A, beta, alpha=alpha, mask=mask, inlets=inlets,
-                    outlets=outlets, bgk=bgk)
+                    outlets=outlets, bgk=coll == "bgk", walls=walls, bgk_colour=coll == "bgk_colour")
         d = np.abs((o.populations() - fl)[:, :, fluid]).max()
         assert d < 1e-14, d

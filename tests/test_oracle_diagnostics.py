@@ -1,0 +1,154 @@
+"""Pins of the oracle's FP64 diagnostics (orc_diagnostics): colour masses
+(Eq. (2)), momentum (Eq. (3)), max |u|, the Eq. (8) colour pressure inside
+and outside a droplet, the equivalent radius and the count of non-finite
+nodes.
+
+Each pin rests on something other than the function itself: uniform states
+whose sums are closed forms, the printed Eq. (8) coefficient, the field
+export of the same state, known droplet geometry, and a planted NaN."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_1711_02003_amd import workloads as W
+from tests.helpers import oracle_for
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")
+
+
+def _uniform(orc, lat, dims, rR, rB, u, alpha=(0.0, 0.0), mask=None):
+    nx, ny, nz = dims
+    sh = (nz, ny, nx)
+    p = orc.Params(lattice=orc.D2Q9 if lat == "D2Q9" else orc.D3Q19, dims=dims, alpha=alpha,
+                   mask=mask)
+    uu = np.zeros((3,) + sh)
+    for a in range(3):
+        uu[a] = u[a]
+    return orc.Oracle(p).init(np.full(sh, rR), np.full(sh, rB), uu)
+
+
+@pytest.mark.parametrize("lat,dims", [("D2Q9", (12, 10, 1)), ("D3Q19", (6, 5, 4))])
+def test_uniform_mixture_at_rest_and_moving(orc, lat, dims):
+    # A uniform state has sums N rho^k and N rho u, and |u| everywhere.
+    N = int(np.prod(dims))
+    u0 = (0.03, -0.02, 0.01 if lat == "D3Q19" else 0.0)
+    for rR, rB in ((0.7, 0.3), (0.25, 0.75)):
+        d = _uniform(orc, lat, dims, rR, rB, u0).diagnostics()
+        assert d["fluid_nodes"] == N and d["nonfinite"] == 0
+        assert d["mass"][0] == pytest.approx(N * rR, rel=1e-14)
+        assert d["mass"][1] == pytest.approx(N * rB, rel=1e-14)
+        for a in range(3):
+            assert d["momentum"][a] == pytest.approx(N * (rR + rB) * u0[a], rel=1e-13, abs=1e-15)
+        assert d["max_u"] == pytest.approx(float(np.linalg.norm(u0)), rel=1e-13)
+        # psi = +-0.4 or -0.5: inside neither bulk
+        assert d["n_in"] == 0 and d["n_out"] == 0 and d["p_in"] == 0 and d["p_out"] == 0
+        psi = (rR - rB) / (rR + rB)
+        assert d["vol_R"] == pytest.approx(N * (1 + psi) / 2, rel=1e-14)
+
+
+@pytest.mark.parametrize("alpha", [0.0, 0.2, 0.6])
+def test_pure_colours_pressure_is_eq8(orc, alpha):
+    # Eq. (8) printed for D2Q9: p^k = 3 rho^k (1 - alpha_k) / 5 (alpha = 0
+    # stands for the equal-density value 4/9, where p = rho/3).  A pure red
+    # box has every node inside (psi = 1), a pure blue box every node outside.
+    g = json.load(open(GOLDEN))["pressure_d2q9"]
+    assert g["coefficient"] == "3(1-alpha)/5"
+    a = alpha if alpha > 0 else 4.0 / 9.0
+    dims = (8, 6, 1)
+    N = 48
+    rho = 1.3
+    d = _uniform(orc, "D2Q9", dims, rho, 0.0, (0, 0, 0), alpha=(alpha, 0.0)).diagnostics()
+    assert d["n_in"] == N and d["n_out"] == 0
+    assert d["p_in"] == pytest.approx(3 * rho * (1 - a) / 5, rel=1e-14)
+    assert d["vol_R"] == pytest.approx(N, rel=1e-15) and d["mass"][1] == 0.0
+    d = _uniform(orc, "D2Q9", dims, 0.0, rho, (0, 0, 0), alpha=(0.0, alpha)).diagnostics()
+    assert d["n_out"] == N and d["n_in"] == 0
+    assert d["p_out"] == pytest.approx(3 * rho * (1 - a) / 5, rel=1e-14)
+    assert d["vol_R"] == 0.0 and d["mass"][0] == 0.0
+
+
+def test_pure_colours_pressure_d3q19(orc):
+    # D3Q19 (phi_i = alpha at rest, (1 - alpha)/12 axis, (1 - alpha)/24
+    # diagonal): the isotropic flux per unit density is 2 (1-alpha)/12 +
+    # 8 (1-alpha)/24 = (1 - alpha)/2, 1/3 for alpha = w_0 = 1/3.
+    for alpha, phat in ((0.0, 1.0 / 3.0), (0.55, 0.45 / 2)):
+        d = _uniform(orc, "D3Q19", (4, 4, 4), 0.9, 0.0, (0, 0, 0), alpha=(alpha, 0.0)).diagnostics()
+        assert d["n_in"] == 64
+        assert d["p_in"] == pytest.approx(phat * 0.9, rel=1e-14)
+
+
+def test_masses_match_field_export_of_an_evolved_state(orc):
+    # The masses, momentum, max |u|, inside/outside means and vol_R of an
+    # evolved droplet equal the same quantities formed here from the field
+    # export of the same state (orc_fields).
+    w = W.config1()
+    o = oracle_for(orc, w, threads=4).step(300)
+    d = o.diagnostics()
+    f = o.fields()
+    rho = f["rhoR"] + f["rhoB"]
+    assert d["mass"][0] == pytest.approx(f["rhoR"].sum(), rel=1e-13)
+    assert d["mass"][1] == pytest.approx(f["rhoB"].sum(), rel=1e-13)
+    j = f["u"] * rho[None]
+    for a in range(3):
+        assert abs(d["momentum"][a] - j[a].sum()) < 1e-13 * w.nodes
+    assert d["max_u"] == pytest.approx(np.sqrt((f["u"] ** 2).sum(0)).max(), rel=1e-12)
+    inside, outside = f["psi"] > 0.99, f["psi"] < -0.99
+    assert d["n_in"] == inside.sum() and d["n_out"] == outside.sum()
+    assert d["p_in"] == pytest.approx((rho[inside] / 3).mean(), rel=1e-13)
+    assert d["p_out"] == pytest.approx((rho[outside] / 3).mean(), rel=1e-13)
+    assert d["p_in"] > d["p_out"]  # the Laplace jump
+    assert d["vol_R"] == pytest.approx(((1 + f["psi"]) / 2).sum(), rel=1e-13)
+    assert d["fluid_nodes"] == w.nodes and d["nonfinite"] == 0
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_equivalent_radius_of_a_droplet(orc, dim):
+    # A droplet with red fraction (1 + tanh((R - r)/w))/2 has the red volume
+    # of a sharp disc or sphere plus the interface's curvature correction:
+    # integrating r (tanh(s/w) - sign(s)) over the interface gives
+    #   2-D: V = pi (R^2 + pi^2 w^2 / 12),  3-D: V = 4/3 pi (R^3 + pi^2 w^2 R / 4),
+    # so R_eff is that closed form (w = 2 here); this fixes both radius
+    # formulas and the red-volume sum.
+    wd = 2.0
+    if dim == 2:
+        R = 16.0
+        w = W.static_droplet_2d(n=64, R=R, width=wd, noise=0.0)
+        expect = np.sqrt(R * R + np.pi ** 2 * wd * wd / 12)
+    else:
+        R = 10.0
+        w = W.static_droplet_3d(n=40, R=R, width=wd)
+        expect = np.cbrt(R ** 3 + np.pi ** 2 * wd * wd * R / 4)
+    d = oracle_for(orc, w).diagnostics()
+    assert abs(d["R_eff"] - expect) < 2e-3
+    # and not the other dimension's formula
+    other = np.cbrt(3 * d["vol_R"] / (4 * np.pi)) if dim == 2 else np.sqrt(d["vol_R"] / np.pi)
+    assert abs(other - R) > 1.0
+
+
+def test_walls_are_not_counted(orc):
+    dims = (8, 7, 1)
+    mask = np.zeros((1, 7, 8), np.uint8)
+    mask[0, 0, :] = 1
+    mask[0, -1, :] = 1
+    d = _uniform(orc, "D2Q9", dims, 0.6, 0.4, (0.01, 0, 0), mask=mask).diagnostics()
+    assert d["fluid_nodes"] == 8 * 5
+    assert d["mass"][0] == pytest.approx(40 * 0.6, rel=1e-14)
+
+
+def test_planted_nan_is_counted_and_left_out(orc):
+    # A NaN in one population of one node: that node is non-finite, and the
+    # sums cover the other nodes only.
+    w = W.config1()
+    o = oracle_for(orc, w).step(10)
+    ref = o.diagnostics()
+    f = o.fields()
+    node = (0, 20, 31)
+    massR_wo = f["rhoR"].sum() - f["rhoR"][node]
+    o.f[node + (1, 3)] = np.nan
+    d = o.diagnostics()
+    assert d["nonfinite"] == 1 and d["fluid_nodes"] == ref["fluid_nodes"]
+    assert d["mass"][0] == pytest.approx(massR_wo, rel=1e-13)
+    o.f[node + (0, 0)] = np.inf
+    assert o.diagnostics()["nonfinite"] == 1
