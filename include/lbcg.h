@@ -55,9 +55,13 @@ extern "C" {
 #define LBCG_F16 2
 
 /* Relaxation: the regularized form of Eq. (11) (default) or the plain BGK
- * form of Eq. (5), both at the node's rate (see tau_B below). */
+ * form of Eq. (5), both at the node's rate (see tau_B below), or Eq. (5) as
+ * it is written, each colour relaxed towards its own equilibrium at its own
+ * rate 1/tau_k (the literal baseline of Fig. 1; it does not keep momentum
+ * where tau_R != tau_B).  Both BGK forms run on the generic kernel only. */
 #define LBCG_REGULARIZED 0
 #define LBCG_BGK 1
+#define LBCG_BGK_COLOUR 2
 
 /* Kernel choice: automatic, the two-pass generic kernel (every lattice,
  * precision, collision and boundary) or the fused single-pass kernel (F32 or
@@ -87,14 +91,19 @@ extern "C" {
 #define LBCG_KERNEL_FUSED 2
 #define LBCG_KERNEL_COMPACT 3
 
-/* Mask codes (one byte per node): 0 fluid; 1 wall (half-way bounce-back);
- * 2 + j inlet j (moving-wall velocity inlet); 128 + j outlet j (pressure
- * outlet).  Non-fluid nodes hold no fluid and are never collided; their
- * storage holds the boundary values that neighbouring fluid nodes pull, and
- * every export reports zeros for them. */
+/* Mask codes (one byte per node): 0 fluid; 1 neutral wall (half-way
+ * bounce-back; the colour gradient sees the fluid node's own phase value
+ * there); 2 + j inlet j, j < 62 (moving-wall velocity inlet); 64 + j wetting
+ * wall j, j < 64 (half-way bounce-back; the colour gradient sees the wall's
+ * phase value psi_w); 128 + j outlet j (pressure outlet).  The paper states
+ * no boundary rule (its devices, Figs. 2 and 5, have walls, inlets and an
+ * outlet); these are this library's.  Non-fluid nodes hold no fluid and are
+ * never collided; their storage holds the boundary values that neighbouring
+ * fluid nodes pull, and every export reports zeros for them. */
 #define LBCG_FLUID 0
 #define LBCG_WALL 1
 #define LBCG_INLET0 2
+#define LBCG_WALL0 64
 #define LBCG_OUTLET0 128
 
 /* Velocity inlet: populations leaving a fluid node towards the inlet node come
@@ -115,10 +124,17 @@ typedef struct {
     double rho;
 } lbcg_outlet;
 
+/* Wetting wall: psi in [-1, 1] is the phase value (rho^R - rho^B)/rho the
+ * colour gradient of a neighbouring fluid node sees at the wall.  +1 makes
+ * colour R wet the wall, -1 colour B; a neutral wall is mask code 1. */
+typedef struct {
+    double psi;
+} lbcg_wall;
+
 typedef struct {
     int32_t lattice;     /* LBCG_D2Q9 or LBCG_D3Q19 */
     int32_t precision;   /* LBCG_F64, LBCG_F32 or LBCG_F16 */
-    int32_t collision;   /* LBCG_REGULARIZED or LBCG_BGK */
+    int32_t collision;   /* LBCG_REGULARIZED, LBCG_BGK or LBCG_BGK_COLOUR */
     int32_t kernel;      /* LBCG_KERNEL_* */
     int64_t dims[3];     /* nx, ny, nz (nz = 1 for D2Q9); each >= 1 */
     const uint8_t *mask; /* host, nx*ny*nz codes; NULL = every node fluid */
@@ -132,17 +148,23 @@ typedef struct {
     double alpha_R;      /* density-ratio parameter alpha_R (Eq. (7)); 0 = w_0 */
     double alpha_B;      /* density-ratio parameter alpha_B; 0 = w_0 */
     double eps_F;        /* |F| at or below which F counts as zero; < 0 = 1e-8 */
-    int32_t n_inlets;    /* entries in inlets (<= 126) */
+    int32_t n_inlets;    /* entries in inlets (<= 62) */
     int32_t n_outlets;   /* entries in outlets (<= 128) */
     const lbcg_inlet *inlets;   /* host, copied */
     const lbcg_outlet *outlets; /* host, copied */
+    int32_t n_walls;     /* entries in walls (<= 64) */
+    const lbcg_wall *walls;     /* host, copied */
     int32_t tile[3];     /* fused-kernel launch shape: rows per block (4 or 8;
                             D3Q19 only), z chunks (D2Q9: row chunks; <= 4096),
                             reserved; 0 = automatic */
 } lbcg_params;
 
 /* FP64 diagnostics of the current state S_t (pre-collision), summed over fluid
- * nodes in a fixed order (bitwise reproducible for a given lattice). */
+ * nodes in a fixed order (bitwise reproducible for a given lattice).  Each
+ * node's colour populations are decoded as lbcg_populations exports them and
+ * its moments summed in FP64 (Eqs. (2), (3), (8)).  A fluid node whose
+ * densities or momentum are not finite counts in `nonfinite` and is left out
+ * of every other sum. */
 typedef struct {
     double mass_R, mass_B;  /* sum of rho^R, rho^B (Eq. (2)) */
     double momentum[3];     /* sum of rho u (Eq. (3)) */
@@ -177,17 +199,24 @@ int lbcg_create(const lbcg_params *p, void *dev_buf, size_t bytes, void *hip_str
  * Resets the step counter. */
 int lbcg_init_fields(lbcg_sim *s, const double *rhoR, const double *rhoB, const double *u);
 
-/* Queue n >= 0 time steps (asynchronous).  Device faults surface at the next
- * synchronizing call. */
+/* Queue n >= 0 time steps (asynchronous).  One time step is Eq. (1): the
+ * composite collision of Eq. (4) at every fluid node - relaxation (Eq. (11),
+ * or Eq. (5) with a BGK collision), the perturbation of Eq. (9) driven by the
+ * colour gradient of the phase field, the recolouring of Eq. (10) - followed
+ * by streaming with the boundary rules of the mask.  Device faults surface at
+ * the next synchronizing call. */
 int lbcg_step(lbcg_sim *s, int64_t n);
 
-/* Fields of the current state S_t: rho^R, rho^B, psi (N doubles each) and u
- * (3N doubles, component-major).  NULL outputs are skipped; non-fluid nodes
- * read 0.  Synchronizes. */
+/* Fields of the current state S_t: the colour densities rho^R, rho^B of
+ * Eq. (2), the phase field psi = (rho^R - rho^B)/(rho^R + rho^B) (N doubles
+ * each) and the common velocity u of Eq. (3) (3N doubles, component-major).
+ * Output pointers select the fields (NULL = skip).  Non-fluid nodes read 0.
+ * Synchronizes. */
 int lbcg_fields(lbcg_sim *s, double *rhoR, double *rhoB, double *u, double *psi);
 
-/* Pre-collision populations of S_t in canonical order f[k][i][n]
- * (k = R, B; i as in the lattice numbering; 2*Q*N doubles).  Synchronizes. */
+/* Pre-collision populations f_i^k of S_t (the distributions of Eq. (1)) in
+ * canonical order f[k][i][n] (k = R, B; i as in the lattice numbering;
+ * 2*Q*N doubles).  Synchronizes. */
 int lbcg_populations(lbcg_sim *s, double *f);
 
 /* Pre-collision populations of S_t at count listed nodes (node indices in
@@ -202,7 +231,11 @@ int lbcg_diagnostics(lbcg_sim *s, lbcg_diag *out);
 
 /* Raw state for checkpoint/restart: lbcg_state_bytes gives the size; get
  * copies it to host memory, set restores it (same parameters required).
- * A restored state continues bitwise-identically.  Synchronizes. */
+ * A restored state continues bitwise-identically.  Synchronizes.  Layout: 8
+ * int64 header words (magic, lattice, precision, nx, ny, nz, post-collision
+ * flag, step), then Q arrays, one per direction, of N value pairs (total
+ * deviation, minority share with the majority flag in its lowest bit) in
+ * the storage precision. */
 int lbcg_state_bytes(lbcg_sim *s, size_t *bytes);
 int lbcg_get_state(lbcg_sim *s, void *host, size_t bytes);
 int lbcg_set_state(lbcg_sim *s, const void *host, size_t bytes);
@@ -248,7 +281,8 @@ int lbcg_tune(lbcg_sim *s, int32_t *rows, int32_t *zchunks);
  * lbcg_batch_step advances lattice j by nsteps[j] >= 0 steps (n entries),
  * asynchronously on the shared stream.  Results per lattice are bitwise those
  * of lbcg_step on the handle alone.  Between batch steps the handles may be
- * used directly (fields, diagnostics, lbcg_step). */
+ * used directly (fields, diagnostics, lbcg_step): a batch has no field call
+ * of its own, since every member is an ordinary handle. */
 typedef struct lbcg_batch lbcg_batch;
 int lbcg_batch_create(lbcg_sim *const *sims, int32_t n, const int32_t *tile, lbcg_batch **out);
 int lbcg_batch_step(lbcg_batch *b, const int64_t *nsteps);

@@ -26,7 +26,11 @@
 
 namespace lbcg {
 
-constexpr uint8_t kFluid = 0, kWall = 1, kInlet0 = 2, kOutlet0 = 128;
+// Mask codes: fluid; neutral wall; inlets 2..63; wetting walls 64..127 (a
+// wall whose phase value the colour gradient sees); outlets 128..255.
+constexpr uint8_t kFluid = 0, kWall = 1, kInlet0 = 2, kWall0 = 64, kOutlet0 = 128;
+__host__ __device__ constexpr bool is_wall(uint8_t c) { return c == kWall || (c >= kWall0 && c < kOutlet0); }
+__host__ __device__ constexpr bool is_inlet(uint8_t c) { return c >= kInlet0 && c < kWall0; }
 
 // ---------------------------------------------------------------- lattices
 // D2Q9: rest, then counter-clockwise from +x alternating axis and diagonal
@@ -105,6 +109,9 @@ struct DevInlet {
 struct DevOutlet {
     double rho;
 };
+struct DevWall {
+    double psi;  // phase value of a wetting wall
+};
 
 // Scalars of the model in the compute type T, built once per launch.
 template <typename T>
@@ -116,7 +123,9 @@ struct Model {
     T dR0, dB0;      // phi_0^k - w_0 = alpha_k - w_0
     T kR, kB;        // (phi_i^k - w_i) / w_i = (w_0 - alpha_k) / (1 - w_0), i > 0
     T eps_F;
-    int bgk;         // plain BGK relaxation (Eq. (5)) instead of Eq. (11)
+    T omR, omB;      // 1/tau_k, the per-colour rates of Eq. (5) (bgk == 2)
+    int bgk;         // 0: Eq. (11); 1: Eq. (5) at the node's rate; 2: Eq. (5)
+                     // with each colour at its own rate
 };
 
 // Everything a kernel needs about one lattice.
@@ -126,6 +135,7 @@ struct Geo {
     const uint8_t *mask;       // nullptr = all fluid
     const DevInlet *inlets;
     const DevOutlet *outlets;
+    const DevWall *walls;      // wetting walls (codes kWall0 + j)
     const uint32_t *links;     // link words (below), with a mask only
 };
 
@@ -575,7 +585,7 @@ __device__ __forceinline__ T dphi(int i, T d0, T k) {
 }
 // sum_i phi_i c_ix^2: (1 - alpha) * sum_{moving} w_i c_ix^2 / (1 - w_0)
 template <class L, typename T>
-__device__ __forceinline__ T phat(T alpha) {
+__host__ __device__ __forceinline__ T phat(T alpha) {
     return (T(1) - alpha) * T((1.0 / 3.0) / (1.0 - wgt<L>(0)));
 }
 
@@ -629,13 +639,18 @@ __device__ __forceinline__ OwnMom<T> own_moments(const typename PairOf<S>::type 
 // Value a fluid node pulls through link i from a non-fluid upstream node of
 // mask code `code`, from the node's own stored new pair of the opposite
 // direction (own_io) and, for outlets, its own moments.  Walls return own_io
-// unchanged; inlet and outlet values are encoded rounded to nearest.
+// unchanged; inlet and outlet values are encoded rounded to nearest.  The
+// total deviation f_i - w_i is formed from deviations only (the stored dfo,
+// the inlet's momentum term, the outlet's density excess, phi - w and the
+// velocity terms), never as a difference of two full populations: in FP32
+// that difference would lose the ~1e-9 absolute precision that the stored
+// deviations keep, and the boundary nodes' velocity with it.
 template <class L, typename S, typename T>
 __device__ __forceinline__ typename PairOf<S>::type boundary_pair(const Geo &g, const Model<T> &mo, int i,
                                                                   uint8_t code,
                                                                   typename PairOf<S>::type own_io,
                                                                   const OwnMom<T> &om) {
-    if (code == kWall) return own_io;
+    if (is_wall(code)) return own_io;
     const int io = L::opp[i];
     bool flo;
     const T dfo = Codec<S>::template df<L, T>(own_io.x, io);
@@ -643,13 +658,14 @@ __device__ __forceinline__ typename PairOf<S>::type boundary_pair(const Geo &g, 
     const T fo = T(wgt<L>(io)) + dfo;
     const T mu = mo_ * fo;
     const T fRo = flo ? fo - mu : mu, fBo = fo - fRo;
-    T fR, fB;
-    if (code < kOutlet0) {
+    T fR, fB, dev;  // the colour populations and the total deviation f - w_i
+    if (is_inlet(code)) {
         const DevInlet in = g.inlets[code - kInlet0];
         const T cu = T(L::cx[io]) * T(in.u[0]) + T(L::cy[io]) * T(in.u[1]) + T(L::cz[io]) * T(in.u[2]);
         const T mom = T(6.0 * wgt<L>(io)) * cu;  // 2 w c.u / c_s^2
         fR = fRo - mom * T(in.rhoR);
         fB = fBo - mom * T(in.rhoB);
+        dev = dfo - mom * (T(in.rhoR) + T(in.rhoB));
     } else {
         const T rout = T(g.outlets[code - kOutlet0].rho);
         const T rwR = rout * om.rR / om.rho, rwB = rout - rwR;
@@ -659,12 +675,16 @@ __device__ __forceinline__ typename PairOf<S>::type boundary_pair(const Geo &g, 
         const T phR = phi<L, T>(io, mo.aR), phB = phi<L, T>(io, mo.aB);
         fR = T(2) * rwR * (phR + wv) - fRo;
         fB = T(2) * rwB * (phB + wv) - fBo;
+        // 2 sum_k rw_k (phi_k + wv) - f_o - w with phi_k = w + (phi_k - w) and
+        // f_o = w + dfo
+        const T dpR = dphi<L, T>(io, mo.dR0, mo.kR), dpB = dphi<L, T>(io, mo.dB0, mo.kB);
+        dev = T(2) * T(wgt<L>(io)) * (rout - T(1)) + T(2) * (rwR * dpR + rwB * dpB) + T(2) * rout * wv - dfo;
     }
     const T f = fR + fB;
     T mm;
     bool fl;
     split_shares<T>(f != T(0) ? fR / f : T(0), f != T(0) ? fB / f : T(0), mm, fl);
-    return encode_pair<L, S, T>(f - T(wgt<L>(i)), mm, fl, i);
+    return encode_pair<L, S, T>(dev, mm, fl, i);
 }
 
 // Pre-collision populations of fluid node (x, y, z) = n at the new time level
@@ -806,7 +826,7 @@ __device__ __forceinline__ void collide(const Model<T> &mo, T drho, T r36R, T r3
             // sum_k rho^k phi_i^k - w_i  +  w_i rho U  +  w_i/(2 c_s^4) Q_i : N
             ev = w * drho + rR * dpR + rB * dpB + w * (T(4.5) * cj * cu - wrho) + T(4.5) * w * qn;
             od = odd_coef<L, T>(i) * cj;
-        } else {
+        } else if (mo.bgk == 1) {
             // (1 - omega) f_i + omega sum_k f_i^{k,eq} - w_i, split into the
             // parts even and odd under i <-> -i (the populations themselves
             // have no symmetry, so both directions are formed here).
@@ -815,6 +835,21 @@ __device__ __forceinline__ void collide(const Model<T> &mo, T drho, T r36R, T r3
             const T lin = om * (odd_coef<L, T>(i) * cj);
             const T di = gm * pin->df[i];
             const T db = gm * pin->df[ib];
+            ev = base + T(0.5) * (di + db);
+            od = lin + T(0.5) * (di - db);
+        } else {
+            // Eq. (5) with each colour at its own rate omega_k:
+            // sum_k (1 - omega_k) f_i^k + omega_k f_i^{k,eq} - w_i, with the
+            // blue part written as f_i - f_i^R:
+            // (1 - omega_B) df_i + (omega_B - omega_R) f_i^R - omega_B w_i +
+            // sum_k omega_k rho^k (phi_i^k + w_i U_i).
+            const T U2 = T(4.5) * cu * cu - T(1.5) * usq;
+            const T base = -mo.omB * w + mo.omR * rR * (w + dpR + w * U2) + mo.omB * rB * (w + dpB + w * U2);
+            const T lin = (mo.omR * rR + mo.omB * rB) * inv_rho * (odd_coef<L, T>(i) * cj);
+            const T dom = mo.omB - mo.omR;
+            const T gB = T(1) - mo.omB;
+            const T di = gB * pin->df[i] + dom * pin->fred(i);
+            const T db = gB * pin->df[ib] + dom * pin->fred(ib);
             ev = base + T(0.5) * (di + db);
             od = lin + T(0.5) * (di - db);
         }

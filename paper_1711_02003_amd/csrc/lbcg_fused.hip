@@ -22,8 +22,9 @@
 //
 // With a geometry mask (compile-time switch) the pull applies the boundary
 // rules of the generic path (walls, velocity inlets, pressure outlets), psi
-// of an inlet node is the inlet's phase value, and a wall or outlet
-// neighbour contributes the centre node's psi to the gradient.
+// of an inlet node is the inlet's phase value, psi of a wetting wall its
+// own phase value, and a neutral wall or outlet neighbour contributes the
+// centre node's psi to the gradient.
 //
 // Block -> work mapping (single lattice): work items (tile, z chunk) are
 // numbered tile-major.  Periodic lattices deal them to the 8 XCDs in
@@ -42,7 +43,7 @@ namespace lbcg {
 
 constexpr int kTX = 64;
 constexpr int kXCD = 8;
-constexpr float kSentinel = 1e30f;  // LDS psi of a wall or outlet node
+constexpr float kSentinel = 1e30f;  // LDS psi of a neutral wall or outlet node
 
 // Barrier that orders LDS accesses only; global loads stay in flight.
 __device__ __forceinline__ void lds_barrier() {
@@ -111,6 +112,7 @@ __device__ __forceinline__ Geo geo_of(const FusedArgs<S> &a) {
     g.mask = a.mask;
     g.inlets = a.inlets;
     g.outlets = a.outlets;
+    g.walls = a.walls;
     g.links = a.links;
     return g;
 }
@@ -181,13 +183,15 @@ __device__ __forceinline__ void sweep(const FusedArgs<S> &a, const Model<T> &mo,
     auto node = [&](int xx, int yy, int zz) {
         return int64_t(xx) + int64_t(a.nx) * (int64_t(yy) + int64_t(a.ny) * zz);
     };
-    // LDS psi of a non-fluid node: the inlet's phase value, or the sentinel
-    // that the gradient replaces by the centre node's own psi
+    // LDS psi of a non-fluid node: the inlet's or the wetting wall's phase
+    // value, or the sentinel that the gradient replaces by the centre node's
+    // own psi
     auto solid_psi = [&](uint8_t c) -> float {
-        if (c >= kInlet0 && c < kOutlet0) {
+        if (is_inlet(c)) {
             const DevInlet in = a.inlets[c - kInlet0];
             return float((in.rhoR - in.rhoB) / (in.rhoR + in.rhoB));
         }
+        if (c >= kWall0 && c < kOutlet0) return float(a.walls[c - kWall0].psi);
         return kSentinel;
     };
     auto fluid = [&](uint32_t lk) { return !MASKED || (lk & kLinkFluid) != 0u; };
@@ -469,6 +473,7 @@ FusedArgs<S> fused_args(const Geo &g, const void *in, void *out, const uint32_t 
     a.mask = g.mask;
     a.inlets = g.inlets;
     a.outlets = g.outlets;
+    a.walls = g.walls;
     a.links = g.links;
     a.ntx = (g.nx + kTX - 1) / kTX;
     a.nty = (g.ny + sh.rows - 1) / sh.rows;

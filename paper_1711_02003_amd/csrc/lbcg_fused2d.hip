@@ -38,6 +38,7 @@ struct Fused2dArgs {
     const uint8_t *mask;       // nullptr = every node fluid
     const DevInlet *inlets;
     const DevOutlet *outlets;
+    const DevWall *walls;
     const uint32_t *links;     // link words (with a mask)
     const uint32_t *ctr_in;
     uint32_t *ctr_out;
@@ -111,13 +112,15 @@ __device__ __forceinline__ void sweep2d(const Fused2dArgs<S> &a, const Model<flo
     auto wrapy = [&](int yy) { return yy < 0 ? yy + a.ny : (yy >= a.ny ? yy - a.ny : yy); };
     auto link = [&](int xx, int yy) { return MASKED ? a.links[int64_t(xx) + int64_t(a.nx) * wrapy(yy)] : kLinkFluid; };
     auto fluid = [&](uint32_t lk) { return !MASKED || (lk & kLinkFluid) != 0u; };
-    // LDS psi of a non-fluid node: the inlet's phase value, or the sentinel
-    // that the gradient replaces by the centre node's own psi
+    // LDS psi of a non-fluid node: the inlet's or the wetting wall's phase
+    // value, or the sentinel that the gradient replaces by the centre node's
+    // own psi
     auto solid_psi = [&](uint8_t c) -> float {
-        if (c >= kInlet0 && c < kOutlet0) {
+        if (is_inlet(c)) {
             const DevInlet in = a.inlets[c - kInlet0];
             return float((in.rhoR - in.rhoB) / (in.rhoR + in.rhoB));
         }
+        if (c >= kWall0 && c < kOutlet0) return float(a.walls[c - kWall0].psi);
         return kSentinel2d;
     };
 
@@ -254,6 +257,7 @@ __device__ __forceinline__ void sweep2d(const Fused2dArgs<S> &a, const Model<flo
                 g.mask = a.mask;
                 g.inlets = a.inlets;
                 g.outlets = a.outlets;
+                g.walls = a.walls;
                 g.links = a.links;
                 const uint32_t yg[3] = {uint32_t(uniform(y == 0 ? a.ny - 1 : y - 1)) * row, yo,
                                         uint32_t(uniform(y == a.ny - 1 ? 0 : y + 1)) * row};
@@ -319,6 +323,7 @@ static hipError_t launch2d(const Geo &g, const ModelD &md, const void *in, void 
     a.mask = g.mask;
     a.inlets = g.inlets;
     a.outlets = g.outlets;
+    a.walls = g.walls;
     a.links = g.links;
     a.ctr_in = ctr_in;
     a.ctr_out = ctr_out;

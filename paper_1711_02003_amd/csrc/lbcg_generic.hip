@@ -74,7 +74,8 @@ __global__ void __launch_bounds__(kBlock) k_psi(Geo g, Model<T> mo, const S *__r
 }
 
 // Colour gradient F = (1/c_s^2) sum_i w_i c_i psi~(x + c_i), psi~ = psi at fluid
-// neighbours, the inlet's phase value at inlets, psi(x) at walls and outlets.
+// neighbours, the inlet's phase value at inlets, the wall's phase value at
+// wetting walls, psi(x) at neutral walls and outlets.
 template <class L, typename T>
 __device__ __forceinline__ void gradient(const Geo &g, const T *__restrict__ psi, int x, int y, int z,
                                          int64_t n, T F[3]) {
@@ -90,10 +91,12 @@ __device__ __forceinline__ void gradient(const Geo &g, const T *__restrict__ psi
         T p;
         if (code == kFluid)
             p = psi[m];
-        else if (code >= kInlet0 && code < kOutlet0) {
+        else if (is_inlet(code)) {
             const DevInlet in = g.inlets[code - kInlet0];
             p = T((in.rhoR - in.rhoB) / (in.rhoR + in.rhoB));
-        } else
+        } else if (code >= kWall0 && code < kOutlet0)
+            p = T(g.walls[code - kWall0].psi);
+        else
             p = pc;
         const T wp = T(3.0 * wgt<L>(i)) * p;
         if (L::cx[i]) fx += L::cx[i] > 0 ? wp : -wp;
@@ -214,43 +217,74 @@ __global__ void __launch_bounds__(kBlock) k_pops_at(Geo g, Model<T> mo, const S 
     }
 }
 
-// Diagnostics partials: per block, values summed over a fixed node order,
-// then reduced in the block by a fixed tree; the final pass sums the block
-// partials sequentially.  Layout of the 13 values: mass_R, mass_B, mom x y z,
-// max|u|, sum p (psi > 0.99), n_in, sum p (psi < -0.99), n_out, vol_R,
-// nonfinite, fluid nodes.
+// Diagnostics.  Each fluid node's colour populations are decoded exactly as
+// the population export decodes them (each colour part formed in the compute
+// type, then widened to FP64), and its moments are summed in FP64 in
+// direction order without fused multiply-adds: rho^k = sum_i f_i^k (Eq. (2)),
+// rho u = sum_i (f_i^R + f_i^B) c_i (Eq. (3)), psi, |u| and the Eq. (8)
+// pressure sum_k phat_k rho^k.  A node whose densities or momentum are not
+// finite is counted and left out of the other sums.  The reduction is fixed:
+// each thread sums its grid-stride nodes in node order, a wave combines its
+// 64 lanes by a butterfly of cross-lane exchanges, the block's waves are
+// added in wave order, and a second kernel reduces the block partials the
+// same way, so a lattice's diagnostics are bitwise reproducible.  Layout of
+// the 13 values: mass_R, mass_B, mom x y z, max|u|, sum p (psi > 0.99),
+// n_in, sum p (psi < -0.99), n_out, vol_R, nonfinite, fluid nodes.
+constexpr int kDiagMax = 5;  // the one value reduced by max (max |u|)
+
+__device__ __forceinline__ double wave_reduce(double v, bool is_max) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const double o = __shfl_xor(v, off, 64);
+        v = is_max ? fmax(v, o) : v + o;
+    }
+    return v;
+}
+
+// pR, pB: phat_k = sum_i phi_i^k c_ix^2 in FP64 (from the FP64 alpha_k, not
+// the compute type's).
 template <class L, typename S, typename T>
 __global__ void __launch_bounds__(kBlock) k_diag(Geo g, Model<T> mo, const S *__restrict__ st, bool pulled,
-                                                 double *__restrict__ partials) {
-    __shared__ double red[kDiagVals][kBlock];
+                                                 double pR, double pB, double *__restrict__ partials) {
+#pragma clang fp contract(off)
+    __shared__ double red[kBlock / 64][kDiagVals];
     double acc[kDiagVals];
 #pragma unroll
     for (int q = 0; q < kDiagVals; ++q) acc[q] = 0.0;
-    const double pR = double(phat<L, T>(mo.aR)), pB = double(phat<L, T>(mo.aB));
     for (int64_t n = int64_t(blockIdx.x) * kBlock + threadIdx.x; n < g.N; n += int64_t(gridDim.x) * kBlock) {
         if (code_at(g, n) != kFluid) continue;
         int x, y, z;
         node_xyz(g, n, x, y, z);
         Pops<L, T> p;
         pull_node<L, S, T>(g, mo, st, x, y, z, n, pulled, p);
-        Mom<T> m;
-        moments<L, T>(p, m);
-        const double rho = 1.0 + double(m.drho);
-        const double r0 = double(m.r36R / T(36)), r1 = double(m.r36B / T(36));
-        const double jx = double(m.j[0]), jy = double(m.j[1]), jz = double(m.j[2]);
+        double r0 = 0.0, r1 = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i) {
+            const T f = T(wgt<L>(i)) + p.df[i];
+            const T r = p.fred(i);
+            const double fr = double(r), fb = double(f - r);
+            r0 += fr;
+            r1 += fb;
+            const double ft = fr + fb;
+            jx += ft * double(L::cx[i]);
+            jy += ft * double(L::cy[i]);
+            jz += ft * double(L::cz[i]);
+        }
         acc[12] += 1.0;
-        if (!(isfinite(rho) && isfinite(r0) && isfinite(r1) && isfinite(jx) && isfinite(jy) && isfinite(jz))) {
+        if (!(isfinite(r0) && isfinite(r1) && isfinite(jx) && isfinite(jy) && isfinite(jz))) {
             acc[11] += 1.0;
             continue;
         }
-        const double psi = double(psi_of<T>(m.drho, m.r36R, m.r36B));
+        const double rho = r0 + r1;
+        const double psi = (r0 - r1) / rho;
+        const double speed = sqrt(jx * jx + jy * jy + jz * jz) / rho;
         const double pres = pR * r0 + pB * r1;  // Eq. (8)
         acc[0] += r0;
         acc[1] += r1;
         acc[2] += jx;
         acc[3] += jy;
         acc[4] += jz;
-        acc[5] = fmax(acc[5], sqrt(jx * jx + jy * jy + jz * jz) / rho);
+        acc[5] = fmax(acc[5], speed);
         if (psi > 0.99) {
             acc[6] += pres;
             acc[7] += 1.0;
@@ -260,31 +294,34 @@ __global__ void __launch_bounds__(kBlock) k_diag(Geo g, Model<T> mo, const S *__
         }
         acc[10] += 0.5 * (1.0 + psi);
     }
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
 #pragma unroll
-    for (int q = 0; q < kDiagVals; ++q) red[q][threadIdx.x] = acc[q];
-    __syncthreads();
-    for (int s = kBlock / 2; s > 0; s >>= 1) {
-        if (threadIdx.x < s) {
-#pragma unroll
-            for (int q = 0; q < kDiagVals; ++q) {
-                const double a = red[q][threadIdx.x], b = red[q][threadIdx.x + s];
-                red[q][threadIdx.x] = q == 5 ? fmax(a, b) : a + b;
-            }
-        }
-        __syncthreads();
+    for (int q = 0; q < kDiagVals; ++q) {
+        const double v = wave_reduce(acc[q], q == kDiagMax);
+        if (lane == 0) red[wave][q] = v;
     }
-    if (threadIdx.x < kDiagVals) partials[blockIdx.x * kDiagVals + threadIdx.x] = red[threadIdx.x][0];
+    __syncthreads();
+    if (threadIdx.x < kDiagVals) {
+        const int q = threadIdx.x;
+        double a = red[0][q];
+        for (int w = 1; w < kBlock / 64; ++w) a = q == kDiagMax ? fmax(a, red[w][q]) : a + red[w][q];
+        partials[blockIdx.x * kDiagVals + q] = a;
+    }
 }
 
-__global__ void k_diag_final(const double *__restrict__ partials, int nblocks, double *__restrict__ res) {
-    const int q = threadIdx.x;
-    if (q >= kDiagVals) return;
+// One wave per value: lane l sums partials l, l + 64, ... in order, then the
+// butterfly.
+__global__ void __launch_bounds__(64 * kDiagVals) k_diag_final(const double *__restrict__ partials, int nblocks,
+                                                              double *__restrict__ res) {
+    const int q = threadIdx.x / 64, lane = threadIdx.x % 64;
+    const bool is_max = q == kDiagMax;
     double a = 0.0;
-    for (int b = 0; b < nblocks; ++b) {
+    for (int b = lane; b < nblocks; b += 64) {
         const double v = partials[b * kDiagVals + q];
-        a = q == 5 ? fmax(a, v) : a + v;
+        a = is_max ? fmax(a, v) : a + v;
     }
-    res[q] = a;
+    a = wave_reduce(a, is_max);
+    if (lane == 0) res[q] = a;
 }
 
 // ---------------------------------------------------------------- dispatch
@@ -360,11 +397,12 @@ template <class L, typename S, typename T>
 struct RunDiag {
     static hipError_t run(const Geo &g, const ModelD &md, const void *st, bool pulled, double *partials,
                           double *res, hipStream_t s) {
+        const double pR = phat<L, double>(md.aR), pB = phat<L, double>(md.aB);
         hipLaunchKernelGGL((k_diag<L, S, T>), dim3(kDiagBlocks), dim3(kBlock), 0, s, g, to_model<T>(md),
-                           static_cast<const S *>(st), pulled, partials);
+                           static_cast<const S *>(st), pulled, pR, pB, partials);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(64), 0, s, partials, kDiagBlocks, res);
+        hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(64 * kDiagVals), 0, s, partials, kDiagBlocks, res);
         return hipGetLastError();
     }
 };

@@ -12,7 +12,8 @@ namespace lbcg {
 struct ModelD {
     double ivR, ivB, Abar, beta, aR, aB, eps_F;  // ivR, ivB: 1/nu_k
     double w0;  // rest weight of the lattice
-    int bgk;
+    double omR, omB;  // 1/tau_k
+    int bgk;    // 0 regularized, 1 BGK at the node's rate, 2 BGK per colour
 };
 
 template <typename T>
@@ -29,6 +30,8 @@ inline Model<T> to_model(const ModelD &m) {
     r.kR = T((m.w0 - m.aR) / (1.0 - m.w0));
     r.kB = T((m.w0 - m.aB) / (1.0 - m.w0));
     r.eps_F = T(m.eps_F);
+    r.omR = T(m.omR);
+    r.omB = T(m.omB);
     r.bgk = m.bgk;
     return r;
 }
@@ -36,7 +39,7 @@ inline Model<T> to_model(const ModelD &m) {
 // Number of doubles per block in the diagnostics partials.
 constexpr int kDiagVals = 13;
 // Blocks of the diagnostics reduction (partials = kDiagBlocks * kDiagVals).
-constexpr int kDiagBlocks = 512;
+constexpr int kDiagBlocks = 1024;
 
 // lattice: 0 = D2Q9, 1 = D3Q19; prec: 0 = F64, 1 = F32, 2 = F16.
 // Equilibrium state (Eq. (6)) of nodes [n0, n0 + cnt) from chunk-local fields
@@ -79,6 +82,7 @@ struct FusedArgs {
     const uint8_t *mask;  // nullptr = every node fluid
     const DevInlet *inlets;
     const DevOutlet *outlets;
+    const DevWall *walls;
     const uint32_t *links;   // link words (with a mask)
     const uint32_t *ctr_in;  // time-step counter of this step
     uint32_t *ctr_out;       // receives ctr_in + 1

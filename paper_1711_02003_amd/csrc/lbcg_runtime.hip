@@ -28,14 +28,15 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 struct Plan {
     int Q;
     int64_t N, pitch, staging_nodes;
-    size_t elem, tsize, state, cstate, psi, mask, links, inl, outl, partials, diag, ctr, staging, total;
+    size_t elem, tsize, state, cstate, psi, mask, links, inl, outl, wall, partials, diag, ctr, staging, total;
 };
 
 int validate(const lbcg_params *p) {
     if (!p) return LBCG_E_INVAL;
     if (p->lattice != LBCG_D2Q9 && p->lattice != LBCG_D3Q19) return LBCG_E_INVAL;
     if (p->precision < LBCG_F64 || p->precision > LBCG_F16) return LBCG_E_INVAL;
-    if (p->collision != LBCG_REGULARIZED && p->collision != LBCG_BGK) return LBCG_E_INVAL;
+    if (p->collision != LBCG_REGULARIZED && p->collision != LBCG_BGK && p->collision != LBCG_BGK_COLOUR)
+        return LBCG_E_INVAL;
     if (p->kernel < LBCG_KERNEL_AUTO || p->kernel > LBCG_KERNEL_COMPACT) return LBCG_E_INVAL;
     for (int a = 0; a < 3; ++a)
         if (p->dims[a] < 1 || p->dims[a] > (int64_t(1) << 20)) return LBCG_E_INVAL;
@@ -47,9 +48,14 @@ int validate(const lbcg_params *p) {
     if (!std::isfinite(p->A_R) || !std::isfinite(p->A_B) || !std::isfinite(p->beta)) return LBCG_E_INVAL;
     if (p->beta < 0.0 || p->beta > 1.0) return LBCG_E_INVAL;
     if (p->alpha_R < 0.0 || p->alpha_R >= 1.0 || p->alpha_B < 0.0 || p->alpha_B >= 1.0) return LBCG_E_INVAL;
-    if (p->n_inlets < 0 || p->n_inlets > 126 || p->n_outlets < 0 || p->n_outlets > 128) return LBCG_E_INVAL;
+    if (p->n_inlets < 0 || p->n_inlets > LBCG_WALL0 - LBCG_INLET0 || p->n_outlets < 0 || p->n_outlets > 128 ||
+        p->n_walls < 0 || p->n_walls > LBCG_OUTLET0 - LBCG_WALL0)
+        return LBCG_E_INVAL;
     if (p->n_inlets > 0 && !p->inlets) return LBCG_E_INVAL;
     if (p->n_outlets > 0 && !p->outlets) return LBCG_E_INVAL;
+    if (p->n_walls > 0 && !p->walls) return LBCG_E_INVAL;
+    for (int j = 0; j < p->n_walls; ++j)
+        if (!(p->walls[j].psi >= -1.0 && p->walls[j].psi <= 1.0)) return LBCG_E_INVAL;
     for (int j = 0; j < p->n_inlets; ++j) {
         const lbcg_inlet &in = p->inlets[j];
         if (!(in.rho_R >= 0.0) || !(in.rho_B >= 0.0) || !(in.rho_R + in.rho_B > 0.0)) return LBCG_E_INVAL;
@@ -62,7 +68,8 @@ int validate(const lbcg_params *p) {
     if (p->mask) {
         for (int64_t n = 0; n < N; ++n) {
             const int m = p->mask[n];
-            if (m >= LBCG_INLET0 && m < LBCG_OUTLET0 && m - LBCG_INLET0 >= p->n_inlets) return LBCG_E_INVAL;
+            if (m >= LBCG_INLET0 && m < LBCG_WALL0 && m - LBCG_INLET0 >= p->n_inlets) return LBCG_E_INVAL;
+            if (m >= LBCG_WALL0 && m < LBCG_OUTLET0 && m - LBCG_WALL0 >= p->n_walls) return LBCG_E_INVAL;
             if (m >= LBCG_OUTLET0 && m - LBCG_OUTLET0 >= p->n_outlets) return LBCG_E_INVAL;
         }
     }
@@ -93,12 +100,13 @@ Plan make_plan(const lbcg_params *p) {
     pl.links = p->mask ? align_up(sizeof(uint32_t) * size_t(pl.pitch), kAlign) : 0;
     pl.inl = align_up(sizeof(DevInlet) * size_t(p->n_inlets > 0 ? p->n_inlets : 1), kAlign);
     pl.outl = align_up(sizeof(DevOutlet) * size_t(p->n_outlets > 0 ? p->n_outlets : 1), kAlign);
+    pl.wall = align_up(sizeof(DevWall) * size_t(p->n_walls > 0 ? p->n_walls : 1), kAlign);
     pl.partials = align_up(sizeof(double) * kDiagBlocks * kDiagVals, kAlign);
     pl.diag = align_up(sizeof(double) * 16, kAlign);
     pl.ctr = kAlign;
     pl.staging = align_up(sizeof(double) * size_t(per) * size_t(pl.staging_nodes), kAlign);
-    pl.total = 2 * pl.state + 2 * pl.cstate + pl.psi + pl.mask + pl.links + pl.inl + pl.outl + pl.partials + pl.diag + pl.ctr +
-               pl.staging + kAlign;
+    pl.total = 2 * pl.state + 2 * pl.cstate + pl.psi + pl.mask + pl.links + pl.inl + pl.outl + pl.wall + pl.partials +
+               pl.diag + pl.ctr + pl.staging + kAlign;
     return pl;
 }
 
@@ -336,7 +344,9 @@ int lbcg_create(const lbcg_params *p, void *dev_buf, size_t bytes, void *hip_str
     s->md.aB = p->alpha_B > 0.0 ? p->alpha_B : w0;
     s->md.eps_F = p->eps_F < 0.0 ? 1e-8 : p->eps_F;
     s->md.w0 = w0;
-    s->md.bgk = p->collision == LBCG_BGK;
+    s->md.omR = 1.0 / p->tau_R;
+    s->md.omB = 1.0 / p->tau_B;
+    s->md.bgk = p->collision == LBCG_BGK ? 1 : (p->collision == LBCG_BGK_COLOUR ? 2 : 0);
 
     if (dev_buf) {
         s->arena = dev_buf;
@@ -370,6 +380,8 @@ int lbcg_create(const lbcg_params *p, void *dev_buf, size_t bytes, void *hip_str
     base += pl.inl;
     s->out_dev = reinterpret_cast<DevOutlet *>(base);
     base += pl.outl;
+    DevWall *wall_dev = reinterpret_cast<DevWall *>(base);
+    base += pl.wall;
     s->partials = reinterpret_cast<double *>(base);
     base += pl.partials;
     s->diag = reinterpret_cast<double *>(base);
@@ -396,6 +408,7 @@ int lbcg_create(const lbcg_params *p, void *dev_buf, size_t bytes, void *hip_str
     s->g.mask = s->mask_dev;
     s->g.inlets = s->in_dev;
     s->g.outlets = s->out_dev;
+    s->g.walls = wall_dev;
     s->g.links = links_dev;
     std::vector<DevInlet> ins(size_t(p->n_inlets > 0 ? p->n_inlets : 1));
     for (int j = 0; j < p->n_inlets; ++j) {
@@ -405,11 +418,15 @@ int lbcg_create(const lbcg_params *p, void *dev_buf, size_t bytes, void *hip_str
     }
     std::vector<DevOutlet> outs(size_t(p->n_outlets > 0 ? p->n_outlets : 1));
     for (int j = 0; j < p->n_outlets; ++j) outs[j].rho = p->outlets[j].rho;
+    std::vector<DevWall> wls(size_t(p->n_walls > 0 ? p->n_walls : 1), DevWall{0.0});
+    for (int j = 0; j < p->n_walls; ++j) wls[j].psi = p->walls[j].psi;
     hipError_t e = hipMemcpyAsync(s->in_dev, ins.data(), sizeof(DevInlet) * ins.size(), hipMemcpyHostToDevice,
                                   s->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(s->out_dev, outs.data(), sizeof(DevOutlet) * outs.size(), hipMemcpyHostToDevice,
                            s->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(wall_dev, wls.data(), sizeof(DevWall) * wls.size(), hipMemcpyHostToDevice, s->stream);
     if (e == hipSuccess && p->mask)
         e = hipMemcpyAsync(s->mask_dev, p->mask, size_t(pl.N), hipMemcpyHostToDevice, s->stream);
     std::vector<uint32_t> links;
@@ -728,16 +745,29 @@ int lbcg_tune(lbcg_sim *s, int32_t *rows, int32_t *zchunks) {
             (void)hipEventDestroy(e0);
             return LBCG_E_DEVICE;
         }
-        // the compact kernel reads the compact state (or the pair state before
-        // its first step) and writes the other compact buffer
-        const bool pair_in = cmp && !s->compact;
-        const void *in = cmp && s->compact ? s->cbuf[s->cur] : s->buf[s->cur];
-        void *out = cmp ? s->cbuf[s->cur ^ 1] : s->buf[s->cur ^ 1];
-        // the counter slot written is the one the next step writes too
+        // The compact kernel is timed as every later step runs it: reading a
+        // compact state.  Before the handle's first compact step (the state is
+        // still the pair state in buf[cur]) one first-step launch converts the
+        // state into the spare compact buffer cbuf[cur ^ 1], and the candidates
+        // step that copy into cbuf[cur], which the handle does not use until its
+        // own first compact step writes it.  Either way the current state is
+        // left as it is.  The counter slot written is the one the next step
+        // writes too.
         const uint32_t *ctr_in = s->ctr + s->cur;
         uint32_t *ctr_out = s->ctr + (s->cur ^ 1);
+        const void *in = s->buf[s->cur];
+        void *out = s->buf[s->cur ^ 1];
+        if (cmp) {
+            in = s->cbuf[s->cur];
+            out = s->cbuf[s->cur ^ 1];
+            if (!s->compact) {
+                HIP_TRY(launch_compact(s, s->buf[s->cur], true, s->cbuf[s->cur ^ 1], ctr_in, ctr_out, s->shape));
+                in = s->cbuf[s->cur ^ 1];
+                out = s->cbuf[s->cur];
+            }
+        }
         auto run = [&](const FusedShape &c) {
-            return cmp ? launch_compact(s, in, pair_in, out, ctr_in, ctr_out, c)
+            return cmp ? launch_compact(s, in, false, out, ctr_in, ctr_out, c)
                        : launch_fused(s, in, out, ctr_in, ctr_out, c);
         };
         // Two passes over the candidates, each keeping its faster time: in a

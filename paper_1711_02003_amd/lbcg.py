@@ -21,7 +21,8 @@ LIB_PATH = os.environ.get("LBCG_LIBRARY", os.path.join(HERE, "liblbcg.so"))
 OK, E_INVAL, E_NOMEM, E_DEVICE, E_UNSTABLE, E_STATE = 0, -1, -2, -3, -4, -5
 D2Q9, D3Q19 = 0, 1
 F64, F32, F16 = 0, 1, 2
-REGULARIZED, BGK = 0, 1
+REGULARIZED, BGK, BGK_COLOUR = 0, 1, 2
+INLET0, WALL0, OUTLET0 = 2, 64, 128  # mask codes: inlet j, wetting wall j, outlet j
 KERNEL_AUTO, KERNEL_GENERIC, KERNEL_FUSED, KERNEL_COMPACT = 0, 1, 2, 3
 PRECISIONS = {"f64": F64, "f32": F32, "f16": F16}
 LATTICES = {"D2Q9": D2Q9, "D3Q19": D3Q19}
@@ -41,6 +42,10 @@ class _Outlet(C.Structure):
     _fields_ = [("rho", C.c_double)]
 
 
+class _Wall(C.Structure):
+    _fields_ = [("psi", C.c_double)]
+
+
 class _Params(C.Structure):
     _fields_ = [
         ("lattice", C.c_int32), ("precision", C.c_int32), ("collision", C.c_int32),
@@ -48,7 +53,8 @@ class _Params(C.Structure):
         ("tau_R", C.c_double), ("tau_B", C.c_double), ("A_R", C.c_double), ("A_B", C.c_double),
         ("beta", C.c_double), ("alpha_R", C.c_double), ("alpha_B", C.c_double),
         ("eps_F", C.c_double), ("n_inlets", C.c_int32), ("n_outlets", C.c_int32),
-        ("inlets", C.POINTER(_Inlet)), ("outlets", C.POINTER(_Outlet)), ("tile", C.c_int32 * 3),
+        ("inlets", C.POINTER(_Inlet)), ("outlets", C.POINTER(_Outlet)),
+        ("n_walls", C.c_int32), ("walls", C.POINTER(_Wall)), ("tile", C.c_int32 * 3),
     ]
 
 
@@ -144,9 +150,14 @@ class Outlet:
     rho: float = 1.0
 
 
+@dataclass
+class Wall:
+    psi: float = 0.0  # phase value the colour gradient sees at a wetting wall
+
+
 def make_params(lattice, dims, tau_R, tau_B, A_R, A_B, beta, precision=F32, collision=REGULARIZED,
                 kernel=KERNEL_AUTO, mask=None, inlets=(), outlets=(), alpha_R=0.0, alpha_B=0.0,
-                eps_F=-1.0, tile=(0, 0, 0)):
+                eps_F=-1.0, tile=(0, 0, 0), walls=()):
     """Build the C parameter block; returns (params, keep-alive list)."""
     p = _Params()
     p.lattice = LATTICES.get(lattice, lattice)
@@ -169,9 +180,14 @@ def make_params(lattice, dims, tau_R, tau_B, A_R, A_B, beta, precision=F32, coll
     for j, o in enumerate(outlets):
         d = o if isinstance(o, dict) else o.__dict__
         outs[j].rho = float(d["rho"])
-    keep += [ins, outs]
+    wls = (_Wall * max(1, len(walls)))()
+    for j, wl in enumerate(walls):
+        d = wl if isinstance(wl, dict) else wl.__dict__
+        wls[j].psi = float(d["psi"])
+    keep += [ins, outs, wls]
     p.n_inlets, p.inlets = len(inlets), ins
     p.n_outlets, p.outlets = len(outlets), outs
+    p.n_walls, p.walls = len(walls), wls
     p.tile[:] = [int(t) for t in tile]
     return p, keep
 
@@ -201,7 +217,7 @@ class Sim:
     def __init__(self, lattice="D3Q19", dims=(64, 64, 64), tau_R=1.0, tau_B=1.0, A=0.01,
                  beta=0.7, precision="f32", collision=REGULARIZED, kernel=KERNEL_AUTO, mask=None,
                  inlets=(), outlets=(), alpha_R=0.0, alpha_B=0.0, eps_F=-1.0, A_B=None,
-                 tile=(0, 0, 0), use_torch=True, stream=None, dev_buf=None):
+                 tile=(0, 0, 0), use_torch=True, stream=None, dev_buf=None, walls=()):
         self._lib = load_library()
         self.lattice = LATTICES.get(lattice, lattice)
         self.Q = 9 if self.lattice == D2Q9 else 19
@@ -210,7 +226,7 @@ class Sim:
         self.precision = PRECISIONS.get(precision, precision)
         self.params, self._keep = make_params(
             self.lattice, self.dims, tau_R, tau_B, A, A if A_B is None else A_B, beta,
-            self.precision, collision, kernel, mask, inlets, outlets, alpha_R, alpha_B, eps_F, tile)
+            self.precision, collision, kernel, mask, inlets, outlets, alpha_R, alpha_B, eps_F, tile, walls)
         self.footprint = footprint(self.params)
         self._buf = None
         dev_ptr, strm = None, stream
@@ -234,7 +250,7 @@ class Sim:
     @classmethod
     def from_workload(cls, w, precision="f32", kernel=KERNEL_AUTO, **kw):
         s = cls(w.lattice, w.dims, w.tau_R, w.tau_B, w.A, w.beta, precision, kernel=kernel,
-                mask=w.mask, inlets=w.inlets, outlets=w.outlets, **kw)
+                mask=w.mask, inlets=w.inlets, outlets=w.outlets, walls=getattr(w, "walls", ()), **kw)
         s.init_fields(w.rhoR, w.rhoB, w.u)
         return s
 

@@ -122,8 +122,11 @@ class Server:
         self.sleep = sleep
         self.keep_results = keep_results
         self.log: List[tuple] = []  # (time, event, request id)
+        # per admitted request: the steps done so far by each request already
+        # running when it joined (shows requests joining part-way through others)
+        self.joined_with: dict = {}
 
-    def _admit(self, r: Request, now: float) -> bool:
+    def _admit(self, r: Request, now: float, running=()) -> bool:
         w = r.make()
         fp = self.backend.footprint(w)
         if fp > self.arena.capacity:
@@ -135,6 +138,7 @@ class Server:
         r.handle = self.backend.create(w, off, fp)
         r.nodes = int(w.fluid_nodes)
         r.t_admit = now
+        self.joined_with[r.id] = {o.id: (o.done_steps, o.steps) for o in running}
         self.log.append((now, "admit", r.id))
         return True
 
@@ -151,7 +155,7 @@ class Server:
             while queue and queue[0].arrival <= now:
                 if self.max_running and len(running) >= self.max_running:
                     break
-                if not self._admit(queue[0], now):
+                if not self._admit(queue[0], now, running):
                     break
                 running.append(queue.pop(0))
             if not running:

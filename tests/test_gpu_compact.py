@@ -68,6 +68,33 @@ def test_compact_config2_recipe_1000_steps(L, orc):
         assert v < 1e-6, (k, v)
 
 
+@pytest.mark.timeout(900)
+def test_compact_config2_recipe_128_1000_steps(L, orc):
+    # The 27-droplet recipe at 128^3 (two full 64-wide x tiles, 16 row tiles)
+    # on the compact kernel in its tuned launch shape, as the benchmark runs
+    # it, after 1000 steps against the FP64 oracle: rel-L2 of psi within 1e-5;
+    # of u within 1e-5 floored at 1e-4 sqrt(N) (the initial N(0, 1e-3)
+    # velocities have decayed to ~1e-5 rms by then, and FP32 forms u to
+    # ~2e-10 absolute from momentum sums that cancel, so the plain ratio
+    # measures that floor: 2.4e-5 here, bounded by 1e-4).
+    w = W.config2(L=128, seed=2)
+    _say("compact f32 128^3 x1000 (tuned shape)")
+    s = L.Sim.from_workload(w, precision="f32", kernel=L.KERNEL_COMPACT)
+    s.step(1)
+    shape = s.tune()
+    _say(f"  tuned shape {shape}")
+    s.step(999)
+    g = s.fields()
+    s.close()
+    o = oracle_for(orc, w, threads=16).step(1000)
+    f = o.fields()
+    eu, ep = rel_l2(g["u"], f["u"]), rel_l2(g["psi"], f["psi"])
+    euf = rel_l2(g["u"], f["u"], floor=1e-4 * np.sqrt(w.nodes))
+    _say(f"  relL2 u {eu:.3e} (floored {euf:.3e}) psi {ep:.3e} (|u|_rms {np.sqrt((f['u'] ** 2).mean()):.2e})")
+    assert euf < 1e-5 and eu < 1e-4
+    assert ep < 1e-5
+
+
 def test_compact_density_ratio_slab(L, orc):
     # alpha_R = 0.55 != alpha_B: the colour equilibria differ per colour, so
     # the scalars' class amplitudes carry the phi_i^k terms.  The bulk ratio

@@ -7,6 +7,9 @@ bitwise the result of stepping it alone; tuning leaves the state untouched;
 FP16 storage stays within 1 % of FP32 on the droplet radius and Laplace
 pressure.
 """
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -14,6 +17,8 @@ from paper_1711_02003_amd import workloads as W
 from tests.helpers import oracle_for, rel_l2
 
 pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "oracle_values.json")
 
 
 @pytest.fixture(scope="module")
@@ -149,7 +154,20 @@ def _boxes(n, seed, lo=20, hi=52):
     return ws
 
 
-def test_batch_matches_plain_bitwise(L, stream):
+def _against_oracle(orc, w, s, steps, fl=None):
+    # each lattice of a batch against the FP64 oracle run alone: phase field
+    # and velocity within the FP32 bar (rel-L2 1e-5; velocity floored at
+    # 1e-4 sqrt(N) as small u cancels)
+    fl = np.ones(w.shape, bool) if fl is None else fl
+    f = oracle_for(orc, w, threads=8).step(steps).fields()
+    g = s.fields()
+    ep = rel_l2(g["psi"][fl], f["psi"][fl])
+    eu = rel_l2(g["u"][:, fl], f["u"][:, fl], floor=1e-4 * np.sqrt(fl.sum()))
+    _say(f"  {w.name} {w.dims} x{steps} vs oracle: relL2 psi {ep:.2e} u {eu:.2e}")
+    assert ep < 1e-5 and eu < 1e-5, (w.name, ep, eu)
+
+
+def test_batch_matches_plain_bitwise(L, orc, stream):
     ws = _boxes(5, seed=11) + [_small_focusing()]
     nsteps = [150, 33, 5, 0, 100, 40]  # runs of >= 32 levels replay graphs
     sims = [L.Sim.from_workload(w, precision="f32", stream=stream.cuda_stream) for w in ws]
@@ -166,6 +184,7 @@ def test_batch_matches_plain_bitwise(L, stream):
         fl = np.ones(w.shape, bool) if w.mask is None else w.mask == 0
         assert np.array_equal(s.populations()[..., fl], ref.populations()[..., fl]), w.name
         assert s.diagnostics()["step"] == 1 + n
+        _against_oracle(orc, w, s, 1 + n, fl)
     # second call with a different order of step counts and an explicit shape
     b.close()
     b2 = L.Batch(sims, tile=(4, 16))
@@ -191,7 +210,7 @@ def test_batch_fresh_handles_and_f16(L, stream):
         assert np.array_equal(s.populations(), ref.populations()), w.name
 
 
-def test_batch_compact_matches_plain_bitwise(L, stream):
+def test_batch_compact_matches_plain_bitwise(L, orc, stream):
     # compact-state lattices batched: each lattice bitwise as stepped alone;
     # fresh handles and restored ones take their pair-state steps alone first
     ws = _boxes(4, seed=14)
@@ -209,6 +228,7 @@ def test_batch_compact_matches_plain_bitwise(L, stream):
         ref.step(pre + n)
         assert np.array_equal(s.populations(), ref.populations()), w.name
         assert s.diagnostics()["step"] == pre + n
+        _against_oracle(orc, w, s, pre + n)
     sims[1].set_state(sims[1].get_state())
     b.step([0, 40, 0, 0])
     ref = L.Sim.from_workload(ws[1], precision="f32", kernel=L.KERNEL_COMPACT)
@@ -249,10 +269,33 @@ def test_tune_keeps_state(L):
     assert np.array_equal(a.populations(), b.populations())
 
 
+@pytest.mark.parametrize("before", [0, 1, 2, 5])
+def test_tune_keeps_state_compact(L, before):
+    # The compact kernel is tuned on a compact state whether or not the
+    # handle has taken its first compact step (0 or 1 steps: still the pair
+    # state), and the trajectory does not change.
+    w = W.config2(L=64, seed=3)
+    a = L.Sim.from_workload(w, precision="f32", kernel=L.KERNEL_COMPACT)
+    a.step(before)
+    p0 = a.populations()
+    shape = a.tune()
+    _say(f"compact tuned after {before} steps: {shape}")
+    assert shape["rows"] == 8 and 1 <= shape["zchunks"] <= 64
+    assert np.array_equal(a.populations(), p0)
+    a.step(37)
+    b = L.Sim.from_workload(w, precision="f32", kernel=L.KERNEL_COMPACT, tile=(8, shape["zchunks"], 0))
+    b.step(before + 37)
+    assert np.array_equal(a.populations(), b.populations())
+
+
 def test_f16_storage_droplet_within_one_percent(L):
-    # Static D3Q19 droplet 96^3, R = 20: FP16 deviation storage vs FP32 on the
+    # Static D3Q19 droplet 96^3, R = 20: FP16 deviation storage against the
+    # FP64 oracle (its R_eff and Laplace jump after the same 3000 steps,
+    # stored by tests/golden/make_oracle_values.py) and against FP32, on the
     # equivalent radius and the Laplace pressure jump after relaxation.
+    gold = json.load(open(GOLDEN))["d3q19_droplet_96_R20"]
     w = W.static_droplet_3d(n=96, R=20.0, tau=(1.0, 1.0), A=0.005, steps=3000)
+    assert gold["steps"] == w.steps
     out = {}
     for prec in ("f32", "f16"):
         s = L.Sim.from_workload(w, precision=prec)
@@ -263,9 +306,13 @@ def test_f16_storage_droplet_within_one_percent(L):
     (r32, dp32, u32), (r16, dp16, u16) = out["f32"], out["f16"]
     _say(f"R_eff f32 {r32:.4f} f16 {r16:.4f}; dp f32 {dp32:.4e} f16 {dp16:.4e}; "
          f"max|u| f32 {u32:.2e} f16 {u16:.2e}")
+    _say(f"oracle R_eff {gold['R_eff']:.4f} dp {gold['dp']:.4e}")
     assert dp32 > 0
     assert abs(r16 - r32) / r32 < 0.01
     assert abs(dp16 - dp32) / dp32 < 0.01
+    for r, dp in ((r16, dp16), (r32, dp32)):
+        assert abs(r / gold["R_eff"] - 1) < 0.01
+        assert abs(dp / gold["dp"] - 1) < 0.01
 
 
 def test_f16_storage_focusing_within_one_percent(L):

@@ -162,18 +162,20 @@ def test_config1_f64(L, orc):
     assert d1["p_in"] > d1["p_out"]
 
 
-@pytest.mark.parametrize("coll", ["reg", "bgk"])
+@pytest.mark.parametrize("coll", ["reg", "bgk", "bgk_colour"])
 def test_fig1_droplet_viscosity_contrast_f64(L, orc, coll):
     # Resting D2Q9 droplet with relaxation time 5 inside and 1 outside (the
-    # Fig. 1 set-up), both collision forms: every node relaxes at the rate of
-    # its mixture viscosity.  1e-12 after 100 steps, then the velocity field
-    # of step 1000 against the oracle's.
+    # Fig. 1 set-up) in the three collision forms: regularized and BGK at the
+    # node's rate (its mixture viscosity), and BGK with each colour at its
+    # own rate.  1e-12 after 100 steps, then the velocity field of step 1000
+    # against the oracle's.
     w = W.static_droplet_2d(n=64, R=16.0, noise=0.0)
     w.tau_R, w.tau_B = 5.0, 1.0
     _say(f"fig1 droplet f64 {coll}")
-    s = L.Sim.from_workload(w, precision="f64", kernel=L.KERNEL_GENERIC,
-                            collision=L.BGK if coll == "bgk" else L.REGULARIZED)
-    o = oracle_for(orc, w, threads=8, collision=orc.BGK if coll == "bgk" else orc.REGULARIZED)
+    cl = {"reg": (L.REGULARIZED, orc.REGULARIZED), "bgk": (L.BGK, orc.BGK),
+          "bgk_colour": (L.BGK_COLOUR, orc.BGK_COLOUR)}[coll]
+    s = L.Sim.from_workload(w, precision="f64", kernel=L.KERNEL_GENERIC, collision=cl[0])
+    o = oracle_for(orc, w, threads=8, collision=cl[1])
     s.step(100)
     o.step(100)
     assert _maxrel(s.populations(), o.populations()) < 1e-12

@@ -1,0 +1,182 @@
+"""GPU parity of the wetting walls (mask codes 64 + j, the colour gradient
+sees the wall's psi_w) and of Eq. (5) with a rate per colour
+(LBCG_BGK_COLOUR), through the C ABI against the FP64 oracle.
+
+Bars: FP64 generic kernel within 1e-12 of the oracle after 100 steps; the
+fused FP32/FP16 sweeps with wetting walls bitwise the generic kernel; a
+sessile droplet on the fused FP32 sweeps within rel-L2 1e-5 of the oracle
+(phase field) and its contact angle within 0.2 degrees."""
+import numpy as np
+import pytest
+
+from paper_1711_02003_amd import workloads as W
+from tests.helpers import oracle_for, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def L():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1711_02003_amd import lbcg
+    lbcg.load_library()
+    return lbcg
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _maxrel(a, b, sel=None):
+    a, b = np.asarray(a), np.asarray(b)
+    if sel is not None:
+        a, b = a[..., sel], b[..., sel]
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+def _random(lat, dims, seed, masked, tau=(1.3, 0.7)):
+    rng = np.random.default_rng(seed)
+    nx, ny, nz = dims
+    sh = (nz, ny, nx)
+    u = rng.uniform(-0.04, 0.04, (3,) + sh)
+    if lat == "D2Q9":
+        u[2] = 0
+    w = W.Workload("random", lat, dims, rng.uniform(0.05, 1, sh), rng.uniform(0.05, 1, sh), u,
+                   tau[0], tau[1], 0.01, 0.7)
+    if masked:
+        m = np.zeros(sh, np.uint8)
+        m[:, 0, :] = 1
+        m[:, -1, :] = 64  # wetting wall 0 along the top
+        m[:, 0, 2:6] = 65          # wetting wall 1 patch in the bottom wall
+        m[:, 1:-1, 0] = 2
+        m[:, 1:-1, -1] = 128
+        if lat == "D3Q19":
+            m[0] = 65
+            m[nz // 2, ny // 2, nx // 2] = 64
+        w.mask = m
+        w.inlets = [{"u": (0.01, 0.002, 0.001 if lat == "D3Q19" else 0.0), "rho_R": 0.8, "rho_B": 0.2}]
+        w.outlets = [{"rho": 1.02}]
+        w.walls = [{"psi": 0.6}, {"psi": -0.85}]
+    return w
+
+
+@pytest.mark.parametrize("lat,dims", [("D2Q9", (17, 11, 1)), ("D3Q19", (13, 9, 7))])
+@pytest.mark.parametrize("coll", ["reg", "bgk_colour"])
+@pytest.mark.parametrize("masked", [False, True])
+def test_f64_matches_oracle(L, orc, lat, dims, coll, masked):
+    if coll == "reg" and not masked:
+        pytest.skip("covered by the plain parity tests")
+    w = _random(lat, dims, sum(dims) + 3 * masked, masked)
+    _say(f"f64 {lat} {dims} {coll} wetting walls={masked}")
+    s = L.Sim.from_workload(w, precision="f64", kernel=L.KERNEL_GENERIC,
+                            collision=L.BGK_COLOUR if coll == "bgk_colour" else L.REGULARIZED)
+    o = oracle_for(orc, w, collision=orc.BGK_COLOUR if coll == "bgk_colour" else orc.REGULARIZED)
+    fl = np.ones(w.shape, bool) if w.mask is None else w.mask == 0
+    s.step(100)
+    o.step(100)
+    d = _maxrel(s.populations(), o.populations(), fl)
+    _say(f"  max rel diff after 100 steps {d:.2e}")
+    assert d < 1e-12
+
+
+def _wetting_focusing():
+    # the quarter-size flow-focusing cross with its z walls turned into
+    # wetting walls (psi_w = +0.5 below, -0.5 above)
+    w = W.flow_focusing(nx=128, ny=48, nz=14, lam=3.0, u_disp=0.02, u_side=0.03, A=0.01)
+    m = w.mask.copy()
+    m[0][m[0] == 1] = 64
+    m[-1][m[-1] == 1] = 65
+    w.mask = m
+    w.walls = [{"psi": 0.5}, {"psi": -0.5}]
+    return w
+
+
+@pytest.mark.parametrize("prec", ["f32", "f16"])
+def test_fused_wetting_matches_generic_bitwise(L, prec):
+    w = _wetting_focusing()
+    _say(f"fused vs generic, wetting walls {w.dims} {prec}")
+    a = L.Sim.from_workload(w, precision=prec, kernel=L.KERNEL_FUSED)
+    b = L.Sim.from_workload(w, precision=prec, kernel=L.KERNEL_GENERIC)
+    assert a.launch_info()["kernel"] == L.KERNEL_FUSED
+    a.step(120)
+    b.step(120)
+    fl = w.mask == 0
+    assert np.array_equal(a.populations()[..., fl], b.populations()[..., fl])
+
+
+@pytest.mark.parametrize("prec", ["f32", "f16"])
+def test_fused2d_wetting_matches_generic_bitwise(L, prec):
+    w = W.flow_focusing_2d(256, 64)
+    m = w.mask.copy()
+    m[0, 0][m[0, 0] == 1] = 64
+    m[0, -1][m[0, -1] == 1] = 65
+    w.mask = m
+    w.walls = [{"psi": 0.7}, {"psi": -0.3}]
+    a = L.Sim.from_workload(w, precision=prec, kernel=L.KERNEL_FUSED)
+    b = L.Sim.from_workload(w, precision=prec, kernel=L.KERNEL_GENERIC)
+    a.step(60)
+    b.step(60)
+    assert np.array_equal(a.populations(), b.populations())
+
+
+def _sessile_2d(psi_w, neutral=False, nx=96, ny=40, R=14.0):
+    yy, xx = np.mgrid[0:ny, 0:nx]
+    r = np.sqrt((xx - (nx - 1) / 2) ** 2 + (yy - 0.5) ** 2)
+    psi = np.tanh((R - r) / 2)[None]
+    m = np.zeros((1, ny, nx), np.uint8)
+    m[0, 0, :] = m[0, -1, :] = 1 if neutral else 64
+    w = W.Workload("sessile_2d", "D2Q9", (nx, ny, 1), (1 + psi) / 2, (1 - psi) / 2, None, 1.0, 1.0, 0.01,
+                   0.7, mask=m)
+    w.walls = [{"psi": psi_w}]
+    return w
+
+
+def _angle_2d(psi, nx, ny):
+    c = nx // 2
+    col = (psi[1:-1, c - 1] + psi[1:-1, c]) / 2
+    h = np.interp(0.0, -col, np.arange(1, ny - 1)) - 0.5
+    b = np.interp(0.0, -psi[1, c:], np.arange(c, nx)) - (nx - 1) / 2
+    return 2 * np.degrees(np.arctan(h / b))
+
+
+@pytest.mark.parametrize("psi_w,neutral", [(0.0, True), (0.5, False), (-0.5, False)])
+def test_sessile_droplet_fused2d_vs_oracle(L, orc, psi_w, neutral):
+    w = _sessile_2d(psi_w, neutral)
+    s = L.Sim.from_workload(w, precision="f32", kernel=L.KERNEL_FUSED)
+    s.step(4000)
+    o = oracle_for(orc, w, threads=8).step(4000)
+    g, f = s.fields(), o.fields()
+    fl = w.mask == 0
+    ep = rel_l2(g["psi"][fl], f["psi"][fl])
+    ag, ao = _angle_2d(g["psi"][0], 96, 40), _angle_2d(f["psi"][0], 96, 40)
+    _say(f"sessile 2-D psi_w {psi_w} neutral={neutral}: angle gpu {ag:.2f} oracle {ao:.2f}, relL2 psi {ep:.2e}")
+    assert ep < 1e-5 and abs(ag - ao) < 0.2
+
+
+def test_sessile_droplet_fused_3d_vs_oracle(L, orc):
+    # hemisphere on a wetting floor (psi_w = +0.5) under a neutral lid,
+    # D3Q19 fused FP32 sweep, 600 steps
+    nx, ny, nz, R = 40, 36, 18, 9.0
+    zz, yy, xx = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    r = np.sqrt((xx - (nx - 1) / 2) ** 2 + (yy - (ny - 1) / 2) ** 2 + (zz - 0.5) ** 2)
+    psi = np.tanh((R - r) / 2)
+    m = np.zeros((nz, ny, nx), np.uint8)
+    m[0] = 64
+    m[-1] = 1
+    w = W.Workload("sessile_3d", "D3Q19", (nx, ny, nz), (1 + psi) / 2, (1 - psi) / 2, None, 1.0, 0.8, 0.01,
+                   0.7, mask=m)
+    w.walls = [{"psi": 0.5}]
+    s = L.Sim.from_workload(w, precision="f32", kernel=L.KERNEL_FUSED)
+    assert s.launch_info()["kernel"] == L.KERNEL_FUSED
+    s.step(600)
+    o = oracle_for(orc, w, threads=8).step(600)
+    g, f = s.fields(), o.fields()
+    fl = m == 0
+    ep = rel_l2(g["psi"][fl], f["psi"][fl])
+    eu = rel_l2(g["u"][:, fl], f["u"][:, fl])
+    _say(f"sessile 3-D: relL2 psi {ep:.2e} u {eu:.2e}")
+    assert ep < 1e-5 and eu < 1e-4
+    # the droplet spreads on the wetting floor: wider at the floor than a hemisphere
+    assert (g["psi"][1] > 0).sum() > np.pi * R * R
