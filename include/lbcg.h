@@ -292,6 +292,29 @@ int lbcg_batch_launch_info(lbcg_batch *b, int32_t *rows, int32_t *zplanes, int64
 /* Waits for the batch's queued work, then releases its tables. */
 void lbcg_batch_destroy(lbcg_batch *b);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): the batched step of
+ * lbcg_batch_step without a batch object, allocating nothing - no device or
+ * host memory, no pinned staging, no HIP graph.  Advances sims[j] by
+ * nsteps[j] >= 0 steps (n entries) with the launch shape tile = {rows per
+ * block (4 or 8; 8 on the compact kernel), z planes per chunk (>= 1)}; the
+ * requirements on the handles are those of lbcg_batch_create, and all must
+ * belong to the device current at the call.  Results per lattice are bitwise
+ * those of lbcg_batch_step and lbcg_step.
+ * The descriptors and block tables live in one fixed area of device memory
+ * that the library holds per device until the process ends (about 1.1 MB),
+ * written by small kernels queued on the handles' stream: at most
+ * LBCG_NOALLOC_MAX_LATTICES lattices per call and LBCG_NOALLOC_MAX_BLOCKS
+ * blocks per level for each of the periodic and the geometry groups; larger
+ * calls fail with LBCG_E_INVAL before queuing anything.  The area keeps the
+ * last call's contents; calls on one stream are ordered, while calls whose
+ * work overlaps on one device (different streams) race on it.  Asynchronous
+ * like lbcg_batch_step.  Errors: LBCG_E_INVAL (requirements, sizes, another
+ * device), LBCG_E_DEVICE (HIP errors). */
+#define LBCG_NOALLOC_MAX_LATTICES 256
+#define LBCG_NOALLOC_MAX_BLOCKS 65536
+int lbcg_batch_step_noalloc(lbcg_sim *const *sims, int32_t n, const int32_t *tile, const int64_t *nsteps);
+
 #ifdef __cplusplus
 }
 #endif

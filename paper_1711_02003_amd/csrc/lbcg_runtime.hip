@@ -324,6 +324,11 @@ int lbcg_create(const lbcg_params *p, void *dev_buf, size_t bytes, void *hip_str
 
     lbcg_sim *s = new (std::nothrow) lbcg_sim();
     if (!s) return LBCG_E_NOMEM;
+    if (hipGetDevice(&s->device) != hipSuccess) {
+        (void)hipGetLastError();
+        delete s;
+        return LBCG_E_DEVICE;
+    }
     s->lattice = p->lattice;
     s->prec = p->precision;
     s->collision = p->collision;

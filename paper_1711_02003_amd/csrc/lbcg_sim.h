@@ -7,6 +7,7 @@
 
 struct lbcg_sim {
     int lattice, prec, collision, kernel;
+    int device;             // HIP device current at creation
     int Q, D;
     lbcg::Geo g;
     lbcg::ModelD md;

@@ -92,7 +92,9 @@ _SIGS = {
     "lbcg_batch_step": (C.c_int, [C.c_void_p, _P(C.c_int64)]),
     "lbcg_batch_launch_info": (C.c_int, [C.c_void_p, _P(C.c_int32), _P(C.c_int32), _P(C.c_int64)]),
     "lbcg_batch_destroy": (None, [C.c_void_p]),
+    "lbcg_batch_step_noalloc": (C.c_int, [_P(C.c_void_p), C.c_int32, _P(C.c_int32), _P(C.c_int64)]),
 }
+NOALLOC_MAX_LATTICES, NOALLOC_MAX_BLOCKS = 256, 65536
 
 _lib = None
 
@@ -394,3 +396,19 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def batch_step_noalloc(sims, nsteps, tile):
+    """lbcg_batch_step_noalloc: advance sims[j] by nsteps[j] steps (an int
+    applies to every lattice) in the launch shape tile = (rows, z planes per
+    chunk), with no batch object and no allocation."""
+    lib = load_library()
+    sims = list(sims)
+    if np.isscalar(nsteps):
+        nsteps = [int(nsteps)] * len(sims)
+    n = np.ascontiguousarray(nsteps, dtype=np.int64)
+    assert n.size == len(sims)
+    arr = (C.c_void_p * len(sims))(*[s._handle().value for s in sims])
+    t = (C.c_int32 * 2)(*[int(v) for v in tile])
+    _check(lib.lbcg_batch_step_noalloc(arr, len(sims), t, n.ctypes.data_as(C.POINTER(C.c_int64))),
+           "lbcg_batch_step_noalloc")
