@@ -16,7 +16,9 @@ of every node (both colours).  Prints one JSON line:
              calibration (null when the kernel source changed since the
              counters were taken);
   cpu_baseline  the FP64 CPU oracle timed on this host on a bounded sample;
-  copy_probe achieved bandwidth of a plain device-to-device copy (context);
+  copy_probe achievable bandwidth of plain streams on this device (context):
+             hand-written copy, read-only and write-only kernels and torch's
+             device copy;
   forms      the other forms of the step, each measured on its own workload:
              pair_f32 (the same lattice on the pair-state sweep: per
              population its total and minority share), f16 (the same lattice
@@ -73,23 +75,84 @@ def read_traffic(kernel):
 
 
 def copy_probe(torch, nbytes=2 << 30, reps=10):
+    """Achievable HBM bandwidth on this device: the hand-written probes of
+    libhbmprobe.so (a copy, a read-only and a write-only stream; 8- or 16-byte
+    loads per lane, non-temporal stores; several grid sizes, best kept) and
+    torch's device copy, each on a 2 GiB buffer, timed with HIP events on the
+    stream they run on."""
+    import ctypes as C
+
+    from paper_1711_02003_amd import build as hipbuild
+    lib = C.CDLL(hipbuild.PROBE_LIB)
+    for fn in (lib.hbm_probe_copy, lib.hbm_probe_read, lib.hbm_probe_write):
+        fn.restype = C.c_int
+    lib.hbm_probe_copy.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int, C.c_int, C.c_void_p]
+    lib.hbm_probe_read.argtypes = [C.c_void_p, C.c_size_t, C.c_void_p, C.c_int, C.c_int, C.c_void_p]
+    lib.hbm_probe_write.argtypes = [C.c_void_p, C.c_size_t, C.c_int, C.c_void_p]
+    stream = torch.cuda.Stream()
     src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
+    sink = torch.zeros(2, dtype=torch.int64, device="cuda")
     src.fill_(1.0)
-    dst.copy_(src)
     torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        dst.copy_(src)
-    e1.record()
-    e1.synchronize()
-    ms = e0.elapsed_time(e1) / reps
-    del src, dst
-    return {"gbps": round(2 * nbytes / ms / 1e6, 1), "bytes_per_copy": 2 * nbytes}
+    h = stream.cuda_stream
+
+    def timed(launch):
+        for _ in range(2):
+            assert launch() == 0
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            assert launch() == 0
+        e1.record(stream)
+        e1.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    out = {"bytes": nbytes}
+    for kind, moved in (("copy", 2 * nbytes), ("read", nbytes), ("write", nbytes)):
+        best, shape = 0.0, None
+        for lane in ((8, 16) if kind != "write" else (8,)):
+            for per_cu in (4, 16, 64):
+                if kind == "copy":
+                    ms = timed(lambda: lib.hbm_probe_copy(dst.data_ptr(), src.data_ptr(), nbytes, lane, per_cu, h))
+                elif kind == "read":
+                    ms = timed(lambda: lib.hbm_probe_read(src.data_ptr(), nbytes, sink.data_ptr(), lane, per_cu, h))
+                else:
+                    ms = timed(lambda: lib.hbm_probe_write(dst.data_ptr(), nbytes, per_cu, h))
+                gbps = moved / ms / 1e6
+                if gbps > best:
+                    best, shape = gbps, {"lane_bytes": lane, "blocks_per_cu": per_cu}
+        out[kind] = {"gbps": round(best, 1), **shape}
+    with torch.cuda.stream(stream):
+        ms = timed(lambda: (dst.copy_(src), 0)[1])
+    out["torch_copy_gbps"] = round(2 * nbytes / ms / 1e6, 1)
+    out["gbps"] = out["copy"]["gbps"]
+    del src, dst, sink
+    return out
 
 
-def cpu_baseline(w, steps=16, threads=16):
+def host_info():
+    """The host the CPU baseline runs on: logical CPUs, CPU model, and the
+    CPUs this process may use."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        usable = os.cpu_count()
+    return {"nproc": os.cpu_count(), "usable_cpus": usable, "model": model,
+            "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
+
+
+def cpu_baseline(w, steps=16, threads=16, steps_1t=2):
+    """The FP64 oracle on this host: `steps` steps of the full lattice on
+    `threads` threads (the value), and `steps_1t` steps on one thread."""
     import oracle
     from tests.helpers import oracle_for
     oracle.build(force=False)
@@ -97,10 +160,18 @@ def cpu_baseline(w, steps=16, threads=16):
     t = time.time()
     o.step(steps)
     dt = time.time() - t
+    del o
+    o1 = oracle_for(oracle, w, threads=1)
+    t = time.time()
+    o1.step(steps_1t)
+    dt1 = time.time() - t
+    del o1
     return {"value": round(w.fluid_nodes * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": threads,
             "kind": "oracle",
-            "sample": f"{steps} of the workload's {w.steps} steps on the full {w.dims[0]}^3 lattice, "
-                      f"FP64, OpenMP over nodes"}
+            "sample": f"{steps} of the workload's {w.steps} steps on the full {w.dims[0]}^3 lattice on "
+                      f"{threads} threads, and {steps_1t} steps on 1 thread; FP64, OpenMP over nodes",
+            "single_thread_mlups": round(w.fluid_nodes * steps_1t / dt1 / 1e6, 3),
+            "host": host_info()}
 
 
 def time_sim(torch, sim, stream, steps, warmup):
@@ -260,38 +331,50 @@ def batched_form(torch, lbcg, W, steps=200, warmup=10, compact=False):
             "rows": info["rows"], "zplanes": info["zplanes"], "blocks": info["blocks"]}
 
 
-def served_form(torch, lbcg, W, n=32, steps_scale=0.1, load=0.8):
+def served_form(torch, lbcg, W, n=64, steps_scale=0.1, loads=(0.8, 1.5)):
+    """Config-5 stand-in: a Poisson stream of n step-emulsifier requests (the
+    config's channel and reservoir sizes, inlet speeds and seed) with step
+    counts scaled by steps_scale, through the continuous-batching server and
+    through the same server one request at a time.  The one-at-a-time capacity
+    (requests per second with every request queued at t = 0) sets the arrival
+    rate of each offered load; p50 / p99 time to result and fluid-node MLUPS
+    per load and mode."""
     from paper_1711_02003_amd import serve
     lo, hi = int(5000 * steps_scale), int(20000 * steps_scale)
 
-    def reqs(rate):
-        return serve.requests_from_stream(
-            W.served_requests(n=n, seed=5, rate=rate, steps_lo=lo, steps_hi=hi), W.step_emulsifier)
+    def reqs(rate, at_zero=False):
+        specs = W.served_requests(n=n, seed=5, rate=rate, steps_lo=lo, steps_hi=hi)
+        if at_zero:
+            specs = [dict(r, arrival=0.0) for r in specs]
+        return serve.requests_from_stream(specs, W.step_emulsifier)
 
-    probe = reqs(1.0)
     fps = []
-    for r in probe:
+    for r in reqs(1.0):
         w = r.make()
         p, _k = lbcg.make_params(w.lattice, w.dims, w.tau_R, w.tau_B, w.A, w.A, w.beta, "f32",
                                  mask=w.mask, inlets=w.inlets, outlets=w.outlets)
         fps.append(lbcg.footprint(p))
     cap = int(sum(sorted(fps)[-8:]) * 1.05)  # room for about eight requests at once
-    # plain: one request at a time (its own tuned-once shape); capacity
-    # measured with every request queued at t = 0
     one = serve.LbcgBackend(cap, precision="f32", fields=False, tune_min=1)
-    sat = serve.requests_from_stream(
-        [dict(r, arrival=0.0) for r in W.served_requests(n=n, seed=5, rate=1.0, steps_lo=lo,
-                                                          steps_hi=hi)], W.step_emulsifier)
-    st0 = serve.Server(one, cap, slice_steps=256, max_running=1, keep_results=False).run(sat)
-    rate = load * st0.completed / st0.makespan_s
-    plain = serve.Server(one, cap, slice_steps=256, max_running=1, keep_results=False).run(reqs(rate))
-    del one
-    be = serve.LbcgBackend(cap, precision="f32", fields=False)
-    served = serve.Server(be, cap, slice_steps=256, keep_results=False).run(reqs(rate))
-    return {"workload": f"{n} step-emulsifier requests (Poisson), steps U{{{lo}..{hi}}}, seed 5",
-            "arrival_rate_per_s": round(rate, 3), "offered_load": load,
-            "arena_bytes": cap, "served": served.as_dict(), "plain": plain.as_dict(),
-            "tile": list(be.tile) if be.tile else None}
+    st0 = serve.Server(one, cap, slice_steps=256, max_running=1, keep_results=False).run(reqs(1.0, True))
+    capacity = st0.completed / st0.makespan_s
+    log(f"served: one-at-a-time capacity {capacity:.2f} requests/s ({st0.as_dict()})")
+    out = {"workload": f"{n} step-emulsifier requests (Poisson), steps U{{{lo}..{hi}}}, seed 5",
+           "stand_in": f"config 5 at reduced scale: {n} of its 256 requests, step counts x {steps_scale} "
+                       f"(U{{{lo}..{hi}}} instead of U{{5000..20000}}); same channel and reservoir sizes, "
+                       "inlet speeds and arrival process",
+           "plain_capacity_per_s": round(capacity, 3), "arena_bytes": cap, "loads": {}}
+    served_be = serve.LbcgBackend(cap, precision="f32", fields=False)
+    for load in loads:
+        rate = load * capacity
+        plain = serve.Server(one, cap, slice_steps=256, max_running=1, keep_results=False).run(reqs(rate))
+        served = serve.Server(served_be, cap, slice_steps=256, keep_results=False).run(reqs(rate))
+        row = {"arrival_rate_per_s": round(rate, 3), "served": served.as_dict(), "plain": plain.as_dict(),
+               "mlups_ratio": round(served.mlups / plain.mlups, 3) if plain.mlups else None}
+        out["loads"][str(load)] = row
+        log(f"served load {load}: {row}")
+    out["tile"] = list(served_be.tile) if served_be.tile else None
+    return out
 
 
 def main():
@@ -308,7 +391,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-copy-probe", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the f16 / batched / served forms")
-    ap.add_argument("--served-requests", type=int, default=32)
+    ap.add_argument("--served-requests", type=int, default=64)
     ap.add_argument("--served-steps-scale", type=float, default=0.1)
     args = ap.parse_args()
     if args.gpus != 1:

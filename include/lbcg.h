@@ -243,6 +243,15 @@ int lbcg_set_state(lbcg_sim *s, const void *host, size_t bytes);
 /* Wait for all queued work of the handle. */
 int lbcg_synchronize(lbcg_sim *s);
 
+/* Queue the handle's later work on another HIP stream (hip_stream; NULL = the
+ * stream the library created for the handle, LBCG_E_INVAL if it created
+ * none).  Nothing is synchronized here: the caller orders the work already
+ * queued on the old stream before the handle's later work (by waiting for
+ * the old stream or for an event recorded on it).  A batch keeps the stream
+ * it was created with.  Lets one thread prepare or read back handles on one
+ * stream while others compute on another (the served form). */
+int lbcg_set_stream(lbcg_sim *s, void *hip_stream);
+
 /* Release library-owned device memory and stream; never frees caller memory. */
 void lbcg_destroy(lbcg_sim *s);
 

@@ -38,6 +38,26 @@ def sources():
     return sorted(glob.glob(os.path.join(CSRC, "*.hip")))
 
 
+PROBE_SRC = os.path.join(HERE, "probe", "hbm_probe.hip")
+PROBE_LIB = os.path.join(HERE, "libhbmprobe.so")
+
+
+def build_probe(verbose: bool = False) -> str:
+    """The benchmark's HBM bandwidth probes (copy, read, write), a library of
+    their own so that liblbcg.so exports only the C ABI of include/lbcg.h."""
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    tmp = PROBE_LIB + ".tmp"
+    cmd = [hipcc] + HIPCC_FLAGS + [PROBE_SRC, "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(r.stdout + r.stderr)
+        raise RuntimeError("hipcc failed on hbm_probe.hip")
+    os.replace(tmp, PROBE_LIB)
+    return PROBE_LIB
+
+
 def build(verbose: bool = False) -> str:
     """Compile every source to an object in parallel, then link the library."""
     import concurrent.futures as cf
@@ -74,3 +94,4 @@ def build(verbose: bool = False) -> str:
 
 if __name__ == "__main__":
     print(build(verbose=True))
+    print(build_probe(verbose=True))

@@ -286,7 +286,7 @@ void release(lbcg_sim *s) {
     for (int k = 0; k < 2; ++k)
         if (s->graph[k]) (void)hipGraphExecDestroy(s->graph[k]);
     if (s->own_arena && s->arena) (void)hipFree(s->arena);
-    if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
+    if (s->owned_stream) (void)hipStreamDestroy(s->owned_stream);
 }
 
 }  // namespace
@@ -397,17 +397,18 @@ int lbcg_create(const lbcg_params *p, void *dev_buf, size_t bytes, void *hip_str
     s->staging_nodes = pl.staging_nodes;
     s->state_bytes = pl.state;
 
+    s->owned_stream = nullptr;
     if (hip_stream) {
         s->stream = static_cast<hipStream_t>(hip_stream);
-        s->own_stream = false;
     } else {
-        if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess) {
+        if (hipStreamCreateWithFlags(&s->owned_stream, hipStreamNonBlocking) != hipSuccess) {
             (void)hipGetLastError();
+            s->owned_stream = nullptr;
             release(s);
             delete s;
             return LBCG_E_DEVICE;
         }
-        s->own_stream = true;
+        s->stream = s->owned_stream;
     }
 
     s->g.mask = s->mask_dev;
@@ -536,6 +537,17 @@ static hipError_t ensure_pairs(lbcg_sim *s) {
                                            : launch_expand(s->g, s->cbuf[s->cur], s->buf[s->cur], s->stream);
     if (e == hipSuccess) s->expanded = true;
     return e;
+}
+
+int lbcg_set_stream(lbcg_sim *s, void *hip_stream) {
+    if (!s) return LBCG_E_INVAL;
+    if (hip_stream) {
+        s->stream = static_cast<hipStream_t>(hip_stream);
+        return LBCG_OK;
+    }
+    if (!s->owned_stream) return LBCG_E_INVAL;
+    s->stream = s->owned_stream;
+    return LBCG_OK;
 }
 
 int lbcg_synchronize(lbcg_sim *s) {

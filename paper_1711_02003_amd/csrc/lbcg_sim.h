@@ -27,8 +27,8 @@ struct lbcg_sim {
     uint8_t *mask_dev;
     lbcg::DevInlet *in_dev;
     lbcg::DevOutlet *out_dev;
-    hipStream_t stream;
-    bool own_stream;
+    hipStream_t stream;         // where the handle's work is queued
+    hipStream_t owned_stream;   // the stream the library created for it, or null
     void *arena;
     bool own_arena;
     size_t arena_bytes;

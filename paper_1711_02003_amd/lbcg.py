@@ -84,6 +84,7 @@ _SIGS = {
     "lbcg_get_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),
     "lbcg_set_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),
     "lbcg_synchronize": (C.c_int, [C.c_void_p]),
+    "lbcg_set_stream": (C.c_int, [C.c_void_p, C.c_void_p]),
     "lbcg_destroy": (None, [C.c_void_p]),
     "lbcg_strerror": (C.c_char_p, [C.c_int]),
     "lbcg_launch_info": (C.c_int, [C.c_void_p, _P(C.c_int32), _P(C.c_int32), _P(C.c_int32)]),
@@ -280,6 +281,12 @@ class Sim:
 
     def synchronize(self):
         _check(self._lib.lbcg_synchronize(self._handle()), "lbcg_synchronize")
+
+    def set_stream(self, stream):
+        """Queue later work on `stream` (a hipStream_t as int, or None for the
+        library's own); the caller orders earlier work before it."""
+        _check(self._lib.lbcg_set_stream(self._handle(), stream), "lbcg_set_stream")
+        return self
 
     def fields(self):
         sh = self.shape

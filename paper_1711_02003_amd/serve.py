@@ -11,6 +11,13 @@ requests leave and queued ones join there).  A finished request's result
 (diagnostics and fields of its final state) is copied to the host before its
 slot is freed.
 
+The loop keeps one slice queued ahead of the one it waits for: it queues
+slice k + 1, then waits for slice k, reads back the requests that slice k
+finished and admits new ones (their set-up and initialisation, and the
+readbacks, go to a second stream), all while slice k + 1 runs.  A request
+that finishes in slice k is no longer a member of slice k + 1, and its arena
+slot is freed only after slice k has completed.
+
 Metrics: time to result (completion minus arrival) per request, its p50 and
 p99, and the aggregate rate in fluid-node updates per second.
 
@@ -142,14 +149,25 @@ class Server:
         self.log.append((now, "admit", r.id))
         return True
 
+    def _finish(self, r: Request, t0: float, finished: List[Request]):
+        res = self.backend.result(r.handle)
+        r.result = res if self.keep_results else None
+        self.backend.release(r.handle)
+        self.arena.free(r.offset)
+        r.handle = None
+        r.t_done = self.clock() - t0
+        self.log.append((r.t_done, "done", r.id))
+        finished.append(r)
+
     def run(self, requests: List[Request]) -> Stats:
         queue = sorted(requests, key=lambda r: (r.arrival, r.id))
-        running: List[Request] = []
+        running: List[Request] = []      # on the device with steps not yet queued
         finished: List[Request] = []
+        inflight = None                  # (event of the queued slice, requests it finishes)
         t0 = self.clock()
         members = None
         updates = 0.0
-        while queue or running:
+        while queue or running or inflight:
             now = self.clock() - t0
             # admission in arrival order; stop at the first request that does not fit
             while queue and queue[0].arrival <= now:
@@ -158,33 +176,35 @@ class Server:
                 if not self._admit(queue[0], now, running):
                     break
                 running.append(queue.pop(0))
-            if not running:
-                self.sleep(max(0.0, queue[0].arrival - now))
-                continue
-            ids = tuple(r.id for r in running)
-            if ids != members:
-                self.backend.regroup([r.handle for r in running])
-                members = ids
-            n = [min(self.slice_steps, r.left) for r in running]
-            self.backend.step([r.handle for r in running], n)
-            self.backend.synchronize()
-            now = self.clock() - t0
-            still = []
-            for r, k in zip(running, n):
-                r.done_steps += k
-                updates += float(r.nodes) * k
-                if r.left == 0:
-                    res = self.backend.result(r.handle)
-                    r.result = res if self.keep_results else None
-                    self.backend.release(r.handle)
-                    self.arena.free(r.offset)
-                    r.handle = None
-                    r.t_done = self.clock() - t0
-                    self.log.append((r.t_done, "done", r.id))
-                    finished.append(r)
-                else:
-                    still.append(r)
-            running = still
+            queued = None
+            if running:
+                ids = tuple(r.id for r in running)
+                if ids != members:
+                    self.backend.regroup([r.handle for r in running])
+                    members = ids
+                n = [min(self.slice_steps, r.left) for r in running]
+                self.backend.step([r.handle for r in running], n)
+                ending = []
+                for r, k in zip(running, n):
+                    r.done_steps += k
+                    updates += float(r.nodes) * k
+                    if r.left == 0:
+                        ending.append(r)
+                running = [r for r in running if r.left > 0]
+                queued = (self.backend.record(), ending)
+            if inflight is not None:
+                # the previous slice: wait for it (the one just queued runs
+                # meanwhile) and read back the requests it finished
+                self.backend.wait(inflight[0])
+                for r in inflight[1]:
+                    self._finish(r, t0, finished)
+            inflight = queued
+            if inflight is None and not running and queue:
+                # idle device: sleep until the next arrival (an arrived
+                # request fits the arena, now empty, at the next pass)
+                now = self.clock() - t0
+                if queue[0].arrival > now:
+                    self.sleep(queue[0].arrival - now)
         self.backend.regroup([])
         makespan = self.clock() - t0
         ttr = [r.t_done - r.arrival for r in finished]
@@ -192,26 +212,32 @@ class Server:
 
 
 class LbcgBackend:
-    """The HIP library: one device arena (a torch uint8 tensor), one stream,
-    handles created in arena slots, stepped through ``lbcg.Batch``."""
+    """The HIP library: one device arena (a torch uint8 tensor), handles
+    created in arena slots, all running requests stepped together by the
+    batched step that needs no batch object (lbcg_batch_step_noalloc), so
+    that membership changes cost nothing.  Two streams: `stream` carries the
+    slices; `side` carries each request's set-up, initialisation and result
+    readback, which therefore never wait for a running slice (lbcg_set_stream
+    moves a handle between them once the work before has completed)."""
 
     def __init__(self, capacity_bytes: int, precision: str = "f32", tile=None, fields: bool = True,
                  tune_min: int = 4, default_tile=(8, 32)):
         import torch
 
         from . import lbcg
+        self.torch = torch
         self.lbcg = lbcg
         self.precision = precision
         self.stream = torch.cuda.Stream()
+        self.side = torch.cuda.Stream()
         self.arena = torch.empty(int(capacity_bytes), dtype=torch.uint8, device="cuda")
         self.base = self.arena.data_ptr()
-        # None: chosen by timing on the first batch of at least tune_min
+        # None: chosen by timing on the first group of at least tune_min
         # requests, then reused (default_tile until then)
         self.tile = tile
         self.tune_min = int(tune_min)
         self.default_tile = tuple(default_tile)
         self.fields = fields
-        self.batch = None
 
     def footprint(self, w) -> int:
         p, _keep = self.lbcg.make_params(w.lattice, w.dims, w.tau_R, w.tau_B, w.A, w.A, w.beta,
@@ -220,29 +246,36 @@ class LbcgBackend:
         return self.lbcg.footprint(p)
 
     def create(self, w, offset: int, nbytes: int):
-        s = self.lbcg.Sim.from_workload(w, precision=self.precision, stream=self.stream.cuda_stream,
+        # set up and initialised on the side stream (which init_fields
+        # synchronizes), then handed to the slice stream
+        s = self.lbcg.Sim.from_workload(w, precision=self.precision, stream=self.side.cuda_stream,
                                         dev_buf=(self.base + offset, nbytes))
+        s.set_stream(self.stream.cuda_stream)
         return s
 
     def regroup(self, handles):
-        if self.batch is not None:
-            self.batch.close()
-            self.batch = None
-        if handles:
-            tune = self.tile is None and len(handles) >= self.tune_min
-            tile = None if tune else (self.tile or self.default_tile)
-            self.batch = self.lbcg.Batch(handles, tile=tile)
-            if tune:
-                info = self.batch.launch_info()
-                self.tile = (info["rows"], info["zplanes"])
+        if handles and self.tile is None and len(handles) >= self.tune_min:
+            # one timing pass over candidate shapes on these states (they do
+            # not change), once; the batch it needs is released again
+            b = self.lbcg.Batch(handles)
+            info = b.launch_info()
+            b.close()
+            self.tile = (info["rows"], info["zplanes"])
 
     def step(self, handles, nsteps):
-        self.batch.step(nsteps)
+        self.lbcg.batch_step_noalloc(handles, nsteps, self.tile or self.default_tile)
 
-    def synchronize(self):
-        self.stream.synchronize()
+    def record(self):
+        e = self.torch.cuda.Event()
+        e.record(self.stream)
+        return e
+
+    def wait(self, event):
+        event.synchronize()
 
     def result(self, s) -> dict:
+        # the slice that finished the request has completed (waited for)
+        s.set_stream(self.side.cuda_stream)
         d = s.diagnostics()
         out = {"diag": d}
         if self.fields:

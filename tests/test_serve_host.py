@@ -1,6 +1,7 @@
 """Host logic of the served form: arena allocator, admission by footprint,
-continuous batching and the latency statistics (no device; a fake backend
-with a simulated clock)."""
+continuous batching, the one-slice-ahead pipeline and the latency statistics
+(no device; a fake backend with a simulated clock and a simulated device
+timeline)."""
 import numpy as np
 import pytest
 
@@ -24,20 +25,28 @@ class FakeClock:
 
 
 class FakeBackend:
-    """Costs 1 s per 1e6 node updates; records every call."""
+    """Device work costs 1 s per 1e6 node updates and runs on a simulated
+    device timeline: a queued slice starts when the device is free and the
+    host goes on at once; waiting for a slice's event moves the host clock to
+    its end.  Set-up and readback cost `host_cost` seconds of host time each.
+    Records every call."""
 
-    def __init__(self, clock, capacity, bytes_per_node=10):
+    def __init__(self, clock, capacity, bytes_per_node=10, host_cost=0.0):
         self.clock, self.capacity, self.bpn = clock, capacity, bytes_per_node
+        self.host_cost = host_cost
         self.live = {}
         self.calls = []
         self.groups = []
         self.peak = 0
         self.server = None
+        self.device_free = 0.0
+        self.busy = 0.0  # total device time
 
     def footprint(self, w):
         return w.fluid_nodes * self.bpn
 
     def create(self, w, off, nbytes):
+        self.clock.t += self.host_cost
         h = {"w": w, "off": off, "bytes": nbytes, "steps": 0}
         for o in self.live.values():  # slots never overlap
             assert off + nbytes <= o["off"] or o["off"] + o["bytes"] <= off
@@ -53,12 +62,20 @@ class FakeBackend:
         self.calls.append(list(n))
         for h, k in zip(handles, n):
             h["steps"] += k
-        self.clock.t += sum(h["w"].fluid_nodes * k for h, k in zip(handles, n)) / 1e6
+            assert id(h) in self.live  # never a released request
+        cost = sum(h["w"].fluid_nodes * k for h, k in zip(handles, n)) / 1e6
+        start = max(self.device_free, self.clock.t)
+        self.device_free = start + cost
+        self.busy += cost
 
-    def synchronize(self):
-        pass
+    def record(self):
+        return self.device_free
+
+    def wait(self, event):
+        self.clock.t = max(self.clock.t, event)
 
     def result(self, h):
+        self.clock.t += self.host_cost
         return {"steps": h["steps"]}
 
     def release(self, h):
@@ -171,3 +188,23 @@ def test_max_running_serialises():
     assert max(be.groups) == 1
     done = sorted(r.t_done for r in reqs)
     assert done == [pytest.approx(20.0 * (i + 1)) for i in range(4)]
+
+
+def test_pipeline_hides_setup_and_readback():
+    # Arrivals every 10 s, each request 300 steps of 100k nodes (30 s of
+    # device time alone; offered load 3), 2 s of host time per set-up and per
+    # readback, slices of 50 steps (5 s of device time per request).  The
+    # loop queues a slice before it waits for the previous one, so the host
+    # work of one iteration (at most one set-up and one readback, 4 s) runs
+    # while the device computes: the device never idles between the first
+    # set-up and the last readback.
+    clk = FakeClock()
+    be = FakeBackend(clk, 100_000_000, host_cost=2.0)
+    srv = Server(be, 100_000_000, slice_steps=50, clock=clk, sleep=clk.sleep)
+    reqs = [_req(i, 10.0 * i, 300, 100_000) for i in range(8)]
+    st = srv.run(reqs)
+    assert st.completed == 8 and all(r.result["steps"] == 300 for r in reqs)
+    assert be.busy == pytest.approx(240.0)
+    assert st.makespan_s <= be.busy + 2.0 + 2.0 + 1e-9
+    # a one-slice-at-a-time loop would add every set-up and readback
+    assert st.makespan_s < be.busy + 8 * 4.0 - 20.0
