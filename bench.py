@@ -388,6 +388,7 @@ def main():
                     help="compact state (FP32 only) or the pair-state sweep")
     ap.add_argument("--rows", type=int, default=0)
     ap.add_argument("--zchunks", type=int, default=0)
+    ap.add_argument("--tile-width", type=int, default=0, help="compact sweep: 64 or 32 (0: tuned)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-copy-probe", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the f16 / batched / served forms")
@@ -411,8 +412,8 @@ def main():
     with torch.cuda.stream(stream):
         sim = lbcg.Sim.from_workload(w, precision=args.precision,
                                      kernel=lbcg.KERNEL_COMPACT if compact else lbcg.KERNEL_FUSED,
-                                     tile=(args.rows, args.zchunks, 0))
-    if not (args.rows or args.zchunks):
+                                     tile=(args.rows, args.zchunks, args.tile_width))
+    if not (args.rows or args.zchunks or args.tile_width):
         sim.step(1)
         sim.tune()  # launch shape chosen by timing candidates on this lattice
     info = sim.launch_info()
@@ -458,7 +459,7 @@ def main():
         "config": {"workload": w.name, "lattice": "D3Q19", "dims": list(w.dims),
                    "droplets": 27, "tau_R": w.tau_R, "tau_B": w.tau_B, "A": w.A, "beta": w.beta,
                    "storage": args.precision, "kernel": "fused compact" if compact else "fused",
-                   "rows": info["rows"], "zchunks": info["zchunks"]},
+                   "rows": info["rows"], "zchunks": info["zchunks"], "tile_width": info["tile_width"]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "bytes_per_node": bytes_node},

@@ -156,7 +156,9 @@ typedef struct {
     const lbcg_wall *walls;     /* host, copied */
     int32_t tile[3];     /* fused-kernel launch shape: rows per block (4 or 8;
                             D3Q19 only), z chunks (D2Q9: row chunks; <= 4096),
-                            reserved; 0 = automatic */
+                            tile width (64; the compact D3Q19 sweep also 32:
+                            256-thread blocks, several per compute unit);
+                            0 = automatic */
 } lbcg_params;
 
 /* FP64 diagnostics of the current state S_t (pre-collision), summed over fluid
@@ -259,15 +261,17 @@ void lbcg_destroy(lbcg_sim *s);
 const char *lbcg_strerror(int status);
 
 /* Launch shape chosen for the handle: kernel kind (LBCG_KERNEL_GENERIC,
- * LBCG_KERNEL_FUSED or LBCG_KERNEL_COMPACT), rows per block, z chunks. */
-int lbcg_launch_info(lbcg_sim *s, int32_t *kernel, int32_t *rows, int32_t *zchunks);
+ * LBCG_KERNEL_FUSED or LBCG_KERNEL_COMPACT), rows per block, z chunks, tile
+ * width (64; or 32 on the compact D3Q19 sweep).  NULL outputs are skipped. */
+int lbcg_launch_info(lbcg_sim *s, int32_t *kernel, int32_t *rows, int32_t *zchunks, int32_t *tile_width);
 
 /* Choose the fused (or compact) kernel's launch shape for this handle by
  * timing candidate shapes on the handle's own lattice (D3Q19: rows 4 or 8,
- * 8 only for the compact kernel, z splits that fill the device once, twice
- * or four times and chunks of 2 to 64 planes; D2Q9: row chunks of 8 to 512
- * rows), stepping the current state into the spare buffer so the state does
- * not change.  Keeps
+ * 8 only for the compact kernel, which also tries 32-wide tiles; z splits
+ * that fill the device once, twice or four times and chunks of 2 to 64
+ * planes; D2Q9: row chunks of 8 to 512 rows), stepping the current state
+ * into the spare buffer so the state does not change (the compact kernel is
+ * timed on a compact state also before the handle's first compact step).  Keeps
  * the fastest shape for later steps and reports it.  No effect on the
  * generic kernel.  Synchronizes. */
 int lbcg_tune(lbcg_sim *s, int32_t *rows, int32_t *zchunks);

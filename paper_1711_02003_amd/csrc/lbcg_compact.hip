@@ -10,18 +10,20 @@ namespace {
 
 // Work items (tile, z chunk), tile-major, dealt to the 8 XCDs in contiguous
 // bands (blocks go to XCDs round-robin), so each XCD sweeps a compact band of
-// tiles and the ring re-reads mostly hit its L2.
-template <bool PAIR_IN>
-__global__ void __launch_bounds__(kCTX * kCR) k_step_compact(CompactArgs a, Model<float> mo) {
+// tiles and the ring re-reads mostly hit its L2.  Tiles TX x 8: TX = 64
+// (512 threads, one block per CU) or 32 (256 threads, several blocks per CU,
+// each with its own barrier).
+template <bool PAIR_IN, int TX>
+__global__ void __launch_bounds__(TX * kCR) k_step_compact(CompactArgs a, Model<float> mo) {
     extern __shared__ float lds[];
     const int total = a.ntx * a.nty * a.zchunks;
     const int xcd = blockIdx.x % kCXCD, l = blockIdx.x / kCXCD;
     const int item = xcd * (total / kCXCD) + min(xcd, total % kCXCD) + l;
     if (item == 0 && threadIdx.x == 0) *a.ctr_out = *a.ctr_in + 1u;
     if (PAIR_IN)
-        sweep_pairs(a, mo, item / a.zchunks, item % a.zchunks, lds);
+        sweep_pairs<TX>(a, mo, item / a.zchunks, item % a.zchunks, lds);
     else
-        sweep_compact<true>(a, mo, item / a.zchunks, item % a.zchunks, lds);
+        sweep_compact<true, TX>(a, mo, item / a.zchunks, item % a.zchunks, lds);
 }
 
 // Pair state of nodes [0, N) from a compact state: each population's
@@ -62,10 +64,14 @@ bool compact_supported(int lattice, int prec, const Geo &g) {
     return lattice == 1 && uint64_t(2 * D3Q19::Q) * uint64_t(g.pitch) * 4u < (uint64_t(1) << 32);
 }
 
-int compact_resident_blocks(int) {
+int compact_resident_blocks(int tx) {
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(&k_step_compact<false>),
-                                                     kCTX * kCR, kCompactLds) != hipSuccess) {
+    const void *fn = tx == 32 ? reinterpret_cast<const void *>(&k_step_compact<false, 32>)
+                              : reinterpret_cast<const void *>(&k_step_compact<false, 64>);
+    if (tx == 32) allow_lds(fn, 1, CTile<32>::lds);
+    else allow_lds(fn, 0, CTile<64>::lds);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, tx * kCR,
+                                                     tx == 32 ? CTile<32>::lds : CTile<64>::lds) != hipSuccess) {
         (void)hipGetLastError();
         per_cu = 1;
     }
@@ -77,7 +83,7 @@ int compact_resident_blocks(int) {
 
 hipError_t launch_step_compact(const Geo &g, const ModelD &md, const void *in, bool pair_in, void *out,
                                const uint32_t *ctr_in, uint32_t *ctr_out, FusedShape sh, hipStream_t s) {
-    if (sh.rows != kCR) return hipErrorInvalidValue;
+    if (sh.rows != kCR || (sh.tx != 64 && sh.tx != 32)) return hipErrorInvalidValue;
     if (g.mask || md.bgk) return hipErrorInvalidValue;
     if (uint64_t(2 * D3Q19::Q) * uint64_t(g.pitch) * 4u >= (uint64_t(1) << 32)) return hipErrorInvalidValue;
     CompactArgs a;
@@ -89,18 +95,26 @@ hipError_t launch_step_compact(const Geo &g, const ModelD &md, const void *in, b
     a.pitch = g.pitch;
     a.ctr_in = ctr_in;
     a.ctr_out = ctr_out;
-    a.ntx = (g.nx + kCTX - 1) / kCTX;
+    a.ntx = (g.nx + sh.tx - 1) / sh.tx;
     a.nty = (g.ny + kCR - 1) / kCR;
     a.zchunks = sh.zchunks < 1 ? 1 : (sh.zchunks > g.nz ? g.nz : sh.zchunks);
     const int64_t nblocks = int64_t(a.ntx) * a.nty * a.zchunks;
     if (nblocks > 0x7fffffff) return hipErrorInvalidValue;
     const Model<float> mo = to_model<float>(md);
-    allow_lds(reinterpret_cast<const void *>(&k_step_compact<false>), 0);
-    const dim3 grid = dim3(unsigned(nblocks)), block = dim3(unsigned(kCTX * kCR));
-    if (pair_in)
-        hipLaunchKernelGGL((k_step_compact<true>), grid, block, kPairInLds, s, a, mo);
-    else
-        hipLaunchKernelGGL((k_step_compact<false>), grid, block, kCompactLds, s, a, mo);
+    const dim3 grid = dim3(unsigned(nblocks)), block = dim3(unsigned(sh.tx * kCR));
+    if (sh.tx == 32) {
+        allow_lds(reinterpret_cast<const void *>(&k_step_compact<false, 32>), 1, CTile<32>::lds);
+        if (pair_in)
+            hipLaunchKernelGGL((k_step_compact<true, 32>), grid, block, CTile<32>::lds_pair, s, a, mo);
+        else
+            hipLaunchKernelGGL((k_step_compact<false, 32>), grid, block, CTile<32>::lds, s, a, mo);
+    } else {
+        allow_lds(reinterpret_cast<const void *>(&k_step_compact<false, 64>), 0, CTile<64>::lds);
+        if (pair_in)
+            hipLaunchKernelGGL((k_step_compact<true, 64>), grid, block, CTile<64>::lds_pair, s, a, mo);
+        else
+            hipLaunchKernelGGL((k_step_compact<false, 64>), grid, block, CTile<64>::lds, s, a, mo);
+    }
     return hipGetLastError();
 }
 

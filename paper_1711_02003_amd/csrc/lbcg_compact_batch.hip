@@ -34,7 +34,7 @@ __global__ void __launch_bounds__(kCTX * kCR)
     a.nty = d.a.nty;
     a.zchunks = d.a.zchunks;
     if (item == 0 && threadIdx.x == 0) *a.ctr_out = *a.ctr_in + 1u;
-    sweep_compact<false>(a, d.mo, item / a.zchunks, item % a.zchunks, lds);
+    sweep_compact<false, kCTX>(a, d.mo, item / a.zchunks, item % a.zchunks, lds);
 }
 
 }  // namespace
@@ -42,7 +42,7 @@ __global__ void __launch_bounds__(kCTX * kCR)
 hipError_t launch_step_compact_batch(const void *desc, const int *blat, const int *bitem, int nblocks,
                                      hipStream_t s) {
     if (nblocks <= 0) return hipSuccess;
-    allow_lds(reinterpret_cast<const void *>(&k_step_compact_batch), 1);
+    allow_lds(reinterpret_cast<const void *>(&k_step_compact_batch), 2, kCompactLds);
     hipLaunchKernelGGL(k_step_compact_batch, dim3(unsigned(nblocks)), dim3(unsigned(kCTX * kCR)), kCompactLds, s,
                        static_cast<const BatchDesc<float> *>(desc), blat, bitem);
     return hipGetLastError();

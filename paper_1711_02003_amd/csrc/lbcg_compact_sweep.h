@@ -52,7 +52,7 @@ namespace lbcg {
 
 namespace {
 
-constexpr int kCTX = 64;
+constexpr int kCTX = 64;                    // tile width of the batched sweep
 constexpr int kCR = 8;                      // tile rows
 constexpr int kCXCD = 8;
 // Scalar records: {M, V_axis} (16 B) in one array after the 19 total
@@ -61,13 +61,29 @@ constexpr int kCXCD = 8;
 constexpr uint32_t kRecA = 16, kRecB = 4;
 constexpr int kRecBytes = int(kRecA + kRecB);
 constexpr int kNS = 5;                      // scalars kept in LDS: M, V_axis, R_d
-constexpr int kSW = kCTX + 4, kSH = kCR + 4, kSN = kSW * kSH;  // record tile with a 2-node halo
 constexpr int kSSlots = 4;
-constexpr int kPW = kCTX + 2, kPH = kCR + 2, kPN = kPW * kPH;  // psi tile with a 1-node halo
 constexpr int kPSlots = 5;
-constexpr int kLoad0 = 192;                 // first record-loading thread (waves 0-2 hold the ring)
-constexpr int kLoaders = kCTX * kCR - kLoad0;
-constexpr int kPerLoader = (kSN + kLoaders - 1) / kLoaders;
+
+// Shape of a tile TX x kCR (one thread per node) and what follows from it:
+// the record tile with a 2-node halo (SW x SH), the psi tile with a 1-node
+// halo (PW x PH), the ring nodes (held by the first threads, whose waves
+// load no records) and the record loaders (the threads of the other waves,
+// PER nodes each), and the LDS of a block.  64 x 8 (512 threads): ring 148
+// in waves 0-2, loaders 320 x 3; 32 x 8 (256 threads): ring 84 in waves
+// 0-1, loaders 128 x 4.
+template <int TX>
+struct CTile {
+    static constexpr int W = TX, R = kCR, threads = TX * kCR;
+    static constexpr int SW = TX + 4, SH = kCR + 4, SN = SW * SH;
+    static constexpr int PW = TX + 2, PH = kCR + 2, PN = PW * PH;
+    static constexpr int ring = 2 * (TX + 2) + 2 * kCR;
+    static constexpr int load0 = (ring + 63) / 64 * 64;
+    static constexpr int loaders = threads - load0;
+    static constexpr int per = (SN + loaders - 1) / loaders;
+    static constexpr size_t lds = (size_t(kPSlots) * PN + size_t(kSSlots) * kNS * SN) * sizeof(float);
+    static constexpr size_t lds_pair = size_t(kPSlots) * PN * sizeof(float);
+    static_assert(loaders > 0 && per <= 4, "tile shape");
+};
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 
@@ -162,7 +178,7 @@ __device__ __forceinline__ void store_compact(const CompactArgs &a, __amdgpu_buf
 // sender), else four arrays M, V_axis x, y, z; then the R_d of every node.
 // The single-lattice sweep measured 0.7 % faster with entries, the batched
 // one 2.7 % slower, so each uses its own.
-template <bool ENTRIES>
+template <bool ENTRIES, int kSW, int kSN>
 __device__ __forceinline__ void split_pulled(const float d[D3Q19::Q], const float *const sl[3], int c,
                                              CPops<D3Q19, float> &p) {
     using L = D3Q19;
@@ -210,11 +226,14 @@ __device__ __forceinline__ void split_pulled(const float d[D3Q19::Q], const floa
 }
 
 // ------------------------------------------------------------- compact in
-template <bool ENTRIES>
+template <bool ENTRIES, int TX>
 __device__ __forceinline__ void sweep_compact(const CompactArgs &a, const Model<float> &mo, int tile, int chunk,
                                               float *lds) {
     using L = D3Q19;
     typedef float T;
+    typedef CTile<TX> S;
+    constexpr int kCTX = TX, kSW = S::SW, kSN = S::SN, kPW = S::PW, kPN = S::PN;
+    constexpr int kLoad0 = S::load0, kLoaders = S::loaders, kPerLoader = S::per;
     const int lane = threadIdx.x % kCTX, row = threadIdx.x / kCTX;
     const int tx = tile % a.ntx, ty = tile / a.ntx;
     const int x0 = tx * kCTX, y0 = ty * kCR;
@@ -226,8 +245,8 @@ __device__ __forceinline__ void sweep_compact(const CompactArgs &a, const Model<
     const bool intile = lane < tw && row < th;
     const int x = x0 + lane, y = y0 + row;
 
-    // ring node of this thread (at most one; threads below 2 (64 + 2) + 2 x 8
-    // = 148, all in waves 0-2)
+    // ring node of this thread (at most one; threads below S::ring, all in
+    // the waves before kLoad0)
     const int nring = 2 * (tw + 2) + 2 * th;
     int rx = 0, ry = 0;
     const bool has_ring = threadIdx.x < nring;
@@ -321,7 +340,7 @@ __device__ __forceinline__ void sweep_compact(const CompactArgs &a, const Model<
     };
     auto split = [&](const float d[L::Q], int zp, int c, CPops<L, T> &q) {
         const float *const sl[3] = {rslot(zp - 1), rslot(zp), rslot(zp + 1)};
-        split_pulled<ENTRIES>(d, sl, c, q);
+        split_pulled<ENTRIES, kSW, kSN>(d, sl, c, q);
     };
     const int ci = (row + 2) * kSW + lane + 2, cr = (ry + 2) * kSW + rx + 2;
     auto ring_finish = [&](int zp) {
@@ -464,11 +483,12 @@ __device__ __forceinline__ void pull_pairs(const CompactArgs &a, __amdgpu_buffer
                                                           uint32_t(su(uint32_t(i) * cs + zo[1 - L::cz[i]])));
 }
 
+template <int TX>
 __device__ __forceinline__ void sweep_pairs(const CompactArgs &a, const Model<float> &mo, int tile, int chunk,
                                             float *lds) {
     using L = D3Q19;
     typedef float T;
-    constexpr int R = kCR, W = kPW, PL = kPN;
+    constexpr int kCTX = TX, R = kCR, W = CTile<TX>::PW, PL = CTile<TX>::PN;
     const int lane = threadIdx.x % kCTX, row = threadIdx.x / kCTX;
     const int tx = tile % a.ntx, ty = tile / a.ntx;
     const int x0 = tx * kCTX, y0 = ty * R;
@@ -596,12 +616,11 @@ __device__ __forceinline__ void sweep_pairs(const CompactArgs &a, const Model<fl
     }
 }
 
-constexpr size_t kCompactLds = (size_t(kPSlots) * kPN + size_t(kSSlots) * kNS * kSN) * sizeof(float);
-constexpr size_t kPairInLds = size_t(kPSlots) * kPN * sizeof(float);
+constexpr size_t kCompactLds = CTile<kCTX>::lds;  // the batched sweep's 64 x 8 tiles
 
-// Allows a compact kernel (k = 0 single, 1 batched) the record ring's LDS
-// beyond 64 KiB, once per device and kernel.
-void allow_lds(const void *fn, int k) {
+// Allows a compact kernel (k = 0, 1: single lattice, 64 and 32 wide; 2:
+// batched) its LDS beyond 64 KiB, once per device and kernel.
+void allow_lds(const void *fn, int k, size_t bytes) {
     static std::mutex mu;
     static std::set<std::pair<int, int>> done;
     int dev = 0;
@@ -611,7 +630,7 @@ void allow_lds(const void *fn, int k) {
     }
     std::lock_guard<std::mutex> lock(mu);
     if (!done.insert({dev, k}).second) return;
-    (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(kCompactLds));
+    (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
     (void)hipGetLastError();
 }
 

@@ -70,6 +70,7 @@ hipError_t launch_diag(int lattice, int prec, const Geo &g, const ModelD &md, co
 struct FusedShape {
     int rows;     // rows of the x-y tile (one wave of 64 nodes per row)
     int zchunks;  // z range split per column of tiles
+    int tx = 64;  // tile width (the compact D3Q19 sweep: 64 or 32)
 };
 
 // Kernel view of one lattice for the fused sweep.
@@ -114,7 +115,7 @@ constexpr int kCompactBytes2d = 9 * 4 + 16;  // D2Q9: 9 totals, 4 scalars
 hipError_t launch_step_compact(const Geo &g, const ModelD &md, const void *in, bool pair_in, void *out,
                                const uint32_t *ctr_in, uint32_t *ctr_out, FusedShape shape, hipStream_t s);
 bool compact_supported(int lattice, int prec, const Geo &g);
-int compact_resident_blocks(int rows);
+int compact_resident_blocks(int tile_width);
 // Pair state (post-collision, as the pair kernels store it) of a compact state.
 hipError_t launch_expand(const Geo &g, const void *cin, void *pout, hipStream_t s);
 // The D2Q9 strip sweep on the compact state (periodic, FP32, regularized):

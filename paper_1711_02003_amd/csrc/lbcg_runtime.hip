@@ -77,6 +77,10 @@ int validate(const lbcg_params *p) {
     if (p->tile[0] != 0 && p->tile[0] != 4 && p->tile[0] != 8) return LBCG_E_INVAL;
     if (p->kernel == LBCG_KERNEL_COMPACT && p->tile[0] == 4) return LBCG_E_INVAL;  // 8-row tiles only
     if (p->tile[1] > 4096) return LBCG_E_INVAL;
+    // tile width: 64, or 32 on the compact D3Q19 sweep; 0 = automatic
+    if (p->tile[2] != 0 && p->tile[2] != 64 &&
+        !(p->tile[2] == 32 && p->kernel == LBCG_KERNEL_COMPACT && p->lattice == LBCG_D3Q19))
+        return LBCG_E_INVAL;
     return LBCG_OK;
 }
 
@@ -168,13 +172,14 @@ FusedShape pick_shape(const lbcg_sim *s, const lbcg_params *p) {
         return sh;
     }
     sh.rows = p->tile[0] ? p->tile[0] : 8;
+    sh.tx = p->tile[2] ? p->tile[2] : 64;
     int zc = p->tile[1];
     if (!zc && (s->kernel == LBCG_KERNEL_FUSED || s->kernel == LBCG_KERNEL_COMPACT)) {
         // One wave of resident blocks: each z chunk re-reads two planes, so use
         // as few (long) chunks as fill the device, but keep chunks >= 8 planes.
-        const int64_t tiles = int64_t((s->g.nx + 63) / 64) * ((s->g.ny + sh.rows - 1) / sh.rows);
+        const int64_t tiles = int64_t((s->g.nx + sh.tx - 1) / sh.tx) * ((s->g.ny + sh.rows - 1) / sh.rows);
         const int64_t resident = s->kernel == LBCG_KERNEL_COMPACT
-                                     ? compact_resident_blocks(sh.rows)
+                                     ? compact_resident_blocks(sh.tx)
                                      : fused_resident_blocks(s->prec, sh.rows, s->g.mask != nullptr);
         int64_t want = (resident + tiles - 1) / tiles;
         const int64_t cap = s->g.nz / 8 > 1 ? s->g.nz / 8 : 1;
@@ -712,11 +717,12 @@ int lbcg_set_state(lbcg_sim *s, const void *host, size_t bytes) {
     return LBCG_OK;
 }
 
-int lbcg_launch_info(lbcg_sim *s, int32_t *kernel, int32_t *rows, int32_t *zchunks) {
+int lbcg_launch_info(lbcg_sim *s, int32_t *kernel, int32_t *rows, int32_t *zchunks, int32_t *tile_width) {
     if (!s) return LBCG_E_INVAL;
     if (kernel) *kernel = s->kernel;
     if (rows) *rows = s->shape.rows;
     if (zchunks) *zchunks = s->shape.zchunks;
+    if (tile_width) *tile_width = s->lattice == LBCG_D3Q19 ? s->shape.tx : 64;
     return LBCG_OK;
 }
 
@@ -741,26 +747,24 @@ int lbcg_tune(lbcg_sim *s, int32_t *rows, int32_t *zchunks) {
                 if (!seen) cand.push_back(FusedShape{1, yc});
             }
         }
-        for (int r : {4, 8}) {
+        // D3Q19: rows 4 or 8 with 64-wide tiles; the compact sweep: 8 rows,
+        // 64- or 32-wide tiles
+        const int shapes[3][2] = {{4, 64}, {8, 64}, {8, 32}};
+        for (const auto &rt : shapes) {
+            const int r = rt[0], tx = rt[1];
             if (s->lattice == LBCG_D2Q9) break;
-            if (cmp && r != 8) continue;
-            const int64_t tiles = int64_t((s->g.nx + 63) / 64) * ((s->g.ny + r - 1) / r);
-            const int64_t resident = cmp ? compact_resident_blocks(r) : fused_resident_blocks(s->prec, r, masked);
+            if (cmp ? r != 8 : tx != 64) continue;
+            const int64_t tiles = int64_t((s->g.nx + tx - 1) / tx) * ((s->g.ny + r - 1) / r);
+            const int64_t resident = cmp ? compact_resident_blocks(tx) : fused_resident_blocks(s->prec, r, masked);
             std::vector<int64_t> zs = {1};
             for (int m : {1, 2, 4}) zs.push_back((m * resident + tiles - 1) / tiles);
             for (int planes : {2, 4, 8, 16, 32, 64}) zs.push_back((s->g.nz + planes - 1) / planes);
             for (int64_t z : zs) {
                 const int zc = int(z < 1 ? 1 : (z > s->g.nz ? s->g.nz : (z > 4096 ? 4096 : z)));
                 bool seen = false;
-                for (const FusedShape &c : cand) seen = seen || (c.rows == r && c.zchunks == zc);
-                if (!seen) cand.push_back(FusedShape{r, zc});
+                for (const FusedShape &c : cand) seen = seen || (c.rows == r && c.zchunks == zc && c.tx == tx);
+                if (!seen) cand.push_back(FusedShape{r, zc, tx});
             }
-        }
-        hipEvent_t e0 = nullptr, e1 = nullptr;
-        HIP_TRY(hipEventCreate(&e0));
-        if (hipEventCreate(&e1) != hipSuccess) {
-            (void)hipEventDestroy(e0);
-            return LBCG_E_DEVICE;
         }
         // The compact kernel is timed as every later step runs it: reading a
         // compact state.  Before the handle's first compact step (the state is
@@ -782,6 +786,12 @@ int lbcg_tune(lbcg_sim *s, int32_t *rows, int32_t *zchunks) {
                 in = s->cbuf[s->cur ^ 1];
                 out = s->cbuf[s->cur];
             }
+        }
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        HIP_TRY(hipEventCreate(&e0));
+        if (hipEventCreate(&e1) != hipSuccess) {
+            (void)hipEventDestroy(e0);
+            return LBCG_E_DEVICE;
         }
         auto run = [&](const FusedShape &c) {
             return cmp ? launch_compact(s, in, false, out, ctr_in, ctr_out, c)
@@ -817,7 +827,7 @@ int lbcg_tune(lbcg_sim *s, int32_t *rows, int32_t *zchunks) {
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         if (e != hipSuccess) return dev_err(e);
-        if (pick.rows != s->shape.rows || pick.zchunks != s->shape.zchunks) {
+        if (pick.rows != s->shape.rows || pick.zchunks != s->shape.zchunks || pick.tx != s->shape.tx) {
             for (int k = 0; k < 2; ++k)
                 if (s->graph[k]) {
                     (void)hipGraphExecDestroy(s->graph[k]);

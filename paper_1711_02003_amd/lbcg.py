@@ -87,7 +87,7 @@ _SIGS = {
     "lbcg_set_stream": (C.c_int, [C.c_void_p, C.c_void_p]),
     "lbcg_destroy": (None, [C.c_void_p]),
     "lbcg_strerror": (C.c_char_p, [C.c_int]),
-    "lbcg_launch_info": (C.c_int, [C.c_void_p, _P(C.c_int32), _P(C.c_int32), _P(C.c_int32)]),
+    "lbcg_launch_info": (C.c_int, [C.c_void_p, _P(C.c_int32), _P(C.c_int32), _P(C.c_int32), _P(C.c_int32)]),
     "lbcg_tune": (C.c_int, [C.c_void_p, _P(C.c_int32), _P(C.c_int32)]),
     "lbcg_batch_create": (C.c_int, [_P(C.c_void_p), C.c_int32, _P(C.c_int32), _P(C.c_void_p)]),
     "lbcg_batch_step": (C.c_int, [C.c_void_p, _P(C.c_int64)]),
@@ -332,16 +332,16 @@ class Sim:
         return self
 
     def launch_info(self):
-        k, r, z = C.c_int32(), C.c_int32(), C.c_int32()
-        _check(self._lib.lbcg_launch_info(self._handle(), C.byref(k), C.byref(r), C.byref(z)),
+        k, r, z, t = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+        _check(self._lib.lbcg_launch_info(self._handle(), C.byref(k), C.byref(r), C.byref(z), C.byref(t)),
                "lbcg_launch_info")
-        return {"kernel": k.value, "rows": r.value, "zchunks": z.value}
+        return {"kernel": k.value, "rows": r.value, "zchunks": z.value, "tile_width": t.value}
 
     def tune(self):
         """Time candidate launch shapes of the fused kernel and keep the fastest."""
         r, z = C.c_int32(), C.c_int32()
         _check(self._lib.lbcg_tune(self._handle(), C.byref(r), C.byref(z)), "lbcg_tune")
-        return {"rows": r.value, "zchunks": z.value}
+        return {"rows": r.value, "zchunks": z.value, "tile_width": self.launch_info()["tile_width"]}
 
     def close(self):
         if self._h is not None:

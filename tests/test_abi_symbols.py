@@ -82,11 +82,18 @@ def test_compact_footprint_adds_two_compact_buffers(lib):
     extra = lbcg.footprint(c) - lbcg.footprint(f)
     one = -(-(19 * 4 + 20) * pitch // 256) * 256
     assert one * 2 - 512 <= extra <= one * 2 + 512, (extra, one)
-    # 8-row tiles only
+    # 8-row tiles only; 32-wide tiles on the compact D3Q19 sweep only
     t, keep3 = lbcg.make_params("D3Q19", dims, 1.0, 0.6, 0.005, 0.005, 0.7, kernel=lbcg.KERNEL_COMPACT,
                                 tile=(4, 0, 0))
     with pytest.raises(lbcg.LbcgError):
         lbcg.footprint(t)
+    t, keep3 = lbcg.make_params("D3Q19", dims, 1.0, 0.6, 0.005, 0.005, 0.7, kernel=lbcg.KERNEL_COMPACT,
+                                tile=(8, 0, 32))
+    assert lbcg.footprint(t) > 0
+    for bad in (dict(kernel=lbcg.KERNEL_FUSED, tile=(8, 0, 32)), dict(kernel=lbcg.KERNEL_COMPACT, tile=(8, 0, 48))):
+        t, keep3 = lbcg.make_params("D3Q19", dims, 1.0, 0.6, 0.005, 0.005, 0.7, **bad)
+        with pytest.raises(lbcg.LbcgError):
+            lbcg.footprint(t)
 
 
 def test_wall_and_collision_validation(lib):

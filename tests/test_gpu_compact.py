@@ -138,13 +138,14 @@ def test_compact_agrees_with_pair_fused_ragged(L):
     assert d < 50 * 4 * EPS32
 
 
-@pytest.mark.parametrize("dims", [(96, 40, 24), (64, 16, 9), (5, 3, 2)])
+@pytest.mark.parametrize("dims", [(96, 40, 24), (64, 16, 9), (5, 3, 2), (33, 17, 12)])
 def test_compact_tile_shape_invariance(L, dims):
-    # every tile height and z split gives bitwise the same state: ring and
-    # interior nodes split the pulled populations by one expression sequence
+    # every tile width (64 or 32), z split and automatic shape gives bitwise
+    # the same state: ring and interior nodes split the pulled populations by
+    # one expression sequence
     w = _droplets(dims, seed=5)
     ref = None
-    for tile in ((8, 1, 0), (8, 3, 0), (8, 8, 0), (8, 0, 0)):
+    for tile in ((8, 1, 0), (8, 3, 0), (8, 8, 0), (8, 0, 0), (8, 1, 32), (8, 3, 32), (8, 0, 32)):
         s = L.Sim.from_workload(w, precision="f32", kernel=L.KERNEL_COMPACT, tile=tile)
         s.step(17)
         p = s.populations()
@@ -164,9 +165,9 @@ def test_compact_concurrent_streams_match_sequential(L):
     ref.step(20)
     ref.synchronize()
     pr = ref.populations()
-    for zc in (64, 8, 2):
-        a = L.Sim.from_workload(w, precision="f32", kernel=L.KERNEL_COMPACT, tile=(8, zc, 0))
-        b = L.Sim.from_workload(w, precision="f32", kernel=L.KERNEL_COMPACT, tile=(8, 1, 0))
+    for zc, tx in ((64, 64), (8, 32), (2, 64), (64, 32)):
+        a = L.Sim.from_workload(w, precision="f32", kernel=L.KERNEL_COMPACT, tile=(8, zc, tx))
+        b = L.Sim.from_workload(w, precision="f32", kernel=L.KERNEL_COMPACT, tile=(8, 1, 96 - tx))
         a.step(20)
         b.step(20)
         assert np.array_equal(a.populations(), pr), zc

@@ -280,10 +280,11 @@ def test_tune_keeps_state_compact(L, before):
     p0 = a.populations()
     shape = a.tune()
     _say(f"compact tuned after {before} steps: {shape}")
-    assert shape["rows"] == 8 and 1 <= shape["zchunks"] <= 64
+    assert shape["rows"] == 8 and 1 <= shape["zchunks"] <= 64 and shape["tile_width"] in (32, 64)
     assert np.array_equal(a.populations(), p0)
     a.step(37)
-    b = L.Sim.from_workload(w, precision="f32", kernel=L.KERNEL_COMPACT, tile=(8, shape["zchunks"], 0))
+    b = L.Sim.from_workload(w, precision="f32", kernel=L.KERNEL_COMPACT,
+                            tile=(8, shape["zchunks"], 96 - shape["tile_width"]))
     b.step(before + 37)
     assert np.array_equal(a.populations(), b.populations())
 
