@@ -10,7 +10,9 @@ of every node (both colours).  Prints one JSON line:
              resident in HBM, timed with HIP events on the simulation's stream;
   roofline   HBM roofline of the step's kernel: algorithmic bytes per node
              (read + write the state once: compact 2 x (19 x 4 + 20) = 192 B,
-             pair state 2 x 38 x 4 = 304 B) x nodes / average kernel time,
+             pair state 2 x 38 x 4 = 304 B; with --precision f16, compact
+             2 x (19 x 2 + 12) = 100 B, pair state 152 B) x nodes / average
+             kernel time,
              against 8 TB/s; traffic = HBM bytes per launch from the rocprofv3
              FETCH_SIZE / WRITE_SIZE counters scaled by a copy-kernel
              calibration (null when the kernel source changed since the
@@ -22,7 +24,7 @@ of every node (both colours).  Prints one JSON line:
   forms      the other forms of the step, each measured on its own workload:
              pair_f32 (the same lattice on the pair-state sweep: per
              population its total and minority share), f16 (the same lattice
-             with FP16 pair storage), d2q9 (a 4096^2 D2Q9 box: compact and
+             with FP16 storage, compact and pair state), d2q9 (a 4096^2 D2Q9 box: compact and
              pair-state strip sweeps and the two-pass generic kernel),
              focusing2d (the 8192 x 2048 D2Q9 junction), focusing (the
              512 x 128 x 64 D3Q19 flow-focusing junction, FP32 and FP16),
@@ -202,19 +204,24 @@ def pair_f32_form(torch, lbcg, W, size, steps=200, warmup=10):
 
 
 def f16_form(torch, lbcg, W, size, steps=200, warmup=10):
+    """FP16 storage (FP32 arithmetic) on the headline lattice: the compact
+    state (100 B per node moved: 19 FP16 totals, M in FP32, V_axis and R_d
+    in FP16, read and written once) and the pair state (152 B), each tuned."""
     w = W.config2(L=size, seed=2)
-    stream = torch.cuda.Stream()
-    sim = lbcg.Sim.from_workload(w, precision="f16", stream=stream.cuda_stream)
-    sim.step(1)
-    shape = sim.tune()
-    ms = time_sim(torch, sim, stream, steps, warmup)
-    sim.close()
-    mlups = w.fluid_nodes * steps / (ms / 1e3) / 1e6
-    gbs = 152 * w.fluid_nodes * steps / (ms / 1e3) / 1e9
-    return {"workload": w.name, "storage": "f16", "mlups": round(mlups, 1),
-            "ms_per_step": round(ms / steps, 4), "achieved_gbs": round(gbs, 1),
-            "frac": round(gbs / HBM_PEAK_GBS, 4), "bytes_per_node": 152, "rows": shape["rows"],
-            "zchunks": shape["zchunks"], "steps": steps}
+    out = {"workload": w.name, "storage": "f16"}
+    for name, kernel, bpn in (("compact", lbcg.KERNEL_COMPACT, 100), ("pairs", lbcg.KERNEL_FUSED, 152)):
+        stream = torch.cuda.Stream()
+        sim = lbcg.Sim.from_workload(w, precision="f16", kernel=kernel, stream=stream.cuda_stream)
+        sim.step(1)
+        shape = sim.tune()
+        ms = time_sim(torch, sim, stream, steps, warmup)
+        sim.close()
+        mlups = w.fluid_nodes * steps / (ms / 1e3) / 1e6
+        gbs = bpn * w.fluid_nodes * steps / (ms / 1e3) / 1e9
+        out[name] = {"mlups": round(mlups, 1), "ms_per_step": round(ms / steps, 4),
+                     "achieved_gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4), "bytes_per_node": bpn,
+                     "shape": shape, "steps": steps}
+    return out
 
 
 def d2q9_form(torch, lbcg, W, steps=200, warmup=10):
@@ -385,7 +392,7 @@ def main():
     ap.add_argument("--size", type=int, default=256)
     ap.add_argument("--precision", default="f32", choices=["f32", "f16"])
     ap.add_argument("--kernel", default="compact", choices=["compact", "fused"],
-                    help="compact state (FP32 only) or the pair-state sweep")
+                    help="compact state or the pair-state sweep")
     ap.add_argument("--rows", type=int, default=0)
     ap.add_argument("--zchunks", type=int, default=0)
     ap.add_argument("--tile-width", type=int, default=0, help="compact sweep: 64 or 32 (0: tuned)")
@@ -406,7 +413,7 @@ def main():
     from paper_1711_02003_amd import workloads as W
 
     w = W.config2(L=args.size, seed=2)
-    compact = args.kernel == "compact" and args.precision == "f32"
+    compact = args.kernel == "compact"
     kname = "k_step_compact" if compact else "k_step_fused"
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
@@ -439,7 +446,7 @@ def main():
 
     N = w.fluid_nodes
     elem = 4 if args.precision == "f32" else 2
-    bytes_node = 2 * (19 * 4 + 20) if compact else 2 * 2 * 19 * elem
+    bytes_node = (2 * (19 * 4 + 20) if elem == 4 else 2 * (19 * 2 + 12)) if compact else 2 * 2 * 19 * elem
     mlups = N * args.steps / (ms / 1e3) / 1e6
     achieved = bytes_node * N / (ms_step / 1e3) / 1e9
     traffic = read_traffic(kname) if args.precision == "f32" and args.size == 256 else None

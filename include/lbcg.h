@@ -69,23 +69,28 @@ extern "C" {
  * D2Q9, any geometry).  Automatic picks the fused kernel where it applies.
  *
  * LBCG_KERNEL_COMPACT (never picked automatically): the fused sweeps on a
- * compact state, for periodic lattices (no mask), F32, regularized
- * collision; D3Q19 with tiles of 8 rows (tile[0] 0 or 8) or D2Q9; 2Q x 4 x
- * pitch bytes below 4 GiB (pitch = node count rounded up to 64).  Eq. (10)
+ * compact state, for periodic lattices (no mask), regularized collision;
+ * D3Q19 with F32 or F16 storage and tiles of 8 rows (tile[0] 0 or 8), or
+ * D2Q9 with F32 storage; the pair state (2Q x 4 x pitch bytes for F32,
+ * 2Q x 2 x pitch for F16) below 4 GiB (pitch = node count rounded up to
+ * 64).  Eq. (10)
  * splits every population of a node with coefficients that depend only on
  * that node and on the speed class of the direction, so each node stores its
  * Q total populations and its colour scalars (its minority share and one
  * vector per speed class) and the receiver of a population splits it: 192
  * bytes of memory traffic per node and step instead of 304 (D3Q19), 104
- * instead of 144 (D2Q9).  Results
- * agree with the pair-state kernels up to rounding.  The first step
+ * instead of 144 (D2Q9).  F16 storage keeps the totals (over w_i), the
+ * axis vector and the diagonal ratio in F16, rounded stochastically, and
+ * the minority share in F32: 100 bytes per node and step instead of the
+ * F16 pair state's 152.  Results agree with the pair-state kernels up to
+ * rounding.  The first step
  * after lbcg_init_fields or lbcg_set_state reads the pair state; the calls
  * that read the state (fields, populations, diagnostics, lbcg_get_state)
  * first convert the compact state to a pair state in the handle's pair
  * buffer, which the compact steps leave unused (one extra kernel, no change
  * to the trajectory).  lbcg_footprint
- * adds the two compact buffers (2 x 96 x pitch bytes for D3Q19, 2 x 52 x
- * pitch for D2Q9). */
+ * adds the two compact buffers (2 x 96 x pitch bytes for D3Q19 F32, 2 x 50
+ * x pitch for D3Q19 F16, 2 x 52 x pitch for D2Q9). */
 #define LBCG_KERNEL_AUTO 0
 #define LBCG_KERNEL_GENERIC 1
 #define LBCG_KERNEL_FUSED 2
@@ -282,8 +287,8 @@ int lbcg_tune(lbcg_sim *s, int32_t *rows, int32_t *zchunks);
  * refers to existing handles; it does not own them, and they must outlive
  * it.  Requirements: every handle initialised, all on the fused kernel
  * (D3Q19, F32 or F16 storage, regularized collision; geometry and periodic
- * lattices may mix) or all on the compact kernel, one storage precision, one
- * stream, no handle listed twice.
+ * lattices may mix) or all on the compact kernel with F32 storage, one
+ * storage precision, one stream, no handle listed twice.
  * tile: {rows per block (4 or 8; 8 on the compact kernel), z planes per
  * chunk (>= 1)}; NULL or {0, 0}
  * = choose by timing candidate shapes on the batch (the states do not

@@ -12,8 +12,8 @@ namespace {
 // bands (blocks go to XCDs round-robin), so each XCD sweeps a compact band of
 // tiles and the ring re-reads mostly hit its L2.  Tiles TX x 8: TX = 64
 // (512 threads, one block per CU) or 32 (256 threads, several blocks per CU,
-// each with its own barrier).
-template <bool PAIR_IN, int TX>
+// each with its own barrier).  S: storage of the state (float or _Float16).
+template <bool PAIR_IN, int TX, typename S>
 __global__ void __launch_bounds__(TX * kCR) k_step_compact(CompactArgs a, Model<float> mo) {
     extern __shared__ float lds[];
     const int total = a.ntx * a.nty * a.zchunks;
@@ -21,26 +21,31 @@ __global__ void __launch_bounds__(TX * kCR) k_step_compact(CompactArgs a, Model<
     const int item = xcd * (total / kCXCD) + min(xcd, total % kCXCD) + l;
     if (item == 0 && threadIdx.x == 0) *a.ctr_out = *a.ctr_in + 1u;
     if (PAIR_IN)
-        sweep_pairs<TX>(a, mo, item / a.zchunks, item % a.zchunks, lds);
+        sweep_pairs<TX, S>(a, mo, item / a.zchunks, item % a.zchunks, lds);
     else
-        sweep_compact<true, TX>(a, mo, item / a.zchunks, item % a.zchunks, lds);
+        sweep_compact<true, TX, S>(a, mo, item / a.zchunks, item % a.zchunks, lds);
 }
 
 // Pair state of nodes [0, N) from a compact state: each population's
 // minority colour part M f_i + (c_i . V_c) / 36 (the split the receiver
 // makes), as a share of f_i, with the flag of the colour it belongs to.
-__global__ void k_expand(const float *__restrict__ cin, typename PairOf<float>::type *__restrict__ pout, int64_t N,
+template <typename S>
+__global__ void k_expand(const uint8_t *__restrict__ cin, typename PairOf<S>::type *__restrict__ pout, int64_t N,
                          int64_t pitch) {
     using L = D3Q19;
+    typedef CStore<S> St;
     const int64_t n = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (n >= N) return;
-    const float *ra = cin + int64_t(L::Q) * pitch + 4 * n, *rb = cin + int64_t(L::Q + 4) * pitch + n;
+    const uint8_t *rec = cin + int64_t(L::Q) * pitch * St::E;
+    const typename St::RawB rb = *reinterpret_cast<const typename St::RawB *>(rec + St::kRecA * pitch + St::kRecB * n);
+    const f4 e = St::entry(*reinterpret_cast<const typename St::RawA *>(rec + St::kRecA * n), rb);
+    const float Rd = St::ratio(rb);
     bool fl;
-    const float M = Codec<float>::col<float>(ra[0], fl);
-    const float Va[3] = {ra[1], ra[2], ra[3]}, Rd = rb[0];
+    const float M = Codec<float>::col<float>(e[0], fl);
+    const float Va[3] = {e[1], e[2], e[3]};
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) {
-        const float d = cin[int64_t(i) * pitch + n];
+        const float d = St::df(*reinterpret_cast<const typename St::Raw *>(cin + (int64_t(i) * pitch + n) * St::E), i);
         const int n2 = csq<L>(i);
         // the receiver's expression: c_i . V_axis, times R_d for a diagonal
         const float cva = float(L::cx[i]) * Va[0] + float(L::cy[i]) * Va[1] + float(L::cz[i]) * Va[2];
@@ -49,29 +54,43 @@ __global__ void k_expand(const float *__restrict__ cin, typename PairOf<float>::
         const float mu36 = M * (float(w36<L>(i)) + 36.0f * d) + vd;
         const float q = f != 0.0f ? mu36 / (36.0f * f) : 0.0f;
         const bool keep = q <= 0.5f;
-        pout[int64_t(i) * pitch + n] = encode_pair<L, float, float>(d, keep ? q : 1.0f - q, keep ? fl : !fl, i);
+        pout[int64_t(i) * pitch + n] = encode_pair<L, S, float>(d, keep ? q : 1.0f - q, keep ? fl : !fl, i);
     }
+}
+
+template <bool PAIR_IN, typename S>
+const void *compact_kernel(int tx) {
+    return tx == 32 ? reinterpret_cast<const void *>(&k_step_compact<PAIR_IN, 32, S>)
+                    : reinterpret_cast<const void *>(&k_step_compact<PAIR_IN, 64, S>);
+}
+
+// The kernel (tile width tx, storage S) and its LDS, allowed beyond 64 KiB.
+template <bool PAIR_IN, typename S>
+const void *compact_fn(int tx, size_t &lds) {
+    lds = PAIR_IN ? (tx == 32 ? CTile<32>::lds_pair : CTile<64>::lds_pair) : (tx == 32 ? CTile<32>::lds : CTile<64>::lds);
+    if (!PAIR_IN) allow_lds(compact_kernel<false, S>(tx), (tx == 32 ? 1 : 0) + (sizeof(S) == 2 ? 3 : 0), lds);
+    return compact_kernel<PAIR_IN, S>(tx);
 }
 
 }  // namespace
 
 
 // The first step reads the pair state, so both layouts must stay within
-// 32-bit byte offsets.
+// 32-bit byte offsets.  The D3Q19 sweep stores FP32 or FP16, the D2Q9 one
+// FP32.
 bool compact_supported(int lattice, int prec, const Geo &g) {
-    if (prec != 1 || g.mask != nullptr) return false;
-    if (lattice == 0) return g.nz == 1 && uint64_t(2 * D2Q9::Q) * uint64_t(g.pitch) * 4u < (uint64_t(1) << 32);
-    return lattice == 1 && uint64_t(2 * D3Q19::Q) * uint64_t(g.pitch) * 4u < (uint64_t(1) << 32);
+    if (g.mask != nullptr) return false;
+    if (lattice == 0) return prec == 1 && g.nz == 1 && uint64_t(2 * D2Q9::Q) * uint64_t(g.pitch) * 4u < (uint64_t(1) << 32);
+    const uint64_t elem = prec == 1 ? 4 : 2;
+    return lattice == 1 && (prec == 1 || prec == 2) &&
+           uint64_t(2 * D3Q19::Q) * uint64_t(g.pitch) * elem < (uint64_t(1) << 32);
 }
 
-int compact_resident_blocks(int tx) {
+int compact_resident_blocks(int tx, int prec) {
     int per_cu = 0;
-    const void *fn = tx == 32 ? reinterpret_cast<const void *>(&k_step_compact<false, 32>)
-                              : reinterpret_cast<const void *>(&k_step_compact<false, 64>);
-    if (tx == 32) allow_lds(fn, 1, CTile<32>::lds);
-    else allow_lds(fn, 0, CTile<64>::lds);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, tx * kCR,
-                                                     tx == 32 ? CTile<32>::lds : CTile<64>::lds) != hipSuccess) {
+    size_t lds = 0;
+    const void *fn = prec == 2 ? compact_fn<false, _Float16>(tx, lds) : compact_fn<false, float>(tx, lds);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, tx * kCR, lds) != hipSuccess) {
         (void)hipGetLastError();
         per_cu = 1;
     }
@@ -81,14 +100,15 @@ int compact_resident_blocks(int tx) {
     return (per_cu > 0 ? per_cu : 1) * cus;
 }
 
-hipError_t launch_step_compact(const Geo &g, const ModelD &md, const void *in, bool pair_in, void *out,
+hipError_t launch_step_compact(int prec, const Geo &g, const ModelD &md, const void *in, bool pair_in, void *out,
                                const uint32_t *ctr_in, uint32_t *ctr_out, FusedShape sh, hipStream_t s) {
     if (sh.rows != kCR || (sh.tx != 64 && sh.tx != 32)) return hipErrorInvalidValue;
-    if (g.mask || md.bgk) return hipErrorInvalidValue;
-    if (uint64_t(2 * D3Q19::Q) * uint64_t(g.pitch) * 4u >= (uint64_t(1) << 32)) return hipErrorInvalidValue;
+    if (g.mask || md.bgk || (prec != 1 && prec != 2)) return hipErrorInvalidValue;
+    if (uint64_t(2 * D3Q19::Q) * uint64_t(g.pitch) * (prec == 1 ? 4u : 2u) >= (uint64_t(1) << 32))
+        return hipErrorInvalidValue;
     CompactArgs a;
-    a.in = static_cast<const float *>(in);
-    a.out = static_cast<float *>(out);
+    a.in = in;
+    a.out = out;
     a.nx = g.nx;
     a.ny = g.ny;
     a.nz = g.nz;
@@ -101,29 +121,23 @@ hipError_t launch_step_compact(const Geo &g, const ModelD &md, const void *in, b
     const int64_t nblocks = int64_t(a.ntx) * a.nty * a.zchunks;
     if (nblocks > 0x7fffffff) return hipErrorInvalidValue;
     const Model<float> mo = to_model<float>(md);
-    const dim3 grid = dim3(unsigned(nblocks)), block = dim3(unsigned(sh.tx * kCR));
-    if (sh.tx == 32) {
-        allow_lds(reinterpret_cast<const void *>(&k_step_compact<false, 32>), 1, CTile<32>::lds);
-        if (pair_in)
-            hipLaunchKernelGGL((k_step_compact<true, 32>), grid, block, CTile<32>::lds_pair, s, a, mo);
-        else
-            hipLaunchKernelGGL((k_step_compact<false, 32>), grid, block, CTile<32>::lds, s, a, mo);
-    } else {
-        allow_lds(reinterpret_cast<const void *>(&k_step_compact<false, 64>), 0, CTile<64>::lds);
-        if (pair_in)
-            hipLaunchKernelGGL((k_step_compact<true, 64>), grid, block, CTile<64>::lds_pair, s, a, mo);
-        else
-            hipLaunchKernelGGL((k_step_compact<false, 64>), grid, block, CTile<64>::lds, s, a, mo);
-    }
-    return hipGetLastError();
+    size_t lds = 0;
+    const void *fn = prec == 2 ? (pair_in ? compact_fn<true, _Float16>(sh.tx, lds) : compact_fn<false, _Float16>(sh.tx, lds))
+                               : (pair_in ? compact_fn<true, float>(sh.tx, lds) : compact_fn<false, float>(sh.tx, lds));
+    void *args[] = {&a, const_cast<Model<float> *>(&mo)};
+    return hipLaunchKernel(fn, dim3(unsigned(nblocks)), dim3(unsigned(sh.tx * kCR)), args, lds, s);
 }
 
-hipError_t launch_expand(const Geo &g, const void *cin, void *pout, hipStream_t s) {
+hipError_t launch_expand(int prec, const Geo &g, const void *cin, void *pout, hipStream_t s) {
     if (g.N <= 0) return hipSuccess;
     const int64_t blocks = (g.N + 255) / 256;
     if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_expand, dim3(unsigned(blocks)), dim3(256), 0, s, static_cast<const float *>(cin),
-                       static_cast<typename PairOf<float>::type *>(pout), g.N, g.pitch);
+    if (prec == 2)
+        hipLaunchKernelGGL(k_expand<_Float16>, dim3(unsigned(blocks)), dim3(256), 0, s, static_cast<const uint8_t *>(cin),
+                           static_cast<typename PairOf<_Float16>::type *>(pout), g.N, g.pitch);
+    else
+        hipLaunchKernelGGL(k_expand<float>, dim3(unsigned(blocks)), dim3(256), 0, s, static_cast<const uint8_t *>(cin),
+                           static_cast<typename PairOf<float>::type *>(pout), g.N, g.pitch);
     return hipGetLastError();
 }
 

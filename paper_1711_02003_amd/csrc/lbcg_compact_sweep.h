@@ -1,7 +1,7 @@
 #pragma once
 // Device code of the fused single-pass D3Q19 RCG step on a compact state
-// (arXiv:1711.02003, Sec. II, Eqs. (1)-(11)), periodic lattices, FP32,
-// shared by the single-lattice kernels (lbcg_compact.hip) and the batched
+// (arXiv:1711.02003, Sec. II, Eqs. (1)-(11)), periodic lattices, FP32 or
+// FP16 storage with FP32 arithmetic, shared by the single-lattice kernels (lbcg_compact.hip) and the batched
 // one (lbcg_compact_batch.hip), which are built as separate objects so that
 // each gets the code-generation options measured best for it.
 //
@@ -16,13 +16,14 @@
 // population: it stores its 19 new total deviations and 5 colour scalars (M
 // with the majority flag in its lowest bit, V_axis, R_d), and the receiver
 // splits each pulled population with the scalars of the node it came from.
-// In exact arithmetic the step is the same as the pair-state step; it moves
-// 2 x (19 x 4 + 20) = 192 bytes per node instead of 2 x 38 x 4 = 304.
+// In exact arithmetic the step is the same as the pair-state step; in FP32
+// it moves 2 x (19 x 4 + 20) = 192 bytes per node instead of 2 x 38 x 4 =
+// 304, in FP16 2 x (19 x 2 + 12) = 100 instead of 152.
 //
-// Layout: 19 arrays of `pitch` floats (array i at i * pitch + node: total
-// deviation f_i - w_i), then `pitch` 16-byte records {M, V_axis x, y, z}
-// (record n at float 19 * pitch + 4 n) and an array of `pitch` floats R_d
-// (at float 23 * pitch + n).
+// Layout (FP32): 19 arrays of `pitch` floats (array i at i * pitch + node:
+// total deviation f_i - w_i), then `pitch` 16-byte records {M, V_axis x, y,
+// z} (record n at float 19 * pitch + 4 n) and an array of `pitch` floats R_d
+// (at float 23 * pitch + n).  The FP16 layout is given with CStore below.
 //
 // The sweep is the pair-state sweep's: a block owns a 64 x 8 column tile and
 // sweeps a chunk of z planes; plane z+1 is pulled (interior and a one-node
@@ -55,11 +56,6 @@ namespace {
 constexpr int kCTX = 64;                    // tile width of the batched sweep
 constexpr int kCR = 8;                      // tile rows
 constexpr int kCXCD = 8;
-// Scalar records: {M, V_axis} (16 B) in one array after the 19 total
-// arrays, R_d (4 B) in a second one; byte offsets from the first total
-// array: 19 x 4 x pitch + 16 n and 23 x 4 x pitch + 4 n.
-constexpr uint32_t kRecA = 16, kRecB = 4;
-constexpr int kRecBytes = int(kRecA + kRecB);
 constexpr int kNS = 5;                      // scalars kept in LDS: M, V_axis, R_d
 constexpr int kSSlots = 4;
 constexpr int kPSlots = 5;
@@ -86,6 +82,148 @@ struct CTile {
 };
 
 typedef float f4 __attribute__((ext_vector_type(4)));
+typedef float f2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+
+// Every buffer access takes its wave-uniform byte offset through
+// readfirstlane at the point of use: the compiler otherwise may merge equal
+// offsets of different accesses into vector registers and then wrap each
+// access in a loop over the distinct values of its scalar offset.
+__device__ __forceinline__ int su(uint32_t v) { return __builtin_amdgcn_readfirstlane(int(v)); }
+
+// Records are written with stores of at most 8 bytes per lane.  A wider
+// store (12 or 16 bytes) may read its data registers after later
+// instructions have been issued, and the compiler reuses those registers at
+// once (seen: the next store's address written into the first data register
+// of a 12-byte store, with its later lanes' data lost under memory
+// back-pressure).
+__device__ __forceinline__ void store_u2(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, u2 v) {
+    __builtin_amdgcn_raw_buffer_store_b64(v, r, int(voff), su(soff), kNonTemporal);
+}
+__device__ __forceinline__ void store_u1(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, uint32_t v) {
+    __builtin_amdgcn_raw_buffer_store_b32(v, r, int(voff), su(soff), kNonTemporal);
+}
+__device__ __forceinline__ void store_h1(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, uint16_t v) {
+    __builtin_amdgcn_raw_buffer_store_b16(v, r, int(voff), su(soff), kNonTemporal);
+}
+
+// Storage of the compact state, S = float or _Float16.  The state is 19
+// arrays of `pitch` totals (E bytes each), then `pitch` records A of kRecA
+// bytes and `pitch` records B of kRecB bytes.
+//   FP32: the values as computed; A = {M, V_axis x, y, z}, B = {R_d}
+//   (16 B and 4 B; 96 B per node).
+//   FP16: totals (f_i - w_i) / w_i, as the FP16 pair state stores them,
+//   rounded stochastically; A = {M as FP32, V_axis x, y as FP16},
+//   B = {V_axis z, R_d as FP16} (8 B and 4 B; 50 B per node).  M stays FP32
+//   because its rounding moves mass between the colours and one M serves
+//   all 19 populations of the node: at FP16 it random-walks each colour's
+//   mass about four times as fast as the FP16 pair state's independent
+//   per-population shares do.  V_axis (|V_axis| <= 9 beta k_axis) and R_d
+//   are rounded stochastically; neither changes a colour's mass (the sum of
+//   c_i . V over the directions of a class is zero).
+// Stochastic rounding takes 8 random bits per value from the node's
+// generator (seeded by the time step and x + nx (y + ny z)), so a rounding
+// error does not repeat step after step in a steady flow.  A sweep keeps
+// pulled totals and loaded records in their stored form while the loads are
+// in flight and decodes them at use; the LDS record planes always hold FP32
+// entries {M with flag, V_axis} and R_d.
+template <typename S>
+struct CStore;
+template <>
+struct CStore<float> {
+    static constexpr uint32_t E = 4, kRecA = 16, kRecB = 4;
+    typedef uint32_t Raw;
+    typedef f4 RawA;
+    typedef uint32_t RawB;
+    __device__ static __forceinline__ Raw load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+        return __builtin_amdgcn_raw_buffer_load_b32(r, int(voff), su(soff), 0);
+    }
+    __device__ static __forceinline__ float df(Raw v, int) { return __builtin_bit_cast(float, v); }
+    __device__ static __forceinline__ RawA load_a(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+        return __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(r, int(voff), su(soff), 0));
+    }
+    __device__ static __forceinline__ RawB load_b(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+        return __builtin_amdgcn_raw_buffer_load_b32(r, int(voff), su(soff), 0);
+    }
+    __device__ static __forceinline__ f4 entry(RawA v, RawB) { return v; }
+    __device__ static __forceinline__ float ratio(RawB v) { return __builtin_bit_cast(float, v); }
+    // Compact output of the node at byte column `own` (E bytes per node) of
+    // the plane that starts at node zcol.
+    __device__ static __forceinline__ void store(__amdgpu_buffer_rsrc_t rout, uint32_t own, uint32_t zcol, uint32_t pitch,
+                                                 const CompactOut<D3Q19, float> &o, uint32_t) {
+        // the direction stride as a value of its own: shared with the pulls'
+        // offsets, the compiler would keep its multiples in vector registers
+        const uint32_t cs = uint32_t(uniform(int(pitch * E)));
+        const uint32_t zoff = zcol * E;
+#pragma unroll
+        for (int i = 0; i < D3Q19::Q; ++i)
+            store_u1(rout, own, uint32_t(i) * cs + zoff, __builtin_bit_cast(uint32_t, o.df[i]));
+        const uint32_t ra = uint32_t(D3Q19::Q) * cs + zcol * kRecA,
+                       rb = uint32_t(D3Q19::Q) * cs + pitch * kRecA + zcol * kRecB;
+        const f2 a01 = {Codec<float>::enc_col<float>(o.M, o.redmaj), o.Va[0]}, a23 = {o.Va[1], o.Va[2]};
+        store_u2(rout, own * (kRecA / E), ra, __builtin_bit_cast(u2, a01));
+        store_u2(rout, own * (kRecA / E), ra + 8u, __builtin_bit_cast(u2, a23));
+        store_u1(rout, own * (kRecB / E), rb, __builtin_bit_cast(uint32_t, o.Rd));
+    }
+};
+template <>
+struct CStore<_Float16> {
+    static constexpr uint32_t E = 2, kRecA = 8, kRecB = 4;
+    typedef uint16_t Raw;
+    typedef u2 RawA;
+    typedef uint32_t RawB;
+    __device__ static __forceinline__ float h2f(uint32_t b) { return float(__builtin_bit_cast(_Float16, uint16_t(b))); }
+    __device__ static __forceinline__ Raw load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+        return __builtin_amdgcn_raw_buffer_load_b16(r, int(voff), su(soff), 0);
+    }
+    __device__ static __forceinline__ float df(Raw v, int i) {
+        return Codec<_Float16>::df<D3Q19, float>(__builtin_bit_cast(_Float16, v), i);
+    }
+    __device__ static __forceinline__ RawA load_a(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+        return __builtin_amdgcn_raw_buffer_load_b64(r, int(voff), su(soff), 0);
+    }
+    __device__ static __forceinline__ RawB load_b(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+        return __builtin_amdgcn_raw_buffer_load_b32(r, int(voff), su(soff), 0);
+    }
+    __device__ static __forceinline__ f4 entry(RawA a, RawB b) {
+        const f4 e = {__builtin_bit_cast(float, a[0]), h2f(a[1] & 0xffffu), h2f(a[1] >> 16), h2f(b & 0xffffu)};
+        return e;
+    }
+    __device__ static __forceinline__ float ratio(RawB b) { return h2f(b >> 16); }
+    // x rounded stochastically to FP16 with the 8 random bits r & 0xff on the
+    // top of its 13 discarded mantissa bits (the rounding of the FP16 pair
+    // state's deviations); the FP16 bits in the low half
+    __device__ static __forceinline__ uint32_t sr(float x, uint32_t r) {
+        const uint32_t t = (__float_as_uint(x) + ((r & 0xffu) << 5) + 16u) & ~0x1fffu;
+        return __builtin_bit_cast(uint16_t, _Float16(__uint_as_float(t)));
+    }
+    // Random words 0-4 give the 19 totals and R_d 8 bits each, word 5 gives
+    // V_axis.
+    __device__ static __forceinline__ void store(__amdgpu_buffer_rsrc_t rout, uint32_t own, uint32_t zcol, uint32_t pitch,
+                                                 const CompactOut<D3Q19, float> &o, uint32_t step) {
+        Dither dz(step, own / E + zcol);
+        uint32_t w = 0;
+        // the direction stride as a value of its own: shared with the pulls'
+        // offsets, the compiler would keep its multiples in vector registers
+        const uint32_t cs = uint32_t(uniform(int(pitch * E)));
+        const uint32_t zoff = zcol * E;
+#pragma unroll
+        for (int i = 0; i < D3Q19::Q; ++i) {
+            if ((i & 3) == 0) w = dz.next();
+            const _Float16 h = Codec<_Float16>::enc_df_sr<D3Q19, float>(o.df[i], i, w >> (8 * (i & 3)));
+            store_h1(rout, own, uint32_t(i) * cs + zoff, __builtin_bit_cast(uint16_t, h));
+        }
+        const uint32_t rd = sr(o.Rd, w >> 24);
+        w = dz.next();
+        const u2 ra = {__float_as_uint(Codec<float>::enc_col<float>(o.M, o.redmaj)),
+                       sr(o.Va[0], w) | (sr(o.Va[1], w >> 8) << 16)};
+        const uint32_t rb = sr(o.Va[2], w >> 16) | (rd << 16);
+        const uint32_t oa = uint32_t(D3Q19::Q) * cs + zcol * kRecA,
+                       ob = uint32_t(D3Q19::Q) * cs + pitch * kRecA + zcol * kRecB;
+        store_u2(rout, own * (kRecA / E), oa, ra);
+        store_u1(rout, own * (kRecB / E), ob, rb);
+    }
+};
 
 __device__ __forceinline__ void c_lds_barrier() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
@@ -94,8 +232,8 @@ __device__ __forceinline__ void c_lds_barrier() {
 }
 
 struct CompactArgs {
-    const float *in;  // compact state, or pair state (pair_in)
-    float *out;       // compact state
+    const void *in;  // compact state, or pair state (pair_in)
+    void *out;       // compact state
     int nx, ny, nz;
     int64_t pitch;
     const uint32_t *ctr_in;
@@ -120,33 +258,6 @@ __device__ __forceinline__ void col_offsets(const CompactArgs &a, int x, int y, 
         for (int c = 0; c < 3; ++c) t[c + 3 * b] = (xs[c] + uint32_t(a.nx) * ys[b]) * E;
 }
 
-// Every buffer access takes its wave-uniform byte offset through
-// readfirstlane at the point of use: the compiler otherwise may merge equal
-// offsets of different accesses into vector registers and then wrap each
-// access in a loop over the distinct values of its scalar offset.
-__device__ __forceinline__ int su(uint32_t v) { return __builtin_amdgcn_readfirstlane(int(v)); }
-
-__device__ __forceinline__ float load_f(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, int(voff), su(soff), 0));
-}
-__device__ __forceinline__ f4 load_f4(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
-    return __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(r, int(voff), su(soff), 0));
-}
-// Records are written with stores of at most 8 bytes per lane.  A wider
-// store (12 or 16 bytes) may read its data registers after later
-// instructions have been issued, and the compiler reuses those registers at
-// once (seen: the next store's address written into the first data register
-// of a 12-byte store, with its later lanes' data lost under memory
-// back-pressure).
-typedef float f2 __attribute__((ext_vector_type(2)));
-typedef unsigned int u2 __attribute__((ext_vector_type(2)));
-__device__ __forceinline__ void store_f2(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, f2 v) {
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, int(voff), su(soff), kNonTemporal);
-}
-__device__ __forceinline__ void store_f1(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, float v) {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, int(voff), su(soff), kNonTemporal);
-}
-
 // Byte offsets of planes z-1, z, z+1 (periodic) for plane size `plane`.
 __device__ __forceinline__ void z_offsets(int z, int nz, uint32_t plane, uint32_t zo[3]) {
     zo[0] = uint32_t(uniform(z == 0 ? nz - 1 : z - 1)) * plane;
@@ -155,21 +266,6 @@ __device__ __forceinline__ void z_offsets(int z, int nz, uint32_t plane, uint32_
 }
 
 __device__ __forceinline__ int wrapz_c(int z, int nz) { return z < 0 ? z + nz : (z >= nz ? z - nz : z); }
-
-// Compact output of one node at byte column `own` of plane z.
-__device__ __forceinline__ void store_compact(const CompactArgs &a, __amdgpu_buffer_rsrc_t rout, uint32_t own,
-                                              int z, const CompactOut<D3Q19, float> &o) {
-    const uint32_t cs = uint32_t(uniform(int(uint32_t(a.pitch) * 4u)));
-    const uint32_t zoff = uint32_t(uniform(z)) * (uint32_t(a.nx) * uint32_t(a.ny) * 4u);
-#pragma unroll
-    for (int i = 0; i < D3Q19::Q; ++i) store_pair<float>(rout, own, uint32_t(su(uint32_t(i) * cs + zoff)), o.df[i]);
-    // records: own and zoff count 4 bytes per node
-    const uint32_t ra = uint32_t(D3Q19::Q) * cs + zoff * 4u, rb = uint32_t(D3Q19::Q + 4) * cs + zoff;
-    const f2 a01 = {Codec<float>::enc_col<float>(o.M, o.redmaj), o.Va[0]}, a23 = {o.Va[1], o.Va[2]};
-    store_f2(rout, own * 4u, ra, a01);
-    store_f2(rout, own * 4u, ra + 8u, a23);
-    store_f1(rout, own, rb, o.Rd);
-}
 
 // Split of the 19 pulled totals d of a node with its senders' scalars, read
 // from the LDS record planes sl[0..2] (planes p-1, p, p+1 of the pulled plane
@@ -226,14 +322,15 @@ __device__ __forceinline__ void split_pulled(const float d[D3Q19::Q], const floa
 }
 
 // ------------------------------------------------------------- compact in
-template <bool ENTRIES, int TX>
+template <bool ENTRIES, int TX, typename S = float>
 __device__ __forceinline__ void sweep_compact(const CompactArgs &a, const Model<float> &mo, int tile, int chunk,
                                               float *lds) {
     using L = D3Q19;
     typedef float T;
-    typedef CTile<TX> S;
-    constexpr int kCTX = TX, kSW = S::SW, kSN = S::SN, kPW = S::PW, kPN = S::PN;
-    constexpr int kLoad0 = S::load0, kLoaders = S::loaders, kPerLoader = S::per;
+    typedef CTile<TX> G;
+    typedef CStore<S> St;
+    constexpr int kCTX = TX, kSW = G::SW, kSN = G::SN, kPW = G::PW, kPN = G::PN;
+    constexpr int kLoad0 = G::load0, kLoaders = G::loaders, kPerLoader = G::per;
     const int lane = threadIdx.x % kCTX, row = threadIdx.x / kCTX;
     const int tx = tile % a.ntx, ty = tile / a.ntx;
     const int x0 = tx * kCTX, y0 = ty * kCR;
@@ -245,7 +342,7 @@ __device__ __forceinline__ void sweep_compact(const CompactArgs &a, const Model<
     const bool intile = lane < tw && row < th;
     const int x = x0 + lane, y = y0 + row;
 
-    // ring node of this thread (at most one; threads below S::ring, all in
+    // ring node of this thread (at most one; threads below G::ring, all in
     // the waves before kLoad0)
     const int nring = 2 * (tw + 2) + 2 * th;
     int rx = 0, ry = 0;
@@ -266,15 +363,18 @@ __device__ __forceinline__ void sweep_compact(const CompactArgs &a, const Model<
     }
     const int gx = wrap_m1(x0 + rx, a.nx), gy = wrap_m1(y0 + ry, a.ny);
 
-    const uint32_t bytes = uint32_t(L::Q) * uint32_t(a.pitch) * 4u + uint32_t(a.pitch) * uint32_t(kRecBytes);
+    const uint32_t pitch = uint32_t(a.pitch);
+    const uint32_t bytes = uint32_t(L::Q) * pitch * St::E + pitch * (St::kRecA + St::kRecB);
     const __amdgpu_buffer_rsrc_t rin = state_rsrc(a.in, bytes);
     const __amdgpu_buffer_rsrc_t rout = state_rsrc(a.out, bytes);
-    const uint32_t cs = uint32_t(uniform(int(uint32_t(a.pitch) * 4u)));
-    const uint32_t plane4 = uint32_t(a.nx) * uint32_t(a.ny) * 4u;
+    const uint32_t cs = uint32_t(uniform(int(pitch * St::E)));
+    const uint32_t planeE = uint32_t(a.nx) * uint32_t(a.ny) * St::E;
     uint32_t ixy[9], rxy[9];
-    col_offsets<4>(a, intile ? x : 0, intile ? y : 0, ixy);
-    col_offsets<4>(a, gx, gy, rxy);
+    col_offsets<St::E>(a, intile ? x : 0, intile ? y : 0, ixy);
+    col_offsets<St::E>(a, gx, gy, rxy);
     const uint32_t own = ixy[4];
+    uint32_t step = 0;  // seeds the stochastic rounding of FP16 output
+    if constexpr (sizeof(S) == 2) step = *a.ctr_in;
 
     // record loaders: up to kPerLoader nodes of the (tw + 4) x (th + 4) tile
     const int sw = tw + 4, sn = sw * (th + 4);
@@ -289,8 +389,8 @@ __device__ __forceinline__ void sweep_compact(const CompactArgs &a, const Model<
         lidx[k] = (sy + 2) * kSW + (sx + 2);
         lcol[k] = uint32_t(wrap_any(x0 + sx, a.nx)) + uint32_t(a.nx) * uint32_t(wrap_any(y0 + sy, a.ny));
     }
-    f4 lq0[kPerLoader];
-    float lq1[kPerLoader];
+    typename St::RawA lq0[kPerLoader];
+    typename St::RawB lq1[kPerLoader];
 
     float *psi_lds = lds;
     float *rec_lds = lds + kPSlots * kPN;
@@ -299,12 +399,13 @@ __device__ __forceinline__ void sweep_compact(const CompactArgs &a, const Model<
 
     auto rec_issue = [&](int q) {
         const uint32_t zq = uint32_t(uniform(wrap_any(q, a.nz))) * (uint32_t(a.nx) * uint32_t(a.ny));
-        const uint32_t ra = uint32_t(L::Q) * cs + zq * kRecA, rb = uint32_t(L::Q + 4) * cs + zq * kRecB;
+        const uint32_t ra = uint32_t(L::Q) * cs + zq * St::kRecA,
+                       rb = uint32_t(L::Q) * cs + pitch * St::kRecA + zq * St::kRecB;
 #pragma unroll
         for (int k = 0; k < kPerLoader; ++k)
             if (lon[k]) {
-                lq0[k] = load_f4(rin, lcol[k] * kRecA, ra);
-                lq1[k] = load_f(rin, lcol[k] * kRecB, rb);
+                lq0[k] = St::load_a(rin, lcol[k] * St::kRecA, ra);
+                lq1[k] = St::load_b(rin, lcol[k] * St::kRecB, rb);
             }
     };
     auto rec_write = [&](int q) {
@@ -312,25 +413,27 @@ __device__ __forceinline__ void sweep_compact(const CompactArgs &a, const Model<
 #pragma unroll
         for (int k = 0; k < kPerLoader; ++k)
             if (lon[k]) {
+                const f4 e = St::entry(lq0[k], lq1[k]);
                 if constexpr (ENTRIES) {
-                    reinterpret_cast<f4 *>(s)[lidx[k]] = lq0[k];
+                    reinterpret_cast<f4 *>(s)[lidx[k]] = e;
                 } else {
-                    s[0 * kSN + lidx[k]] = lq0[k][0];
-                    s[1 * kSN + lidx[k]] = lq0[k][1];
-                    s[2 * kSN + lidx[k]] = lq0[k][2];
-                    s[3 * kSN + lidx[k]] = lq0[k][3];
+                    s[0 * kSN + lidx[k]] = e[0];
+                    s[1 * kSN + lidx[k]] = e[1];
+                    s[2 * kSN + lidx[k]] = e[2];
+                    s[3 * kSN + lidx[k]] = e[3];
                 }
-                s[4 * kSN + lidx[k]] = lq1[k];
+                s[4 * kSN + lidx[k]] = St::ratio(lq1[k]);
             }
     };
 
-    float rd[L::Q], id[L::Q];  // pulled totals of the ring node and of the interior node
-    auto pull = [&](const uint32_t t[9], int zp, float d[L::Q]) {
+    // pulled totals of the ring node and of the interior node, as stored
+    typename St::Raw rd[L::Q], id[L::Q];
+    auto pull = [&](const uint32_t t[9], int zp, typename St::Raw d[L::Q]) {
         uint32_t zo[3];
-        z_offsets(wrapz_c(zp, a.nz), a.nz, plane4, zo);
+        z_offsets(wrapz_c(zp, a.nz), a.nz, planeE, zo);
 #pragma unroll
         for (int i = 0; i < L::Q; ++i)
-            d[i] = load_f(rin, t[(1 - L::cx[i]) + 3 * (1 - L::cy[i])], uint32_t(i) * cs + zo[1 - L::cz[i]]);
+            d[i] = St::load(rin, t[(1 - L::cx[i]) + 3 * (1 - L::cy[i])], uint32_t(i) * cs + zo[1 - L::cz[i]]);
     };
     auto ring_issue = [&](int zp) {
         if (has_ring) pull(rxy, zp, rd);
@@ -338,8 +441,11 @@ __device__ __forceinline__ void sweep_compact(const CompactArgs &a, const Model<
     auto interior_issue = [&](int zp) {
         if (intile) pull(ixy, zp, id);
     };
-    auto split = [&](const float d[L::Q], int zp, int c, CPops<L, T> &q) {
+    auto split = [&](const typename St::Raw raw[L::Q], int zp, int c, CPops<L, T> &q) {
         const float *const sl[3] = {rslot(zp - 1), rslot(zp), rslot(zp + 1)};
+        float d[L::Q];
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i) d[i] = St::df(raw[i], i);
         split_pulled<ENTRIES, kSW, kSN>(d, sl, c, q);
     };
     const int ci = (row + 2) * kSW + lane + 2, cr = (ry + 2) * kSW + rx + 2;
@@ -440,7 +546,7 @@ __device__ __forceinline__ void sweep_compact(const CompactArgs &a, const Model<
             const T F[3] = {fx, fy, fz};
             CompactOut<L, T> o;
             collide<L, T>(mo, cd, cR, cB, cj, cS, F, nullptr, o);
-            store_compact(a, rout, own, z, o);
+            St::store(rout, own, uint32_t(uniform(z)) * (uint32_t(a.nx) * uint32_t(a.ny)), pitch, o, step);
         }
         cd = nd;
         cR = nR;
@@ -455,39 +561,43 @@ __device__ __forceinline__ void sweep_compact(const CompactArgs &a, const Model<
 // ------------------------------------------------------------- pair in
 // The first step after an initialisation or a restore: pulls (total
 // deviation, share) pairs, whose colour split needs no sender scalars.
+template <typename S>
 struct PendP {
-    typename PairOf<float>::type v[D3Q19::Q];
+    typename PairOf<S>::type v[D3Q19::Q];
     __device__ __forceinline__ void take(CPops<D3Q19, float> &p) const {
         p.red = 0;
 #pragma unroll
         for (int i = 0; i < D3Q19::Q; ++i) {
             bool fl;
-            p.df[i] = v[i].x;
-            p.mm[i] = Codec<float>::col<float>(v[i].y, fl);
+            p.df[i] = Codec<S>::template df<D3Q19, float>(v[i].x, i);
+            p.mm[i] = Codec<S>::template col<float>(v[i].y, fl);
             p.red |= fl ? (1u << i) : 0u;
             p.vd[i] = 0.0f;
         }
     }
 };
 
+template <typename S>
 __device__ __forceinline__ void pull_pairs(const CompactArgs &a, __amdgpu_buffer_rsrc_t r, const uint32_t t[9],
-                                           int z, PendP &pd) {
+                                           int z, PendP<S> &pd) {
     using L = D3Q19;
-    const uint32_t plane = uint32_t(a.nx) * uint32_t(a.ny) * 8u;
-    const uint32_t cs = uint32_t(uniform(int(uint32_t(a.pitch) * 8u)));
+    typedef typename PairOf<S>::type P;
+    const uint32_t plane = uint32_t(a.nx) * uint32_t(a.ny) * uint32_t(sizeof(P));
+    const uint32_t cs = uint32_t(uniform(int(uint32_t(a.pitch) * uint32_t(sizeof(P)))));
     uint32_t zo[3];
     z_offsets(z, a.nz, plane, zo);
 #pragma unroll
     for (int i = 0; i < L::Q; ++i)
-        pd.v[i] = load_pair<typename PairOf<float>::type>(r, t[(1 - L::cx[i]) + 3 * (1 - L::cy[i])],
-                                                          uint32_t(su(uint32_t(i) * cs + zo[1 - L::cz[i]])));
+        pd.v[i] = load_pair<P>(r, t[(1 - L::cx[i]) + 3 * (1 - L::cy[i])], uint32_t(su(uint32_t(i) * cs + zo[1 - L::cz[i]])));
 }
 
-template <int TX>
+template <int TX, typename S = float>
 __device__ __forceinline__ void sweep_pairs(const CompactArgs &a, const Model<float> &mo, int tile, int chunk,
                                             float *lds) {
     using L = D3Q19;
     typedef float T;
+    typedef CStore<S> St;
+    constexpr uint32_t PB = sizeof(typename PairOf<S>::type);
     constexpr int kCTX = TX, R = kCR, W = CTile<TX>::PW, PL = CTile<TX>::PN;
     const int lane = threadIdx.x % kCTX, row = threadIdx.x / kCTX;
     const int tx = tile % a.ntx, ty = tile / a.ntx;
@@ -518,16 +628,21 @@ __device__ __forceinline__ void sweep_pairs(const CompactArgs &a, const Model<fl
     }
     const int gx = wrap_m1(x0 + rx, a.nx), gy = wrap_m1(y0 + ry, a.ny);
 
-    const __amdgpu_buffer_rsrc_t rin = state_rsrc(a.in, uint32_t(2 * L::Q) * uint32_t(a.pitch) * 4u);
-    const __amdgpu_buffer_rsrc_t rout =
-        state_rsrc(a.out, uint32_t(L::Q) * uint32_t(a.pitch) * 4u + uint32_t(a.pitch) * uint32_t(kRecBytes));
+    const uint32_t pitch = uint32_t(a.pitch);
+    const __amdgpu_buffer_rsrc_t rin = state_rsrc(a.in, uint32_t(L::Q) * pitch * PB);
+    const __amdgpu_buffer_rsrc_t rout = state_rsrc(a.out, uint32_t(L::Q) * pitch * St::E + pitch * (St::kRecA + St::kRecB));
+    const uint32_t cs = uint32_t(uniform(int(pitch * St::E)));
+    const uint32_t plane = uint32_t(a.nx) * uint32_t(a.ny);
     uint32_t ixy[9], rxy[9], oxy[9];
-    col_offsets<8>(a, intile ? x : 0, intile ? y : 0, ixy);
-    col_offsets<8>(a, gx, gy, rxy);
-    col_offsets<4>(a, intile ? x : 0, intile ? y : 0, oxy);
+    col_offsets<PB>(a, intile ? x : 0, intile ? y : 0, ixy);
+    col_offsets<PB>(a, gx, gy, rxy);
+    col_offsets<St::E>(a, intile ? x : 0, intile ? y : 0, oxy);
+    const uint32_t own = oxy[4];
+    uint32_t step = 0;  // seeds the stochastic rounding of FP16 output
+    if constexpr (sizeof(S) == 2) step = *a.ctr_in;
 
     auto slot_of = [&](int zp) { return lds + ((zp - z0 + 1) % kPSlots) * PL; };
-    PendP rp, pp;
+    PendP<S> rp, pp;
     auto ring_issue = [&](int zp) {
         if (has_ring) pull_pairs(a, rin, rxy, wrapz_c(zp, a.nz), rp);
     };
@@ -604,7 +719,7 @@ __device__ __forceinline__ void sweep_pairs(const CompactArgs &a, const Model<fl
             const T F[3] = {fx, fy, fz};
             CompactOut<L, T> o;
             collide<L, T>(mo, cd, cR, cB, cj, cS, F, nullptr, o);
-            store_compact(a, rout, oxy[4], z, o);
+            St::store(rout, own, uint32_t(uniform(z)) * plane, pitch, o, step);
         }
         cd = nd;
         cR = nR;
@@ -618,8 +733,9 @@ __device__ __forceinline__ void sweep_pairs(const CompactArgs &a, const Model<fl
 
 constexpr size_t kCompactLds = CTile<kCTX>::lds;  // the batched sweep's 64 x 8 tiles
 
-// Allows a compact kernel (k = 0, 1: single lattice, 64 and 32 wide; 2:
-// batched) its LDS beyond 64 KiB, once per device and kernel.
+// Allows a compact kernel (k = 0, 1: single lattice, FP32, 64 and 32 wide;
+// 2: batched; 3, 4: single lattice, FP16, 64 and 32 wide) its LDS beyond
+// 64 KiB, once per device and kernel.
 void allow_lds(const void *fn, int k, size_t bytes) {
     static std::mutex mu;
     static std::set<std::pair<int, int>> done;

@@ -105,19 +105,21 @@ hipError_t launch_step_fused2d(int prec, const Geo &g, const ModelD &md, const v
                                const uint32_t *ctr_in, uint32_t *ctr_out, int ychunks, hipStream_t s);
 bool fused2d_supported(int prec, const Geo &g);
 
-// Fused D3Q19 step on the compact state (periodic, FP32, regularized, tiles
-// of 8 rows): 19 arrays of pitch floats (total deviations) and 5 colour
-// scalars per node in two record arrays, kCompactBytes per pitch node.  pair_in: `in` is
-// a pair state (the first step after an initialisation or a restore); `out`
-// is always compact.
-constexpr int kCompactBytes = 19 * 4 + 20;  // D3Q19: 19 totals, 5 scalars
-constexpr int kCompactBytes2d = 9 * 4 + 16;  // D2Q9: 9 totals, 4 scalars
-hipError_t launch_step_compact(const Geo &g, const ModelD &md, const void *in, bool pair_in, void *out,
+// Fused D3Q19 step on the compact state (periodic, regularized, tiles of 8
+// rows, FP32 or FP16 storage): 19 arrays of pitch totals and 5 colour
+// scalars per node in two record arrays, kCompactBytes (FP32) or
+// kCompactBytes16 (FP16) per pitch node.  pair_in: `in` is a pair state of
+// the same precision (the first step after an initialisation or a restore);
+// `out` is always compact.
+constexpr int kCompactBytes = 19 * 4 + 20;    // D3Q19, FP32: 19 totals, 5 scalars
+constexpr int kCompactBytes16 = 19 * 2 + 12;  // D3Q19, FP16 (M kept FP32)
+constexpr int kCompactBytes2d = 9 * 4 + 16;   // D2Q9: 9 totals, 4 scalars
+hipError_t launch_step_compact(int prec, const Geo &g, const ModelD &md, const void *in, bool pair_in, void *out,
                                const uint32_t *ctr_in, uint32_t *ctr_out, FusedShape shape, hipStream_t s);
 bool compact_supported(int lattice, int prec, const Geo &g);
-int compact_resident_blocks(int tile_width);
+int compact_resident_blocks(int tile_width, int prec);
 // Pair state (post-collision, as the pair kernels store it) of a compact state.
-hipError_t launch_expand(const Geo &g, const void *cin, void *pout, hipStream_t s);
+hipError_t launch_expand(int prec, const Geo &g, const void *cin, void *pout, hipStream_t s);
 // The D2Q9 strip sweep on the compact state (periodic, FP32, regularized):
 // 9 arrays of pitch floats and 4 colour scalars per node in one record
 // array, kCompactBytes2d per pitch node; rows split into ychunks.

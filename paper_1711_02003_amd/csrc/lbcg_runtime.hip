@@ -95,7 +95,8 @@ Plan make_plan(const lbcg_params *p) {
     const int per = 2 * pl.Q > 6 ? 2 * pl.Q : 6;
     pl.state = align_up(size_t(2 * pl.Q) * size_t(pl.pitch) * pl.elem, kAlign);
     pl.cstate = p->kernel == LBCG_KERNEL_COMPACT
-                    ? align_up(size_t(p->lattice == LBCG_D2Q9 ? kCompactBytes2d : kCompactBytes) *
+                    ? align_up(size_t(p->lattice == LBCG_D2Q9 ? kCompactBytes2d
+                                                                  : (p->precision == LBCG_F16 ? kCompactBytes16 : kCompactBytes)) *
                                    size_t(pl.pitch),
                                kAlign)
                     : 0;
@@ -150,7 +151,7 @@ hipError_t launch_compact(const lbcg_sim *s, const void *in, bool pair_in, void 
                           uint32_t *ctr_out, FusedShape shape) {
     if (s->lattice == LBCG_D2Q9)
         return launch_step_compact2d(s->g, s->md, in, pair_in, out, ctr_in, ctr_out, shape.zchunks, s->stream);
-    return launch_step_compact(s->g, s->md, in, pair_in, out, ctr_in, ctr_out, shape, s->stream);
+    return launch_step_compact(s->prec, s->g, s->md, in, pair_in, out, ctr_in, ctr_out, shape, s->stream);
 }
 
 FusedShape pick_shape(const lbcg_sim *s, const lbcg_params *p) {
@@ -179,7 +180,7 @@ FusedShape pick_shape(const lbcg_sim *s, const lbcg_params *p) {
         // as few (long) chunks as fill the device, but keep chunks >= 8 planes.
         const int64_t tiles = int64_t((s->g.nx + sh.tx - 1) / sh.tx) * ((s->g.ny + sh.rows - 1) / sh.rows);
         const int64_t resident = s->kernel == LBCG_KERNEL_COMPACT
-                                     ? compact_resident_blocks(sh.tx)
+                                     ? compact_resident_blocks(sh.tx, s->prec)
                                      : fused_resident_blocks(s->prec, sh.rows, s->g.mask != nullptr);
         int64_t want = (resident + tiles - 1) / tiles;
         const int64_t cap = s->g.nz / 8 > 1 ? s->g.nz / 8 : 1;
@@ -539,7 +540,7 @@ int lbcg_step(lbcg_sim *s, int64_t n) {
 static hipError_t ensure_pairs(lbcg_sim *s) {
     if (!s->compact || s->expanded) return hipSuccess;
     hipError_t e = s->lattice == LBCG_D2Q9 ? launch_expand2d(s->g, s->cbuf[s->cur], s->buf[s->cur], s->stream)
-                                           : launch_expand(s->g, s->cbuf[s->cur], s->buf[s->cur], s->stream);
+                                           : launch_expand(s->prec, s->g, s->cbuf[s->cur], s->buf[s->cur], s->stream);
     if (e == hipSuccess) s->expanded = true;
     return e;
 }
@@ -755,7 +756,7 @@ int lbcg_tune(lbcg_sim *s, int32_t *rows, int32_t *zchunks) {
             if (s->lattice == LBCG_D2Q9) break;
             if (cmp ? r != 8 : tx != 64) continue;
             const int64_t tiles = int64_t((s->g.nx + tx - 1) / tx) * ((s->g.ny + r - 1) / r);
-            const int64_t resident = cmp ? compact_resident_blocks(tx) : fused_resident_blocks(s->prec, r, masked);
+            const int64_t resident = cmp ? compact_resident_blocks(tx, s->prec) : fused_resident_blocks(s->prec, r, masked);
             std::vector<int64_t> zs = {1};
             for (int m : {1, 2, 4}) zs.push_back((m * resident + tiles - 1) / tiles);
             for (int planes : {2, 4, 8, 16, 32, 64}) zs.push_back((s->g.nz + planes - 1) / planes);

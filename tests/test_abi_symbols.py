@@ -82,6 +82,12 @@ def test_compact_footprint_adds_two_compact_buffers(lib):
     extra = lbcg.footprint(c) - lbcg.footprint(f)
     one = -(-(19 * 4 + 20) * pitch // 256) * 256
     assert one * 2 - 512 <= extra <= one * 2 + 512, (extra, one)
+    # FP16: 19 x 2 B of totals, 12 B of colour scalars (M in FP32)
+    f16, keep4 = lbcg.make_params("D3Q19", dims, 1.0, 0.6, 0.005, 0.005, 0.7, "f16", kernel=lbcg.KERNEL_FUSED)
+    c16, keep5 = lbcg.make_params("D3Q19", dims, 1.0, 0.6, 0.005, 0.005, 0.7, "f16", kernel=lbcg.KERNEL_COMPACT)
+    extra = lbcg.footprint(c16) - lbcg.footprint(f16)
+    one = -(-(19 * 2 + 12) * pitch // 256) * 256
+    assert one * 2 - 512 <= extra <= one * 2 + 512, (extra, one)
     # 8-row tiles only; 32-wide tiles on the compact D3Q19 sweep only
     t, keep3 = lbcg.make_params("D3Q19", dims, 1.0, 0.6, 0.005, 0.005, 0.7, kernel=lbcg.KERNEL_COMPACT,
                                 tile=(4, 0, 0))

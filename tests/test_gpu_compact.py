@@ -269,7 +269,7 @@ def test_compact_largest_lattice_and_beyond(L, orc):
 
 def test_compact_rejects_what_it_does_not_cover(L):
     w = _droplets((16, 8, 8), seed=1)
-    for kw in ({"precision": "f16"}, {"precision": "f64"}, {"collision": L.BGK}):
+    for kw in ({"precision": "f64"}, {"collision": L.BGK}):
         with pytest.raises(L.LbcgError):
             L.Sim.from_workload(w, kernel=L.KERNEL_COMPACT, **kw)
     m = np.zeros(w.shape, np.uint8)
