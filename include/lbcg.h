@@ -163,7 +163,10 @@ typedef struct {
                             D3Q19 only), z chunks (D2Q9: row chunks; <= 4096),
                             tile width (64; the compact D3Q19 sweep also 32:
                             256-thread blocks, several per compute unit);
-                            0 = automatic */
+                            0 = automatic.  With a geometry mask on D3Q19,
+                            rows and z chunks both automatic pick the split
+                            step (reported as rows 0) when at most half the
+                            nodes are fluid, else the column sweep */
 } lbcg_params;
 
 /* FP64 diagnostics of the current state S_t (pre-collision), summed over fluid
@@ -267,12 +270,19 @@ const char *lbcg_strerror(int status);
 
 /* Launch shape chosen for the handle: kernel kind (LBCG_KERNEL_GENERIC,
  * LBCG_KERNEL_FUSED or LBCG_KERNEL_COMPACT), rows per block, z chunks, tile
- * width (64; or 32 on the compact D3Q19 sweep).  NULL outputs are skipped. */
+ * width (64; or 32 on the compact D3Q19 sweep).  rows 0 on the fused kernel:
+ * the split step of a D3Q19 lattice with geometry (one kernel pulls and
+ * writes every fluid node's psi and collision moments, a second forms the
+ * gradient, collides and stores, a third stores inlet and outlet values;
+ * bitwise the column sweep's results, without the sweep's recomputed tile
+ * ring and chunk halo, which dominate where the fluid fills few tiles).
+ * NULL outputs are skipped. */
 int lbcg_launch_info(lbcg_sim *s, int32_t *kernel, int32_t *rows, int32_t *zchunks, int32_t *tile_width);
 
 /* Choose the fused (or compact) kernel's launch shape for this handle by
  * timing candidate shapes on the handle's own lattice (D3Q19: rows 4 or 8,
- * 8 only for the compact kernel, which also tries 32-wide tiles; z splits
+ * 8 only for the compact kernel, which also tries 32-wide tiles, and with a
+ * geometry mask the split step; z splits
  * that fill the device once, twice or four times and chunks of 2 to 64
  * planes; D2Q9: row chunks of 8 to 512 rows), stepping the current state
  * into the spare buffer so the state does not change (the compact kernel is

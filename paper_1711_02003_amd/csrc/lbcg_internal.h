@@ -99,6 +99,29 @@ bool fused_supported(int lattice, int prec, const Geo &g);
 // Blocks of the fused kernel that fit on the device at once.
 int fused_resident_blocks(int prec, int rows, bool masked);
 
+// Split D3Q19 step for lattices with geometry (F32 or F16 storage,
+// regularized): a moments kernel writes psi (`psi`, pitch floats) and the
+// kSplitMoments collision moments of every fluid node, a collision kernel
+// takes the gradient, collides and stores, and a boundary kernel stores the
+// inlet and outlet values.  Bitwise the column sweep's results; chosen by
+// FusedShape rows 0.  The kernels run blocks of kSplitGX x kSplitGY nodes of
+// one z plane, only those with fluid (the boundary kernel: only those with
+// links from inlets or outlets), from block lists that split_prepare builds
+// on the device once per lattice in `scratch` (split_scratch_bytes: the
+// moments, then the lists).
+constexpr int kSplitMoments = 12;
+constexpr int kSplitGX = 64, kSplitGY = 4;
+int64_t split_blocks(int nx, int ny, int nz);
+size_t split_scratch_bytes(int64_t pitch, int nx, int ny, int nz);
+struct SplitPlan {
+    int64_t active = 0, io = 0;  // blocks with fluid, blocks with inlet or outlet links
+};
+// Builds the block lists and returns their lengths (waits for the stream).
+hipError_t split_prepare(const Geo &g, void *scratch, SplitPlan &sp, hipStream_t s);
+hipError_t launch_step_split(int prec, const Geo &g, const ModelD &md, const void *in, void *out, void *psi,
+                             void *scratch, const SplitPlan &sp, const uint32_t *ctr_in, uint32_t *ctr_out,
+                             hipStream_t s);
+
 // Fused single-pass D2Q9 step on periodic lattices, F32 or F16 storage:
 // strips of 64 columns, each row range split into ychunks.
 hipError_t launch_step_fused2d(int prec, const Geo &g, const ModelD &md, const void *in, void *out,

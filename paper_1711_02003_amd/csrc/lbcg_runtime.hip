@@ -28,7 +28,7 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 struct Plan {
     int Q;
     int64_t N, pitch, staging_nodes;
-    size_t elem, tsize, state, cstate, psi, mask, links, inl, outl, wall, partials, diag, ctr, staging, total;
+    size_t elem, tsize, state, cstate, psi, moms, mask, links, inl, outl, wall, partials, diag, ctr, staging, total;
 };
 
 int validate(const lbcg_params *p) {
@@ -101,6 +101,11 @@ Plan make_plan(const lbcg_params *p) {
                                kAlign)
                     : 0;
     pl.psi = align_up(size_t(pl.pitch) * pl.tsize, kAlign);
+    // the split geometry step's moments: D3Q19 with a mask, F32 or F16
+    pl.moms = p->mask && p->lattice == LBCG_D3Q19 && p->precision != LBCG_F64 &&
+                      (p->kernel == LBCG_KERNEL_AUTO || p->kernel == LBCG_KERNEL_FUSED)
+                  ? align_up(split_scratch_bytes(pl.pitch, p->dims[0], p->dims[1], p->dims[2]), kAlign)
+                  : 0;
     pl.mask = p->mask ? align_up(size_t(pl.pitch), kAlign) : 0;
     pl.links = p->mask ? align_up(sizeof(uint32_t) * size_t(pl.pitch), kAlign) : 0;
     pl.inl = align_up(sizeof(DevInlet) * size_t(p->n_inlets > 0 ? p->n_inlets : 1), kAlign);
@@ -110,7 +115,7 @@ Plan make_plan(const lbcg_params *p) {
     pl.diag = align_up(sizeof(double) * 16, kAlign);
     pl.ctr = kAlign;
     pl.staging = align_up(sizeof(double) * size_t(per) * size_t(pl.staging_nodes), kAlign);
-    pl.total = 2 * pl.state + 2 * pl.cstate + pl.psi + pl.mask + pl.links + pl.inl + pl.outl + pl.wall + pl.partials +
+    pl.total = 2 * pl.state + 2 * pl.cstate + pl.psi + pl.moms + pl.mask + pl.links + pl.inl + pl.outl + pl.wall + pl.partials +
                pl.diag + pl.ctr + pl.staging + kAlign;
     return pl;
 }
@@ -140,6 +145,9 @@ bool any_fused_supported(int lattice, int prec, const Geo &g) {
 
 hipError_t launch_fused(const lbcg_sim *s, const void *in, void *out, const uint32_t *ctr_in, uint32_t *ctr_out,
                         FusedShape shape) {
+    if (shape.rows == 0)
+        return launch_step_split(s->prec, s->g, s->md, in, out, s->psi, s->moms, s->split, ctr_in, ctr_out,
+                                 s->stream);
     if (s->lattice == LBCG_D2Q9)
         return launch_step_fused2d(s->prec, s->g, s->md, in, out, ctr_in, ctr_out, shape.zchunks, s->stream);
     return launch_step_fused(s->prec, s->g, s->md, in, out, ctr_in, ctr_out, shape, s->stream);
@@ -171,6 +179,18 @@ FusedShape pick_shape(const lbcg_sim *s, const lbcg_params *p) {
         }
         sh.zchunks = yc < 1 ? 1 : yc;
         return sh;
+    }
+    if (s->kernel == LBCG_KERNEL_FUSED && s->moms && !p->tile[0] && !p->tile[1] && p->mask) {
+        // With geometry, the split step when at most half the nodes are
+        // fluid: the fluid then fills few column tiles, which the sweep can
+        // spread over the device only in short z chunks.
+        int64_t fluid = 0;
+        for (int64_t n = 0; n < s->g.N; ++n) fluid += p->mask[n] == kFluid ? 1 : 0;
+        if (2 * fluid <= s->g.N) {
+            sh.rows = 0;
+            sh.zchunks = 1;
+            return sh;
+        }
     }
     sh.rows = p->tile[0] ? p->tile[0] : 8;
     sh.tx = p->tile[2] ? p->tile[2] : 64;
@@ -383,6 +403,8 @@ int lbcg_create(const lbcg_params *p, void *dev_buf, size_t bytes, void *hip_str
     base += pl.cstate;
     s->psi = base;
     base += pl.psi;
+    s->moms = pl.moms ? base : nullptr;
+    base += pl.moms;
     s->mask_dev = p->mask ? reinterpret_cast<uint8_t *>(base) : nullptr;
     base += pl.mask;
     uint32_t *links_dev = pl.links ? reinterpret_cast<uint32_t *>(base) : nullptr;
@@ -449,6 +471,8 @@ int lbcg_create(const lbcg_params *p, void *dev_buf, size_t bytes, void *hip_str
                            s->stream);
     }
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    s->split = SplitPlan{};
+    if (e == hipSuccess && s->moms) e = split_prepare(s->g, s->moms, s->split, s->stream);
     if (e != hipSuccess) {
         (void)hipGetLastError();
         release(s);
@@ -748,8 +772,9 @@ int lbcg_tune(lbcg_sim *s, int32_t *rows, int32_t *zchunks) {
                 if (!seen) cand.push_back(FusedShape{1, yc});
             }
         }
-        // D3Q19: rows 4 or 8 with 64-wide tiles; the compact sweep: 8 rows,
-        // 64- or 32-wide tiles
+        // D3Q19: rows 4 or 8 with 64-wide tiles, and with geometry the split
+        // step (rows 0); the compact sweep: 8 rows, 64- or 32-wide tiles
+        if (s->lattice == LBCG_D3Q19 && !cmp && s->moms) cand.push_back(FusedShape{0, 1, 64});
         const int shapes[3][2] = {{4, 64}, {8, 64}, {8, 32}};
         for (const auto &rt : shapes) {
             const int r = rt[0], tx = rt[1];

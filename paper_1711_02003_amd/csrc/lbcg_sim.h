@@ -20,6 +20,8 @@ struct lbcg_sim {
     bool initialised;
     int64_t step;
     void *psi;              // generic phase-field scratch (N values of the compute type)
+    void *moms;             // split geometry step: its scratch (split_scratch_bytes), or null
+    lbcg::SplitPlan split;  // its block list lengths
     double *partials, *diag;
     uint32_t *ctr;          // time-step counter pair: ctr[cur] = steps taken since initialisation
     double *staging;        // field / population staging

@@ -55,11 +55,14 @@ def _small_focusing():
 
 
 def test_fused_masked_matches_generic_bitwise(L):
+    # the automatic shape on this channel geometry (a quarter of the nodes
+    # fluid) is the split step (rows 0)
     w = _small_focusing()
     _say(f"fused vs generic masked {w.dims}")
     a = L.Sim.from_workload(w, precision="f32", kernel=L.KERNEL_FUSED)
     b = L.Sim.from_workload(w, precision="f32", kernel=L.KERNEL_GENERIC)
     assert a.launch_info()["kernel"] == L.KERNEL_FUSED
+    assert a.launch_info()["rows"] == 0
     a.step(200)
     b.step(200)
     fl = w.mask == 0
@@ -68,11 +71,16 @@ def test_fused_masked_matches_generic_bitwise(L):
     assert np.array_equal(pa, pb)
 
 
-@pytest.mark.parametrize("tile", [(4, 1, 0), (8, 3, 0), (4, 0, 0)])
-def test_fused_masked_tile_invariance(L, tile):
+@pytest.mark.parametrize("prec", ["f32", "f16"])
+@pytest.mark.parametrize("tile", [(4, 1, 0), (8, 3, 0), (4, 0, 0), (0, 0, 0)])
+def test_fused_masked_tile_invariance(L, tile, prec):
+    # column sweeps of any shape and the split step (the automatic shape
+    # here) give bitwise the same state, also with FP16 storage (stochastic
+    # rounding seeded by step and node)
     w = _small_focusing()
-    ref = L.Sim.from_workload(w, precision="f32", kernel=L.KERNEL_FUSED, tile=(8, 1, 0))
-    s = L.Sim.from_workload(w, precision="f32", kernel=L.KERNEL_FUSED, tile=tile)
+    ref = L.Sim.from_workload(w, precision=prec, kernel=L.KERNEL_FUSED, tile=(8, 1, 0))
+    s = L.Sim.from_workload(w, precision=prec, kernel=L.KERNEL_FUSED, tile=tile)
+    assert (s.launch_info()["rows"] == 0) == (tile[0] == 0)
     ref.step(41)
     s.step(41)
     fl = w.mask == 0
