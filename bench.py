@@ -47,8 +47,10 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FORMS = ("pair_f32", "f16", "d2q9", "focusing2d", "focusing", "batched", "batched_compact", "served")
 TRAFFIC_FILES = {"k_step_compact": os.path.join(ROOT, "profiles", "compact_d3q19_f32_256_traffic.txt"),
-                 "k_step_fused": os.path.join(ROOT, "profiles", "fused_d3q19_f32_256_traffic.txt")}
+                 "k_step_fused": os.path.join(ROOT, "profiles", "fused_d3q19_f32_256_traffic.txt"),
+                 "geo_split": os.path.join(ROOT, "profiles", "geo_split_d3q19_f32_junction_traffic.txt")}
 
 
 def log(msg):
@@ -275,16 +277,19 @@ def focusing2d_form(torch, lbcg, W, steps=200, warmup=10):
     return out
 
 
-def focusing_form(torch, lbcg, W, steps=200, warmup=10):
+def focusing_form(torch, lbcg, W, steps=200, warmup=10, tune=True):
     """Flow-focusing cross junction 512 x 128 x 64 (walls, inlets, outlet):
-    FP32 and FP16 storage, fluid-node MLUPS and all-node MLUPS."""
+    FP32 and FP16 storage, fluid-node MLUPS and all-node MLUPS, the tuned
+    shape (rows 0: the split step) and its fraction of HBM peak on
+    2 x 38 x E + 4 bytes per fluid node; for FP32 on the split step, the
+    HBM bytes per step from the committed counter summary (when current)."""
     w = W.flow_focusing(lam=3.0)
     out = {"workload": w.name, "fluid_nodes": w.fluid_nodes, "nodes": w.nodes, "steps": steps}
     for prec in ("f32", "f16"):
         stream = torch.cuda.Stream()
         sim = lbcg.Sim.from_workload(w, precision=prec, stream=stream.cuda_stream)
         sim.step(1)
-        shape = sim.tune()
+        shape = sim.tune() if tune else sim.launch_info()
         ms = time_sim(torch, sim, stream, steps, warmup)
         sim.close()
         elem = 4 if prec == "f32" else 2
@@ -293,6 +298,8 @@ def focusing_form(torch, lbcg, W, steps=200, warmup=10):
                      "ms_per_step": round(ms / steps, 4),
                      "frac": round((2 * 38 * elem + 4) * w.fluid_nodes * steps / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
                      "rows": shape["rows"], "zchunks": shape["zchunks"]}
+        if prec == "f32" and shape["rows"] == 0:
+            out[prec]["traffic"] = read_traffic("geo_split")
     return out
 
 
@@ -399,6 +406,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-copy-probe", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the f16 / batched / served forms")
+    ap.add_argument("--forms", default=",".join(FORMS),
+                    help="comma-separated forms to run (default: all of " + ", ".join(FORMS) + ")")
+    ap.add_argument("--no-form-tune", action="store_true",
+                    help="focusing form: keep the automatic launch shape (for counter runs, where the "
+                         "counted kernels run slower than the others the tuner compares them with)")
     ap.add_argument("--served-requests", type=int, default=64)
     ap.add_argument("--served-steps-scale", type=float, default=0.1)
     args = ap.parse_args()
@@ -476,23 +488,22 @@ def main():
     if not args.no_copy_probe:
         out["copy_probe"] = copy_probe(torch)
     if not args.no_forms:
-        forms = {"pair_f32": pair_f32_form(torch, lbcg, W, args.size)}
-        log(f"pair_f32 {forms['pair_f32']}")
-        forms["f16"] = f16_form(torch, lbcg, W, args.size)
-        log(f"f16 {forms['f16']}")
-        forms["d2q9"] = d2q9_form(torch, lbcg, W)
-        log(f"d2q9 {forms['d2q9']}")
-        forms["focusing2d"] = focusing2d_form(torch, lbcg, W)
-        log(f"focusing2d {forms['focusing2d']}")
-        forms["focusing"] = focusing_form(torch, lbcg, W)
-        log(f"focusing {forms['focusing']}")
-        forms["batched"] = batched_form(torch, lbcg, W)
-        log(f"batched {forms['batched']}")
-        forms["batched_compact"] = batched_form(torch, lbcg, W, compact=True)
-        log(f"batched_compact {forms['batched_compact']}")
-        forms["served"] = served_form(torch, lbcg, W, n=args.served_requests,
-                                      steps_scale=args.served_steps_scale)
-        log(f"served {forms['served']}")
+        run = {
+            "pair_f32": lambda: pair_f32_form(torch, lbcg, W, args.size),
+            "f16": lambda: f16_form(torch, lbcg, W, args.size),
+            "d2q9": lambda: d2q9_form(torch, lbcg, W),
+            "focusing2d": lambda: focusing2d_form(torch, lbcg, W),
+            "focusing": lambda: focusing_form(torch, lbcg, W, tune=not args.no_form_tune),
+            "batched": lambda: batched_form(torch, lbcg, W),
+            "batched_compact": lambda: batched_form(torch, lbcg, W, compact=True),
+            "served": lambda: served_form(torch, lbcg, W, n=args.served_requests,
+                                          steps_scale=args.served_steps_scale),
+        }
+        forms = {}
+        for name in FORMS:
+            if name in args.forms.split(","):
+                forms[name] = run[name]()
+                log(f"{name} {forms[name]}")
         out["forms"] = forms
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
