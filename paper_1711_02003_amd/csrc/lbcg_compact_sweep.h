@@ -190,11 +190,10 @@ struct CStore<_Float16> {
         return e;
     }
     __device__ static __forceinline__ float ratio(RawB b) { return h2f(b >> 16); }
-    // x rounded stochastically to FP16 with the 8 random bits r & 0xff on the
-    // top of its 13 discarded mantissa bits (the rounding of the FP16 pair
-    // state's deviations); the FP16 bits in the low half
+    // x rounded stochastically to FP16 with 8 random bits r (the rounding of
+    // the FP16 pair state's deviations); the FP16 bits in the low half
     __device__ static __forceinline__ uint32_t sr(float x, uint32_t r) {
-        const uint32_t t = (__float_as_uint(x) + ((r & 0xffu) << 5) + 16u) & ~0x1fffu;
+        const uint32_t t = Codec<_Float16>::sr_bits<13>(__float_as_uint(x), r);
         return __builtin_bit_cast(uint16_t, _Float16(__uint_as_float(t)));
     }
     // Random words 0-4 give the 19 totals and R_d 8 bits each, word 5 gives
