@@ -121,7 +121,7 @@ __device__ __forceinline__ void store_h1(__amdgpu_buffer_rsrc_t r, uint32_t voff
 //   per-population shares do.  V_axis (|V_axis| <= 9 beta k_axis) and R_d
 //   are rounded stochastically; neither changes a colour's mass (the sum of
 //   c_i . V over the directions of a class is zero).
-// Stochastic rounding takes 8 random bits per value from the node's
+// Stochastic rounding takes 13 random bits per value from the node's
 // generator (seeded by the time step and x + nx (y + ny z)), so a rounding
 // error does not repeat step after step in a steady flow.  A sweep keeps
 // pulled totals and loaded records in their stored form while the loads are
@@ -190,14 +190,15 @@ struct CStore<_Float16> {
         return e;
     }
     __device__ static __forceinline__ float ratio(RawB b) { return h2f(b >> 16); }
-    // x rounded stochastically to FP16 with 8 random bits r (the rounding of
-    // the FP16 pair state's deviations); the FP16 bits in the low half
+    // x rounded stochastically to FP16 with the 13 low random bits of r (the
+    // rounding of the FP16 pair state's deviations); the FP16 bits in the
+    // low half
     __device__ static __forceinline__ uint32_t sr(float x, uint32_t r) {
         const uint32_t t = Codec<_Float16>::sr_bits<13>(__float_as_uint(x), r);
         return __builtin_bit_cast(uint16_t, _Float16(__uint_as_float(t)));
     }
-    // Random words 0-4 give the 19 totals and R_d 8 bits each, word 5 gives
-    // V_axis.
+    // Random bits: 13 per value, two values per 32-bit draw (bits 0-12 and
+    // 16-28): draws 0-9 for the 19 totals and R_d, 10-11 for V_axis.
     __device__ static __forceinline__ void store(__amdgpu_buffer_rsrc_t rout, uint32_t own, uint32_t zcol, uint32_t pitch,
                                                  const CompactOut<D3Q19, float> &o, uint32_t step) {
         Dither dz(step, own / E + zcol);
@@ -208,15 +209,15 @@ struct CStore<_Float16> {
         const uint32_t zoff = zcol * E;
 #pragma unroll
         for (int i = 0; i < D3Q19::Q; ++i) {
-            if ((i & 3) == 0) w = dz.next();
-            const _Float16 h = Codec<_Float16>::enc_df_sr<D3Q19, float>(o.df[i], i, w >> (8 * (i & 3)));
+            if ((i & 1) == 0) w = dz.next();
+            const _Float16 h = Codec<_Float16>::enc_df_sr<D3Q19, float>(o.df[i], i, (i & 1) ? w >> 16 : w);
             store_h1(rout, own, uint32_t(i) * cs + zoff, __builtin_bit_cast(uint16_t, h));
         }
-        const uint32_t rd = sr(o.Rd, w >> 24);
+        const uint32_t rd = sr(o.Rd, w >> 16);
         w = dz.next();
         const u2 ra = {__float_as_uint(Codec<float>::enc_col<float>(o.M, o.redmaj)),
-                       sr(o.Va[0], w) | (sr(o.Va[1], w >> 8) << 16)};
-        const uint32_t rb = sr(o.Va[2], w >> 16) | (rd << 16);
+                       sr(o.Va[0], w) | (sr(o.Va[1], w >> 16) << 16)};
+        const uint32_t rb = sr(o.Va[2], dz.next()) | (rd << 16);
         const uint32_t oa = uint32_t(D3Q19::Q) * cs + zcol * kRecA,
                        ob = uint32_t(D3Q19::Q) * cs + pitch * kRecA + zcol * kRecB;
         store_u2(rout, own * (kRecA / E), oa, ra);
