@@ -190,7 +190,7 @@ def time_sim(torch, sim, stream, steps, warmup):
 
 
 def pair_f32_form(torch, lbcg, W, size, steps=200, warmup=10):
-    w = W.config2(L=size, seed=2)
+    w = W.droplets_27(L=size, seed=2)
     stream = torch.cuda.Stream()
     sim = lbcg.Sim.from_workload(w, precision="f32", kernel=lbcg.KERNEL_FUSED, stream=stream.cuda_stream)
     sim.step(1)
@@ -209,7 +209,7 @@ def f16_form(torch, lbcg, W, size, steps=200, warmup=10):
     """FP16 storage (FP32 arithmetic) on the headline lattice: the compact
     state (100 B per node moved: 19 FP16 totals, M in FP32, V_axis and R_d
     in FP16, read and written once) and the pair state (152 B), each tuned."""
-    w = W.config2(L=size, seed=2)
+    w = W.droplets_27(L=size, seed=2)
     out = {"workload": w.name, "storage": "f16"}
     for name, kernel, bpn in (("compact", lbcg.KERNEL_COMPACT, 100), ("pairs", lbcg.KERNEL_FUSED, 152)):
         stream = torch.cuda.Stream()
@@ -345,16 +345,24 @@ def batched_form(torch, lbcg, W, steps=200, warmup=10, compact=False):
             "rows": info["rows"], "zplanes": info["zplanes"], "blocks": info["blocks"]}
 
 
-def served_form(torch, lbcg, W, n=64, steps_scale=0.1, loads=(0.8, 1.5)):
-    """Config-5 stand-in: a Poisson stream of n step-emulsifier requests (the
-    config's channel and reservoir sizes, inlet speeds and seed) with step
-    counts scaled by steps_scale, through the continuous-batching server and
+def served_form(torch, lbcg, W, n=64, steps_scale=0.1, loads=(0.8, 1.5), capacity=0.0):
+    """A Poisson stream of n step-emulsifier requests (channel and reservoir
+    sizes, inlet speeds and seed of the full 256-request stream) with step
+    counts U{5000..20000} scaled by steps_scale, through the continuous-batching server and
     through the same server one request at a time.  The one-at-a-time capacity
     (requests per second with every request queued at t = 0) sets the arrival
     rate of each offered load; p50 / p99 time to result and fluid-node MLUPS
-    per load and mode."""
+    per load and mode.  capacity > 0: use that one-at-a-time capacity (from an
+    earlier run) instead of measuring it."""
     from paper_1711_02003_amd import serve
     lo, hi = int(5000 * steps_scale), int(20000 * steps_scale)
+    last = [time.perf_counter()]
+
+    def progress(done, total):
+        # a line a minute at most, and the last one
+        if done == total or time.perf_counter() - last[0] > 60:
+            last[0] = time.perf_counter()
+            log(f"served: {done} of {total} requests done")
 
     def reqs(rate, at_zero=False):
         specs = W.served_requests(n=n, seed=5, rate=rate, steps_lo=lo, steps_hi=hi)
@@ -370,19 +378,25 @@ def served_form(torch, lbcg, W, n=64, steps_scale=0.1, loads=(0.8, 1.5)):
         fps.append(lbcg.footprint(p))
     cap = int(sum(sorted(fps)[-8:]) * 1.05)  # room for about eight requests at once
     one = serve.LbcgBackend(cap, precision="f32", fields=False, tune_min=1)
-    st0 = serve.Server(one, cap, slice_steps=256, max_running=1, keep_results=False).run(reqs(1.0, True))
-    capacity = st0.completed / st0.makespan_s
-    log(f"served: one-at-a-time capacity {capacity:.2f} requests/s ({st0.as_dict()})")
+    measured = capacity <= 0
+    if measured:
+        st0 = serve.Server(one, cap, slice_steps=256, max_running=1, keep_results=False,
+                           progress=progress).run(reqs(1.0, True))
+        capacity = st0.completed / st0.makespan_s
+        log(f"served: one-at-a-time capacity {capacity:.2f} requests/s ({st0.as_dict()})")
     out = {"workload": f"{n} step-emulsifier requests (Poisson), steps U{{{lo}..{hi}}}, seed 5",
-           "stand_in": f"config 5 at reduced scale: {n} of its 256 requests, step counts x {steps_scale} "
-                       f"(U{{{lo}..{hi}}} instead of U{{5000..20000}}); same channel and reservoir sizes, "
-                       "inlet speeds and arrival process",
-           "plain_capacity_per_s": round(capacity, 3), "arena_bytes": cap, "loads": {}}
+           "stand_in": "the full stream (256 requests, steps U{5000..20000})" if (n, lo, hi) == (256, 5000, 20000)
+                       else f"the 256-request stream at reduced scale: {n} of its requests, step counts x "
+                            f"{steps_scale} (U{{{lo}..{hi}}} instead of U{{5000..20000}}); same channel and "
+                            "reservoir sizes, inlet speeds and arrival process",
+           "plain_capacity_per_s": round(capacity, 3), "capacity_measured": measured, "arena_bytes": cap,
+           "loads": {}}
     served_be = serve.LbcgBackend(cap, precision="f32", fields=False)
     for load in loads:
         rate = load * capacity
-        plain = serve.Server(one, cap, slice_steps=256, max_running=1, keep_results=False).run(reqs(rate))
-        served = serve.Server(served_be, cap, slice_steps=256, keep_results=False).run(reqs(rate))
+        plain = serve.Server(one, cap, slice_steps=256, max_running=1, keep_results=False,
+                             progress=progress).run(reqs(rate))
+        served = serve.Server(served_be, cap, slice_steps=256, keep_results=False, progress=progress).run(reqs(rate))
         row = {"arrival_rate_per_s": round(rate, 3), "served": served.as_dict(), "plain": plain.as_dict(),
                "mlups_ratio": round(served.mlups / plain.mlups, 3) if plain.mlups else None}
         out["loads"][str(load)] = row
@@ -413,6 +427,10 @@ def main():
                          "counted kernels run slower than the others the tuner compares them with)")
     ap.add_argument("--served-requests", type=int, default=64)
     ap.add_argument("--served-steps-scale", type=float, default=0.1)
+    ap.add_argument("--served-loads", default="0.8,1.5",
+                    help="offered loads, as fractions of the one-at-a-time capacity (comma-separated; empty: none)")
+    ap.add_argument("--served-capacity", type=float, default=0.0,
+                    help="one-at-a-time capacity in requests/s from an earlier run (0: measure it)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
@@ -424,7 +442,7 @@ def main():
     from paper_1711_02003_amd import lbcg
     from paper_1711_02003_amd import workloads as W
 
-    w = W.config2(L=args.size, seed=2)
+    w = W.droplets_27(L=args.size, seed=2)
     compact = args.kernel == "compact"
     kname = "k_step_compact" if compact else "k_step_fused"
     stream = torch.cuda.Stream()
@@ -497,7 +515,9 @@ def main():
             "batched": lambda: batched_form(torch, lbcg, W),
             "batched_compact": lambda: batched_form(torch, lbcg, W, compact=True),
             "served": lambda: served_form(torch, lbcg, W, n=args.served_requests,
-                                          steps_scale=args.served_steps_scale),
+                                          steps_scale=args.served_steps_scale,
+                                          loads=tuple(float(v) for v in args.served_loads.split(",") if v),
+                                          capacity=args.served_capacity),
         }
         forms = {}
         for name in FORMS:

@@ -120,7 +120,7 @@ class Server:
     def __init__(self, backend, capacity_bytes: int, slice_steps: int = 256,
                  clock: Callable[[], float] = time.perf_counter,
                  sleep: Callable[[float], None] = time.sleep, keep_results: bool = True,
-                 max_running: int = 0):
+                 max_running: int = 0, progress: Optional[Callable[[int, int], None]] = None):
         self.backend = backend
         self.max_running = int(max_running)  # 0 = no limit besides the arena
         self.arena = Arena(capacity_bytes)
@@ -128,6 +128,7 @@ class Server:
         self.clock = clock
         self.sleep = sleep
         self.keep_results = keep_results
+        self.progress = progress  # called as progress(completed, total) after each completion
         self.log: List[tuple] = []  # (time, event, request id)
         # per admitted request: the steps done so far by each request already
         # running when it joined (shows requests joining part-way through others)
@@ -158,8 +159,11 @@ class Server:
         r.t_done = self.clock() - t0
         self.log.append((r.t_done, "done", r.id))
         finished.append(r)
+        if self.progress is not None:
+            self.progress(len(finished), self.total)
 
     def run(self, requests: List[Request]) -> Stats:
+        self.total = len(requests)
         queue = sorted(requests, key=lambda r: (r.arrival, r.id))
         running: List[Request] = []      # on the device with steps not yet queued
         finished: List[Request] = []

@@ -122,7 +122,7 @@ def static_droplet_2d(n: int = 64, R: float = 16.0, width: float = 2.0, noise: f
                     beta, steps=steps)
 
 
-def config1(seed: int = 1) -> Workload:
+def droplet_2d_64(seed: int = 1) -> Workload:
     """D2Q9 static droplet 64x64 periodic, R = 16, tanh width 2, +-1e-6 noise,
     tau_R = tau_B = 1, A = 0.01, beta = 0.7, 2000 steps."""
     w = static_droplet_2d(64, 16.0, 2.0, 1e-6, seed)
@@ -140,7 +140,7 @@ def static_droplet_3d(n: int = 64, R: float = 16.0, width: float = 2.0, tau=(1.0
                     beta, steps=steps)
 
 
-def config2(L: int = 256, seed: int = 2, steps: int = 1000) -> Workload:
+def droplets_27(L: int = 256, seed: int = 2, steps: int = 1000) -> Workload:
     """D3Q19 periodic box with 27 droplets on a jittered 3x3x3 lattice.
 
     At L = 256: centres (i + 1/2) L/3 + U(-8, 8) per axis, radii U[12, 24];
@@ -169,7 +169,7 @@ def config2(L: int = 256, seed: int = 2, steps: int = 1000) -> Workload:
 
 def droplets_2d(n: int = 4096, seed: int = 6, steps: int = 1000) -> Workload:
     """D2Q9 periodic square with 256 droplets on a jittered 16 x 16 lattice
-    (the 2-D counterpart of config2).
+    (the 2-D counterpart of droplets_27).
 
     At n = 4096: centres (i + 1/2) n/16 + U(-32, 32) per axis, radii
     U[24, 56]; other n scale the jitter and radii by n/4096.  Velocity

@@ -46,9 +46,9 @@ def _droplets(dims, seed, tau=(1.2, 0.7), A=0.01):
                       A, 0.7)
 
 
-def test_compact_config2_recipe_1000_steps(L, orc):
+def test_compact_droplets_27_recipe_1000_steps(L, orc):
     # The 27-droplet recipe at 48^3 (tau_R = 1, tau_B = 0.6, A = 0.005).
-    w = W.config2(L=48, seed=2)
+    w = W.droplets_27(L=48, seed=2)
     _say("compact f32 48^3 x1000")
     s = L.Sim.from_workload(w, precision="f32", kernel=L.KERNEL_COMPACT)
     assert s.launch_info()["kernel"] == L.KERNEL_COMPACT
@@ -69,7 +69,7 @@ def test_compact_config2_recipe_1000_steps(L, orc):
 
 
 @pytest.mark.timeout(900)
-def test_compact_config2_recipe_128_1000_steps(L, orc):
+def test_compact_droplets_27_recipe_128_1000_steps(L, orc):
     # The 27-droplet recipe at 128^3 (two full 64-wide x tiles, 16 row tiles)
     # on the compact kernel in its tuned launch shape, as the benchmark runs
     # it, after 1000 steps against the FP64 oracle: rel-L2 of psi within 1e-5;
@@ -77,7 +77,7 @@ def test_compact_config2_recipe_128_1000_steps(L, orc):
     # velocities have decayed to ~1e-5 rms by then, and FP32 forms u to
     # ~2e-10 absolute from momentum sums that cancel, so the plain ratio
     # measures that floor: 2.4e-5 here, bounded by 1e-4).
-    w = W.config2(L=128, seed=2)
+    w = W.droplets_27(L=128, seed=2)
     _say("compact f32 128^3 x1000 (tuned shape)")
     s = L.Sim.from_workload(w, precision="f32", kernel=L.KERNEL_COMPACT)
     s.step(1)
@@ -160,7 +160,7 @@ def test_compact_concurrent_streams_match_sequential(L):
     # handles on their own streams stepping at the same time, with chunks
     # down to one plane (every record plane read by other blocks than the
     # one that wrote it): bitwise the result of one handle stepped alone
-    w = W.config2(L=64, seed=3)
+    w = W.droplets_27(L=64, seed=3)
     ref = L.Sim.from_workload(w, precision="f32", kernel=L.KERNEL_COMPACT, tile=(8, 1, 0))
     ref.step(20)
     ref.synchronize()
@@ -195,7 +195,7 @@ def test_compact_reads_leave_trajectory_unchanged(L):
 def test_compact_checkpoint_resume(L):
     # a checkpoint of a compact handle is a pair state: it resumes on a
     # compact or a pair-state handle, within rounding of the uninterrupted run
-    w = W.config2(L=40, seed=9)
+    w = W.droplets_27(L=40, seed=9)
     a = L.Sim.from_workload(w, precision="f32", kernel=L.KERNEL_COMPACT)
     a.step(40)
     pa = a.populations()
@@ -213,10 +213,10 @@ def test_compact_checkpoint_resume(L):
         c.close()
 
 
-def test_compact_full_size_config2_sampled(L, orc):
+def test_compact_full_size_droplets_27_sampled(L, orc):
     # Full 256^3 lattice: sampled nodes' next state against the oracle's step
     # from the same (converted) state, and colour masses over 20 steps.
-    w = W.config2(L=256, seed=2)
+    w = W.droplets_27(L=256, seed=2)
     _say("full size 256^3 compact f32")
     s = L.Sim.from_workload(w, precision="f32", kernel=L.KERNEL_COMPACT)
     _say(f"  launch {s.launch_info()}")
@@ -254,7 +254,7 @@ def test_compact_largest_lattice_and_beyond(L, orc):
     # 304^3 (4.27 GB per pair buffer) is the largest cube the compact kernel
     # takes; 306^3 is refused (the automatic choice would use the generic
     # kernel there).
-    w = W.config2(L=304, seed=2)
+    w = W.droplets_27(L=304, seed=2)
     _say("304^3 compact f32")
     s = L.Sim.from_workload(w, precision="f32", kernel=L.KERNEL_COMPACT)
     assert s.launch_info()["kernel"] == L.KERNEL_COMPACT

@@ -80,10 +80,10 @@ def test_compact_f16_droplet_within_one_percent(L):
     assert abs(r16 / r32 - 1) < 0.01 and abs(dp16 / dp32 - 1) < 0.01
 
 
-def test_compact_f16_config2_vs_oracle_and_drift(L, orc):
+def test_compact_f16_droplets_27_vs_oracle_and_drift(L, orc):
     # The 27-droplet recipe at 48^3 after 1000 steps: phase field within 1 %
     # (rel-L2) of the FP64 oracle's, per-colour mass drift below 1e-4.
-    w = W.config2(L=48, seed=2)
+    w = W.droplets_27(L=48, seed=2)
     _say("compact f16 48^3 x1000")
     s = _compact16(L, w)
     d0 = s.diagnostics()
@@ -123,7 +123,7 @@ def test_compact_f16_reads_and_resume(L):
     # Reads leave the trajectory bitwise unchanged; a checkpoint (a pair
     # state) resumes on the FP16 compact or pair-state kernel within a few
     # FP16 units of the uninterrupted run.
-    w = W.config2(L=40, seed=9)
+    w = W.droplets_27(L=40, seed=9)
     a = _compact16(L, w)
     b = _compact16(L, w)
     for _ in range(4):
@@ -168,7 +168,7 @@ def test_compact_f16_full_size_sampled(L, orc):
     # against the oracle's step from the same (read-out) state.  The read-out
     # and the stored output are each within one FP16 unit, so the bound is
     # twice a share's unit.
-    w = W.config2(L=256, seed=2)
+    w = W.droplets_27(L=256, seed=2)
     _say("full size 256^3 compact f16")
     s = _compact16(L, w)
     s.step(1)
@@ -186,7 +186,7 @@ def test_compact_f16_full_size_sampled(L, orc):
 
 def test_compact_f16_not_batched(L, stream):
     # the batched compact sweep stores FP32: FP16 compact handles are refused
-    ws = [W.config2(L=16, seed=k) for k in range(2)]
+    ws = [W.droplets_27(L=16, seed=k) for k in range(2)]
     sims = [_compact16(L, w, stream=stream.cuda_stream) for w in ws]
     for s in sims:
         s.step(1)

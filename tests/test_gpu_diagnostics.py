@@ -99,10 +99,10 @@ def _random_masked(lat, dims, seed):
     return w
 
 
-@pytest.mark.parametrize("case", ["config1", "d2q9_masked", "d3q19_masked", "d3q19_droplet"])
+@pytest.mark.parametrize("case", ["droplet_2d_64", "d2q9_masked", "d3q19_masked", "d3q19_droplet"])
 def test_f64_diagnostics_match_oracle(L, orc, case):
-    if case == "config1":
-        w = W.config1()
+    if case == "droplet_2d_64":
+        w = W.droplet_2d_64()
     elif case == "d2q9_masked":
         w = _random_masked("D2Q9", (30, 17, 1), 5)
     elif case == "d3q19_masked":
@@ -128,7 +128,7 @@ def test_same_state_reduction(L, orc, kernel):
     # FP16 storage.  Per-node moments agree bitwise, so max |u| may differ
     # by the last bit at most (both sides round sqrt and division correctly).
     if kernel == "compact":
-        w = W.config2(L=128, seed=2)
+        w = W.droplets_27(L=128, seed=2)
         s = L.Sim.from_workload(w, precision="f32", kernel=L.KERNEL_COMPACT)
     else:
         w = W.static_droplet_3d(n=64, R=16.0, tau=(1.0, 0.7), A=0.005)
@@ -144,7 +144,7 @@ def test_same_state_reduction(L, orc, kernel):
 @pytest.mark.timeout(900)
 def test_compact_256_diagnostics_vs_oracle_trajectory(L, orc):
     # the benchmark's lattice (27 droplets, 256^3) and kernel, 10 steps
-    w = W.config2(L=256, seed=2)
+    w = W.droplets_27(L=256, seed=2)
     _say("compact 256^3 x10 diagnostics vs the oracle's own trajectory")
     s = L.Sim.from_workload(w, precision="f32", kernel=L.KERNEL_COMPACT)
     s.step(1)

@@ -263,7 +263,7 @@ def test_batch_rejects_mixed_streams(L, stream):
 
 
 def test_tune_keeps_state(L):
-    w = W.config2(L=64, seed=3)
+    w = W.droplets_27(L=64, seed=3)
     a = L.Sim.from_workload(w, precision="f32")
     a.step(3)
     p0 = a.populations()
@@ -282,7 +282,7 @@ def test_tune_keeps_state_compact(L, before):
     # The compact kernel is tuned on a compact state whether or not the
     # handle has taken its first compact step (0 or 1 steps: still the pair
     # state), and the trajectory does not change.
-    w = W.config2(L=64, seed=3)
+    w = W.droplets_27(L=64, seed=3)
     a = L.Sim.from_workload(w, precision="f32", kernel=L.KERNEL_COMPACT)
     a.step(before)
     p0 = a.populations()
@@ -355,7 +355,7 @@ def test_f16_fused_matches_generic_and_checkpoint(L):
     # FP16 rounds the stored colour share stochastically, seeded by the time
     # step: the fused and generic kernels must still agree bitwise, and a
     # restored checkpoint must continue bitwise.
-    for w in (W.config2(L=32, seed=7), _small_focusing()):
+    for w in (W.droplets_27(L=32, seed=7), _small_focusing()):
         fl = np.ones(w.shape, bool) if w.mask is None else w.mask == 0
         a = L.Sim.from_workload(w, precision="f16", kernel=L.KERNEL_FUSED)
         b = L.Sim.from_workload(w, precision="f16", kernel=L.KERNEL_GENERIC)
@@ -378,7 +378,7 @@ def test_f16_colour_mass_drift(L):
     # scheme; the storage rounds the colour shares without bias and without
     # repeating its error from step to step, so the drift stays a random
     # walk far below the 1e-3 a repeated rounding error would reach.
-    w = W.config2(L=48, seed=2)
+    w = W.droplets_27(L=48, seed=2)
     s = L.Sim.from_workload(w, precision="f16")
     d0 = s.diagnostics()
     s.step(1000)

@@ -139,11 +139,11 @@ def test_fused_f32_density_ratio_slab(L, orc):
     assert _maxrel(g["rhoB"][..., :6], f["rhoB"][..., :6]) < 1e-5
 
 
-def test_config1_f64(L, orc):
+def test_droplet_2d_64_f64(L, orc):
     # D2Q9 static droplet 64x64 (2000 steps): 1e-12 after 100 steps, then
     # per-colour mass conserved to round-off over the whole run (GPU FP64
     # diagnostics).
-    w = W.config1()
+    w = W.droplet_2d_64()
     s = L.Sim.from_workload(w, precision="f64", kernel=L.KERNEL_GENERIC)
     o = oracle_for(orc, w, threads=8)
     d0 = s.diagnostics()
@@ -153,7 +153,7 @@ def test_config1_f64(L, orc):
     s.step(w.steps - 100)
     o.step(w.steps - 100)
     g, f = s.fields(), o.fields()
-    _say(f"config1 2000 steps: relL2 psi {rel_l2(g['psi'], f['psi']):.2e} u {rel_l2(g['u'], f['u']):.2e}")
+    _say(f"droplet_2d_64 2000 steps: relL2 psi {rel_l2(g['psi'], f['psi']):.2e} u {rel_l2(g['u'], f['u']):.2e}")
     assert rel_l2(g["psi"], f["psi"]) < 1e-10
     d1 = s.diagnostics(check=True)
     eps = np.finfo(float).eps
@@ -187,10 +187,10 @@ def test_fig1_droplet_viscosity_contrast_f64(L, orc, coll):
     assert d < 1e-9
 
 
-def test_fused_f32_config2_recipe_1000_steps(L, orc):
+def test_fused_f32_droplets_27_recipe_1000_steps(L, orc):
     # The 27-droplet recipe at 48^3 (tau_R = 1, tau_B = 0.6, A = 0.005):
     # FP32 fused kernel vs FP64 oracle after 1000 steps.
-    w = W.config2(L=48, seed=2)
+    w = W.droplets_27(L=48, seed=2)
     _say("fused f32 48^3 x1000")
     s = L.Sim.from_workload(w, precision="f32", kernel=L.KERNEL_FUSED)
     assert s.launch_info()["kernel"] == L.KERNEL_FUSED
@@ -215,7 +215,7 @@ def test_fused_f32_config2_recipe_1000_steps(L, orc):
 
 def test_fused_matches_generic_ragged(L):
     # nx not a multiple of 64, ny not a multiple of the tile rows
-    w = W.config2(L=32, seed=7)
+    w = W.droplets_27(L=32, seed=7)
     rng = np.random.default_rng(1)
     nx, ny, nz = 70, 37, 20
     sh = (nz, ny, nx)
@@ -257,7 +257,7 @@ def test_fused_tile_shape_invariance(L, dims):
 
 
 def test_determinism_and_checkpoint(L):
-    w = W.config2(L=40, seed=9)
+    w = W.droplets_27(L=40, seed=9)
     a = L.Sim.from_workload(w, precision="f32")
     a.step(40)
     pa = a.populations()
@@ -302,9 +302,9 @@ def _sampled_one_step(L, orc, w, s, n_samples=48, seed=0):
     return worst
 
 
-def test_full_size_config2_sampled(L, orc):
+def test_full_size_droplets_27_sampled(L, orc):
     # Full 256^3 lattice in the benchmark's launch configuration.
-    w = W.config2(L=256, seed=2)
+    w = W.droplets_27(L=256, seed=2)
     _say("full size 256^3 fused f32")
     s = L.Sim.from_workload(w, precision="f32")
     info = s.launch_info()
@@ -326,7 +326,7 @@ def test_largest_fused_lattice_and_beyond(L, orc, edge, kernel):
     # 304^3 FP32 (4.27 GB per buffer) is the largest cube it takes, with
     # offsets up to 2^32 - 25 MB; at 306^3 (4.36 GB) the automatic choice
     # falls back to the generic kernel.  Both stay within the one-step bar.
-    w = W.config2(L=edge, seed=2)
+    w = W.droplets_27(L=edge, seed=2)
     _say(f"{edge}^3 f32, expect {kernel}")
     s = L.Sim.from_workload(w, precision="f32")
     info = s.launch_info()
@@ -347,7 +347,7 @@ def test_library_loaded_before_torch_in_fresh_process(L):
     import sys
     code = ("import sys; sys.path.insert(0, '.');"
             "from paper_1711_02003_amd import lbcg, workloads as W;"
-            "w = W.config2(L=16, seed=2);"
+            "w = W.droplets_27(L=16, seed=2);"
             "s = lbcg.Sim.from_workload(w, precision='f32');"
             "s.step(3); f = s.fields();"
             "assert abs(f['rhoR'].sum() + f['rhoB'].sum() - 16 ** 3) < 1e-2;"

@@ -83,7 +83,7 @@ def test_masses_match_field_export_of_an_evolved_state(orc):
     # The masses, momentum, max |u|, inside/outside means and vol_R of an
     # evolved droplet equal the same quantities formed here from the field
     # export of the same state (orc_fields).
-    w = W.config1()
+    w = W.droplet_2d_64()
     o = oracle_for(orc, w, threads=4).step(300)
     d = o.diagnostics()
     f = o.fields()
@@ -140,7 +140,7 @@ def test_walls_are_not_counted(orc):
 def test_planted_nan_is_counted_and_left_out(orc):
     # A NaN in one population of one node: that node is non-finite, and the
     # sums cover the other nodes only.
-    w = W.config1()
+    w = W.droplet_2d_64()
     o = oracle_for(orc, w).step(10)
     ref = o.diagnostics()
     f = o.fields()

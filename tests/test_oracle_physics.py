@@ -16,10 +16,10 @@ from tests.helpers import oracle_for, oracle_params
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")
 
 
-def test_mass_conservation_config1(orc):
+def test_mass_conservation_droplet_2d_64(orc):
     # Per-colour mass is conserved by collision, perturbation, recolouring and
     # periodic streaming: 2000 steps of the 64x64 static droplet.
-    w = W.config1()
+    w = W.droplet_2d_64()
     o = oracle_for(orc, w, threads=4)
     f0 = o.fields()
     m0 = f0["rhoR"].sum(), f0["rhoB"].sum()
@@ -52,9 +52,9 @@ def test_mass_conservation_closed_box_3d(orc):
 
 
 def test_momentum_conservation_periodic(orc):
-    # Config-2 recipe on a 24^3 box (tau_R = 1, tau_B = 0.6): the total
+    # 27-droplet recipe on a 24^3 box (tau_R = 1, tau_B = 0.6): the total
     # momentum of a periodic box is conserved to round-off.
-    w = W.config2(L=24, seed=2)
+    w = W.droplets_27(L=24, seed=2)
     o = oracle_for(orc, w, threads=4)
 
     def mom(o):
@@ -203,7 +203,7 @@ def test_interface_width(orc):
     # After relaxation the 10-90 % width of the colour profile across the
     # interface is a few nodes (the paper quotes about five lattice units).
     g = json.load(open(GOLDEN))["interface_width"]
-    w = W.config1()
+    w = W.droplet_2d_64()
     o = oracle_for(orc, w, threads=4)
     o.step(1000)
     psi = o.fields()["psi"][0]
