@@ -646,6 +646,28 @@ __device__ __forceinline__ OwnMom<T> own_moments(const typename PairOf<S>::type 
     return om;
 }
 
+// The scalars of an inlet (velocity and colour densities) or an outlet
+// (density) in the compute type; zero for walls.
+template <typename T>
+struct IoVals {
+    T u[3], rhoR, rhoB, rout;
+};
+template <typename T>
+__device__ __forceinline__ IoVals<T> io_vals(const Geo &g, uint8_t code) {
+    IoVals<T> v{};
+    if (is_inlet(code)) {
+        const DevInlet in = g.inlets[code - kInlet0];
+        v.u[0] = T(in.u[0]);
+        v.u[1] = T(in.u[1]);
+        v.u[2] = T(in.u[2]);
+        v.rhoR = T(in.rhoR);
+        v.rhoB = T(in.rhoB);
+    } else if (!is_wall(code)) {
+        v.rout = T(g.outlets[code - kOutlet0].rho);
+    }
+    return v;
+}
+
 // Value a fluid node pulls through link i from a non-fluid upstream node of
 // mask code `code`, from the node's own stored new pair of the opposite
 // direction (own_io) and, for outlets, its own moments.  Walls return own_io
@@ -656,10 +678,10 @@ __device__ __forceinline__ OwnMom<T> own_moments(const typename PairOf<S>::type 
 // that difference would lose the ~1e-9 absolute precision that the stored
 // deviations keep, and the boundary nodes' velocity with it.
 template <class L, typename S, typename T>
-__device__ __forceinline__ typename PairOf<S>::type boundary_pair(const Geo &g, const Model<T> &mo, int i,
-                                                                  uint8_t code,
-                                                                  typename PairOf<S>::type own_io,
-                                                                  const OwnMom<T> &om) {
+__device__ __forceinline__ typename PairOf<S>::type boundary_pair_v(const Model<T> &mo, int i, uint8_t code,
+                                                                    const IoVals<T> &iv,
+                                                                    typename PairOf<S>::type own_io,
+                                                                    const OwnMom<T> &om) {
     if (is_wall(code)) return own_io;
     const int io = L::opp[i];
     bool flo;
@@ -670,14 +692,13 @@ __device__ __forceinline__ typename PairOf<S>::type boundary_pair(const Geo &g, 
     const T fRo = flo ? fo - mu : mu, fBo = fo - fRo;
     T fR, fB, dev;  // the colour populations and the total deviation f - w_i
     if (is_inlet(code)) {
-        const DevInlet in = g.inlets[code - kInlet0];
-        const T cu = T(L::cx[io]) * T(in.u[0]) + T(L::cy[io]) * T(in.u[1]) + T(L::cz[io]) * T(in.u[2]);
+        const T cu = T(L::cx[io]) * iv.u[0] + T(L::cy[io]) * iv.u[1] + T(L::cz[io]) * iv.u[2];
         const T mom = T(6.0 * wgt<L>(io)) * cu;  // 2 w c.u / c_s^2
-        fR = fRo - mom * T(in.rhoR);
-        fB = fBo - mom * T(in.rhoB);
-        dev = dfo - mom * (T(in.rhoR) + T(in.rhoB));
+        fR = fRo - mom * iv.rhoR;
+        fB = fBo - mom * iv.rhoB;
+        dev = dfo - mom * (iv.rhoR + iv.rhoB);
     } else {
-        const T rout = T(g.outlets[code - kOutlet0].rho);
+        const T rout = iv.rout;
         const T rwR = rout * om.rR / om.rho, rwB = rout - rwR;
         const T cu = T(L::cx[io]) * om.u[0] + T(L::cy[io]) * om.u[1] + T(L::cz[io]) * om.u[2];
         const T uu = om.u[0] * om.u[0] + om.u[1] * om.u[1] + om.u[2] * om.u[2];
@@ -695,6 +716,15 @@ __device__ __forceinline__ typename PairOf<S>::type boundary_pair(const Geo &g, 
     bool fl;
     split_shares<T>(f != T(0) ? fR / f : T(0), f != T(0) ? fB / f : T(0), mm, fl);
     return encode_pair<L, S, T>(dev, mm, fl, i);
+}
+
+// The same with the inlet's or outlet's scalars read from the lattice.
+template <class L, typename S, typename T>
+__device__ __forceinline__ typename PairOf<S>::type boundary_pair(const Geo &g, const Model<T> &mo, int i,
+                                                                  uint8_t code,
+                                                                  typename PairOf<S>::type own_io,
+                                                                  const OwnMom<T> &om) {
+    return boundary_pair_v<L, S, T>(mo, i, code, io_vals<T>(g, code), own_io, om);
 }
 
 // Pre-collision populations of fluid node (x, y, z) = n at the new time level

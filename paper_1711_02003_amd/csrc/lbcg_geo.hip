@@ -15,7 +15,8 @@
 //     stores its 19 new pairs and, for links from walls, their bounce-back
 //     values;
 //   k_geo_boundary: each fluid node with links from inlets or outlets
-//     stores their values (from its new pairs, read back).
+//     stores their values (from its new pairs, read back); one thread per
+//     such node and direction, from a list of the nodes.
 // Every value is computed by the expressions and in the order of the column
 // sweep, so the results are bitwise those of the sweep.  Traffic per fluid
 // node: pairs read and written once (2 x 38 x E bytes), plus 12 moments and
@@ -46,16 +47,18 @@ struct SplitArgs {
     FusedArgs<S> a;
     float *psi;                 // psi of every fluid node
     float *mom;                 // kNM arrays of pitch floats
-    const uint32_t *blocks;     // the kernel's block list
+    const uint32_t *blocks;     // the kernel's block list (the boundary kernel's: its node list)
 };
 
-// Scratch layout: the moments, then the per-block flags, the list of blocks
-// with fluid, the list of blocks with inlet or outlet links and the two
-// lengths.
+// Scratch layout: the moments, then the per-block flags, the per-block
+// counts of nodes with inlet or outlet links, the list of blocks with fluid,
+// the list of blocks with inlet or outlet links, the offsets of their nodes
+// in the node list, the node list and the three lengths.
 struct ScratchMap {
     float *mom;
     uint8_t *flags;
-    uint32_t *act, *io, *counts;
+    uint16_t *ioc;
+    uint32_t *act, *io, *ioofs, *ionodes, *counts;
 };
 __host__ __device__ inline size_t align256(size_t v) { return (v + 255) / 256 * 256; }
 inline ScratchMap scratch_map(void *scratch, int64_t pitch, int64_t nb) {
@@ -65,10 +68,16 @@ inline ScratchMap scratch_map(void *scratch, int64_t pitch, int64_t nb) {
     p += align256(sizeof(float) * kNM * size_t(pitch));
     m.flags = reinterpret_cast<uint8_t *>(p);
     p += align256(size_t(nb));
+    m.ioc = reinterpret_cast<uint16_t *>(p);
+    p += align256(sizeof(uint16_t) * size_t(nb));
     m.act = reinterpret_cast<uint32_t *>(p);
     p += align256(sizeof(uint32_t) * size_t(nb));
     m.io = reinterpret_cast<uint32_t *>(p);
     p += align256(sizeof(uint32_t) * size_t(nb));
+    m.ioofs = reinterpret_cast<uint32_t *>(p);
+    p += align256(sizeof(uint32_t) * size_t(nb));
+    m.ionodes = reinterpret_cast<uint32_t *>(p);
+    p += align256(sizeof(uint32_t) * size_t(pitch));
     m.counts = reinterpret_cast<uint32_t *>(p);
     return m;
 }
@@ -101,53 +110,104 @@ __device__ __forceinline__ bool has_io_link(uint32_t lk) {
     return (lk & kLinkFluid) && (lk & kLinkBits) && ((lk & kLinkMixed) || !is_wall(link_code(lk)));
 }
 
+// Rank of this thread's node among the block's nodes with `pred` (in
+// thread order) and, through `total`, their count.
+__device__ __forceinline__ uint32_t block_rank(bool pred, uint32_t &total) {
+    __shared__ uint32_t wc[kGeoBlock / 64];
+    const uint64_t bal = __builtin_amdgcn_ballot_w64(pred);
+    const uint32_t lane = __builtin_amdgcn_mbcnt_hi(uint32_t(bal >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(bal), 0u));
+    const int w = int(threadIdx.x / 64);
+    if (threadIdx.x % 64 == 0) wc[w] = uint32_t(__builtin_popcountll(bal));
+    __syncthreads();
+    uint32_t before = 0, all = 0;
+    for (int k = 0; k < kGeoBlock / 64; ++k) {
+        before += k < w ? wc[k] : 0u;
+        all += wc[k];
+    }
+    total = all;
+    return before + lane;
+}
+
 // Flags of block b: 1 = some node fluid, 2 = some node with an inlet or
-// outlet link (mixed codes count: the boundary kernel checks each link).
+// outlet link (mixed codes count: the boundary kernel checks each link);
+// and the number of such nodes.
 __global__ void __launch_bounds__(kGeoBlock) k_geo_flags(const uint32_t *__restrict__ links, int nx, int ny, int nz,
-                                                        uint8_t *__restrict__ flags) {
+                                                        uint8_t *__restrict__ flags, uint16_t *__restrict__ ioc) {
     Here h;
     const bool in = here(nx, ny, nz, blockIdx.x, h);
     const uint32_t lk = in ? links[h.n] : 0u;
-    const int f = __syncthreads_or((lk & kLinkFluid) != 0u), io = __syncthreads_or(has_io_link(lk));
-    if (threadIdx.x == 0) flags[blockIdx.x] = uint8_t((f ? 1 : 0) | (io ? 2 : 0));
+    const int f = __syncthreads_or((lk & kLinkFluid) != 0u);
+    uint32_t nio = 0;
+    block_rank(has_io_link(lk), nio);
+    if (threadIdx.x == 0) {
+        flags[blockIdx.x] = uint8_t((f ? 1 : 0) | (nio ? 2 : 0));
+        ioc[blockIdx.x] = uint16_t(nio);
+    }
 }
 
-// The two block lists in ascending block order, by one block: thread t
-// takes the flags of a contiguous range, counts, and writes its ids after
-// the counts of the threads before it.
+// The two block lists in ascending block order, and for each listed io
+// block the offset of its nodes in the io node list, by one block: thread t
+// takes the flags of a contiguous range, counts, and writes its entries
+// after the counts of the threads before it.
 constexpr int kListThreads = 1024;
-__global__ void __launch_bounds__(kListThreads) k_geo_lists(const uint8_t *__restrict__ flags, uint32_t nb,
+__global__ void __launch_bounds__(kListThreads) k_geo_lists(const uint8_t *__restrict__ flags,
+                                                           const uint16_t *__restrict__ ioc, uint32_t nb,
                                                            uint32_t *__restrict__ act, uint32_t *__restrict__ io,
+                                                           uint32_t *__restrict__ ioofs,
                                                            uint32_t *__restrict__ counts) {
-    __shared__ uint32_t ca[kListThreads], ci[kListThreads];
+    __shared__ uint32_t ca[kListThreads], ci[kListThreads], cn[kListThreads], tot[3];
     const uint32_t per = (nb + kListThreads - 1) / kListThreads;
     const uint32_t b0 = min(nb, threadIdx.x * per), b1 = min(nb, b0 + per);
-    uint32_t na = 0, ni = 0;
+    uint32_t na = 0, ni = 0, nn = 0;
     for (uint32_t b = b0; b < b1; ++b) {
         na += flags[b] & 1u;
         ni += (flags[b] >> 1) & 1u;
+        nn += ioc[b];
     }
     ca[threadIdx.x] = na;
     ci[threadIdx.x] = ni;
+    cn[threadIdx.x] = nn;
     __syncthreads();
     if (threadIdx.x == 0) {
-        uint32_t sa = 0, si = 0;
+        uint32_t sa = 0, si = 0, sn = 0;
         for (int t = 0; t < kListThreads; ++t) {
-            const uint32_t va = ca[t], vi = ci[t];
+            const uint32_t va = ca[t], vi = ci[t], vn = cn[t];
             ca[t] = sa;
             ci[t] = si;
+            cn[t] = sn;
             sa += va;
             si += vi;
+            sn += vn;
         }
-        counts[0] = sa;
-        counts[1] = si;
+        tot[0] = sa;
+        tot[1] = si;
+        tot[2] = sn;
     }
     __syncthreads();
-    uint32_t oa = ca[threadIdx.x], oi = ci[threadIdx.x];
+    if (threadIdx.x < 3) counts[threadIdx.x] = tot[threadIdx.x];  // a lane each: no wide store
+    uint32_t oa = ca[threadIdx.x], oi = ci[threadIdx.x], on = cn[threadIdx.x];
     for (uint32_t b = b0; b < b1; ++b) {
         if (flags[b] & 1u) act[oa++] = b;
-        if (flags[b] & 2u) io[oi++] = b;
+        if (flags[b] & 2u) {
+            ioofs[oi] = on;
+            io[oi++] = b;
+            on += ioc[b];
+        }
     }
+}
+
+// The io node list: block k of the io block list writes its nodes with
+// inlet or outlet links, in thread order, from offset ioofs[k].
+__global__ void __launch_bounds__(kGeoBlock) k_geo_ionodes(const uint32_t *__restrict__ links, int nx, int ny, int nz,
+                                                          const uint32_t *__restrict__ io,
+                                                          const uint32_t *__restrict__ ioofs,
+                                                          uint32_t *__restrict__ ionodes) {
+    Here h;
+    const bool in = here(nx, ny, nz, io[blockIdx.x], h);
+    const bool mine = in && has_io_link(links[h.n]);
+    uint32_t total = 0;
+    const uint32_t r = block_rank(mine, total);
+    if (mine) ionodes[ioofs[blockIdx.x] + r] = h.n;
 }
 
 // psi that a non-fluid node shows the gradient of a fluid neighbour: the
@@ -259,44 +319,98 @@ __global__ void __launch_bounds__(kGeoBlock) k_geo_collide(SplitArgs<S> sa, Mode
 // the value it will pull through it at the next step into the upstream
 // node's slot (the rules of the column sweep, from the same stored pairs).
 // Kept out of the collision kernel, whose registers they would take from 59
-// to 137.
-template <typename S>
-__global__ void __launch_bounds__(kGeoBlock) k_geo_boundary(SplitArgs<S> sa, Model<float> mo) {
+// to 137.  A wave takes one direction i (uniform over the wave) for 64 nodes
+// of the io node list; lanes whose node has no inlet or outlet link i leave
+// at once.  One thread per node looping over its 18 links took 12-13 us on
+// the 512 x 128 x 64 junction (7 936 such nodes, one wave per CU, each wave
+// running the 18 links' code one after another); one thread per block node
+// over the io blocks, 13 us.
+constexpr int kIoBlock = 64;
+
+// Opposite of D3Q19 direction i from the numbering (rest; +x -x +y -y +z -z;
+// then per plane (+,+) (+,-) (-,+) (-,-)), for a direction known only at run
+// time; checked against the lattice table at compile time.
+__host__ __device__ constexpr int opp19(int i) {
+    return i == 0 ? 0 : i <= 6 ? ((i & 1) ? i + 1 : i - 1) : i - 2 * ((i - 7) % 4) + 3;
+}
+constexpr bool opp19_matches() {
+    for (int i = 0; i < D3Q19::Q; ++i)
+        if (opp19(i) != D3Q19::opp[i]) return false;
+    return true;
+}
+static_assert(opp19_matches(), "D3Q19 opposite directions");
+
+// Link I of node n; so_i and so_o are the byte offsets of the arrays of
+// directions I and opp(I), passed in from before any branch that lanes take
+// differently, so that they stay in scalar registers.
+template <int I, typename S>
+__device__ __forceinline__ void io_link(const FusedArgs<S> &a, const Model<float> &mo, uint32_t n, uint32_t so_i,
+                                        uint32_t so_o) {
     using L = D3Q19;
     typedef float T;
     typedef typename PairOf<S>::type P2;
     constexpr uint32_t E = sizeof(P2);
-    const FusedArgs<S> &a = sa.a;
-    Here h;
-    if (!here(a.nx, a.ny, a.nz, sa.blocks[blockIdx.x], h)) return;
-    const uint32_t n = h.n;
     const uint32_t clk = a.links[n];
-    if (!has_io_link(clk)) return;
+    if (!((clk >> I) & 1u)) return;
+    Here h;
+    const uint32_t t = n / uint32_t(a.nx);
+    h.n = n;
+    h.x = int(n - t * uint32_t(a.nx));
+    h.z = int(t / uint32_t(a.ny));
+    h.y = int(t - uint32_t(h.z) * uint32_t(a.ny));
+    const uint32_t m = nbr(a.nx, a.ny, a.nz, h, -L::cx[I], -L::cy[I], -L::cz[I]);
+    const uint8_t c = (clk & kLinkMixed) ? a.mask[m] : link_code(clk);
+    if (is_wall(c)) return;
     const uint32_t cstride = uint32_t(a.pitch) * E;
     const __amdgpu_buffer_rsrc_t rout = state_rsrc(a.out, uint32_t(L::Q) * cstride);
-    P2 ov[L::Q];
-#pragma unroll
-    for (int i = 0; i < L::Q; ++i) ov[i] = load_pair<P2>(rout, n * E, uint32_t(i) * cstride);
-    Geo g;
-    g.nx = a.nx;
-    g.ny = a.ny;
-    g.nz = a.nz;
-    g.N = int64_t(a.nx) * a.ny * a.nz;
-    g.pitch = a.pitch;
-    g.mask = a.mask;
+    Geo g{};
     g.inlets = a.inlets;
     g.outlets = a.outlets;
-    g.walls = a.walls;
-    g.links = a.links;
     OwnMom<T> om{};
-    if (clk & kLinkOutlet) om = own_moments<L, S, T>(ov);
+    P2 own;
+    if (c >= kOutlet0) {
+        // outlet values need the node's own moments, from all its new pairs
+        P2 ov[L::Q];
 #pragma unroll
-    for (int i = 1; i < L::Q; ++i) {
-        if (!((clk >> i) & 1u)) continue;
-        const uint32_t m = nbr(a.nx, a.ny, a.nz, h, -L::cx[i], -L::cy[i], -L::cz[i]);
-        const uint8_t c = (clk & kLinkMixed) ? a.mask[m] : link_code(clk);
-        if (!is_wall(c))
-            store_pair<P2>(rout, m * E, uint32_t(i) * cstride, boundary_pair<L, S, T>(g, mo, i, c, ov[L::opp[i]], om));
+        for (int i = 0; i < L::Q; ++i) ov[i] = load_pair<P2>(rout, n * E, uint32_t(i) * cstride);
+        om = own_moments<L, S, T>(ov);
+        own = ov[L::opp[I]];
+    } else {
+        own = load_pair<P2>(rout, n * E, uint32_t(uniform(int(so_o))));
+    }
+    store_pair<P2>(rout, m * E, uint32_t(uniform(int(so_i))),
+                   boundary_pair_v<L, S, T>(mo, I, c, io_vals<T>(g, c), own, om));
+}
+
+template <typename S>
+__global__ void __launch_bounds__(kIoBlock) k_geo_boundary(SplitArgs<S> sa, Model<float> mo, uint32_t count) {
+    // block b: direction 1 + b % 18 of list entries 64 (b / 18) .. + 63
+    typedef typename PairOf<S>::type P2;
+    const uint32_t b = blockIdx.x, chunk = b / 18u, dir = 1u + (b - chunk * 18u);
+    const uint32_t cstride = uint32_t(sa.a.pitch) * uint32_t(sizeof(P2));
+    const uint32_t so_i = dir * cstride, so_o = uint32_t(opp19(int(dir))) * cstride;
+    const uint32_t k = chunk * kIoBlock + threadIdx.x;
+    if (k >= count) return;
+    const uint32_t n = sa.blocks[k];
+    switch (dir) {
+        case 1: io_link<1, S>(sa.a, mo, n, so_i, so_o); break;
+        case 2: io_link<2, S>(sa.a, mo, n, so_i, so_o); break;
+        case 3: io_link<3, S>(sa.a, mo, n, so_i, so_o); break;
+        case 4: io_link<4, S>(sa.a, mo, n, so_i, so_o); break;
+        case 5: io_link<5, S>(sa.a, mo, n, so_i, so_o); break;
+        case 6: io_link<6, S>(sa.a, mo, n, so_i, so_o); break;
+        case 7: io_link<7, S>(sa.a, mo, n, so_i, so_o); break;
+        case 8: io_link<8, S>(sa.a, mo, n, so_i, so_o); break;
+        case 9: io_link<9, S>(sa.a, mo, n, so_i, so_o); break;
+        case 10: io_link<10, S>(sa.a, mo, n, so_i, so_o); break;
+        case 11: io_link<11, S>(sa.a, mo, n, so_i, so_o); break;
+        case 12: io_link<12, S>(sa.a, mo, n, so_i, so_o); break;
+        case 13: io_link<13, S>(sa.a, mo, n, so_i, so_o); break;
+        case 14: io_link<14, S>(sa.a, mo, n, so_i, so_o); break;
+        case 15: io_link<15, S>(sa.a, mo, n, so_i, so_o); break;
+        case 16: io_link<16, S>(sa.a, mo, n, so_i, so_o); break;
+        case 17: io_link<17, S>(sa.a, mo, n, so_i, so_o); break;
+        default: io_link<18, S>(sa.a, mo, n, so_i, so_o); break;
     }
 }
 
@@ -309,6 +423,7 @@ hipError_t run_split(const Geo &g, const ModelD &md, const void *in, void *out, 
     const int64_t nb = split_blocks(g.nx, g.ny, g.nz);
     if (nb <= 0 || nb > 0x7fffffff || sp.active > nb || sp.io > nb || sp.active < 0 || sp.io < 0)
         return hipErrorInvalidValue;
+    if (sp.ionodes < 0 || sp.ionodes > g.pitch || (sp.ionodes > 0) != (sp.io > 0)) return hipErrorInvalidValue;
     const ScratchMap m = scratch_map(scratch, g.pitch, nb);
     SplitArgs<S> sa;
     sa.a = fused_args<S>(g, in, out, ctr_in, ctr_out, FusedShape{8, 1});
@@ -321,8 +436,10 @@ hipError_t run_split(const Geo &g, const ModelD &md, const void *in, void *out, 
     if (sp.active == 0) sa.blocks = nullptr;
     hipLaunchKernelGGL(k_geo_collide<S>, dim3(unsigned(sp.active > 0 ? sp.active : 1)), dim3(kGeoBlock), 0, s, sa,
                        mo);
-    sa.blocks = m.io;
-    if (sp.io > 0) hipLaunchKernelGGL(k_geo_boundary<S>, dim3(unsigned(sp.io)), dim3(kGeoBlock), 0, s, sa, mo);
+    sa.blocks = m.ionodes;
+    if (sp.ionodes > 0)
+        hipLaunchKernelGGL(k_geo_boundary<S>, dim3(unsigned(18 * ((sp.ionodes + kIoBlock - 1) / kIoBlock))),
+                           dim3(kIoBlock), 0, s, sa, mo, uint32_t(sp.ionodes));
     return hipGetLastError();
 }
 
@@ -334,8 +451,9 @@ int64_t split_blocks(int nx, int ny, int nz) {
 
 size_t split_scratch_bytes(int64_t pitch, int nx, int ny, int nz) {
     const int64_t nb = split_blocks(nx, ny, nz);
-    return align256(sizeof(float) * kNM * size_t(pitch)) + align256(size_t(nb)) +
-           2 * align256(sizeof(uint32_t) * size_t(nb)) + align256(2 * sizeof(uint32_t));
+    return align256(sizeof(float) * kNM * size_t(pitch)) + align256(size_t(nb)) + align256(sizeof(uint16_t) * size_t(nb)) +
+           3 * align256(sizeof(uint32_t) * size_t(nb)) + align256(sizeof(uint32_t) * size_t(pitch)) +
+           align256(3 * sizeof(uint32_t));
 }
 
 hipError_t split_prepare(const Geo &g, void *scratch, SplitPlan &sp, hipStream_t s) {
@@ -344,16 +462,27 @@ hipError_t split_prepare(const Geo &g, void *scratch, SplitPlan &sp, hipStream_t
     const int64_t nb = split_blocks(g.nx, g.ny, g.nz);
     if (nb <= 0 || nb > 0x7fffffff) return hipErrorInvalidValue;
     const ScratchMap m = scratch_map(scratch, g.pitch, nb);
-    hipLaunchKernelGGL(k_geo_flags, dim3(unsigned(nb)), dim3(kGeoBlock), 0, s, g.links, g.nx, g.ny, g.nz, m.flags);
-    hipLaunchKernelGGL(k_geo_lists, dim3(1), dim3(kListThreads), 0, s, m.flags, uint32_t(nb), m.act, m.io, m.counts);
+    hipLaunchKernelGGL(k_geo_flags, dim3(unsigned(nb)), dim3(kGeoBlock), 0, s, g.links, g.nx, g.ny, g.nz, m.flags,
+                       m.ioc);
+    hipLaunchKernelGGL(k_geo_lists, dim3(1), dim3(kListThreads), 0, s, m.flags, m.ioc, uint32_t(nb), m.act, m.io,
+                       m.ioofs, m.counts);
     hipError_t e = hipGetLastError();
-    uint32_t c[2] = {0, 0};
+    uint32_t c[3] = {0, 0, 0};
     if (e == hipSuccess) e = hipMemcpyAsync(c, m.counts, sizeof(c), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return e;
-    if (int64_t(c[0]) > nb || int64_t(c[1]) > nb) return hipErrorUnknown;
+    if (int64_t(c[0]) > nb || int64_t(c[1]) > nb || int64_t(c[2]) > g.pitch || (c[1] > 0) != (c[2] > 0))
+        return hipErrorUnknown;
+    if (c[1] > 0) {
+        hipLaunchKernelGGL(k_geo_ionodes, dim3(c[1]), dim3(kGeoBlock), 0, s, g.links, g.nx, g.ny, g.nz, m.io, m.ioofs,
+                           m.ionodes);
+        e = hipGetLastError();
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return e;
+    }
     sp.active = c[0];
     sp.io = c[1];
+    sp.ionodes = c[2];
     return hipSuccess;
 }
 

@@ -104,17 +104,19 @@ int fused_resident_blocks(int prec, int rows, bool masked);
 // kSplitMoments collision moments of every fluid node, a collision kernel
 // takes the gradient, collides and stores, and a boundary kernel stores the
 // inlet and outlet values.  Bitwise the column sweep's results; chosen by
-// FusedShape rows 0.  The kernels run blocks of kSplitGX x kSplitGY nodes of
-// one z plane, only those with fluid (the boundary kernel: only those with
-// links from inlets or outlets), from block lists that split_prepare builds
-// on the device once per lattice in `scratch` (split_scratch_bytes: the
-// moments, then the lists).
+// FusedShape rows 0.  The moments and collision kernels run blocks of
+// kSplitGX x kSplitGY nodes of one z plane, only those with fluid, from a
+// block list; the boundary kernel runs one thread per node with links from
+// inlets or outlets, from a node list.  split_prepare builds the lists on the
+// device once per lattice in `scratch` (split_scratch_bytes: the moments,
+// then the lists).
 constexpr int kSplitMoments = 12;
 constexpr int kSplitGX = 64, kSplitGY = 4;
 int64_t split_blocks(int nx, int ny, int nz);
 size_t split_scratch_bytes(int64_t pitch, int nx, int ny, int nz);
 struct SplitPlan {
     int64_t active = 0, io = 0;  // blocks with fluid, blocks with inlet or outlet links
+    int64_t ionodes = 0;         // nodes with inlet or outlet links
 };
 // Builds the block lists and returns their lengths (waits for the stream).
 hipError_t split_prepare(const Geo &g, void *scratch, SplitPlan &sp, hipStream_t s);
