@@ -192,8 +192,11 @@ typedef struct {
 typedef struct lbcg_sim lbcg_sim;
 
 /* Device bytes lbcg_create needs for these parameters (two state buffers, the
- * phase-field scratch, the mask, reduction scratch and a field staging
- * area).  Used for admission by footprint. */
+ * phase-field scratch, the mask and link words, reduction scratch, a field
+ * staging area, the two compact buffers of the compact kernel and, for a
+ * D3Q19 F32 or F16 lattice with geometry, the split step's scratch: 12
+ * collision moments and a node-list entry per node, and per-block lists).
+ * Used for admission by footprint. */
 int lbcg_footprint(const lbcg_params *p, size_t *bytes);
 
 /* Create a simulation on the current HIP device.  dev_buf: NULL = the library
