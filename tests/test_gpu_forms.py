@@ -277,6 +277,28 @@ def test_tune_keeps_state(L):
     assert np.array_equal(a.populations(), b.populations())
 
 
+@pytest.mark.parametrize("prec", ["f32", "f16"])
+def test_tune_keeps_state_with_geometry(L, prec):
+    # a lattice with walls, inlets and an outlet: the tuner times the column
+    # sweep's shapes and the split step (its moments and lists in their own
+    # scratch) on the current state without changing it or the step
+    # counter, and any shape it keeps continues the same trajectory
+    w = _small_focusing()
+    fl = w.mask == 0
+    a = L.Sim.from_workload(w, precision=prec, kernel=L.KERNEL_FUSED)
+    a.step(3)
+    p0 = a.populations()
+    shape = a.tune()
+    _say(f"tuned shape, focusing 128x48x14 {prec}: {shape}")
+    assert np.array_equal(a.populations(), p0)
+    assert a.diagnostics()["step"] == 3
+    a.step(40)
+    b = L.Sim.from_workload(w, precision=prec, kernel=L.KERNEL_FUSED)
+    b.step(43)
+    assert np.array_equal(a.populations()[..., fl], b.populations()[..., fl])
+    assert a.diagnostics()["step"] == 43
+
+
 @pytest.mark.parametrize("before", [0, 1, 2, 5])
 def test_tune_keeps_state_compact(L, before):
     # The compact kernel is tuned on a compact state whether or not the
