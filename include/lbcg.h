@@ -58,15 +58,19 @@ extern "C" {
  * form of Eq. (5), both at the node's rate (see tau_B below), or Eq. (5) as
  * it is written, each colour relaxed towards its own equilibrium at its own
  * rate 1/tau_k (the literal baseline of Fig. 1; it does not keep momentum
- * where tau_R != tau_B).  Both BGK forms run on the generic kernel only. */
+ * where tau_R != tau_B).  Both BGK forms run on the generic kernel and, for
+ * D3Q19 with F32 or F16 storage, on the fused column sweep (tiles of 8 rows,
+ * tile[0] 0 or 8; not the split step of lattices with geometry, the compact
+ * state, the batched sweeps or the D2Q9 sweep). */
 #define LBCG_REGULARIZED 0
 #define LBCG_BGK 1
 #define LBCG_BGK_COLOUR 2
 
 /* Kernel choice: automatic, the two-pass generic kernel (every lattice,
  * precision, collision and boundary) or the fused single-pass kernel (F32 or
- * F16 storage, regularized collision, state buffers below 4 GiB; D3Q19 or
- * D2Q9, any geometry).  Automatic picks the fused kernel where it applies.
+ * F16 storage, state buffers below 4 GiB; D3Q19 with any collision form or
+ * D2Q9 with the regularized collision, any geometry).  Automatic picks the
+ * fused kernel where it applies.
  *
  * LBCG_KERNEL_COMPACT (never picked automatically): the fused sweeps on a
  * compact state, for periodic lattices (no mask), regularized collision;

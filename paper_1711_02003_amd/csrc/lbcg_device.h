@@ -858,7 +858,9 @@ __device__ __forceinline__ void collide(const Model<T> &mo, T drho, T r36R, T r3
         const T cu = cx * ux + cy * uy + cz * uz;
         const T dpR = dphi<L, T>(i, mo.dR0, mo.kR), dpB = dphi<L, T>(i, mo.dB0, mo.kB);
         T ev, od;  // even and odd parts of the new total deviation of direction i
-        if (!mo.bgk) {
+        // (kernels that pass no populations run the regularized form only;
+        // the runtime keeps BGK lattices off them)
+        if (!mo.bgk || pin == nullptr) {
             T qn = (cx * cx - T(1.0 / 3.0)) * N[0] + (cy * cy - T(1.0 / 3.0)) * N[1];
             if (L::D == 3) qn += (cz * cz - T(1.0 / 3.0)) * N[2];
             qn += T(2) * cx * cy * N[3];
@@ -869,27 +871,33 @@ __device__ __forceinline__ void collide(const Model<T> &mo, T drho, T r36R, T r3
         } else if (mo.bgk == 1) {
             // (1 - omega) f_i + omega sum_k f_i^{k,eq} - w_i, split into the
             // parts even and odd under i <-> -i (the populations themselves
-            // have no symmetry, so both directions are formed here).
-            const T U2 = T(4.5) * cu * cu - T(1.5) * usq;
-            const T base = -om * w + om * (rR * (w + dpR + w * U2) + rB * (w + dpB + w * U2));
+            // have no symmetry, so both directions are formed here).  The
+            // equilibrium's deviation sum_k f_i^{k,eq} - w_i is formed from
+            // deviations, as in the regularized form (w_i drho + sum_k rho^k
+            // (phi_i^k - w_i) + w_i rho U_i), not as the difference of two
+            // full populations, which in FP32 would leave an error of ~1e-9
+            // in every population every step.
+            const T eq = w * drho + rR * dpR + rB * dpB + w * (T(4.5) * cj * cu - wrho);
             const T lin = om * (odd_coef<L, T>(i) * cj);
             const T di = gm * pin->df[i];
             const T db = gm * pin->df[ib];
-            ev = base + T(0.5) * (di + db);
+            ev = om * eq + T(0.5) * (di + db);
             od = lin + T(0.5) * (di - db);
         } else {
             // Eq. (5) with each colour at its own rate omega_k:
             // sum_k (1 - omega_k) f_i^k + omega_k f_i^{k,eq} - w_i, with the
-            // blue part written as f_i - f_i^R:
-            // (1 - omega_B) df_i + (omega_B - omega_R) f_i^R - omega_B w_i +
-            // sum_k omega_k rho^k (phi_i^k + w_i U_i).
+            // blue part written as f_i - f_i^R and the terms grouped into
+            // deviations (as above):
+            // (1 - omega_B) df_i + (omega_B - omega_R) (f_i^R - rho^R w_i) +
+            // omega_B w_i drho + sum_k omega_k rho^k ((phi_i^k - w_i) + w_i U_i).
             const T U2 = T(4.5) * cu * cu - T(1.5) * usq;
-            const T base = -mo.omB * w + mo.omR * rR * (w + dpR + w * U2) + mo.omB * rB * (w + dpB + w * U2);
+            const T base = mo.omB * w * drho + mo.omR * rR * (dpR + w * U2) + mo.omB * rB * (dpB + w * U2);
             const T lin = (mo.omR * rR + mo.omB * rB) * inv_rho * (odd_coef<L, T>(i) * cj);
             const T dom = mo.omB - mo.omR;
             const T gB = T(1) - mo.omB;
-            const T di = gB * pin->df[i] + dom * pin->fred(i);
-            const T db = gB * pin->df[ib] + dom * pin->fred(ib);
+            const T rw = rR * w;
+            const T di = gB * pin->df[i] + dom * (pin->fred(i) - rw);
+            const T db = gB * pin->df[ib] + dom * (pin->fred(ib) - rw);
             ev = base + T(0.5) * (di + db);
             od = lin + T(0.5) * (di - db);
         }

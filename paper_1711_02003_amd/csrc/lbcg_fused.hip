@@ -36,6 +36,8 @@
 // fluid evenly and still keeps each chunk's x-y neighbours on one XCD.  The
 // batched form steps many lattices in one launch from a block -> (lattice,
 // item) table, dealt the same two ways.
+#include <type_traits>
+
 #include "lbcg_buffer.h"
 #include "lbcg_internal.h"
 
@@ -117,8 +119,11 @@ __device__ __forceinline__ Geo geo_of(const FusedArgs<S> &a) {
     return g;
 }
 
-// One work item: column tile `tile`, z chunk `chunk` of one lattice.
-template <typename S, typename T, int R, bool MASKED>
+// One work item: column tile `tile`, z chunk `chunk` of one lattice.  POPS:
+// the collision needs the node's populations, not only its moments (plain
+// BGK, Eq. (5)): the decoded populations of the plane being collided are
+// kept beside the moments until its collision.
+template <typename S, typename T, int R, bool MASKED, bool POPS = false>
 __device__ __forceinline__ void sweep(const FusedArgs<S> &a, const Model<T> &mo, int tile, int chunk,
                                       float *lds) {
     using L = D3Q19;
@@ -239,6 +244,11 @@ __device__ __forceinline__ void sweep(const FusedArgs<S> &a, const Model<T> &mo,
     // of plane z+1 are in flight.
     T cd = 0, cR = 0, cB = 0, cj[3] = {0, 0, 0}, cS[6] = {0, 0, 0, 0, 0, 0};
     bool cfl = false;
+    // plain BGK: populations of the plane being collided (cq) and of the
+    // plane whose moments were just taken (nq); nothing otherwise
+    struct NoPops {};
+    using Kept = typename std::conditional<POPS, Pops<L, T>, NoPops>::type;
+    Kept cq{}, nq{};
     uint32_t clk = 0;  // link word of the plane being collided
     Pending<S, T> pp;
     pp.lk = kLinkFluid;
@@ -262,6 +272,7 @@ __device__ __forceinline__ void sweep(const FusedArgs<S> &a, const Model<T> &mo,
         interior_take(q);
         Mom<T> m;
         moments<L, T>(q, m);
+        if constexpr (POPS) nq = q;
         d = m.drho;
         r36R = m.r36R;
         r36B = m.r36B;
@@ -294,6 +305,7 @@ __device__ __forceinline__ void sweep(const FusedArgs<S> &a, const Model<T> &mo,
     ring_issue(z0);
     interior_issue(z0);
     if (intile) slot_of(z0)[(row + 1) * W + lane + 1] = interior_moments(cd, cR, cB, cj, cS, cfl);
+    if constexpr (POPS) cq = nq;
     clk = pp.lk;
     ring_finish(z0);
     ring_issue(z0 + 1);
@@ -356,7 +368,9 @@ __device__ __forceinline__ void sweep(const FusedArgs<S> &a, const Model<T> &mo,
             }
             const T F[3] = {fx, fy, fz};
             PostOut<L, T> o;
-            collide<L, T>(mo, cd, cR, cB, cj, cS, F, nullptr, o);
+            const Pops<L, T> *pin = nullptr;
+            if constexpr (POPS) pin = &cq;
+            collide<L, T>(mo, cd, cR, cB, cj, cS, F, pin, o);
             Dither dz(step, uint32_t(x) + uint32_t(a.nx) * (uint32_t(y) + uint32_t(a.ny) * uint32_t(z)));
 #pragma unroll
             for (int i = 0; i < L::Q; ++i) ov[i] = encode_step<L, S, T>(o.df[i], o.mm[i], (o.red >> i) & 1u, i, dz);
@@ -386,6 +400,7 @@ __device__ __forceinline__ void sweep(const FusedArgs<S> &a, const Model<T> &mo,
         if (!kDelayStores) flush();
         cfl = nfl;
         clk = nlk;
+        if constexpr (POPS) cq = nq;
         cd = nd;
         cR = nR;
         cB = nB;
@@ -407,12 +422,12 @@ __device__ __forceinline__ int work_index(int total) {
 }
 
 // Single lattice (see the file comment for the work mapping).
-template <typename S, typename T, int R, bool MASKED>
+template <typename S, typename T, int R, bool MASKED, bool POPS>
 __global__ void __launch_bounds__(kTX * R) k_step_fused(FusedArgs<S> a, Model<T> mo) {
     extern __shared__ float lds[];
     const int item = work_index<MASKED>(a.ntx * a.nty * a.zchunks);
     if (item == 0 && threadIdx.x == 0) *a.ctr_out = *a.ctr_in + 1u;
-    sweep<S, T, R, MASKED>(a, mo, item / a.zchunks, item % a.zchunks, lds);
+    sweep<S, T, R, MASKED, POPS>(a, mo, item / a.zchunks, item % a.zchunks, lds);
 }
 
 // Many lattices in one launch: the grid covers table entries [0, gridDim.x),
@@ -440,14 +455,20 @@ static size_t fused_lds(int R) { return size_t(5) * (R + 2) * (kTX + 2) * sizeof
 
 template <typename S, int R>
 static const void *fused_fn(bool masked) {
-    return masked ? reinterpret_cast<const void *>(&k_step_fused<S, float, R, true>)
-                  : reinterpret_cast<const void *>(&k_step_fused<S, float, R, false>);
+    return masked ? reinterpret_cast<const void *>(&k_step_fused<S, float, R, true, false>)
+                  : reinterpret_cast<const void *>(&k_step_fused<S, float, R, false, false>);
+}
+template <typename S>
+static const void *fused_fn_pops(bool masked) {
+    return masked ? reinterpret_cast<const void *>(&k_step_fused<S, float, 8, true, true>)
+                  : reinterpret_cast<const void *>(&k_step_fused<S, float, 8, false, true>);
 }
 
-int fused_resident_blocks(int prec, int rows, bool masked) {
+int fused_resident_blocks(int prec, int rows, bool masked, bool pops) {
     int per_cu = 0;
-    const void *fn = prec == 2 ? (rows == 4 ? fused_fn<_Float16, 4>(masked) : fused_fn<_Float16, 8>(masked))
-                               : (rows == 4 ? fused_fn<float, 4>(masked) : fused_fn<float, 8>(masked));
+    const void *fn = pops ? (prec == 2 ? fused_fn_pops<_Float16>(masked) : fused_fn_pops<float>(masked))
+                     : prec == 2 ? (rows == 4 ? fused_fn<_Float16, 4>(masked) : fused_fn<_Float16, 8>(masked))
+                                 : (rows == 4 ? fused_fn<float, 4>(masked) : fused_fn<float, 8>(masked));
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kTX * rows, fused_lds(rows)) != hipSuccess) {
         (void)hipGetLastError();
         per_cu = 1;
@@ -485,9 +506,10 @@ template FusedArgs<float> fused_args<float>(const Geo &, const void *, void *, c
 template FusedArgs<_Float16> fused_args<_Float16>(const Geo &, const void *, void *, const uint32_t *, uint32_t *,
                                                   FusedShape);
 
-template <typename S, int R, bool MASKED>
+template <typename S, int R, bool MASKED, bool POPS = false>
 static void launch_one(const FusedArgs<S> &a, const Model<float> &mo, unsigned nblocks, hipStream_t s) {
-    hipLaunchKernelGGL((k_step_fused<S, float, R, MASKED>), dim3(nblocks), dim3(kTX * R), fused_lds(R), s, a, mo);
+    hipLaunchKernelGGL((k_step_fused<S, float, R, MASKED, POPS>), dim3(nblocks), dim3(kTX * R), fused_lds(R), s, a,
+                       mo);
 }
 
 template <typename S>
@@ -506,6 +528,12 @@ static hipError_t run_fused(const Geo &g, const ModelD &md, const void *in, void
     const Model<float> mo = to_model<float>(md);
     const bool masked = g.mask != nullptr;
     const unsigned nb = unsigned(nblocks);
+    if (md.bgk) {
+        // plain BGK keeps a plane of populations per thread: 8-row tiles only
+        if (R != 8) return hipErrorInvalidValue;
+        masked ? launch_one<S, 8, true, true>(a, mo, nb, s) : launch_one<S, 8, false, true>(a, mo, nb, s);
+        return hipGetLastError();
+    }
     if (R == 4)
         masked ? launch_one<S, 4, true>(a, mo, nb, s) : launch_one<S, 4, false>(a, mo, nb, s);
     else

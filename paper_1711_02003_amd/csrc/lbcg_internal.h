@@ -66,7 +66,8 @@ hipError_t launch_pops_at(int lattice, int prec, const Geo &g, const ModelD &md,
 hipError_t launch_diag(int lattice, int prec, const Geo &g, const ModelD &md, const void *st,
                        bool pulled, double *partials, double *res, hipStream_t s);
 
-// Fused single-pass D3Q19 step; F32 or F16 storage, with or without geometry.
+// Fused single-pass D3Q19 step; F32 or F16 storage, with or without geometry;
+// the regularized collision, or plain BGK (md.bgk: 8-row tiles only).
 struct FusedShape {
     int rows;     // rows of the x-y tile (one wave of 64 nodes per row)
     int zchunks;  // z range split per column of tiles
@@ -96,8 +97,9 @@ FusedArgs<S> fused_args(const Geo &g, const void *in, void *out, const uint32_t 
 hipError_t launch_step_fused(int prec, const Geo &g, const ModelD &md, const void *in, void *out,
                              const uint32_t *ctr_in, uint32_t *ctr_out, FusedShape shape, hipStream_t s);
 bool fused_supported(int lattice, int prec, const Geo &g);
-// Blocks of the fused kernel that fit on the device at once.
-int fused_resident_blocks(int prec, int rows, bool masked);
+// Blocks of the fused kernel that fit on the device at once (pops: its plain
+// BGK form).
+int fused_resident_blocks(int prec, int rows, bool masked, bool pops = false);
 
 // Split D3Q19 step for lattices with geometry (F32 or F16 storage,
 // regularized): a moments kernel writes psi (`psi`, pitch floats) and the

@@ -134,6 +134,8 @@ extern "C" int lbcg_batch_step_noalloc(lbcg_sim *const *sims, int32_t n, const i
         const lbcg_sim *s = sims[j];
         if (!s || !s->initialised || s->lattice != LBCG_D3Q19) return LBCG_E_INVAL;
         if (s->kernel != LBCG_KERNEL_FUSED && s->kernel != LBCG_KERNEL_COMPACT) return LBCG_E_INVAL;
+        // the batched sweeps relax with the regularized collision only
+        if (s->collision != LBCG_REGULARIZED) return LBCG_E_INVAL;
         // the batched compact sweep stores FP32
         if (s->kernel == LBCG_KERNEL_COMPACT && s->prec != LBCG_F32) return LBCG_E_INVAL;
         if (s->kernel != s0->kernel || s->prec != s0->prec || s->stream != s0->stream || s->device != s0->device)

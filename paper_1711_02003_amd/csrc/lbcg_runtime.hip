@@ -76,6 +76,10 @@ int validate(const lbcg_params *p) {
     if (p->tile[0] < 0 || p->tile[1] < 0) return LBCG_E_INVAL;
     if (p->tile[0] != 0 && p->tile[0] != 4 && p->tile[0] != 8) return LBCG_E_INVAL;
     if (p->kernel == LBCG_KERNEL_COMPACT && p->tile[0] == 4) return LBCG_E_INVAL;  // 8-row tiles only
+    // plain BGK on the fused D3Q19 sweep: 8-row tiles only
+    if (p->collision != LBCG_REGULARIZED && p->lattice == LBCG_D3Q19 && p->precision != LBCG_F64 &&
+        p->tile[0] == 4 && p->kernel != LBCG_KERNEL_GENERIC)
+        return LBCG_E_INVAL;
     if (p->tile[1] > 4096) return LBCG_E_INVAL;
     // tile width: 64, or 32 on the compact D3Q19 sweep; 0 = automatic
     if (p->tile[2] != 0 && p->tile[2] != 64 &&
@@ -101,8 +105,9 @@ Plan make_plan(const lbcg_params *p) {
                                kAlign)
                     : 0;
     pl.psi = align_up(size_t(pl.pitch) * pl.tsize, kAlign);
-    // the split geometry step's moments: D3Q19 with a mask, F32 or F16
-    pl.moms = p->mask && p->lattice == LBCG_D3Q19 && p->precision != LBCG_F64 &&
+    // the split geometry step's moments: D3Q19 with a mask, F32 or F16,
+    // regularized collision
+    pl.moms = p->mask && p->lattice == LBCG_D3Q19 && p->precision != LBCG_F64 && p->collision == LBCG_REGULARIZED &&
                       (p->kernel == LBCG_KERNEL_AUTO || p->kernel == LBCG_KERNEL_FUSED)
                   ? align_up(split_scratch_bytes(pl.pitch, p->dims[0], p->dims[1], p->dims[2]), kAlign)
                   : 0;
@@ -201,7 +206,8 @@ FusedShape pick_shape(const lbcg_sim *s, const lbcg_params *p) {
         const int64_t tiles = int64_t((s->g.nx + sh.tx - 1) / sh.tx) * ((s->g.ny + sh.rows - 1) / sh.rows);
         const int64_t resident = s->kernel == LBCG_KERNEL_COMPACT
                                      ? compact_resident_blocks(sh.tx, s->prec)
-                                     : fused_resident_blocks(s->prec, sh.rows, s->g.mask != nullptr);
+                                     : fused_resident_blocks(s->prec, sh.rows, s->g.mask != nullptr,
+                                                             s->collision != LBCG_REGULARIZED);
         int64_t want = (resident + tiles - 1) / tiles;
         const int64_t cap = s->g.nz / 8 > 1 ? s->g.nz / 8 : 1;
         zc = int(want < 1 ? 1 : (want > cap ? cap : want));
@@ -480,13 +486,13 @@ int lbcg_create(const lbcg_params *p, void *dev_buf, size_t bytes, void *hip_str
         return dev_err(e);
     }
 
+    // plain BGK runs on the D3Q19 column sweep (not the D2Q9 strip sweep,
+    // the split step or the compact state)
+    const bool fused_ok = any_fused_supported(s->lattice, s->prec, s->g) &&
+                          (s->collision == LBCG_REGULARIZED || s->lattice == LBCG_D3Q19);
     int kind = p->kernel;
-    if (kind == LBCG_KERNEL_AUTO)
-        kind = (any_fused_supported(s->lattice, s->prec, s->g) && s->collision == LBCG_REGULARIZED)
-                   ? LBCG_KERNEL_FUSED
-                   : LBCG_KERNEL_GENERIC;
-    if ((kind == LBCG_KERNEL_FUSED &&
-         (!any_fused_supported(s->lattice, s->prec, s->g) || s->collision != LBCG_REGULARIZED)) ||
+    if (kind == LBCG_KERNEL_AUTO) kind = fused_ok ? LBCG_KERNEL_FUSED : LBCG_KERNEL_GENERIC;
+    if ((kind == LBCG_KERNEL_FUSED && !fused_ok) ||
         (kind == LBCG_KERNEL_COMPACT &&
          (!compact_supported(s->lattice, s->prec, s->g) || s->collision != LBCG_REGULARIZED))) {
         release(s);
@@ -781,7 +787,9 @@ int lbcg_tune(lbcg_sim *s, int32_t *rows, int32_t *zchunks) {
             if (s->lattice == LBCG_D2Q9) break;
             if (cmp ? r != 8 : tx != 64) continue;
             const int64_t tiles = int64_t((s->g.nx + tx - 1) / tx) * ((s->g.ny + r - 1) / r);
-            const int64_t resident = cmp ? compact_resident_blocks(tx, s->prec) : fused_resident_blocks(s->prec, r, masked);
+            if (s->collision != LBCG_REGULARIZED && r != 8) continue;  // plain BGK: 8-row tiles
+            const int64_t resident = cmp ? compact_resident_blocks(tx, s->prec)
+                                         : fused_resident_blocks(s->prec, r, masked, s->collision != LBCG_REGULARIZED);
             std::vector<int64_t> zs = {1};
             for (int m : {1, 2, 4}) zs.push_back((m * resident + tiles - 1) / tiles);
             for (int planes : {2, 4, 8, 16, 32, 64}) zs.push_back((s->g.nz + planes - 1) / planes);

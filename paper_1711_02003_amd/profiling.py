@@ -50,7 +50,7 @@ KERNELS = {
                         "paper_1711_02003_amd/csrc/lbcg_device.h"],
                        2 * (19 * 4 + 20), [r"k_step_compact<false, \d+, float>"]),
     "k_step_fused": (["paper_1711_02003_amd/csrc/lbcg_fused.hip", "paper_1711_02003_amd/csrc/lbcg_device.h"],
-                     2 * 38 * 4, [r"k_step_fused<float, float, \d, false>"]),
+                     2 * 38 * 4, [r"k_step_fused<float, float, \d, false, false>"]),
     "geo_split": (["paper_1711_02003_amd/csrc/lbcg_geo.hip", "paper_1711_02003_amd/csrc/lbcg_device.h"],
                   2 * 38 * 4 + 4, [r"k_geo_moments<float>", r"k_geo_collide<float>", r"k_geo_boundary<float>"]),
 }
@@ -184,9 +184,9 @@ def traffic_summary(fetch_csv, write_csv, kernel_sub, timed, nodes, out_txt, com
 
 # Per benchmark form: its kernels, as patterns of their dispatch names
 # (FP16 instantiations appear mangled).
-FORM_KERNELS = [("D3Q19 256³ droplets, FP32 pairs", r"k_step_fused<float, float, \d, false>"),
+FORM_KERNELS = [("D3Q19 256³ droplets, FP32 pairs", r"k_step_fused<float, float, \d, false, false>"),
                 ("D3Q19 256³ droplets, FP16 compact", r"k_step_compactILb0ELi\d+EDF16_"),
-                ("D3Q19 256³ droplets, FP16 pairs", r"k_step_fusedIDF16_fLi\dELb0E"),
+                ("D3Q19 256³ droplets, FP16 pairs", r"k_step_fusedIDF16_fLi\dELb0ELb0E"),
                 ("D2Q9 4096² droplets, FP32 compact", r"k_step_compact2d<false>"),
                 ("D2Q9 4096² droplets, FP32", r"k_step_fused2d<float, false>"),
                 ("D2Q9 junction 8192×2048, FP32", r"k_step_fused2d<float, true>"),
