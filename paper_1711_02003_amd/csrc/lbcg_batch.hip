@@ -227,7 +227,8 @@ int lbcg_batch_create(lbcg_sim *const *sims, int32_t n, const int32_t *tile, lbc
         if (s->kernel != LBCG_KERNEL_FUSED && s->kernel != LBCG_KERNEL_COMPACT) return LBCG_E_INVAL;
         // the batched sweeps relax with the regularized collision only
         if (s->collision != LBCG_REGULARIZED) return LBCG_E_INVAL;
-        // the batched compact sweep stores FP32
+        // the batched compact sweep: periodic lattices, FP32
+        if (s->kernel == LBCG_KERNEL_COMPACT && s->g.mask) return LBCG_E_INVAL;
         if (s->kernel == LBCG_KERNEL_COMPACT && s->prec != LBCG_F32) return LBCG_E_INVAL;
         if (s->kernel != sims[0]->kernel || s->prec != sims[0]->prec || s->stream != sims[0]->stream)
             return LBCG_E_INVAL;

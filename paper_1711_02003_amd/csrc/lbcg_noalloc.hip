@@ -136,7 +136,8 @@ extern "C" int lbcg_batch_step_noalloc(lbcg_sim *const *sims, int32_t n, const i
         if (s->kernel != LBCG_KERNEL_FUSED && s->kernel != LBCG_KERNEL_COMPACT) return LBCG_E_INVAL;
         // the batched sweeps relax with the regularized collision only
         if (s->collision != LBCG_REGULARIZED) return LBCG_E_INVAL;
-        // the batched compact sweep stores FP32
+        // the batched compact sweep: periodic lattices, FP32
+        if (s->kernel == LBCG_KERNEL_COMPACT && s->g.mask) return LBCG_E_INVAL;
         if (s->kernel == LBCG_KERNEL_COMPACT && s->prec != LBCG_F32) return LBCG_E_INVAL;
         if (s->kernel != s0->kernel || s->prec != s0->prec || s->stream != s0->stream || s->device != s0->device)
             return LBCG_E_INVAL;

@@ -76,6 +76,8 @@ int validate(const lbcg_params *p) {
     if (p->tile[0] < 0 || p->tile[1] < 0) return LBCG_E_INVAL;
     if (p->tile[0] != 0 && p->tile[0] != 4 && p->tile[0] != 8) return LBCG_E_INVAL;
     if (p->kernel == LBCG_KERNEL_COMPACT && p->tile[0] == 4) return LBCG_E_INVAL;  // 8-row tiles only
+    // the compact state with geometry runs the split step only
+    if (p->kernel == LBCG_KERNEL_COMPACT && p->mask && (p->tile[0] || p->tile[1] || p->tile[2])) return LBCG_E_INVAL;
     // plain BGK on the fused D3Q19 sweep: 8-row tiles only
     if (p->collision != LBCG_REGULARIZED && p->lattice == LBCG_D3Q19 && p->precision != LBCG_F64 &&
         p->tile[0] == 4 && p->kernel != LBCG_KERNEL_GENERIC)
@@ -108,7 +110,8 @@ Plan make_plan(const lbcg_params *p) {
     // the split geometry step's moments: D3Q19 with a mask, F32 or F16,
     // regularized collision
     pl.moms = p->mask && p->lattice == LBCG_D3Q19 && p->precision != LBCG_F64 && p->collision == LBCG_REGULARIZED &&
-                      (p->kernel == LBCG_KERNEL_AUTO || p->kernel == LBCG_KERNEL_FUSED)
+                      (p->kernel == LBCG_KERNEL_AUTO || p->kernel == LBCG_KERNEL_FUSED ||
+                       (p->kernel == LBCG_KERNEL_COMPACT && p->precision == LBCG_F32))
                   ? align_up(split_scratch_bytes(pl.pitch, p->dims[0], p->dims[1], p->dims[2]), kAlign)
                   : 0;
     pl.mask = p->mask ? align_up(size_t(pl.pitch), kAlign) : 0;
@@ -185,6 +188,11 @@ FusedShape pick_shape(const lbcg_sim *s, const lbcg_params *p) {
         sh.zchunks = yc < 1 ? 1 : yc;
         return sh;
     }
+    if (s->kernel == LBCG_KERNEL_COMPACT && s->g.mask) {
+        sh.rows = 0;  // the compact state with geometry: the split step
+        sh.zchunks = 1;
+        return sh;
+    }
     if (s->kernel == LBCG_KERNEL_FUSED && s->moms && !p->tile[0] && !p->tile[1] && p->mask) {
         // With geometry, the split step when at most half the nodes are
         // fluid: the fluid then fills few column tiles, which the sweep can
@@ -227,8 +235,12 @@ hipError_t enqueue_step(lbcg_sim *s, bool pulled) {
     uint32_t *ctr_out = s->ctr + (s->cur ^ 1);
     if (s->kernel == LBCG_KERNEL_COMPACT && pulled) {
         const bool pair_in = !s->compact;
-        hipError_t e = launch_compact(s, pair_in ? s->buf[s->cur] : s->cbuf[s->cur], pair_in, s->cbuf[s->cur ^ 1],
-                                      ctr_in, ctr_out, s->shape);
+        hipError_t e =
+            s->g.mask ? launch_step_cgeo(s->g, s->md, pair_in, pair_in ? s->buf[s->cur] : s->cbuf[s->cur],
+                                         s->buf[s->cur], s->cbuf[s->cur ^ 1], s->buf[s->cur ^ 1], s->psi, s->moms,
+                                         s->split, ctr_in, ctr_out, s->stream)
+                      : launch_compact(s, pair_in ? s->buf[s->cur] : s->cbuf[s->cur], pair_in, s->cbuf[s->cur ^ 1],
+                                       ctr_in, ctr_out, s->shape);
         if (e == hipSuccess) {
             s->compact = true;
             s->expanded = false;
@@ -570,7 +582,9 @@ int lbcg_step(lbcg_sim *s, int64_t n) {
 static hipError_t ensure_pairs(lbcg_sim *s) {
     if (!s->compact || s->expanded) return hipSuccess;
     hipError_t e = s->lattice == LBCG_D2Q9 ? launch_expand2d(s->g, s->cbuf[s->cur], s->buf[s->cur], s->stream)
-                                           : launch_expand(s->prec, s->g, s->cbuf[s->cur], s->buf[s->cur], s->stream);
+                   : s->g.mask           ? launch_expand_cgeo(s->g, s->cbuf[s->cur], s->buf[s->cur], s->moms, s->split,
+                                                              s->stream)
+                                         : launch_expand(s->prec, s->g, s->cbuf[s->cur], s->buf[s->cur], s->stream);
     if (e == hipSuccess) s->expanded = true;
     return e;
 }
@@ -760,6 +774,12 @@ int lbcg_launch_info(lbcg_sim *s, int32_t *kernel, int32_t *rows, int32_t *zchun
 int lbcg_tune(lbcg_sim *s, int32_t *rows, int32_t *zchunks) {
     if (!s) return LBCG_E_INVAL;
     if (!s->initialised) return LBCG_E_STATE;
+    if (s->kernel == LBCG_KERNEL_COMPACT && s->g.mask) {
+        // the compact state with geometry has one launch shape: the split step
+        if (rows) *rows = s->shape.rows;
+        if (zchunks) *zchunks = s->shape.zchunks;
+        return LBCG_OK;
+    }
     if (s->kernel == LBCG_KERNEL_FUSED || s->kernel == LBCG_KERNEL_COMPACT) {
         const bool cmp = s->kernel == LBCG_KERNEL_COMPACT;
         // Candidate shapes: both tile heights, z splits that fill the device

@@ -275,11 +275,18 @@ def test_compact_rejects_what_it_does_not_cover(L):
     m = np.zeros(w.shape, np.uint8)
     m[:, 0, :] = 1
     w.mask = m
+    # with geometry: D3Q19 FP32 only, on the split step
+    assert L.Sim.from_workload(w, precision="f32", kernel=L.KERNEL_COMPACT).launch_info()["rows"] == 0
     with pytest.raises(L.LbcgError):
-        L.Sim.from_workload(w, precision="f32", kernel=L.KERNEL_COMPACT)
+        L.Sim.from_workload(w, precision="f16", kernel=L.KERNEL_COMPACT)
     w2 = W.droplets_2d(n=64, seed=1)
     with pytest.raises(L.LbcgError):
         L.Sim.from_workload(w2, precision="f16", kernel=L.KERNEL_COMPACT)
+    m2 = np.zeros(w2.rhoR.shape, np.uint8)
+    m2[:, 0, :] = 1
+    w2.mask = m2
+    with pytest.raises(L.LbcgError):
+        L.Sim.from_workload(w2, precision="f32", kernel=L.KERNEL_COMPACT)
     w.mask = None
     with pytest.raises(L.LbcgError):  # 8-row tiles only
         L.Sim.from_workload(w, precision="f32", kernel=L.KERNEL_COMPACT, tile=(4, 0, 0))
