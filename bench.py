@@ -283,7 +283,7 @@ def focusing_form(torch, lbcg, W, steps=200, warmup=10, tune=True):
     shape (rows 0: the split step) and its fraction of HBM peak on
     2 x 38 x E + 4 bytes per fluid node; for FP32 on the split step, the
     HBM bytes per step from the committed counter summary (when current);
-    and the FP32 compact state on the split step."""
+    and the compact state (FP32 and FP16) on the split step."""
     w = W.flow_focusing(lam=3.0)
     out = {"workload": w.name, "fluid_nodes": w.fluid_nodes, "nodes": w.nodes, "steps": steps}
     for prec in ("f32", "f16"):
@@ -301,19 +301,19 @@ def focusing_form(torch, lbcg, W, steps=200, warmup=10, tune=True):
                      "rows": shape["rows"], "zchunks": shape["zchunks"]}
         if prec == "f32" and shape["rows"] == 0:
             out[prec]["traffic"] = read_traffic("geo_split")
-    # the compact state (FP32, the split step): 2 x (19 x 4 + 20) + 4 bytes
-    # per fluid node
-    stream = torch.cuda.Stream()
-    sim = lbcg.Sim.from_workload(w, precision="f32", kernel=lbcg.KERNEL_COMPACT, stream=stream.cuda_stream)
-    sim.step(1)
-    ms = time_sim(torch, sim, stream, steps, warmup)
-    sim.close()
-    out["f32_compact"] = {"mlups": round(w.fluid_nodes * steps / (ms / 1e3) / 1e6, 1),
-                          "lattice_mlups": round(w.nodes * steps / (ms / 1e3) / 1e6, 1),
-                          "ms_per_step": round(ms / steps, 4),
-                          "frac": round((2 * (19 * 4 + 20) + 4) * w.fluid_nodes * steps / (ms / 1e3) / 1e9
-                                        / HBM_PEAK_GBS, 4),
-                          "bytes_per_fluid_node": 2 * (19 * 4 + 20) + 4}
+    # the compact state on the split step: 2 x 96 (FP32) or 2 x 50 (FP16)
+    # bytes per fluid node, plus the link word
+    for prec, nbytes in (("f32", 2 * 96 + 4), ("f16", 2 * 50 + 4)):
+        stream = torch.cuda.Stream()
+        sim = lbcg.Sim.from_workload(w, precision=prec, kernel=lbcg.KERNEL_COMPACT, stream=stream.cuda_stream)
+        sim.step(1)
+        ms = time_sim(torch, sim, stream, steps, warmup)
+        sim.close()
+        out[prec + "_compact"] = {"mlups": round(w.fluid_nodes * steps / (ms / 1e3) / 1e6, 1),
+                                  "lattice_mlups": round(w.nodes * steps / (ms / 1e3) / 1e6, 1),
+                                  "ms_per_step": round(ms / steps, 4),
+                                  "frac": round(nbytes * w.fluid_nodes * steps / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                                  "bytes_per_fluid_node": nbytes}
     return out
 
 

@@ -75,7 +75,7 @@ extern "C" {
  * LBCG_KERNEL_COMPACT (never picked automatically): the fused sweeps on a
  * compact state, regularized collision; for periodic lattices D3Q19 with
  * F32 or F16 storage and tiles of 8 rows (tile[0] 0 or 8), or D2Q9 with F32
- * storage; with a geometry mask D3Q19 with F32 storage on the split step of
+ * storage; with a geometry mask D3Q19 with F32 or F16 storage on the split step of
  * the fused kernel (launch shape fixed: tile all 0; a link from a wall
  * brings back the node's own population, a link from an inlet or outlet
  * reads the pair the boundary kernel stores in the pair buffer); the pair

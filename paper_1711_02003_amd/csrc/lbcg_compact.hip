@@ -79,9 +79,10 @@ const void *compact_fn(int tx, size_t &lds) {
 // 32-bit byte offsets.  The D3Q19 sweep stores FP32 or FP16, the D2Q9 one
 // FP32.
 bool compact_supported(int lattice, int prec, const Geo &g) {
-    // with geometry: D3Q19 F32, on the split step
+    // with geometry: D3Q19, on the split step
     if (g.mask != nullptr)
-        return lattice == 1 && prec == 1 && uint64_t(2 * D3Q19::Q) * uint64_t(g.pitch) * 4u < (uint64_t(1) << 32);
+        return lattice == 1 && (prec == 1 || prec == 2) &&
+               uint64_t(2 * D3Q19::Q) * uint64_t(g.pitch) * (prec == 1 ? 4u : 2u) < (uint64_t(1) << 32);
     if (lattice == 0) return prec == 1 && g.nz == 1 && uint64_t(2 * D2Q9::Q) * uint64_t(g.pitch) * 4u < (uint64_t(1) << 32);
     const uint64_t elem = prec == 1 ? 4 : 2;
     return lattice == 1 && (prec == 1 || prec == 2) &&

@@ -23,6 +23,7 @@
 // psi written and read once (2 x 52 bytes), the neighbours' psi from cache,
 // and at nodes next to a boundary their new pairs read back.
 #include "lbcg_buffer.h"
+#include "lbcg_compact_sweep.h"  // CStore: the compact state's storage
 #include "lbcg_internal.h"
 
 namespace lbcg {
@@ -415,30 +416,26 @@ __global__ void __launch_bounds__(kIoBlock) k_geo_boundary(SplitArgs<S> sa, Mode
 }
 
 // ------------------------------------------------------------ compact state
-// The same split step on the compact state (FP32; the layout of the
-// periodic compact sweep: 19 arrays of totals f_i - w_i, then 16-byte records
-// {M with the majority flag, V_axis}, then R_d; 96 B per node).  A receiver
-// splits each pulled total with its sender's record (the recolouring of
-// Eq. (10) done at the receiver).  A link from a wall brings back the node's
-// own new total of the opposite direction, split with its own record for
-// that direction, so walls need no stored values.  A link from an inlet or an
-// outlet reads the pair (total deviation, minority share) that the boundary
-// kernel stored in that node's slot of a pair buffer (the values of the
-// pair-state step, formed from the node's own new populations).
+// The same split step on the compact state, FP32 or FP16 storage (the
+// layout and rounding of the periodic compact sweep, CStore: 19 arrays of
+// totals, then records {M with the majority flag, V_axis} and R_d; 96 or 50
+// B per node).  A receiver splits each pulled total with its sender's record
+// (the recolouring of Eq. (10) done at the receiver).  A link from a wall
+// brings back the node's own new total of the opposite direction, split with
+// its own record for that direction, so walls need no stored values.  A link
+// from an inlet or an outlet reads the pair (total deviation, minority share)
+// that the boundary kernel stored in that node's slot of a pair buffer (the
+// values of the pair-state step, formed from the node's own new
+// populations).
+template <typename S>
 struct CGeoArgs {
-    SplitArgs<float> s;  // s.a.in: pair buffer read (inlet and outlet values), s.a.out: pair buffer written
-    const float *cin;    // compact state read
-    float *cout;         // compact state written
+    SplitArgs<S> s;      // s.a.in: pair buffer read (inlet and outlet values), s.a.out: pair buffer written
+    const uint8_t *cin;  // compact state read
+    uint8_t *cout;       // compact state written
 };
-constexpr uint32_t kCFloats = 24;  // floats per node of the compact state
-
-__device__ __forceinline__ void st_b32(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, uint32_t v) {
-    __builtin_amdgcn_raw_buffer_store_b32(v, r, int(voff), uniform(int(soff)), kNonTemporal);
-}
-__device__ __forceinline__ void st_b64(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, float a, float b) {
-    typedef unsigned int u2v __attribute__((ext_vector_type(2)));
-    const u2v v = {__float_as_uint(a), __float_as_uint(b)};
-    __builtin_amdgcn_raw_buffer_store_b64(v, r, int(voff), uniform(int(soff)), kNonTemporal);
+template <typename S>
+constexpr uint32_t c_bytes() {  // bytes per node of the compact state
+    return uint32_t(D3Q19::Q) * CStore<S>::E + CStore<S>::kRecA + CStore<S>::kRecB;
 }
 
 // Record of node u: minority share M and majority flag, V_axis, R_d.
@@ -446,23 +443,25 @@ struct CRec {
     float M, Va[3], Rd;
     bool fl;
 };
+template <typename S>
 __device__ __forceinline__ CRec c_record(__amdgpu_buffer_rsrc_t rc, uint32_t u, uint32_t pitch) {
-    typedef float f4v __attribute__((ext_vector_type(4)));
-    const uint32_t cs = pitch * 4u;
-    const f4v r = __builtin_bit_cast(
-        f4v, __builtin_amdgcn_raw_buffer_load_b128(rc, int(u * 16u), uniform(int(19u * cs)), 0));
+    typedef CStore<S> St;
+    const uint32_t base = uint32_t(D3Q19::Q) * pitch * St::E;
+    const typename St::RawB rb = St::load_b(rc, u * St::kRecB, base + pitch * St::kRecA);
+    const f4 e = St::entry(St::load_a(rc, u * St::kRecA, base), rb);
     CRec c;
-    c.M = Codec<float>::col<float>(r[0], c.fl);
-    c.Va[0] = r[1];
-    c.Va[1] = r[2];
-    c.Va[2] = r[3];
-    c.Rd = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rc, int(u * 4u),
-                                                                          uniform(int(19u * cs + pitch * 16u)), 0));
+    c.M = Codec<float>::col<float>(e[0], c.fl);
+    c.Va[0] = e[1];
+    c.Va[1] = e[2];
+    c.Va[2] = e[3];
+    c.Rd = St::ratio(rb);
     return c;
 }
-__device__ __forceinline__ float c_total(__amdgpu_buffer_rsrc_t rc, uint32_t u, int i, uint32_t pitch) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rc, int(u * 4u),
-                                                                          uniform(int(uint32_t(i) * pitch * 4u)), 0));
+// Total deviation f_i - w_i stored at element `at` of the totals (i * pitch
+// + node; a direction of the speed class of i).
+template <typename S>
+__device__ __forceinline__ float c_total(__amdgpu_buffer_rsrc_t rc, uint32_t at, int i) {
+    return CStore<S>::df(CStore<S>::load(rc, at * CStore<S>::E, 0u), i);
 }
 // 36 x the recolouring term of a population the record's node sends along
 // c_i: c_i . V_axis, times R_d on a diagonal (the periodic sweep's split)
@@ -475,22 +474,20 @@ __device__ __forceinline__ float c_vd(int i, const CRec &r) {
 // Pair (total deviation, minority share with flag) of the population the
 // record's node sends along c_i with total deviation d: the conversion the
 // periodic compact state's export uses.
-__device__ __forceinline__ PairOf<float>::type c_pair(float d, int i, const CRec &r) {
+template <typename S>
+__device__ __forceinline__ typename PairOf<S>::type c_pair(float d, int i, const CRec &r) {
     using L = D3Q19;
     const float f = float(wgt<L>(i)) + d;
     const float mu36 = r.M * (float(w36<L>(i)) + 36.0f * d) + c_vd(i, r);
     const float q = f != 0.0f ? mu36 / (36.0f * f) : 0.0f;
     const bool keep = q <= 0.5f;
-    return encode_pair<L, float, float>(d, keep ? q : 1.0f - q, keep ? r.fl : !r.fl, i);
+    return encode_pair<L, S, float>(d, keep ? q : 1.0f - q, keep ? r.fl : !r.fl, i);
 }
 
-// Each link is one load of a total and one of a record (from the cache: a
-// record serves up to 19 receivers).  Staging the block's records with a
-// one-node halo in LDS first (66 x 6 x 3 per block) measured slower on the
-// 512 x 128 x 64 junction: 0.129 against 0.119 ms per step.
 // The node's own moments (density, red density, velocity) from its new
 // totals and record: own_moments of its populations, each split as a
 // receiver splits it (no division per population).
+template <typename S>
 __device__ __forceinline__ OwnMom<float> c_own_moments(__amdgpu_buffer_rsrc_t rc, uint32_t n, uint32_t pitch,
                                                        const CRec &r) {
     using L = D3Q19;
@@ -498,7 +495,7 @@ __device__ __forceinline__ OwnMom<float> c_own_moments(__amdgpu_buffer_rsrc_t rc
     int K = 0;
 #pragma unroll
     for (int k = 0; k < L::Q; ++k) {
-        const float d = c_total(rc, n, k, pitch);
+        const float d = c_total<S>(rc, uint32_t(k) * pitch + n, k);
         const float mu = r.M * (float(w36<L>(k)) + 36.0f * d) + c_vd(k, r);
         const float t = 36.0f * d - mu;
         drho += d;
@@ -517,16 +514,21 @@ __device__ __forceinline__ OwnMom<float> c_own_moments(__amdgpu_buffer_rsrc_t rc
     return om;
 }
 
-__global__ void __launch_bounds__(kGeoBlock) k_cgeo_moments(CGeoArgs ca) {
+// Each link is one load of a total and one of a record (from the cache: a
+// record serves up to 19 receivers).  Staging the block's records with a
+// one-node halo in LDS first (66 x 6 x 3 per block) measured slower on the
+// 512 x 128 x 64 junction: 0.129 against 0.119 ms per step.
+template <typename S>
+__global__ void __launch_bounds__(kGeoBlock) k_cgeo_moments(CGeoArgs<S> ca) {
     using L = D3Q19;
     typedef float T;
-    typedef PairOf<float>::type P2;
+    typedef typename PairOf<S>::type P2;
     constexpr uint32_t E = sizeof(P2);
-    const FusedArgs<float> &a = ca.s.a;
+    const FusedArgs<S> &a = ca.s.a;
     Here h;
     if (!here(a.nx, a.ny, a.nz, ca.s.blocks[blockIdx.x], h)) return;
     const uint32_t pitch = uint32_t(a.pitch);
-    const __amdgpu_buffer_rsrc_t rc = state_rsrc(ca.cin, kCFloats * pitch * 4u);
+    const __amdgpu_buffer_rsrc_t rc = state_rsrc(ca.cin, c_bytes<S>() * pitch);
     const uint32_t n = h.n;
     const uint32_t clk = a.links[n];
     if (!(clk & kLinkFluid)) return;
@@ -554,8 +556,8 @@ __global__ void __launch_bounds__(kGeoBlock) k_cgeo_moments(CGeoArgs ca) {
         const bool wl = (wall >> i) & 1u;
         const uint32_t u = nbr(a.nx, a.ny, a.nz, h, -L::cx[i], -L::cy[i], -L::cz[i]);
         const uint32_t src = wl ? uint32_t(L::opp[i]) * pitch + n : uint32_t(i) * pitch + u;
-        const float d = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rc, int(src * 4u), 0, 0));
-        const CRec r = c_record(rc, wl ? n : u, pitch);
+        const float d = c_total<S>(rc, src, i);
+        const CRec r = c_record<S>(rc, wl ? n : u, pitch);
         const float vd = c_vd(i, r);
         q.df[i] = d;
         q.mm[i] = r.M;
@@ -570,8 +572,8 @@ __global__ void __launch_bounds__(kGeoBlock) k_cgeo_moments(CGeoArgs ca) {
             const uint32_t u = nbr(a.nx, a.ny, a.nz, h, -L::cx[i], -L::cy[i], -L::cz[i]);
             const P2 v = load_pair<P2>(rg, u * E, uniform(int(uint32_t(i) * pitch * E)));
             bool fl;
-            q.df[i] = Codec<float>::df<L, T>(v.x, i);
-            q.mm[i] = Codec<float>::col<T>(v.y, fl);
+            q.df[i] = Codec<S>::template df<L, T>(v.x, i);
+            q.mm[i] = Codec<S>::template col<T>(v.y, fl);
             q.vd[i] = 0.0f;
             q.red = fl ? (q.red | (1u << i)) : (q.red & ~(1u << i));
         }
@@ -585,10 +587,11 @@ __global__ void __launch_bounds__(kGeoBlock) k_cgeo_moments(CGeoArgs ca) {
     for (int k = 0; k < kNM; ++k) ca.s.mom[int64_t(k) * a.pitch + n] = vals[k];
 }
 
-__global__ void __launch_bounds__(kGeoBlock) k_cgeo_collide(CGeoArgs ca, Model<float> mo) {
+template <typename S>
+__global__ void __launch_bounds__(kGeoBlock) k_cgeo_collide(CGeoArgs<S> ca, Model<float> mo) {
     using L = D3Q19;
     typedef float T;
-    const FusedArgs<float> &a = ca.s.a;
+    const FusedArgs<S> &a = ca.s.a;
     if (blockIdx.x == 0 && threadIdx.x == 0) *a.ctr_out = *a.ctr_in + 1u;
     if (!ca.s.blocks) return;  // no fluid node
     Here h;
@@ -596,6 +599,7 @@ __global__ void __launch_bounds__(kGeoBlock) k_cgeo_collide(CGeoArgs ca, Model<f
     const uint32_t n = h.n;
     const uint32_t clk = a.links[n];
     if (!(clk & kLinkFluid)) return;
+    const uint32_t step = *a.ctr_in;  // seeds the stochastic rounding of FP16 storage
     const float pc = ca.s.psi[n];
     T fx = 0, fy = 0, fz = 0;
 #pragma unroll
@@ -614,24 +618,22 @@ __global__ void __launch_bounds__(kGeoBlock) k_cgeo_collide(CGeoArgs ca, Model<f
     const T cj[3] = {mv[3], mv[4], mv[5]}, cS[6] = {mv[6], mv[7], mv[8], mv[9], mv[10], mv[11]};
     CompactOut<L, T> o;
     collide<L, T>(mo, mv[0], mv[1], mv[2], cj, cS, F, nullptr, o);
-    const uint32_t pitch = uint32_t(a.pitch), cs = pitch * 4u;
-    const __amdgpu_buffer_rsrc_t rout = state_rsrc(ca.cout, kCFloats * pitch * 4u);
-#pragma unroll
-    for (int i = 0; i < L::Q; ++i) st_b32(rout, n * 4u, uint32_t(i) * cs, __float_as_uint(o.df[i]));
-    st_b64(rout, n * 16u, 19u * cs, Codec<float>::enc_col<float>(o.M, o.redmaj), o.Va[0]);
-    st_b64(rout, n * 16u, 19u * cs + 8u, o.Va[1], o.Va[2]);
-    st_b32(rout, n * 4u, 19u * cs + pitch * 16u, __float_as_uint(o.Rd));
+    const uint32_t pitch = uint32_t(a.pitch);
+    const __amdgpu_buffer_rsrc_t rout = state_rsrc(ca.cout, c_bytes<S>() * pitch);
+    // the node's totals at byte n E of each array, its records at n kRecA
+    // and n kRecB (the periodic sweep's store, with the plane offset 0)
+    CStore<S>::store(rout, n * CStore<S>::E, 0u, pitch, o, step);
 }
 
 // Inlet and outlet values on the compact state: as k_geo_boundary (a wave
 // per direction and 64 listed nodes), from the node's new totals and record.
-template <int I>
-__device__ __forceinline__ void cio_link(const CGeoArgs &ca, const Model<float> &mo, uint32_t n, uint32_t so_i) {
+template <int I, typename S>
+__device__ __forceinline__ void cio_link(const CGeoArgs<S> &ca, const Model<float> &mo, uint32_t n, uint32_t so_i) {
     using L = D3Q19;
     typedef float T;
-    typedef PairOf<float>::type P2;
+    typedef typename PairOf<S>::type P2;
     constexpr uint32_t E = sizeof(P2);
-    const FusedArgs<float> &a = ca.s.a;
+    const FusedArgs<S> &a = ca.s.a;
     const uint32_t clk = a.links[n];
     if (!((clk >> I) & 1u)) return;
     Here h;
@@ -644,45 +646,46 @@ __device__ __forceinline__ void cio_link(const CGeoArgs &ca, const Model<float> 
     const uint8_t c = (clk & kLinkMixed) ? a.mask[m] : link_code(clk);
     if (is_wall(c)) return;
     const uint32_t pitch = uint32_t(a.pitch);
-    const __amdgpu_buffer_rsrc_t rc = state_rsrc(ca.cout, kCFloats * pitch * 4u);
+    const __amdgpu_buffer_rsrc_t rc = state_rsrc(ca.cout, c_bytes<S>() * pitch);
     const __amdgpu_buffer_rsrc_t rg = state_rsrc(a.out, uint32_t(L::Q) * pitch * E);
-    const CRec own = c_record(rc, n, pitch);
+    const CRec own = c_record<S>(rc, n, pitch);
     Geo g{};
     g.inlets = a.inlets;
     g.outlets = a.outlets;
     OwnMom<T> om{};
-    if (c >= kOutlet0) om = c_own_moments(rc, n, pitch, own);
-    const P2 ov = c_pair(c_total(rc, n, L::opp[I], pitch), L::opp[I], own);
+    if (c >= kOutlet0) om = c_own_moments<S>(rc, n, pitch, own);
+    const P2 ov = c_pair<S>(c_total<S>(rc, uint32_t(L::opp[I]) * pitch + n, L::opp[I]), L::opp[I], own);
     store_pair<P2>(rg, m * E, uint32_t(uniform(int(so_i))),
-                   boundary_pair_v<L, float, T>(mo, I, c, io_vals<T>(g, c), ov, om));
+                   boundary_pair_v<L, S, T>(mo, I, c, io_vals<T>(g, c), ov, om));
 }
 
-__global__ void __launch_bounds__(kIoBlock) k_cgeo_boundary(CGeoArgs ca, Model<float> mo, uint32_t count) {
-    constexpr uint32_t E = sizeof(PairOf<float>::type);
+template <typename S>
+__global__ void __launch_bounds__(kIoBlock) k_cgeo_boundary(CGeoArgs<S> ca, Model<float> mo, uint32_t count) {
+    constexpr uint32_t E = sizeof(typename PairOf<S>::type);
     const uint32_t b = blockIdx.x, chunk = b / 18u, dir = 1u + (b - chunk * 18u);
     const uint32_t so_i = dir * uint32_t(ca.s.a.pitch) * E;
     const uint32_t k = chunk * kIoBlock + threadIdx.x;
     if (k >= count) return;
     const uint32_t n = ca.s.blocks[k];
     switch (dir) {
-        case 1: cio_link<1>(ca, mo, n, so_i); break;
-        case 2: cio_link<2>(ca, mo, n, so_i); break;
-        case 3: cio_link<3>(ca, mo, n, so_i); break;
-        case 4: cio_link<4>(ca, mo, n, so_i); break;
-        case 5: cio_link<5>(ca, mo, n, so_i); break;
-        case 6: cio_link<6>(ca, mo, n, so_i); break;
-        case 7: cio_link<7>(ca, mo, n, so_i); break;
-        case 8: cio_link<8>(ca, mo, n, so_i); break;
-        case 9: cio_link<9>(ca, mo, n, so_i); break;
-        case 10: cio_link<10>(ca, mo, n, so_i); break;
-        case 11: cio_link<11>(ca, mo, n, so_i); break;
-        case 12: cio_link<12>(ca, mo, n, so_i); break;
-        case 13: cio_link<13>(ca, mo, n, so_i); break;
-        case 14: cio_link<14>(ca, mo, n, so_i); break;
-        case 15: cio_link<15>(ca, mo, n, so_i); break;
-        case 16: cio_link<16>(ca, mo, n, so_i); break;
-        case 17: cio_link<17>(ca, mo, n, so_i); break;
-        default: cio_link<18>(ca, mo, n, so_i); break;
+        case 1: cio_link<1, S>(ca, mo, n, so_i); break;
+        case 2: cio_link<2, S>(ca, mo, n, so_i); break;
+        case 3: cio_link<3, S>(ca, mo, n, so_i); break;
+        case 4: cio_link<4, S>(ca, mo, n, so_i); break;
+        case 5: cio_link<5, S>(ca, mo, n, so_i); break;
+        case 6: cio_link<6, S>(ca, mo, n, so_i); break;
+        case 7: cio_link<7, S>(ca, mo, n, so_i); break;
+        case 8: cio_link<8, S>(ca, mo, n, so_i); break;
+        case 9: cio_link<9, S>(ca, mo, n, so_i); break;
+        case 10: cio_link<10, S>(ca, mo, n, so_i); break;
+        case 11: cio_link<11, S>(ca, mo, n, so_i); break;
+        case 12: cio_link<12, S>(ca, mo, n, so_i); break;
+        case 13: cio_link<13, S>(ca, mo, n, so_i); break;
+        case 14: cio_link<14, S>(ca, mo, n, so_i); break;
+        case 15: cio_link<15, S>(ca, mo, n, so_i); break;
+        case 16: cio_link<16, S>(ca, mo, n, so_i); break;
+        case 17: cio_link<17, S>(ca, mo, n, so_i); break;
+        default: cio_link<18, S>(ca, mo, n, so_i); break;
     }
 }
 
@@ -690,24 +693,25 @@ __global__ void __launch_bounds__(kIoBlock) k_cgeo_boundary(CGeoArgs ca, Model<f
 // each fluid node's 19 pairs in its own slots and, for links from walls, its
 // bounce-back values in the wall nodes' slots; the inlet and outlet values
 // are already in the pair buffer.
-__global__ void __launch_bounds__(kGeoBlock) k_cgeo_expand(CGeoArgs ca) {
+template <typename S>
+__global__ void __launch_bounds__(kGeoBlock) k_cgeo_expand(CGeoArgs<S> ca) {
     using L = D3Q19;
-    typedef PairOf<float>::type P2;
+    typedef typename PairOf<S>::type P2;
     constexpr uint32_t E = sizeof(P2);
-    const FusedArgs<float> &a = ca.s.a;
+    const FusedArgs<S> &a = ca.s.a;
     Here h;
     if (!here(a.nx, a.ny, a.nz, ca.s.blocks[blockIdx.x], h)) return;
     const uint32_t n = h.n;
     const uint32_t clk = a.links[n];
     if (!(clk & kLinkFluid)) return;
     const uint32_t pitch = uint32_t(a.pitch);
-    const __amdgpu_buffer_rsrc_t rc = state_rsrc(ca.cin, kCFloats * pitch * 4u);
+    const __amdgpu_buffer_rsrc_t rc = state_rsrc(ca.cin, c_bytes<S>() * pitch);
     const __amdgpu_buffer_rsrc_t rg = state_rsrc(a.out, uint32_t(L::Q) * pitch * E);
-    const CRec own = c_record(rc, n, pitch);
+    const CRec own = c_record<S>(rc, n, pitch);
     P2 ov[L::Q];
 #pragma unroll
     for (int j = 0; j < L::Q; ++j) {
-        ov[j] = c_pair(c_total(rc, n, j, pitch), j, own);
+        ov[j] = c_pair<S>(c_total<S>(rc, uint32_t(j) * pitch + n, j), j, own);
         store_pair<P2>(rg, n * E, uint32_t(uniform(int(uint32_t(j) * pitch * E))), ov[j]);
     }
 #pragma unroll
@@ -717,6 +721,63 @@ __global__ void __launch_bounds__(kGeoBlock) k_cgeo_expand(CGeoArgs ca) {
         if (is_wall((clk & kLinkMixed) ? a.mask[m] : link_code(clk)))
             store_pair<P2>(rg, m * E, uint32_t(uniform(int(uint32_t(i) * pitch * E))), ov[L::opp[i]]);
     }
+}
+
+template <typename S>
+hipError_t run_cgeo(const Geo &g, const ModelD &md, bool pair_in, const void *in, const void *gin, void *cout,
+                    void *gout, void *psi, void *scratch, const SplitPlan &sp, const uint32_t *ctr_in,
+                    uint32_t *ctr_out, hipStream_t s) {
+    typedef typename PairOf<S>::type P2;
+    if (md.bgk || !g.mask || !g.links || !psi || !scratch) return hipErrorInvalidValue;
+    if (uint64_t(D3Q19::Q) * uint64_t(g.pitch) * sizeof(P2) >= (uint64_t(1) << 32)) return hipErrorInvalidValue;
+    const int64_t nb = split_blocks(g.nx, g.ny, g.nz);
+    if (nb <= 0 || nb > 0x7fffffff || sp.active > nb || sp.io > nb || sp.active < 0 || sp.io < 0 ||
+        sp.ionodes < 0 || sp.ionodes > g.pitch || (sp.ionodes > 0) != (sp.io > 0))
+        return hipErrorInvalidValue;
+    const ScratchMap m = scratch_map(scratch, g.pitch, nb);
+    CGeoArgs<S> ca;
+    // the pair buffer read: the pair state on a first step (pulled as pairs)
+    // or the inlet and outlet values; the pair buffer written: those values
+    ca.s.a = fused_args<S>(g, pair_in ? in : gin, gout, ctr_in, ctr_out, FusedShape{8, 1});
+    ca.s.psi = static_cast<float *>(psi);
+    ca.s.mom = m.mom;
+    ca.s.blocks = m.act;
+    ca.cin = static_cast<const uint8_t *>(in);
+    ca.cout = static_cast<uint8_t *>(cout);
+    const Model<float> mo = to_model<float>(md);
+    if (sp.active > 0) {
+        if (pair_in)
+            hipLaunchKernelGGL(k_geo_moments<S>, dim3(unsigned(sp.active)), dim3(kGeoBlock), 0, s, ca.s);
+        else
+            hipLaunchKernelGGL(k_cgeo_moments<S>, dim3(unsigned(sp.active)), dim3(kGeoBlock), 0, s, ca);
+    }
+    if (sp.active == 0) ca.s.blocks = nullptr;
+    hipLaunchKernelGGL(k_cgeo_collide<S>, dim3(unsigned(sp.active > 0 ? sp.active : 1)), dim3(kGeoBlock), 0, s, ca,
+                       mo);
+    ca.s.blocks = m.ionodes;
+    if (sp.ionodes > 0)
+        hipLaunchKernelGGL(k_cgeo_boundary<S>, dim3(unsigned(18 * ((sp.ionodes + kIoBlock - 1) / kIoBlock))),
+                           dim3(kIoBlock), 0, s, ca, mo, uint32_t(sp.ionodes));
+    return hipGetLastError();
+}
+
+template <typename S>
+hipError_t run_expand_cgeo(const Geo &g, const void *cin, void *pout, void *scratch, const SplitPlan &sp,
+                           hipStream_t s) {
+    if (!g.mask || !g.links || !scratch) return hipErrorInvalidValue;
+    const int64_t nb = split_blocks(g.nx, g.ny, g.nz);
+    if (nb <= 0 || nb > 0x7fffffff || sp.active > nb || sp.active < 0) return hipErrorInvalidValue;
+    if (sp.active == 0) return hipSuccess;
+    const ScratchMap m = scratch_map(scratch, g.pitch, nb);
+    CGeoArgs<S> ca;
+    ca.s.a = fused_args<S>(g, nullptr, pout, nullptr, nullptr, FusedShape{8, 1});
+    ca.s.psi = nullptr;
+    ca.s.mom = nullptr;
+    ca.s.blocks = m.act;
+    ca.cin = static_cast<const uint8_t *>(cin);
+    ca.cout = nullptr;
+    hipLaunchKernelGGL(k_cgeo_expand<S>, dim3(unsigned(sp.active)), dim3(kGeoBlock), 0, s, ca);
+    return hipGetLastError();
 }
 
 template <typename S>
@@ -791,57 +852,21 @@ hipError_t split_prepare(const Geo &g, void *scratch, SplitPlan &sp, hipStream_t
     return hipSuccess;
 }
 
-hipError_t launch_step_cgeo(const Geo &g, const ModelD &md, bool pair_in, const void *in, const void *gin, void *cout,
-                            void *gout, void *psi, void *scratch, const SplitPlan &sp, const uint32_t *ctr_in,
-                            uint32_t *ctr_out, hipStream_t s) {
-    if (md.bgk || !g.mask || !g.links || !psi || !scratch) return hipErrorInvalidValue;
-    if (uint64_t(2 * D3Q19::Q) * uint64_t(g.pitch) * 4u >= (uint64_t(1) << 32)) return hipErrorInvalidValue;
-    const int64_t nb = split_blocks(g.nx, g.ny, g.nz);
-    if (nb <= 0 || nb > 0x7fffffff || sp.active > nb || sp.io > nb || sp.active < 0 || sp.io < 0 ||
-        sp.ionodes < 0 || sp.ionodes > g.pitch || (sp.ionodes > 0) != (sp.io > 0))
-        return hipErrorInvalidValue;
-    const ScratchMap m = scratch_map(scratch, g.pitch, nb);
-    CGeoArgs ca;
-    // the pair buffer read: the pair state on a first step (pulled as pairs)
-    // or the inlet and outlet values; the pair buffer written: those values
-    ca.s.a = fused_args<float>(g, pair_in ? in : gin, gout, ctr_in, ctr_out, FusedShape{8, 1});
-    ca.s.psi = static_cast<float *>(psi);
-    ca.s.mom = m.mom;
-    ca.s.blocks = m.act;
-    ca.cin = static_cast<const float *>(in);
-    ca.cout = static_cast<float *>(cout);
-    const Model<float> mo = to_model<float>(md);
-    if (sp.active > 0) {
-        if (pair_in)
-            hipLaunchKernelGGL(k_geo_moments<float>, dim3(unsigned(sp.active)), dim3(kGeoBlock), 0, s, ca.s);
-        else
-            hipLaunchKernelGGL(k_cgeo_moments, dim3(unsigned(sp.active)), dim3(kGeoBlock), 0, s, ca);
-    }
-    if (sp.active == 0) ca.s.blocks = nullptr;
-    hipLaunchKernelGGL(k_cgeo_collide, dim3(unsigned(sp.active > 0 ? sp.active : 1)), dim3(kGeoBlock), 0, s, ca, mo);
-    ca.s.blocks = m.ionodes;
-    if (sp.ionodes > 0)
-        hipLaunchKernelGGL(k_cgeo_boundary, dim3(unsigned(18 * ((sp.ionodes + kIoBlock - 1) / kIoBlock))),
-                           dim3(kIoBlock), 0, s, ca, mo, uint32_t(sp.ionodes));
-    return hipGetLastError();
+hipError_t launch_step_cgeo(int prec, const Geo &g, const ModelD &md, bool pair_in, const void *in, const void *gin,
+                            void *cout, void *gout, void *psi, void *scratch, const SplitPlan &sp,
+                            const uint32_t *ctr_in, uint32_t *ctr_out, hipStream_t s) {
+    if (prec == 1)
+        return run_cgeo<float>(g, md, pair_in, in, gin, cout, gout, psi, scratch, sp, ctr_in, ctr_out, s);
+    if (prec == 2)
+        return run_cgeo<_Float16>(g, md, pair_in, in, gin, cout, gout, psi, scratch, sp, ctr_in, ctr_out, s);
+    return hipErrorInvalidValue;
 }
 
-hipError_t launch_expand_cgeo(const Geo &g, const void *cin, void *pout, void *scratch, const SplitPlan &sp,
+hipError_t launch_expand_cgeo(int prec, const Geo &g, const void *cin, void *pout, void *scratch, const SplitPlan &sp,
                               hipStream_t s) {
-    if (!g.mask || !g.links || !scratch) return hipErrorInvalidValue;
-    const int64_t nb = split_blocks(g.nx, g.ny, g.nz);
-    if (nb <= 0 || nb > 0x7fffffff || sp.active > nb || sp.active < 0) return hipErrorInvalidValue;
-    if (sp.active == 0) return hipSuccess;
-    const ScratchMap m = scratch_map(scratch, g.pitch, nb);
-    CGeoArgs ca;
-    ca.s.a = fused_args<float>(g, nullptr, pout, nullptr, nullptr, FusedShape{8, 1});
-    ca.s.psi = nullptr;
-    ca.s.mom = nullptr;
-    ca.s.blocks = m.act;
-    ca.cin = static_cast<const float *>(cin);
-    ca.cout = nullptr;
-    hipLaunchKernelGGL(k_cgeo_expand, dim3(unsigned(sp.active)), dim3(kGeoBlock), 0, s, ca);
-    return hipGetLastError();
+    if (prec == 1) return run_expand_cgeo<float>(g, cin, pout, scratch, sp, s);
+    if (prec == 2) return run_expand_cgeo<_Float16>(g, cin, pout, scratch, sp, s);
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_step_split(int prec, const Geo &g, const ModelD &md, const void *in, void *out, void *psi,

@@ -122,17 +122,17 @@ struct SplitPlan {
 };
 // Builds the block lists and returns their lengths (waits for the stream).
 hipError_t split_prepare(const Geo &g, void *scratch, SplitPlan &sp, hipStream_t s);
-// The split step on the compact state (D3Q19 F32 with geometry): reads the
+// The split step on the compact state (D3Q19 F32 or F16 with geometry): reads the
 // compact state `in` (or, with pair_in, the pair state `in`, on the first
 // step after an initialisation or a restore), the inlet and outlet values in
 // the pair buffer gin, writes the compact state `cout` and the new inlet and
 // outlet values into the pair buffer gout.
-hipError_t launch_step_cgeo(const Geo &g, const ModelD &md, bool pair_in, const void *in, const void *gin, void *cout,
-                            void *gout, void *psi, void *scratch, const SplitPlan &sp, const uint32_t *ctr_in,
-                            uint32_t *ctr_out, hipStream_t s);
+hipError_t launch_step_cgeo(int prec, const Geo &g, const ModelD &md, bool pair_in, const void *in, const void *gin,
+                            void *cout, void *gout, void *psi, void *scratch, const SplitPlan &sp,
+                            const uint32_t *ctr_in, uint32_t *ctr_out, hipStream_t s);
 // Its compact state as pairs (fluid nodes and wall values) into pout, which
 // already holds the inlet and outlet values.
-hipError_t launch_expand_cgeo(const Geo &g, const void *cin, void *pout, void *scratch, const SplitPlan &sp,
+hipError_t launch_expand_cgeo(int prec, const Geo &g, const void *cin, void *pout, void *scratch, const SplitPlan &sp,
                               hipStream_t s);
 hipError_t launch_step_split(int prec, const Geo &g, const ModelD &md, const void *in, void *out, void *psi,
                              void *scratch, const SplitPlan &sp, const uint32_t *ctr_in, uint32_t *ctr_out,

@@ -111,7 +111,7 @@ Plan make_plan(const lbcg_params *p) {
     // regularized collision
     pl.moms = p->mask && p->lattice == LBCG_D3Q19 && p->precision != LBCG_F64 && p->collision == LBCG_REGULARIZED &&
                       (p->kernel == LBCG_KERNEL_AUTO || p->kernel == LBCG_KERNEL_FUSED ||
-                       (p->kernel == LBCG_KERNEL_COMPACT && p->precision == LBCG_F32))
+                       p->kernel == LBCG_KERNEL_COMPACT)
                   ? align_up(split_scratch_bytes(pl.pitch, p->dims[0], p->dims[1], p->dims[2]), kAlign)
                   : 0;
     pl.mask = p->mask ? align_up(size_t(pl.pitch), kAlign) : 0;
@@ -236,7 +236,7 @@ hipError_t enqueue_step(lbcg_sim *s, bool pulled) {
     if (s->kernel == LBCG_KERNEL_COMPACT && pulled) {
         const bool pair_in = !s->compact;
         hipError_t e =
-            s->g.mask ? launch_step_cgeo(s->g, s->md, pair_in, pair_in ? s->buf[s->cur] : s->cbuf[s->cur],
+            s->g.mask ? launch_step_cgeo(s->prec, s->g, s->md, pair_in, pair_in ? s->buf[s->cur] : s->cbuf[s->cur],
                                          s->buf[s->cur], s->cbuf[s->cur ^ 1], s->buf[s->cur ^ 1], s->psi, s->moms,
                                          s->split, ctr_in, ctr_out, s->stream)
                       : launch_compact(s, pair_in ? s->buf[s->cur] : s->cbuf[s->cur], pair_in, s->cbuf[s->cur ^ 1],
@@ -582,8 +582,8 @@ int lbcg_step(lbcg_sim *s, int64_t n) {
 static hipError_t ensure_pairs(lbcg_sim *s) {
     if (!s->compact || s->expanded) return hipSuccess;
     hipError_t e = s->lattice == LBCG_D2Q9 ? launch_expand2d(s->g, s->cbuf[s->cur], s->buf[s->cur], s->stream)
-                   : s->g.mask           ? launch_expand_cgeo(s->g, s->cbuf[s->cur], s->buf[s->cur], s->moms, s->split,
-                                                              s->stream)
+                   : s->g.mask           ? launch_expand_cgeo(s->prec, s->g, s->cbuf[s->cur], s->buf[s->cur], s->moms,
+                                                              s->split, s->stream)
                                          : launch_expand(s->prec, s->g, s->cbuf[s->cur], s->buf[s->cur], s->stream);
     if (e == hipSuccess) s->expanded = true;
     return e;

@@ -193,9 +193,12 @@ FORM_KERNELS = [("D3Q19 256³ droplets, FP32 pairs", r"k_step_fused<float, float
                 ("D3Q19 junction 512×128×64, FP32 split: moments", r"k_geo_moments<float>"),
                 ("D3Q19 junction 512×128×64, FP32 split: collision", r"k_geo_collide<float>"),
                 ("D3Q19 junction 512×128×64, FP32 split: inlets, outlets", r"k_geo_boundary<float>"),
-                ("D3Q19 junction 512×128×64, FP32 compact split: moments", r"k_cgeo_moments"),
-                ("D3Q19 junction 512×128×64, FP32 compact split: collision", r"k_cgeo_collide"),
-                ("D3Q19 junction 512×128×64, FP32 compact split: inlets, outlets", r"k_cgeo_boundary"),
+                ("D3Q19 junction 512×128×64, FP32 compact split: moments", r"k_cgeo_moments<float>"),
+                ("D3Q19 junction 512×128×64, FP32 compact split: collision", r"k_cgeo_collide<float>"),
+                ("D3Q19 junction 512×128×64, FP32 compact split: inlets, outlets", r"k_cgeo_boundary<float>"),
+                ("D3Q19 junction 512×128×64, FP16 compact split: moments", r"k_cgeo_momentsIDF16_"),
+                ("D3Q19 junction 512×128×64, FP16 compact split: collision", r"k_cgeo_collideIDF16_"),
+                ("D3Q19 junction 512×128×64, FP16 compact split: inlets, outlets", r"k_cgeo_boundaryIDF16_"),
                 ("D3Q19 junction 512×128×64, FP16 split: moments", r"k_geo_momentsIDF16_"),
                 ("D3Q19 junction 512×128×64, FP16 split: collision", r"k_geo_collideIDF16_"),
                 ("D3Q19 junction 512×128×64, FP16 split: inlets, outlets", r"k_geo_boundaryIDF16_"),

@@ -1,4 +1,5 @@
-"""The compact state on lattices with geometry (D3Q19 FP32, the split step).
+"""The compact state on lattices with geometry (D3Q19 FP32 and FP16, the
+split step).
 
 Every fluid node stores its 19 new totals and its colour record; a receiver
 splits what it pulls with its sender's record, a link from a wall brings back
@@ -114,11 +115,66 @@ def test_compact_geometry_checkpoint_and_limits(L):
         assert d < 25 * 4 * EPS32
         assert c.diagnostics()["step"] == 40
         c.close()
-    # one launch shape; no tile, no FP16, no batch
+    # one launch shape; no tile, no batch
     assert a.tune()["rows"] == 0
     with pytest.raises(L.LbcgError):
         L.Sim.from_workload(w, precision="f32", kernel=L.KERNEL_COMPACT, tile=(8, 2, 0))
     with pytest.raises(L.LbcgError):
-        L.Sim.from_workload(w, precision="f16", kernel=L.KERNEL_COMPACT)
-    with pytest.raises(L.LbcgError):
         L.Batch([a])
+
+
+def test_compact_geometry_f16_within_one_percent(L):
+    # FP16 storage (totals, V_axis and R_d rounded stochastically, M in FP32)
+    # against FP32 on the flow-focusing junction after 3000 steps: the
+    # equivalent radius of the dispersed colour past the junction and the
+    # tip of the dispersed thread, as for the FP16 pair state
+    w = _focusing()
+    nx, ny, nz = w.dims
+    xj = nx // 4
+    fl = w.mask == 0
+    out = {}
+    for prec, kernel in (("f32", L.KERNEL_FUSED), ("f16", L.KERNEL_COMPACT), ("f32c", L.KERNEL_COMPACT)):
+        s = L.Sim.from_workload(w, precision=prec[:3], kernel=kernel)
+        assert s.launch_info()["rows"] == 0
+        s.step(3000)
+        f = s.fields()
+        assert np.isfinite(f["psi"][fl]).all()
+        s.close()
+        red = np.where(fl, 0.5 * (1.0 + f["psi"]), 0.0)
+        vol = red[:, :, xj:].sum()
+        out[prec] = ((3.0 * vol / (4.0 * np.pi)) ** (1.0 / 3.0),
+                     int(np.flatnonzero(f["psi"][nz // 2, ny // 2, :] > 0.0).max()))
+    (r32, t32) = out["f32"]
+    _say(f"focusing 3000 steps: R_eq, tip: pair f32 {out['f32']}, compact f16 {out['f16']}, compact f32 {out['f32c']}")
+    assert r32 > 3.0 and t32 > xj
+    for k in ("f16", "f32c"):
+        r, t = out[k]
+        assert abs(r - r32) / r32 < 0.01
+        assert abs(t - t32) <= max(1, 0.01 * t32)
+
+
+def test_compact_geometry_f16_walls_and_reads(L):
+    # walls of three codes, periodic elsewhere: colour masses kept to the
+    # random walk of the stochastic rounding; a checkpoint resumes on the
+    # compact and the pair state
+    w = _sparse_geometry((70, 13, 9), seed=92, io=False)
+    fl = w.mask == 0
+    a = L.Sim.from_workload(w, precision="f16", kernel=L.KERNEL_COMPACT)
+    d0 = a.diagnostics()
+    a.step(300)
+    d1 = a.diagnostics()
+    dm = max(abs(d1["mass_R"] / d0["mass_R"] - 1), abs(d1["mass_B"] / d0["mass_B"] - 1))
+    _say(f"compact geometry f16, walls, 300 steps: colour mass {dm:.1e}")
+    assert dm < 2e-5
+    blob = a.get_state()
+    a.step(20)
+    pa = a.fields()["psi"][fl]
+    for kernel in (L.KERNEL_COMPACT, L.KERNEL_FUSED):
+        c = L.Sim.from_workload(w, precision="f16", kernel=kernel)
+        c.set_state(blob)
+        c.step(20)
+        d = float(np.abs(c.fields()["psi"][fl] - pa).max())
+        _say(f"  f16 resume on kernel {kernel}: max |dpsi| {d:.1e}")
+        assert d < 5e-3
+        assert c.diagnostics()["step"] == 320
+        c.close()
