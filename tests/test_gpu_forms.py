@@ -102,15 +102,18 @@ def test_fused_masked_matches_oracle(L, orc):
     assert eu < 1e-5 and ep < 1e-5
 
 
-def test_full_size_focusing_sampled(L, orc):
+@pytest.mark.parametrize("kernel", ["fused", "compact"])
+def test_full_size_focusing_sampled(L, orc, kernel):
     # Flow-focusing cross at full size (512 x 128 x 64) in the benchmark's
-    # launch configuration.  A node's next state depends on the stored state
-    # and mask within two nodes, so the oracle steps 5^3 cuts (mask and
-    # boundary tables included) around sampled fluid nodes.
+    # launch configuration (the pair-state split step, and the compact
+    # state's).  A node's next state depends on the stored state and mask
+    # within two nodes, so the oracle steps 5^3 cuts (mask and boundary
+    # tables included) around sampled fluid nodes.
     w = W.flow_focusing(lam=3.0)
     nx, ny, nz = w.dims
-    s = L.Sim.from_workload(w, precision="f32")
-    assert s.launch_info()["kernel"] == L.KERNEL_FUSED
+    k = {"fused": L.KERNEL_FUSED, "compact": L.KERNEL_COMPACT}[kernel]
+    s = L.Sim.from_workload(w, precision="f32", kernel=k)
+    assert s.launch_info()["kernel"] == k and s.launch_info()["rows"] == 0
     s.step(30)
     rng = np.random.default_rng(3)
     fluid = np.flatnonzero(w.mask.reshape(-1) == 0)
@@ -140,7 +143,7 @@ def test_full_size_focusing_sampled(L, orc):
         o.step(1)
         ref = o.populations()[:, :, 2, 2, 2]
         worst = max(worst, float(np.abs(after[j] - ref).max() / np.abs(ref).max()))
-    _say(f"  focusing sampled one-step max rel diff {worst:.2e}")
+    _say(f"  focusing ({kernel}) sampled one-step max rel diff {worst:.2e}")
     assert worst < 2e-6
 
 
