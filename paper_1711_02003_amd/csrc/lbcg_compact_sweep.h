@@ -3,7 +3,9 @@
 // (arXiv:1711.02003, Sec. II, Eqs. (1)-(11)), periodic lattices, FP32 or
 // FP16 storage with FP32 arithmetic, shared by the single-lattice kernels (lbcg_compact.hip) and the batched
 // one (lbcg_compact_batch.hip), which are built as separate objects so that
-// each gets the code-generation options measured best for it.
+// each gets the code-generation options measured best for it.  The split
+// step of lattices with geometry (lbcg_geo.hip) stores and reads the same
+// layout through CStore.
 //
 // The recolouring of Eq. (10) splits each post-collision population f_i into
 // colours with coefficients that depend only on the sending node (its colour

@@ -21,7 +21,9 @@
 // sweep, so the results are bitwise those of the sweep.  Traffic per fluid
 // node: pairs read and written once (2 x 38 x E bytes), plus 12 moments and
 // psi written and read once (2 x 52 bytes), the neighbours' psi from cache,
-// and at nodes next to a boundary their new pairs read back.
+// and at nodes next to a boundary their new pairs read back.  The same three
+// kernels also run on the compact state (below): 2 x 96 (FP32) or 2 x 50
+// (FP16) bytes of state per fluid node instead of 2 x 152 or 2 x 76.
 #include "lbcg_buffer.h"
 #include "lbcg_compact_sweep.h"  // CStore: the compact state's storage
 #include "lbcg_internal.h"
