@@ -131,3 +131,45 @@ def test_wall_and_collision_validation(lib):
     p, keep = lbcg.make_params("D3Q19", (8, 8, 8), 1.0, 0.7, 0.0, 0.0, 0.7, collision=3)
     with pytest.raises(lbcg.LbcgError):
         lbcg.footprint(p)
+
+
+def test_geometry_compact_and_bgk_validation(lib):
+    # The compact state with a mask runs the split step: its footprint adds
+    # the split step's scratch (12 moments and a node-list entry per node,
+    # block lists), it takes no launch shape, and plain BGK takes 8-row tiles
+    # on the fused D3Q19 sweep (any on the generic kernel); BGK lattices
+    # carry no split-step scratch.
+    import numpy as np
+
+    from paper_1711_02003_amd import lbcg
+    lbcg._lib = None
+    dims = (70, 13, 9)
+    pitch = -(-70 * 13 * 9 // 64) * 64
+    m = np.zeros((9, 13, 70), np.uint8)
+    m[:, 0, :] = 1
+    kw = dict(mask=m)
+    per = dict(kernel=lbcg.KERNEL_COMPACT)
+    c, k1 = lbcg.make_params("D3Q19", dims, 1.0, 0.6, 0.005, 0.005, 0.7, kernel=lbcg.KERNEL_COMPACT)
+    cm, k2 = lbcg.make_params("D3Q19", dims, 1.0, 0.6, 0.005, 0.005, 0.7, **per, **kw)
+    extra = lbcg.footprint(cm) - lbcg.footprint(c)
+    # mask (1 B), link words (4 B), moments (48 B) and node list (4 B) per node
+    assert (1 + 4 + 48 + 4) * pitch <= extra <= (1 + 4 + 48 + 4) * pitch + 64 * 1024, extra
+    for prec in ("f32", "f16"):
+        p, k3 = lbcg.make_params("D3Q19", dims, 1.0, 0.6, 0.005, 0.005, 0.7, prec, **per, **kw)
+        assert lbcg.footprint(p) > 0
+        p, k3 = lbcg.make_params("D3Q19", dims, 1.0, 0.6, 0.005, 0.005, 0.7, prec, **per, **kw, tile=(8, 2, 0))
+        with pytest.raises(lbcg.LbcgError):
+            lbcg.footprint(p)
+    for kernel, ok in ((lbcg.KERNEL_FUSED, False), (lbcg.KERNEL_AUTO, False), (lbcg.KERNEL_GENERIC, True)):
+        p, k4 = lbcg.make_params("D3Q19", dims, 1.0, 0.6, 0.005, 0.005, 0.7, collision=lbcg.BGK, kernel=kernel,
+                                 tile=(4, 0, 0))
+        if ok:
+            assert lbcg.footprint(p) > 0
+        else:
+            with pytest.raises(lbcg.LbcgError):
+                lbcg.footprint(p)
+    p, k5 = lbcg.make_params("D3Q19", dims, 1.0, 0.6, 0.005, 0.005, 0.7, "f64", collision=lbcg.BGK, tile=(4, 0, 0))
+    assert lbcg.footprint(p) > 0
+    reg, k6 = lbcg.make_params("D3Q19", dims, 1.0, 0.6, 0.005, 0.005, 0.7, **kw)
+    bgk, k7 = lbcg.make_params("D3Q19", dims, 1.0, 0.6, 0.005, 0.005, 0.7, collision=lbcg.BGK, **kw)
+    assert lbcg.footprint(reg) - lbcg.footprint(bgk) >= (48 + 4) * pitch
