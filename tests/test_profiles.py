@@ -21,3 +21,13 @@ def test_traffic_summary_is_current(kernel):
     assert moved is not None, f"{bench.TRAFFIC_FILES[kernel]} is missing or was taken from other sources"
     ratio = moved / ALGORITHMIC[kernel]
     assert 1.0 <= ratio < LIMIT[kernel], ratio
+
+
+def test_bench_refuses_more_than_one_gpu():
+    # one GPU only: any other count ends with a JSON line that says so
+    import json
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, bench.__file__, "--gpus", "2"], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in json.loads(r.stdout.strip().splitlines()[-1])["error"]
