@@ -50,7 +50,8 @@ HBM_PEAK_GBS = 8000.0
 FORMS = ("pair_f32", "f16", "d2q9", "focusing2d", "focusing", "batched", "batched_compact", "served")
 TRAFFIC_FILES = {"k_step_compact": os.path.join(ROOT, "profiles", "compact_d3q19_f32_256_traffic.txt"),
                  "k_step_fused": os.path.join(ROOT, "profiles", "fused_d3q19_f32_256_traffic.txt"),
-                 "geo_split": os.path.join(ROOT, "profiles", "geo_split_d3q19_f32_junction_traffic.txt")}
+                 "geo_split": os.path.join(ROOT, "profiles", "geo_split_d3q19_f32_junction_traffic.txt"),
+                 "geo_split_compact": os.path.join(ROOT, "profiles", "geo_split_compact_d3q19_f32_junction_traffic.txt")}
 
 
 def log(msg):
@@ -314,6 +315,8 @@ def focusing_form(torch, lbcg, W, steps=200, warmup=10, tune=True):
                                   "ms_per_step": round(ms / steps, 4),
                                   "frac": round(nbytes * w.fluid_nodes * steps / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
                                   "bytes_per_fluid_node": nbytes}
+        if prec == "f32":
+            out[prec + "_compact"]["traffic"] = read_traffic("geo_split_compact")
     return out
 
 

@@ -53,6 +53,10 @@ KERNELS = {
                      2 * 38 * 4, [r"k_step_fused<float, float, \d, false, false>"]),
     "geo_split": (["paper_1711_02003_amd/csrc/lbcg_geo.hip", "paper_1711_02003_amd/csrc/lbcg_device.h"],
                   2 * 38 * 4 + 4, [r"k_geo_moments<float>", r"k_geo_collide<float>", r"k_geo_boundary<float>"]),
+    "geo_split_compact": (["paper_1711_02003_amd/csrc/lbcg_geo.hip", "paper_1711_02003_amd/csrc/lbcg_device.h",
+                           "paper_1711_02003_amd/csrc/lbcg_compact_sweep.h"],
+                          2 * (19 * 4 + 20) + 4,
+                          [r"k_cgeo_moments<float>", r"k_cgeo_collide<float>", r"k_cgeo_boundary<float>"]),
 }
 
 
