@@ -73,33 +73,31 @@ extern "C" {
  * fused kernel where it applies.
  *
  * LBCG_KERNEL_COMPACT (never picked automatically): the fused sweeps on a
- * compact state, regularized collision; for periodic lattices D3Q19 with
- * F32 or F16 storage and tiles of 8 rows (tile[0] 0 or 8), or D2Q9 with F32
- * storage; with a geometry mask D3Q19 with F32 or F16 storage on the split step of
- * the fused kernel (launch shape fixed: tile all 0; a link from a wall
- * brings back the node's own population, a link from an inlet or outlet
- * reads the pair the boundary kernel stores in the pair buffer); the pair
- * state (2Q x 4 x pitch bytes for F32,
- * 2Q x 2 x pitch for F16) below 4 GiB (pitch = node count rounded up to
- * 64).  Eq. (10)
- * splits every population of a node with coefficients that depend only on
- * that node and on the speed class of the direction, so each node stores its
- * Q total populations and its colour scalars (its minority share and one
+ * compact state, regularized collision: for periodic lattices D3Q19 with F32
+ * or F16 storage and tiles of 8 rows (tile[0] 0 or 8), or D2Q9 with F32
+ * storage; with a geometry mask D3Q19 with F32 or F16 storage on the split
+ * step of the fused kernel (launch shape fixed, tile all 0; a link from a
+ * wall brings back the node's own population, a link from an inlet or an
+ * outlet reads the pair that the boundary kernel stores in the pair
+ * buffer); the pair state (2Q x 4 x pitch bytes for F32, 2Q x 2 x pitch for
+ * F16) below 4 GiB (pitch = node count rounded up to 64).  Eq. (10) splits
+ * every population of a node with coefficients that depend only on that
+ * node and on the speed class of the direction, so each node stores its Q
+ * total populations and its colour scalars (its minority share and one
  * vector per speed class) and the receiver of a population splits it: 192
  * bytes of memory traffic per node and step instead of 304 (D3Q19), 104
- * instead of 144 (D2Q9).  F16 storage keeps the totals (over w_i), the
- * axis vector and the diagonal ratio in F16, rounded stochastically, and
- * the minority share in F32: 100 bytes per node and step instead of the
- * F16 pair state's 152.  Results agree with the pair-state kernels up to
- * rounding.  The first step
- * after lbcg_init_fields or lbcg_set_state reads the pair state; the calls
- * that read the state (fields, populations, diagnostics, lbcg_get_state)
- * first convert the compact state to a pair state in the handle's pair
- * buffer, which the compact steps leave unused but for those inlet and
- * outlet values (one extra kernel, no change to the trajectory).
- * lbcg_footprint
- * adds the two compact buffers (2 x 96 x pitch bytes for D3Q19 F32, 2 x 50
- * x pitch for D3Q19 F16, 2 x 52 x pitch for D2Q9). */
+ * instead of 144 (D2Q9).  F16 storage keeps the totals (over w_i), the axis
+ * vector and the diagonal ratio in F16, rounded stochastically, and the
+ * minority share in F32: 100 bytes per node and step instead of the F16
+ * pair state's 152.  Results agree with the pair-state kernels up to
+ * rounding.  The first step after lbcg_init_fields or lbcg_set_state reads
+ * the pair state; the calls that read the state (fields, populations,
+ * diagnostics, lbcg_get_state) first convert the compact state to a pair
+ * state in the handle's pair buffer, which the compact steps leave unused
+ * but for those inlet and outlet values (one extra kernel, no change to the
+ * trajectory).  lbcg_footprint adds the two compact buffers (2 x 96 x pitch
+ * bytes for D3Q19 F32, 2 x 50 x pitch for D3Q19 F16, 2 x 52 x pitch for
+ * D2Q9). */
 #define LBCG_KERNEL_AUTO 0
 #define LBCG_KERNEL_GENERIC 1
 #define LBCG_KERNEL_FUSED 2
