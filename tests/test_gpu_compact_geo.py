@@ -178,3 +178,90 @@ def test_compact_geometry_f16_walls_and_reads(L):
         assert d < 5e-3
         assert c.diagnostics()["step"] == 320
         c.close()
+
+
+@pytest.mark.parametrize("prec", ["f32", "f16"])
+def test_compact_geometry_single_fluid_node_and_no_fluid(L, prec):
+    # one fluid node in a lattice of walls (every link from a wall, so every
+    # pull is the node's own total of the opposite direction); and a lattice
+    # with no fluid node at all, which still advances the step counter and
+    # exports zeros
+    m = np.ones((4, 6, 70), np.uint8)
+    m[2, 3, 66] = 0
+    sh = m.shape
+    u = np.zeros((3,) + sh)
+    u[:, 2, 3, 66] = (0.02, -0.01, 0.015)
+    w = W.Workload("one", "D3Q19", (70, 6, 4), np.full(sh, 0.6), np.full(sh, 0.4), u, 1.0, 0.8, 0.01, 0.7,
+                   mask=m)
+    fl = m == 0
+    a = L.Sim.from_workload(w, precision=prec, kernel=L.KERNEL_COMPACT)
+    b = L.Sim.from_workload(w, precision=prec, kernel=L.KERNEL_FUSED)
+    assert a.launch_info()["rows"] == 0 and b.launch_info()["rows"] == 0
+    d0 = a.diagnostics()
+    a.step(30)
+    b.step(30)
+    pa, pb = a.populations()[..., fl], b.populations()[..., fl]
+    d = float(np.abs(pa - pb).max() / np.abs(pb).max())
+    d1 = a.diagnostics()
+    dm = max(abs(d1["mass_R"] / d0["mass_R"] - 1), abs(d1["mass_B"] / d0["mass_B"] - 1))
+    _say(f"compact geometry {prec}, one fluid node x30: max rel difference {d:.2e}, colour mass {dm:.1e}")
+    assert np.isfinite(pa).all()
+    assert d < (60 * EPS32 if prec == "f32" else 5e-3)
+    assert dm < (1e-6 if prec == "f32" else 1e-4)
+    assert d1["step"] == 30 and d1["status"] == 0
+    w.mask = np.ones_like(m)
+    e = L.Sim.from_workload(w, precision=prec, kernel=L.KERNEL_COMPACT)
+    assert e.launch_info()["rows"] == 0
+    e.step(7)
+    assert e.diagnostics()["step"] == 7
+    assert not np.any(e.populations())
+    e.step(2)
+    assert e.diagnostics()["step"] == 9
+
+
+def test_compact_geometry_largest_lattice(L):
+    # The compact state with geometry takes lattices whose FP32 pair state
+    # stays below 4 GiB: 304^3 (pair buffers of 4.27 GB, compact buffers of
+    # 2.70 GB, 32-bit byte offsets up to 2^32 - 25 MB) here with a neutral
+    # and a wetting wall face, an inlet and an outlet face.  Sampled fluid
+    # nodes, those of the last planes among them, agree with the pair state's
+    # column sweep to FP32 rounding after 3 steps; at 306^3 the compact kernel
+    # is refused.
+    edge = 304
+    w = W.droplets_27(L=edge, seed=2)
+    m = np.zeros((edge,) * 3, np.uint8)
+    m[:, 0, :] = 1
+    m[:, -1, :] = 64
+    m[:, 1:-1, 0] = 2
+    m[:, 1:-1, -1] = 128
+    w.mask = m
+    w.inlets = [{"u": (0.01, 0.0, 0.0), "rho_R": 0.9, "rho_B": 0.1}]
+    w.outlets = [{"rho": 1.0}]
+    w.walls = [{"psi": 0.5}]
+    rng = np.random.default_rng(304)
+    x = np.concatenate([rng.integers(1, edge - 1, 200), [1, edge - 2, edge - 2, 1]])
+    y = np.concatenate([rng.integers(1, edge - 1, 200), [1, edge - 2, 1, edge - 2]])
+    z = np.concatenate([rng.integers(0, edge, 150), np.full(50, edge - 1), [edge - 1, edge - 1, 0, 0]])
+    nodes = (x + edge * (y + edge * z)).astype(np.int64)
+    assert (m.reshape(-1)[nodes] == 0).all()
+    out = {}
+    for name, kernel in (("compact", L.KERNEL_COMPACT), ("pair", L.KERNEL_FUSED)):
+        _say(f"{edge}^3 f32 with geometry, {name}")
+        s = L.Sim.from_workload(w, precision="f32", kernel=kernel)
+        assert s.launch_info()["rows"] == (0 if name == "compact" else 8)  # mostly fluid: the column sweep
+        s.step(3)
+        out[name] = s.populations_at(nodes)
+        d = s.diagnostics()
+        assert d["step"] == 3 and d["status"] == 0
+        s.close()
+    pa, pb = out["compact"], out["pair"]
+    assert np.isfinite(pa).all()
+    diff = float(np.abs(pa - pb).max() / np.abs(pb).max())
+    _say(f"  sampled max rel difference compact vs pair {diff:.2e}")
+    assert diff < 30 * EPS32
+    del w, m
+    sh = (306,) * 3
+    big = W.Workload("channel", "D3Q19", sh, np.full(sh, 0.6), np.full(sh, 0.4), None, 1.0, 0.8, 0.01, 0.7,
+                     mask=np.pad(np.zeros((306, 304, 306), np.uint8), ((0, 0), (1, 1), (0, 0)), constant_values=1))
+    with pytest.raises(L.LbcgError):
+        L.Sim.from_workload(big, precision="f32", kernel=L.KERNEL_COMPACT)
