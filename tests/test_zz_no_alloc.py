@@ -115,3 +115,17 @@ def test_noalloc_refuses_beyond_its_area(L):
         L.batch_step_noalloc([comp], 1, (4, 8))
     with pytest.raises(L.LbcgError):
         L.batch_step_noalloc([sims[0], comp], 1, (8, 8))
+    # plain BGK and the compact state with geometry stay off the batched
+    # sweeps: refused, nothing stepped
+    bgk = L.Sim.from_workload(tiny, precision="f32", collision=L.BGK, stream=stream.cuda_stream)
+    assert bgk.launch_info()["kernel"] == L.KERNEL_FUSED
+    geo = _focusing()
+    cgeo = L.Sim.from_workload(geo, precision="f32", kernel=L.KERNEL_COMPACT, stream=stream.cuda_stream)
+    for group in ([bgk], [sims[0], bgk], [cgeo]):
+        with pytest.raises(L.LbcgError) as e:
+            L.batch_step_noalloc(group, 1, (8, 8))
+        assert e.value.status == L.E_INVAL
+    assert bgk.diagnostics()["step"] == 0 and cgeo.diagnostics()["step"] == 0
+    assert sims[0].diagnostics()["step"] == 1
+    for s in sims + [comp, bgk, cgeo]:
+        s.close()
