@@ -58,6 +58,24 @@ def test_compact_geometry_matches_oracle(L, orc):
     assert s.diagnostics()["step"] == 200
 
 
+def test_geometry_split_steps_1000_steps_match_oracle(L, orc):
+    # the split step on the pair state and on the compact state, FP32, after
+    # 1000 steps of driven flow through the quarter-size junction
+    w = _focusing()
+    fl = w.mask == 0
+    f = oracle_for(orc, w, threads=16).step(1000).fields()
+    for kernel in (L.KERNEL_FUSED, L.KERNEL_COMPACT):
+        s = L.Sim.from_workload(w, precision="f32", kernel=kernel)
+        assert s.launch_info()["rows"] == 0
+        s.step(1000)
+        g = s.fields()
+        s.close()
+        ep = rel_l2(g["psi"][fl], f["psi"][fl])
+        eu = rel_l2(g["u"][:, fl], f["u"][:, fl])
+        _say(f"split step (kernel {kernel}) vs oracle, focusing 128x48x14 x1000: relL2 psi {ep:.2e} u {eu:.2e}")
+        assert ep < 1e-5 and eu < 1e-5
+
+
 @pytest.mark.parametrize("dims", [(70, 13, 9), (5, 7, 6)])
 def test_compact_geometry_walls_matches_oracle(L, orc, dims):
     # walls of three codes (neutral and two wetting), periodic elsewhere,
