@@ -275,9 +275,10 @@ def test_determinism_and_checkpoint(L):
     assert c.diagnostics()["step"] == 40
 
 
-def _sampled_one_step(L, orc, w, s, n_samples=48, seed=0):
+def _sampled_one_step(L, orc, w, s, n_samples=48, seed=0, advance=None):
     # Each sampled node's next state depends only on the current state within
     # two nodes, so the oracle steps a periodic 5^3 box cut around it.
+    # advance: what takes s one step (default s.step(1); a batch's level).
     nx, ny, nz = w.dims
     rng = np.random.default_rng(seed)
     centres = np.stack([rng.integers(0, nx, n_samples), rng.integers(0, ny, n_samples),
@@ -289,7 +290,10 @@ def _sampled_one_step(L, orc, w, s, n_samples=48, seed=0):
         boxes.append((xx + nx * (yy + ny * zz)).reshape(-1))
     nodes = np.concatenate(boxes)
     before = s.populations_at(nodes).reshape(len(centres), 5, 5, 5, 2, 19)
-    s.step(1)
+    if advance is None:
+        s.step(1)
+    else:
+        advance()
     after = s.populations_at(np.array([b[62] for b in boxes]))  # 62 = centre of a 5^3 box
     p = orc.Params(lattice=orc.D3Q19, dims=(5, 5, 5), tau=(w.tau_R, w.tau_B), A=(w.A, w.A), beta=w.beta)
     worst = 0.0
