@@ -363,11 +363,15 @@ def test_library_loaded_before_torch_in_fresh_process(L):
     assert "fresh process ok" in r.stdout
 
 
-def test_laplace_law_3d_fused_f32_matches_oracle(L, orc):
+_LAPLACE_ORACLE = {}
+
+
+@pytest.mark.parametrize("kernel", ["fused", "compact"])
+def test_laplace_law_3d_fused_f32_matches_oracle(L, orc, kernel):
     # Static spheres R in {6, 8, 10} in 32^3 (tau = 1, A = 0.005, 1500 steps):
-    # the FP32 fused D3Q19 sweep gives the oracle's effective radii, pressure
-    # jumps (p = rho / 3, Eq. (8) for D3Q19 with alpha = w_0) and fitted
-    # surface tension of dp = 2 sigma / R.
+    # the FP32 fused D3Q19 sweep, on the pair and on the compact state, gives
+    # the oracle's effective radii, pressure jumps (p = rho / 3, Eq. (8) for
+    # D3Q19 with alpha = w_0) and fitted surface tension of dp = 2 sigma / R.
     n = 32
     zz, yy, xx = np.mgrid[0:n, 0:n, 0:n]
     c = (n - 1) / 2
@@ -378,15 +382,18 @@ def test_laplace_law_3d_fused_f32_matches_oracle(L, orc):
         Reff = (3 * ((1 + f["psi"]) / 2).sum() / (4 * np.pi)) ** (1 / 3)
         return Reff, p[r < Reff - 4].mean() - p[r > Reff + 5].mean()
 
+    kid = {"fused": L.KERNEL_FUSED, "compact": L.KERNEL_COMPACT}[kernel]
     res = {"gpu": [], "orc": []}
     for R in (6.0, 8.0, 10.0):
         w = W.static_droplet_3d(n, R=R, A=0.005)
-        s = L.Sim.from_workload(w, precision="f32")
-        assert s.launch_info()["kernel"] == L.KERNEL_FUSED
+        s = L.Sim.from_workload(w, precision="f32", kernel=kid)
+        assert s.launch_info()["kernel"] == kid
         s.step(1500)
         res["gpu"].append(jump(s.fields()))
         s.close()
-        res["orc"].append(jump(oracle_for(orc, w, threads=16).step(1500).fields()))
+        if R not in _LAPLACE_ORACLE:
+            _LAPLACE_ORACLE[R] = jump(oracle_for(orc, w, threads=16).step(1500).fields())
+        res["orc"].append(_LAPLACE_ORACLE[R])
     fits = {}
     for k, v in res.items():
         Rs, dps = np.array(v).T
