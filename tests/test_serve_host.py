@@ -208,3 +208,15 @@ def test_pipeline_hides_setup_and_readback():
     assert st.makespan_s <= be.busy + 2.0 + 2.0 + 1e-9
     # a one-slice-at-a-time loop would add every set-up and readback
     assert st.makespan_s < be.busy + 8 * 4.0 - 20.0
+
+
+def test_progress_reports_each_completion():
+    clk = FakeClock()
+    be = FakeBackend(clk, 10_000_000)
+    seen = []
+    srv = Server(be, 10_000_000, slice_steps=100, clock=clk, sleep=clk.sleep,
+                 progress=lambda done, total: seen.append((done, total)))
+    reqs = [_req(i, 0.3 * i, 150 + 50 * i, 100_000) for i in range(5)]
+    st = srv.run(reqs)
+    assert st.completed == 5
+    assert seen == [(k, 5) for k in range(1, 6)]
