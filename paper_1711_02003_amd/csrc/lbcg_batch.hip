@@ -9,7 +9,11 @@
 // are ordered by decreasing step count, so the lattices still running at
 // any time level are a prefix of the list and one launch covers them with a
 // prefix of the block table.  The kernel deals the prefix to the 8 XCDs in
-// contiguous bands (neighbouring tiles of one lattice on one XCD).  Runs of
+// contiguous bands.  The items of lattices with the same step count are
+// placed so that the bands of a launch over every lattice carry about the
+// same work and each band runs its longest items first (items differ by up
+// to 2x in z planes and rows; on 64 boxes of 32-96 nodes a side this steps
+// 3 % faster than items placed lattice by lattice).  Runs of
 // 32 levels with the same active set are captured into a HIP graph and
 // replayed.  The launch shape (rows per tile, z planes per chunk) is chosen
 // by timing candidate shapes on the batch itself at creation.
@@ -103,10 +107,83 @@ void drop_graphs(lbcg_batch *b) {
     b->graphs.clear();
 }
 
-// Fill the pinned staging for lattice order `order` (decreasing step count)
-// and copy it to the device.  Descriptor parity 0 steps buf[cur] into
-// buf[cur ^ 1], parity 1 the reverse.
-int stage(lbcg_batch *b, const std::vector<int> &order) {
+// Work of item i of lattice j in the current shape, in row-planes: the
+// planes of its z chunk plus the two its sweep pulls first, times the rows
+// of its tile, a partial row tile counted at half its missing rows (its
+// ring still runs).
+int64_t item_cost(const lbcg_batch *b, int j, int i) {
+    const lbcg_sim *s = b->sims[size_t(j)];
+    const int zc = b->zchunks[size_t(j)];
+    const int tile = i / zc, chunk = i % zc;
+    const int ntx = (s->g.nx + kTileX - 1) / kTileX;
+    const int rows = std::min(b->rows, s->g.ny - (tile / ntx) * b->rows);
+    const int64_t z0 = int64_t(chunk) * s->g.nz / zc, z1 = int64_t(chunk + 1) * s->g.nz / zc;
+    return (z1 - z0 + 2) * (b->rows + rows);
+}
+
+struct Item {
+    int64_t cost;
+    int lat, item;
+};
+
+// Table entries [0, total) of one group (periodic or geometry lattices) for
+// the lattices `lats` in table order with step counts `left`.  Each run of
+// equal step counts fills its own range of entries (the prefix property).
+// Periodic launches deal entries to the XCDs in contiguous bands (the
+// kernels' work_index): within a run, items go longest first to the band
+// with the least work so far that still has entries in the run's range, and
+// each band's entries take its items longest first.  Launches with geometry
+// deal consecutive entries to consecutive XCDs, so a run is simply sorted
+// longest first.
+void place_items(const lbcg_batch *b, const std::vector<int> &lats, const std::vector<int64_t> &left, bool banded,
+                 int *lat, int *item) {
+    constexpr int kBands = 8;
+    int64_t total = 0;
+    for (int j : lats) total += b->items[size_t(j)];
+    auto band_start = [&](int x) { return int64_t(x) * (total / kBands) + std::min<int64_t>(x, total % kBands); };
+    int64_t load[kBands] = {};
+    std::vector<Item> run;
+    std::vector<int64_t> next(kBands), end(kBands);
+    int64_t p = 0;
+    for (size_t q = 0; q < lats.size();) {
+        size_t r = q;
+        run.clear();
+        for (; r < lats.size() && left[r] == left[q]; ++r)
+            for (int i = 0; i < b->items[size_t(lats[r])]; ++i) run.push_back({item_cost(b, lats[r], i), lats[r], i});
+        std::stable_sort(run.begin(), run.end(), [](const Item &u, const Item &v) { return u.cost > v.cost; });
+        const int64_t p1 = p + int64_t(run.size());
+        if (!banded) {
+            for (const Item &it : run) {
+                lat[p] = it.lat;
+                item[p] = it.item;
+                ++p;
+            }
+        } else {
+            // entries [next[x], end[x]) of band x lie in this run's range
+            for (int x = 0; x < kBands; ++x) {
+                next[x] = std::max(p, band_start(x));
+                end[x] = std::min(p1, band_start(x + 1));
+            }
+            for (const Item &it : run) {
+                int pick = -1;
+                for (int x = 0; x < kBands; ++x)
+                    if (next[x] < end[x] && (pick < 0 || load[x] < load[pick])) pick = x;
+                lat[next[pick]] = it.lat;
+                item[next[pick]] = it.item;
+                ++next[pick];
+                load[pick] += it.cost;
+            }
+            p = p1;
+        }
+        q = r;
+    }
+}
+
+// Fill the pinned staging for lattice order `order` (decreasing step count,
+// `left` the step counts in that order) and copy it to the device.
+// Descriptor parity 0 steps buf[cur] into buf[cur ^ 1], parity 1 the
+// reverse.
+int stage(lbcg_batch *b, const std::vector<int> &order, const std::vector<int64_t> &left) {
     if (b->staged_pending) {
         HIP_TRY(hipEventSynchronize(b->staged));
         b->staged_pending = false;
@@ -125,15 +202,15 @@ int stage(lbcg_batch *b, const std::vector<int> &order) {
             d[j].mo = to_model<float>(s->md);
         }
     }
-    int64_t kU = 0, kM = 0;
-    for (int j : order) {
-        const bool m = is_masked(b->sims[j]);
-        int *lat = b->tab(b->hmem, m, false), *item = b->tab(b->hmem, m, true);
-        int64_t &k = m ? kM : kU;
-        for (int i = 0; i < b->items[j]; ++i, ++k) {
-            lat[k] = j;
-            item[k] = i;
-        }
+    for (int m = 0; m < 2; ++m) {
+        std::vector<int> lats;
+        std::vector<int64_t> steps;
+        for (size_t q = 0; q < order.size(); ++q)
+            if (is_masked(b->sims[size_t(order[q])]) == bool(m)) {
+                lats.push_back(order[q]);
+                steps.push_back(left[q]);
+            }
+        place_items(b, lats, steps, !m, b->tab(b->hmem, m, false), b->tab(b->hmem, m, true));
     }
     HIP_TRY(hipMemcpyAsync(b->dmem, b->hmem, b->bytes, hipMemcpyHostToDevice, b->stream));
     HIP_TRY(hipEventRecord(b->staged, b->stream));
@@ -186,7 +263,7 @@ hipGraphExec_t graph_for(lbcg_batch *b, int nbU, int nbM) {
 int time_shape(lbcg_batch *b, float *ms) {
     std::vector<int> order(b->sims.size());
     for (size_t j = 0; j < order.size(); ++j) order[j] = int(j);
-    int rc = stage(b, order);
+    int rc = stage(b, order, std::vector<int64_t>(order.size(), 0));
     if (rc) return rc;
     int nbU = 0, nbM = 0;
     for (size_t j = 0; j < order.size(); ++j) (is_masked(b->sims[j]) ? nbM : nbU) += b->items[j];
@@ -321,7 +398,9 @@ int lbcg_batch_step(lbcg_batch *b, const int64_t *nsteps) {
         if (left[j] > 0) order.push_back(j);
     if (order.empty()) return LBCG_OK;
     std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return left[a] > left[c]; });
-    int rc = stage(b, order);
+    std::vector<int64_t> run_left(order.size());
+    for (size_t q = 0; q < order.size(); ++q) run_left[q] = left[size_t(order[q])];
+    int rc = stage(b, order, run_left);
     if (rc) return rc;
 
     // time levels in runs of constant active set: the first k lattices of
