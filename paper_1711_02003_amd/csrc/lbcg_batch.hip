@@ -11,9 +11,9 @@
 // prefix of the block table.  The kernel deals the prefix to the 8 XCDs in
 // contiguous bands.  The items of lattices with the same step count are
 // placed so that the bands of a launch over every lattice carry about the
-// same work and each band runs its longest items first (items differ by up
-// to 2x in z planes and rows; on 64 boxes of 32-96 nodes a side this steps
-// 3 % faster than items placed lattice by lattice).  Runs of
+// same work and each band runs its longest items first (z chunks differ by
+// up to 2x in planes; on 64 boxes of 32-96 nodes a side this steps 6-7 %
+// faster than items placed lattice by lattice).  Runs of
 // 32 levels with the same active set are captured into a HIP graph and
 // replayed.  The launch shape (rows per tile, z planes per chunk) is chosen
 // by timing candidate shapes on the batch itself at creation.
@@ -107,18 +107,17 @@ void drop_graphs(lbcg_batch *b) {
     b->graphs.clear();
 }
 
-// Work of item i of lattice j in the current shape, in row-planes: the
-// planes of its z chunk plus the two its sweep pulls first, times the rows
-// of its tile, a partial row tile counted at half its missing rows (its
-// ring still runs).
+// Work of item i of lattice j in the current shape, in planes: those of
+// its z chunk plus the two its sweep pulls first.  A tile that the lattice
+// fills only in part takes about as long as a full one (it still steps
+// every plane with all its waves): weighting items by their rows or lanes
+// measured slower on the 64 boxes.
 int64_t item_cost(const lbcg_batch *b, int j, int i) {
     const lbcg_sim *s = b->sims[size_t(j)];
     const int zc = b->zchunks[size_t(j)];
-    const int tile = i / zc, chunk = i % zc;
-    const int ntx = (s->g.nx + kTileX - 1) / kTileX;
-    const int rows = std::min(b->rows, s->g.ny - (tile / ntx) * b->rows);
+    const int chunk = i % zc;
     const int64_t z0 = int64_t(chunk) * s->g.nz / zc, z1 = int64_t(chunk + 1) * s->g.nz / zc;
-    return (z1 - z0 + 2) * (b->rows + rows);
+    return z1 - z0 + 2;
 }
 
 struct Item {
