@@ -192,12 +192,18 @@ extern "C" int lbcg_batch_step_noalloc(lbcg_sim *const *sims, int32_t n, const i
     for (int j = 0; j < n; ++j)
         if (left[j] > 0) order[k++] = j;
     if (k == 0) return LBCG_OK;
-    // decreasing step count, ties in handle order (a stable insertion sort:
-    // the library's sorts may take a temporary buffer from the heap)
+    // decreasing step count; among equal counts, lattices with geometry
+    // (whose blocks go to the XCDs in table order) by decreasing planes per
+    // z chunk, so that the longest work items start first, and the others in
+    // handle order (a stable insertion sort: the library's sorts may take a
+    // temporary buffer from the heap)
+    int planes[kMaxLat];
+    for (int j = 0; j < n; ++j) planes[j] = sims[j]->g.mask ? (sims[j]->g.nz + zch[j] - 1) / zch[j] : 0;
+    auto before = [&](int u, int v) { return left[u] > left[v] || (left[u] == left[v] && planes[u] > planes[v]); };
     for (int q = 1; q < k; ++q) {
         const int v = order[q];
         int p = q;
-        for (; p > 0 && left[order[p - 1]] < left[v]; --p) order[p] = order[p - 1];
+        for (; p > 0 && before(v, order[p - 1]); --p) order[p] = order[p - 1];
         order[p] = v;
     }
     const hipStream_t st = s0->stream;
