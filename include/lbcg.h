@@ -307,8 +307,8 @@ int lbcg_tune(lbcg_sim *s, int32_t *rows, int32_t *zchunks);
  * refers to existing handles; it does not own them, and they must outlive
  * it.  Requirements: every handle initialised, all on the fused kernel
  * (D3Q19, F32 or F16 storage, regularized collision; geometry and periodic
- * lattices may mix) or all on the compact kernel with F32 storage, one
- * storage precision, one stream, no handle listed twice.
+ * lattices may mix) or all on the compact kernel (periodic D3Q19, F32 or
+ * F16 storage), one storage precision, one stream, no handle listed twice.
  * tile: {rows per block (4 or 8; 8 on the compact kernel), z planes per
  * chunk (>= 1)}; NULL or {0, 0}
  * = choose by timing candidate shapes on the batch (the states do not

@@ -219,7 +219,7 @@ int stage(lbcg_batch *b, const std::vector<int> &order, const std::vector<int64_
 
 hipError_t launch_level(lbcg_batch *b, int parity, int nbU, int nbM) {
     if (b->compact)
-        return launch_step_compact_batch(b->desc(b->dmem, parity), b->tab(b->dmem, false, false),
+        return launch_step_compact_batch(b->prec, b->desc(b->dmem, parity), b->tab(b->dmem, false, false),
                                          b->tab(b->dmem, false, true), nbU, b->stream);
     hipError_t e = hipSuccess;
     if (nbU > 0)
@@ -303,9 +303,8 @@ int lbcg_batch_create(lbcg_sim *const *sims, int32_t n, const int32_t *tile, lbc
         if (s->kernel != LBCG_KERNEL_FUSED && s->kernel != LBCG_KERNEL_COMPACT) return LBCG_E_INVAL;
         // the batched sweeps relax with the regularized collision only
         if (s->collision != LBCG_REGULARIZED) return LBCG_E_INVAL;
-        // the batched compact sweep: periodic lattices, FP32
+        // the batched compact sweep: periodic lattices
         if (s->kernel == LBCG_KERNEL_COMPACT && s->g.mask) return LBCG_E_INVAL;
-        if (s->kernel == LBCG_KERNEL_COMPACT && s->prec != LBCG_F32) return LBCG_E_INVAL;
         if (s->kernel != sims[0]->kernel || s->prec != sims[0]->prec || s->stream != sims[0]->stream)
             return LBCG_E_INVAL;
         for (int k = 0; k < j; ++k)

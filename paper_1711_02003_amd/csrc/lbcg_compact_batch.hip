@@ -11,7 +11,8 @@ namespace {
 // work item bitem[k] of lattice blat[k]; entries are dealt to the 8 XCDs in
 // contiguous bands (blocks go to XCDs round-robin), as the single-lattice
 // kernel deals its work items.  Every lattice is compact and periodic with
-// 8-row tiles.
+// 8-row tiles and storage S (float or _Float16).
+template <typename S>
 __global__ void __launch_bounds__(kCTX * kCR)
     k_step_compact_batch(const BatchDesc<float> *__restrict__ desc, const int *__restrict__ blat,
                          const int *__restrict__ bitem) {
@@ -34,17 +35,24 @@ __global__ void __launch_bounds__(kCTX * kCR)
     a.nty = d.a.nty;
     a.zchunks = d.a.zchunks;
     if (item == 0 && threadIdx.x == 0) *a.ctr_out = *a.ctr_in + 1u;
-    sweep_compact<false, kCTX>(a, d.mo, item / a.zchunks, item % a.zchunks, lds);
+    sweep_compact<false, kCTX, S>(a, d.mo, item / a.zchunks, item % a.zchunks, lds);
 }
 
 }  // namespace
 
-hipError_t launch_step_compact_batch(const void *desc, const int *blat, const int *bitem, int nblocks,
+hipError_t launch_step_compact_batch(int prec, const void *desc, const int *blat, const int *bitem, int nblocks,
                                      hipStream_t s) {
+    if (prec != 1 && prec != 2) return hipErrorInvalidValue;
     if (nblocks <= 0) return hipSuccess;
-    allow_lds(reinterpret_cast<const void *>(&k_step_compact_batch), 2, kCompactLds);
-    hipLaunchKernelGGL(k_step_compact_batch, dim3(unsigned(nblocks)), dim3(unsigned(kCTX * kCR)), kCompactLds, s,
-                       static_cast<const BatchDesc<float> *>(desc), blat, bitem);
+    const BatchDesc<float> *d = static_cast<const BatchDesc<float> *>(desc);
+    const dim3 grid{unsigned(nblocks)}, block{unsigned(kCTX * kCR)};
+    if (prec == 1) {
+        allow_lds(reinterpret_cast<const void *>(&k_step_compact_batch<float>), 0, kCompactLds);
+        hipLaunchKernelGGL(k_step_compact_batch<float>, grid, block, kCompactLds, s, d, blat, bitem);
+    } else {
+        allow_lds(reinterpret_cast<const void *>(&k_step_compact_batch<_Float16>), 1, kCompactLds);
+        hipLaunchKernelGGL(k_step_compact_batch<_Float16>, grid, block, kCompactLds, s, d, blat, bitem);
+    }
     return hipGetLastError();
 }
 

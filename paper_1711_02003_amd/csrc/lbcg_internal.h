@@ -177,8 +177,9 @@ struct BatchDesc {
 hipError_t launch_step_fused_batch(int prec, const void *desc, const int *blat, const int *bitem, int nblocks,
                                    int rows, bool masked, hipStream_t s);
 // Batched compact step: desc are BatchDesc<float> of compact lattices (in,
-// out: compact buffers; shapes of 8 rows).
-hipError_t launch_step_compact_batch(const void *desc, const int *blat, const int *bitem, int nblocks,
+// out: compact buffers of storage prec, 1 = F32 or 2 = F16; shapes of 8
+// rows).
+hipError_t launch_step_compact_batch(int prec, const void *desc, const int *blat, const int *bitem, int nblocks,
                                      hipStream_t s);
 
 }  // namespace lbcg

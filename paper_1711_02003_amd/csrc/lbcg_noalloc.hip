@@ -136,9 +136,8 @@ extern "C" int lbcg_batch_step_noalloc(lbcg_sim *const *sims, int32_t n, const i
         if (s->kernel != LBCG_KERNEL_FUSED && s->kernel != LBCG_KERNEL_COMPACT) return LBCG_E_INVAL;
         // the batched sweeps relax with the regularized collision only
         if (s->collision != LBCG_REGULARIZED) return LBCG_E_INVAL;
-        // the batched compact sweep: periodic lattices, FP32
+        // the batched compact sweep: periodic lattices
         if (s->kernel == LBCG_KERNEL_COMPACT && s->g.mask) return LBCG_E_INVAL;
-        if (s->kernel == LBCG_KERNEL_COMPACT && s->prec != LBCG_F32) return LBCG_E_INVAL;
         if (s->kernel != s0->kernel || s->prec != s0->prec || s->stream != s0->stream || s->device != s0->device)
             return LBCG_E_INVAL;
         if (nsteps[j] < 0) return LBCG_E_INVAL;
@@ -262,7 +261,7 @@ extern "C" int lbcg_batch_step_noalloc(lbcg_sim *const *sims, int32_t n, const i
             const int par = int(t & 1);
             hipError_t e = hipSuccess;
             if (compact) {
-                e = launch_step_compact_batch(desc + size_t(par) * kMaxLat, latU, itemU, nbU, st);
+                e = launch_step_compact_batch(s0->prec, desc + size_t(par) * kMaxLat, latU, itemU, nbU, st);
             } else {
                 if (nbU > 0)
                     e = launch_step_fused_batch(s0->prec, desc + size_t(par) * kMaxLat, latU, itemU, nbU, rows, false,

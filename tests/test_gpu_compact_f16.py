@@ -184,15 +184,32 @@ def test_compact_f16_full_size_sampled(L, orc):
     s.close()
 
 
-def test_compact_f16_not_batched(L, stream):
-    # the batched compact sweep stores FP32: FP16 compact handles are refused
-    ws = [W.droplets_27(L=16, seed=k) for k in range(2)]
+def test_compact_f16_batched_matches_plain_bitwise(L, stream):
+    # FP16 compact lattices batched (and through the allocation-free step):
+    # each lattice bitwise as stepped alone (the stochastic rounding draws
+    # from the node's own generator, so the launch does not matter); fresh
+    # handles take their pair-state step alone first; mixing precisions or
+    # geometry is refused
+    ws = W.batch_boxes(n_boxes=3, seed=15, edge_lo=20, edge_hi=52)
+    nsteps = [40, 7, 33]  # a run of >= 32 levels replays graphs
     sims = [_compact16(L, w, stream=stream.cuda_stream) for w in ws]
-    for s in sims:
-        s.step(1)
+    b = L.Batch(sims)
+    info = b.launch_info()
+    _say(f"FP16 compact batch shape {info}")
+    assert info["rows"] == 8
+    b.step(nsteps)
+    b.close()
+    L.batch_step_noalloc(sims, [3, 0, 5], (8, 16))
+    for w, s, n in zip(ws, sims, [43, 7, 38]):
+        ref = _compact16(L, w)
+        ref.step(n)
+        assert np.array_equal(s.populations(), ref.populations()), w.name
+        assert s.diagnostics()["step"] == n
+        ref.close()
+    f32 = L.Sim.from_workload(ws[0], precision="f32", kernel=L.KERNEL_COMPACT, stream=stream.cuda_stream)
     with pytest.raises(L.LbcgError):
-        L.Batch(sims)
+        L.Batch([sims[0], f32])
     with pytest.raises(L.LbcgError):
-        L.batch_step_noalloc(sims, [1, 1], (8, 4))
-    for s in sims:
+        L.batch_step_noalloc([sims[0], f32], [1, 1], (8, 8))
+    for s in sims + [f32]:
         s.close()
