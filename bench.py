@@ -28,8 +28,9 @@ of every node (both colours).  Prints one JSON line:
              pair-state strip sweeps and the two-pass generic kernel),
              focusing2d (the 8192 x 2048 D2Q9 junction), focusing (the
              512 x 128 x 64 D3Q19 flow-focusing junction, FP32 and FP16),
-             batched and batched_compact (64 uneven periodic boxes in one
-             launch per time level, pair and compact state, vs the same boxes
+             batched, batched_compact and batched_compact_f16 (64 uneven
+             periodic boxes in one launch per time level, pair and compact
+             state, the latter also with FP16 storage, vs the same boxes
              stepped one after another) and served (a Poisson stream of
              step-emulsifier requests through the continuous-batching server
              vs one request at a time; p50 / p99 time to result).
@@ -47,7 +48,8 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-FORMS = ("pair_f32", "f16", "d2q9", "focusing2d", "focusing", "batched", "batched_compact", "served")
+FORMS = ("pair_f32", "f16", "d2q9", "focusing2d", "focusing", "batched", "batched_compact", "batched_compact_f16",
+         "served")
 TRAFFIC_FILES = {"k_step_compact": os.path.join(ROOT, "profiles", "compact_d3q19_f32_256_traffic.txt"),
                  "k_step_fused": os.path.join(ROOT, "profiles", "fused_d3q19_f32_256_traffic.txt"),
                  "geo_split": os.path.join(ROOT, "profiles", "geo_split_d3q19_f32_junction_traffic.txt"),
@@ -320,12 +322,12 @@ def focusing_form(torch, lbcg, W, steps=200, warmup=10, tune=True):
     return out
 
 
-def batched_form(torch, lbcg, W, steps=200, warmup=10, compact=False):
+def batched_form(torch, lbcg, W, steps=200, warmup=10, compact=False, precision="f32"):
     ws = W.batch_boxes(n_boxes=64, seed=4)
     nodes = sum(w.fluid_nodes for w in ws)
     stream = torch.cuda.Stream()
     kernel = lbcg.KERNEL_COMPACT if compact else lbcg.KERNEL_FUSED
-    sims = [lbcg.Sim.from_workload(w, precision="f32", kernel=kernel, stream=stream.cuda_stream) for w in ws]
+    sims = [lbcg.Sim.from_workload(w, precision=precision, kernel=kernel, stream=stream.cuda_stream) for w in ws]
     for s in sims:
         s.step(2)
     b = lbcg.Batch(sims)
@@ -354,9 +356,12 @@ def batched_form(torch, lbcg, W, steps=200, warmup=10, compact=False):
         s.close()
     mb = nodes * steps / (ms_b / 1e3) / 1e6
     mp = nodes * steps / (ms_p / 1e3) / 1e6
-    bpn = 2 * (19 * 4 + 20) if compact else 304
+    if compact:
+        bpn = 2 * (19 * 4 + 20) if precision == "f32" else 2 * (19 * 2 + 12)
+    else:
+        bpn = 2 * 19 * 2 * (4 if precision == "f32" else 2)
     return {"workload": "64 periodic D3Q19 boxes, edges U{32..96}, seed 4", "nodes": nodes,
-            "state": "compact" if compact else "pairs", "bytes_per_node": bpn,
+            "state": "compact" if compact else "pairs", "storage": precision, "bytes_per_node": bpn,
             "steps": steps, "batched_mlups": round(mb, 1), "plain_mlups": round(mp, 1),
             "speedup": round(mb / mp, 3), "frac": round(mb * bpn / 1e3 / HBM_PEAK_GBS, 4),
             "rows": info["rows"], "zplanes": info["zplanes"], "blocks": info["blocks"]}
@@ -531,6 +536,7 @@ def main():
             "focusing": lambda: focusing_form(torch, lbcg, W, tune=not args.no_form_tune),
             "batched": lambda: batched_form(torch, lbcg, W),
             "batched_compact": lambda: batched_form(torch, lbcg, W, compact=True),
+            "batched_compact_f16": lambda: batched_form(torch, lbcg, W, compact=True, precision="f16"),
             "served": lambda: served_form(torch, lbcg, W, n=args.served_requests,
                                           steps_scale=args.served_steps_scale,
                                           loads=tuple(float(v) for v in args.served_loads.split(",") if v),
