@@ -123,3 +123,22 @@ def test_bgk_fused_limits(L):
     assert shape["rows"] == 8
     b.step(3)
     assert b.diagnostics()["status"] == 0
+
+
+@pytest.mark.parametrize("coll", ["bgk", "bgk_colour"])
+def test_bgk_fused_largest_lattice_sampled(L, orc, coll):
+    # Plain BGK on the fused sweep at the largest cube it takes (304^3 FP32,
+    # byte offsets up to 2^32 - 25 MB), in the automatic launch shape: one
+    # step at 32 sampled nodes against the oracle on 5^3 cuts
+    from tests.test_gpu_parity import _sampled_one_step
+    c = {"bgk": (L.BGK, orc.BGK), "bgk_colour": (L.BGK_COLOUR, orc.BGK_COLOUR)}[coll]
+    w = W.droplets_27(L=304, seed=2)
+    s = L.Sim.from_workload(w, precision="f32", collision=c[0])
+    info = s.launch_info()
+    _say(f"BGK {coll} 304^3 f32: launch {info}")
+    assert info["kernel"] == L.KERNEL_FUSED and info["rows"] == 8
+    s.step(3)
+    worst = _sampled_one_step(L, orc, w, s, n_samples=32, seed=304, collision=c[1])
+    _say(f"  sampled one-step max rel diff {worst:.2e}")
+    assert worst < 2e-6
+    s.close()

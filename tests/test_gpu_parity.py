@@ -275,10 +275,11 @@ def test_determinism_and_checkpoint(L):
     assert c.diagnostics()["step"] == 40
 
 
-def _sampled_one_step(L, orc, w, s, n_samples=48, seed=0, advance=None):
+def _sampled_one_step(L, orc, w, s, n_samples=48, seed=0, advance=None, collision=None):
     # Each sampled node's next state depends only on the current state within
     # two nodes, so the oracle steps a periodic 5^3 box cut around it.
-    # advance: what takes s one step (default s.step(1); a batch's level).
+    # advance: what takes s one step (default s.step(1); a batch's level);
+    # collision: the oracle's relaxation form (default regularized).
     nx, ny, nz = w.dims
     rng = np.random.default_rng(seed)
     centres = np.stack([rng.integers(0, nx, n_samples), rng.integers(0, ny, n_samples),
@@ -295,7 +296,8 @@ def _sampled_one_step(L, orc, w, s, n_samples=48, seed=0, advance=None):
     else:
         advance()
     after = s.populations_at(np.array([b[62] for b in boxes]))  # 62 = centre of a 5^3 box
-    p = orc.Params(lattice=orc.D3Q19, dims=(5, 5, 5), tau=(w.tau_R, w.tau_B), A=(w.A, w.A), beta=w.beta)
+    p = orc.Params(lattice=orc.D3Q19, dims=(5, 5, 5), tau=(w.tau_R, w.tau_B), A=(w.A, w.A), beta=w.beta,
+                   collision=orc.REGULARIZED if collision is None else collision)
     worst = 0.0
     for j in range(len(centres)):
         o = orc.Oracle(p)
