@@ -372,18 +372,13 @@ def test_compact2d_f32_matches_oracle_1000_steps(L, orc):
     assert abs(d1["mass_B"] - d0["mass_B"]) / d0["mass_B"] < 1e-6
 
 
-def test_compact2d_full_size_sampled(L, orc):
-    # the benchmark's 4096^2 D2Q9 lattice: sampled nodes' next state against
-    # the oracle's step of a periodic 5 x 5 box cut around each
-    w = W.droplets_2d(n=4096, seed=6)
-    _say("full size 4096^2 compact2d f32")
-    s = L.Sim.from_workload(w, precision="f32", kernel=L.KERNEL_COMPACT)
-    s.step(2)
-    s.tune()
-    s.step(18)
+def _sampled_one_step_2d(orc, w, s, n_samples=48, seed=3):
+    # A D2Q9 node's next state depends only on the current state within two
+    # nodes, so the oracle steps a periodic 5 x 5 box cut around each
+    # sampled node; the largest relative difference of its populations.
     nx, ny, _ = w.dims
-    rng = np.random.default_rng(3)
-    centres = np.stack([rng.integers(0, nx, 48), rng.integers(0, ny, 48)], 1)
+    rng = np.random.default_rng(seed)
+    centres = np.stack([rng.integers(0, nx, n_samples), rng.integers(0, ny, n_samples)], 1)
     off = np.arange(-2, 3)
     boxes = []
     for cx, cy in centres:
@@ -400,8 +395,45 @@ def test_compact2d_full_size_sampled(L, orc):
         o.step(1)
         ref = o.populations()[:, :, 0, 2, 2]
         worst = max(worst, float(np.abs(after[j] - ref).max() / np.abs(ref).max()))
+    return worst
+
+
+def test_compact2d_full_size_sampled(L, orc):
+    # the benchmark's 4096^2 D2Q9 lattice in its tuned launch shape
+    w = W.droplets_2d(n=4096, seed=6)
+    _say("full size 4096^2 compact2d f32")
+    s = L.Sim.from_workload(w, precision="f32", kernel=L.KERNEL_COMPACT)
+    s.step(2)
+    s.tune()
+    s.step(18)
+    worst = _sampled_one_step_2d(orc, w, s)
     _say(f"  sampled one-step max rel diff {worst:.2e}")
     assert worst < 2e-6
+
+
+@pytest.mark.parametrize("kernel", ["fused", "compact"])
+def test_d2q9_largest_lattice_and_beyond(L, orc, kernel):
+    # The D2Q9 strip sweeps (pair and compact state) address the pair state
+    # with 32-bit byte offsets: 7712^2 FP32 (4.28 GB per pair buffer, offsets
+    # up to 2^32 - 13 MB) is the largest square they take, one step at 32
+    # sampled nodes against the oracle; at 7744^2 (4.32 GB) both refuse and
+    # the automatic choice is the generic kernel.
+    k = {"fused": L.KERNEL_FUSED, "compact": L.KERNEL_COMPACT}[kernel]
+    w = W.droplets_2d(n=7712, seed=6)
+    _say(f"7712^2 D2Q9 f32 {kernel}")
+    s = L.Sim.from_workload(w, precision="f32", kernel=k)
+    assert s.launch_info()["kernel"] == k
+    s.step(3)
+    worst = _sampled_one_step_2d(orc, w, s, n_samples=32, seed=7712)
+    _say(f"  sampled one-step max rel diff {worst:.2e}")
+    assert worst < 2e-6
+    s.close()
+    del w
+    with pytest.raises(L.LbcgError):
+        L.Sim("D2Q9", (7744, 7744, 1), 1.0, 0.6, 0.005, 0.7, "f32", kernel=k)
+    g = L.Sim("D2Q9", (7744, 7744, 1), 1.0, 0.6, 0.005, 0.7, "f32")
+    assert g.launch_info()["kernel"] == L.KERNEL_GENERIC
+    g.close()
 
 
 def test_compact2d_reads_and_resume(L):
