@@ -184,6 +184,28 @@ def test_compact_f16_full_size_sampled(L, orc):
     s.close()
 
 
+@pytest.mark.parametrize("kernel", ["fused", "compact"])
+def test_f16_largest_lattice_and_beyond(L, orc, kernel):
+    # FP16 storage halves the bytes per population, so the sweeps take
+    # larger lattices within their 32-bit byte offsets: 383^3 (4.27 GB per
+    # FP16 pair buffer) is the largest cube, one step at 32 sampled nodes
+    # against the oracle within two units of a stored share; 384^3 (4.30 GB)
+    # is refused.
+    k = {"fused": L.KERNEL_FUSED, "compact": L.KERNEL_COMPACT}[kernel]
+    w = W.droplets_27(L=383, seed=2)
+    _say(f"383^3 f16 {kernel}")
+    s = L.Sim.from_workload(w, precision="f16", kernel=k)
+    assert s.launch_info()["kernel"] == k
+    s.step(3)
+    worst = _sampled_one_step(L, orc, w, s, n_samples=32, seed=383)
+    _say(f"  sampled one-step max rel diff {worst:.2e}")
+    assert worst < 2 * U16_SHARE
+    s.close()
+    del w
+    with pytest.raises(L.LbcgError):
+        L.Sim("D3Q19", (384, 384, 384), 1.0, 0.6, 0.005, 0.7, "f16", kernel=k)
+
+
 def test_compact_f16_batched_matches_plain_bitwise(L, stream):
     # FP16 compact lattices batched (and through the allocation-free step):
     # each lattice bitwise as stepped alone (the stochastic rounding draws
