@@ -58,10 +58,11 @@ extern "C" {
  * form of Eq. (5), both at the node's rate (see tau_B below), or Eq. (5) as
  * it is written, each colour relaxed towards its own equilibrium at its own
  * rate 1/tau_k (the literal baseline of Fig. 1; it does not keep momentum
- * where tau_R != tau_B).  Both BGK forms run on the generic kernel and, for
- * D3Q19 with F32 or F16 storage, on the fused column sweep (tiles of 8 rows,
- * tile[0] 0 or 8; not the split step of lattices with geometry, the compact
- * state, the batched sweeps or the D2Q9 sweep). */
+ * where tau_R != tau_B).  Both BGK forms run on the generic kernel and,
+ * with F32 or F16 storage, on the fused sweeps: the D3Q19 column sweep
+ * (tiles of 8 rows, tile[0] 0 or 8) and the D2Q9 strip sweep; not on the
+ * split step of D3Q19 lattices with geometry, the compact state or the
+ * batched sweeps. */
 #define LBCG_REGULARIZED 0
 #define LBCG_BGK 1
 #define LBCG_BGK_COLOUR 2

@@ -20,6 +20,12 @@
 // Every stored population is read from HBM once and written once: 2 x 18 x
 // sizeof(storage) bytes per node (144 B FP32), against ~224 B for the
 // two-pass step (psi pass plus step pass).
+//
+// POPS (plain BGK, Eq. (5), at the node's rate or per colour): every
+// population relaxes from its own pulled value, so the sweep keeps the
+// decoded populations of the row being collided beside its moments.
+#include <type_traits>
+
 #include "lbcg_buffer.h"
 #include "lbcg_internal.h"
 
@@ -75,11 +81,16 @@ __device__ __forceinline__ void take2d(const Pending2d<S> &p, Pops<D2Q9, float> 
 
 constexpr float kSentinel2d = 1e30f;  // LDS psi of a wall or outlet node
 
-template <typename S, bool MASKED>
+struct NoPops2d {};
+
+template <typename S, bool MASKED, bool POPS>
 __device__ __forceinline__ void sweep2d(const Fused2dArgs<S> &a, const Model<float> &mo, int strip, int chunk,
                                         float *lds) {
     using L = D2Q9;
     using T = float;
+    // the decoded populations of the row being collided (POPS) and of the
+    // row after it
+    typedef typename std::conditional<POPS, Pops<L, T>, NoPops2d>::type Kept;
     typedef typename PairOf<S>::type P2;
     constexpr uint32_t E = sizeof(P2);
     const int lane = threadIdx.x % kStrip;
@@ -159,11 +170,13 @@ __device__ __forceinline__ void sweep2d(const Fused2dArgs<S> &a, const Model<flo
         }
     };
     T cd = 0, cR = 0, cB = 0, cj[3] = {0, 0, 0}, cS[6] = {0, 0, 0, 0, 0, 0};
+    Kept cq{}, nq{};
     auto interior = [&](int yy, T &d, T &r36R, T &r36B, T j[3], T flux[6]) {
         if (intile && !fluid(plk)) slot(yy)[lane + 1] = solid_psi(link_code(plk));
         if (intile && fluid(plk)) {
             Pops<L, T> q;
             take2d<S>(pp, q);
+            if constexpr (POPS) nq = q;
             Mom<T> m;
             moments<L, T>(q, m);
             d = m.drho;
@@ -209,6 +222,7 @@ __device__ __forceinline__ void sweep2d(const Fused2dArgs<S> &a, const Model<flo
     wait_memory();
     ring_psi(y0);
     interior(y0, cd, cR, cB, cj, cS);
+    cq = nq;
     uint32_t clk = plk;  // link word of the row being collided
     issue(y0 + 1);
 
@@ -239,7 +253,9 @@ __device__ __forceinline__ void sweep2d(const Fused2dArgs<S> &a, const Model<flo
             }
             const T F[3] = {fx, fy, T(0)};
             PostOut<L, T> o;
-            collide<L, T>(mo, cd, cR, cB, cj, cS, F, nullptr, o);
+            const Pops<L, T> *pin = nullptr;
+            if constexpr (POPS) pin = &cq;
+            collide<L, T>(mo, cd, cR, cB, cj, cS, F, pin, o);
             P2 enc[L::Q];
             encode_out<L, S, T>(o, step, uint32_t(x) + uint32_t(a.nx) * uint32_t(y), enc);
             const uint32_t yo = uint32_t(uniform(y)) * row;
@@ -277,6 +293,7 @@ __device__ __forceinline__ void sweep2d(const Fused2dArgs<S> &a, const Model<flo
         }
         __builtin_amdgcn_wave_barrier();
         clk = nlk;
+        cq = nq;
         cd = nd;
         cR = nR;
         cB = nB;
@@ -293,7 +310,7 @@ __device__ __forceinline__ void sweep2d(const Fused2dArgs<S> &a, const Model<flo
 // channel form runs of consecutive blocks (busy blocks interleaved with
 // blocks that return at once were measured to crowd onto fewer CUs), and the
 // tuner picks short chunks that spread a channel over the device.
-template <typename S, bool MASKED>
+template <typename S, bool MASKED, bool POPS>
 __global__ void __launch_bounds__(kStrip * kStripWaves) k_step_fused2d(Fused2dArgs<S> a, Model<float> mo) {
     __shared__ float lds[kStripWaves * 3 * kRing];
     const int wave = threadIdx.x / kStrip;
@@ -302,7 +319,7 @@ __global__ void __launch_bounds__(kStrip * kStripWaves) k_step_fused2d(Fused2dAr
     if (item >= a.nstrips * a.ychunks) return;  // uniform over the wave
     const int strip = MASKED ? item / a.ychunks : item % a.nstrips;
     const int chunk = MASKED ? item % a.ychunks : item / a.nstrips;
-    sweep2d<S, MASKED>(a, mo, strip, chunk, lds + wave * 3 * kRing);
+    sweep2d<S, MASKED, POPS>(a, mo, strip, chunk, lds + wave * 3 * kRing);
 }
 
 bool fused2d_supported(int prec, const Geo &g) {
@@ -330,13 +347,19 @@ static hipError_t launch2d(const Geo &g, const ModelD &md, const void *in, void 
     a.nstrips = (g.nx + kStrip - 1) / kStrip;
     a.ychunks = ychunks < 1 ? 1 : (ychunks > g.ny ? g.ny : ychunks);
     const int items = a.nstrips * a.ychunks;
-    const int blocks = (items + kStripWaves - 1) / kStripWaves;
-    if (g.mask)
-        hipLaunchKernelGGL((k_step_fused2d<S, true>), dim3(blocks), dim3(kStrip * kStripWaves), 0, s, a,
-                           to_model<float>(md));
-    else
-        hipLaunchKernelGGL((k_step_fused2d<S, false>), dim3(blocks), dim3(kStrip * kStripWaves), 0, s, a,
-                           to_model<float>(md));
+    const dim3 grid{unsigned((items + kStripWaves - 1) / kStripWaves)}, block{unsigned(kStrip * kStripWaves)};
+    const Model<float> mo = to_model<float>(md);
+    if (md.bgk) {
+        if (g.mask)
+            hipLaunchKernelGGL((k_step_fused2d<S, true, true>), grid, block, 0, s, a, mo);
+        else
+            hipLaunchKernelGGL((k_step_fused2d<S, false, true>), grid, block, 0, s, a, mo);
+    } else {
+        if (g.mask)
+            hipLaunchKernelGGL((k_step_fused2d<S, true, false>), grid, block, 0, s, a, mo);
+        else
+            hipLaunchKernelGGL((k_step_fused2d<S, false, false>), grid, block, 0, s, a, mo);
+    }
     return hipGetLastError();
 }
 

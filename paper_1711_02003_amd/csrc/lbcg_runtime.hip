@@ -498,10 +498,9 @@ int lbcg_create(const lbcg_params *p, void *dev_buf, size_t bytes, void *hip_str
         return dev_err(e);
     }
 
-    // plain BGK runs on the D3Q19 column sweep (not the D2Q9 strip sweep,
-    // the split step or the compact state)
-    const bool fused_ok = any_fused_supported(s->lattice, s->prec, s->g) &&
-                          (s->collision == LBCG_REGULARIZED || s->lattice == LBCG_D3Q19);
+    // plain BGK runs on the D3Q19 column sweep and the D2Q9 strip sweep
+    // (not the split step or the compact state)
+    const bool fused_ok = any_fused_supported(s->lattice, s->prec, s->g);
     int kind = p->kernel;
     if (kind == LBCG_KERNEL_AUTO) kind = fused_ok ? LBCG_KERNEL_FUSED : LBCG_KERNEL_GENERIC;
     if ((kind == LBCG_KERNEL_FUSED && !fused_ok) ||
