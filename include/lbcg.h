@@ -69,9 +69,8 @@ extern "C" {
 
 /* Kernel choice: automatic, the two-pass generic kernel (every lattice,
  * precision, collision and boundary) or the fused single-pass kernel (F32 or
- * F16 storage, state buffers below 4 GiB; D3Q19 with any collision form or
- * D2Q9 with the regularized collision, any geometry).  Automatic picks the
- * fused kernel where it applies.
+ * F16 storage, state buffers below 4 GiB; D3Q19 or D2Q9, any collision
+ * form, any geometry).  Automatic picks the fused kernel where it applies.
  *
  * LBCG_KERNEL_COMPACT (never picked automatically): the fused sweeps on a
  * compact state, regularized collision: for periodic lattices D3Q19 with F32
