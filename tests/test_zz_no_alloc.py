@@ -2,8 +2,8 @@
 allocate) against lbcg_batch_step, through the C ABI: bitwise the same
 populations for every lattice, on two calls in a row (the second with fewer
 and smaller lattices), on the pair-state sweep (periodic and geometry
-lattices, FP32 and FP16) and on the compact sweep; calls beyond the fixed
-area's limits are refused before anything is queued."""
+lattices, FP32 and FP16) and on the compact sweep (FP32 and FP16); calls
+beyond the fixed area's limits are refused before anything is queued."""
 import numpy as np
 import pytest
 
@@ -43,7 +43,7 @@ def _same(L, a, b, ws):
         assert sa.diagnostics()["step"] == sb.diagnostics()["step"]
 
 
-@pytest.mark.parametrize("prec,kernel", [("f32", "fused"), ("f16", "fused"), ("f32", "compact")])
+@pytest.mark.parametrize("prec,kernel", [("f32", "fused"), ("f16", "fused"), ("f32", "compact"), ("f16", "compact")])
 def test_noalloc_matches_batch_two_calls(L, prec, kernel):
     import torch
     stream = torch.cuda.Stream()
